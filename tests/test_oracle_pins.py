@@ -1,0 +1,226 @@
+"""Pins for the CPU oracle (Sturm bisection), against facts fixed by mathematics
+rather than by the oracle itself: closed forms, invariants, exact rational brute
+force, an independent dense high-precision eigensolver, and special cases.
+
+Each pin is chosen so that a plausible slip in the oracle (a dropped square on
+e, a shifted index in the pivot recurrence, a wrong comparison in the bisection
+update, a lost scale factor) fails at least one test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import tdgen
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def _err(a, b, d, e):
+    diff = np.abs(np.asarray(a) - np.asarray(b)).max()
+    tn = tdgen.tnorm1(d, e)
+    if tn == 0.0:
+        return 0.0 if diff == 0.0 else np.inf
+    return diff / (tn * EPS)
+
+
+# --- closed form -------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 17, 64, 257, 1000])
+@pytest.mark.parametrize("a,b", [(2.0, -1.0), (2.0, 0.25), (-0.5, 3.0), (0.0, 1e-3)])
+def test_toeplitz_closed_form(n, a, b):
+    # Eigenvalues of the Toeplitz tridiagonal (d = a, e = b): a + 2 b cos(k pi/(n+1)), k = 1..n.
+    import mpmath
+
+    d = np.full(n, a)
+    e = np.full(n - 1, b)
+    with mpmath.workdps(40):
+        exact = np.sort([float(a + 2 * mpmath.mpf(b) * mpmath.cos(k * mpmath.pi / (n + 1)))
+                         for k in range(1, n + 1)])
+    assert np.abs(oracle.eigvals(d, e) - exact).max() <= 4.0 * EPS * (abs(a) + 2 * abs(b))
+
+
+# --- invariants --------------------------------------------------------------
+
+@pytest.mark.parametrize("fam", ["uniform", "normal", "wilkinson", "clustered", "paper_normal"])
+def test_trace_and_frobenius(fam):
+    n = 700
+    d, e = tdgen.tridiag(fam, n)
+    lam = oracle.eigvals(d, e)
+    tn = tdgen.tnorm1(d, e)
+    # trace(T) = sum d_i = sum lambda_k
+    assert abs(math.fsum(lam) - math.fsum(d)) <= n * 4 * EPS * tn
+    # ||T||_F^2 = sum d_i^2 + 2 sum e_i^2 = sum lambda_k^2
+    fro = math.fsum(d * d) + 2.0 * math.fsum(e * e)
+    assert abs(math.fsum(lam * lam) - fro) <= 2 * n * tn * 4 * EPS * tn
+    # ascending, and inside the Gershgorin discs' hull
+    assert np.all(np.diff(lam) >= 0)
+    assert lam[0] >= -tn and lam[-1] <= tn
+
+
+# --- exact brute force -------------------------------------------------------
+
+@pytest.mark.parametrize("n", range(1, 9))
+@pytest.mark.parametrize("fam", ["uniform", "normal", "wilkinson", "clustered"])
+def test_exact_charpoly_tiny(n, fam):
+    for inst in range(3):
+        d, e = tdgen.tridiag(fam, n, inst=inst)
+        exact = np.array([float(x) for x in oracle.exact_charpoly_roots(d, e)])
+        assert _err(oracle.eigvals(d, e), exact, d, e) <= 4.0
+
+
+def test_wilkinson21_exact():
+    # W+_21: d_i = |i - 10|, e = 1.  Its top eigenvalues come in pairs that agree
+    # to about 14 digits, a classic stress case for any eigensolver.
+    d, e = tdgen.tridiag("wilkinson", 21)
+    exact = np.array([float(x) for x in oracle.exact_charpoly_roots(d, e, dps=100)])
+    got = oracle.eigvals(d, e)
+    assert _err(got, exact, d, e) <= 4.0
+    assert abs(exact[-1] - 10.746194182903393) < 1e-12  # largest eigenvalue of W+_21
+
+
+@pytest.mark.parametrize("fam", ["uniform", "wilkinson", "paper_clustered"])
+def test_dense_high_precision(fam):
+    # An independent dense symmetric eigensolver (mpmath Jacobi, 40 digits).
+    import mpmath
+
+    n = 48
+    d, e = tdgen.tridiag(fam, n, inst=7)
+    with mpmath.workdps(40):
+        A = mpmath.matrix(n, n)
+        for i in range(n):
+            A[i, i] = d[i]
+        for i in range(n - 1):
+            A[i, i + 1] = e[i]
+            A[i + 1, i] = e[i]
+        ev = mpmath.eigsy(A, eigvals_only=True)
+        exact = np.array(sorted(float(x) for x in ev))
+    assert _err(oracle.eigvals(d, e), exact, d, e) <= 4.0
+
+
+def test_library_crosscheck():
+    # LAPACK's bisection (dstebz) through scipy: an independent implementation.
+    from scipy.linalg import eigvalsh_tridiagonal
+
+    for fam in ["uniform", "normal", "wilkinson", "clustered"]:
+        d, e = tdgen.tridiag(fam, 1500)
+        ref = eigvalsh_tridiagonal(d, e, lapack_driver="stebz")
+        assert _err(oracle.eigvals(d, e), ref, d, e) <= 8.0
+
+
+# --- special cases -------------------------------------------------------------
+
+def test_n1_and_n0():
+    for v in [3.25, -1e-7, 6.0e12]:
+        assert abs(oracle.eigvals(np.array([v]), np.zeros(0))[0] - v) <= 2 * EPS * abs(v)
+    assert oracle.eigvals(np.array([0.0]), np.zeros(0))[0] == 0.0
+    assert oracle.eigvals(np.zeros(0), np.zeros(0)).size == 0
+
+
+def test_n2_closed_form():
+    g = tdgen.rng(tdgen.CFG_TEST, 0, 2, 0)
+    for _ in range(50):
+        d = g.uniform(-3, 3, 2)
+        e = g.uniform(-3, 3, 1)
+        m = 0.5 * (d[0] + d[1])
+        r = math.hypot(0.5 * (d[0] - d[1]), e[0])
+        assert _err(oracle.eigvals(d, e), [m - r, m + r], d, e) <= 4.0
+
+
+def test_diagonal_gives_sorted_d():
+    d, _ = tdgen.tridiag("normal", 300)
+    lam = oracle.eigvals(d, np.zeros(299))
+    assert np.all(np.abs(lam - np.sort(d)) <= 2 * EPS * np.abs(np.sort(d)) + 1e-300)
+
+
+def test_scale_and_shift_equivariance():
+    d, e = tdgen.tridiag("uniform", 400)
+    lam = oracle.eigvals(d, e)
+    # alpha a power of two: scaling is exact, so the result scales bitwise.
+    for alpha in [2.0**-30, 0.5, 8.0, 2.0**40]:
+        assert np.array_equal(oracle.eigvals(alpha * d, alpha * e), alpha * lam)
+    beta = 0.375
+    assert _err(oracle.eigvals(d + beta, e), lam + beta, d, e) <= 4.0
+
+
+def test_sign_and_reversal_invariance():
+    d, e = tdgen.tridiag("normal", 333)
+    lam = oracle.eigvals(d, e)
+    # flipping off-diagonal signs is a diagonal similarity; the recurrence sees only e^2
+    assert np.array_equal(oracle.eigvals(d, -e), lam)
+    # reversing the index order is a permutation similarity (different pivots, same spectrum)
+    assert _err(oracle.eigvals(d[::-1].copy(), e[::-1].copy()), lam, d, e) <= 4.0
+
+
+def test_direct_sum():
+    d1, e1 = tdgen.tridiag("uniform", 37, inst=1)
+    d2, e2 = tdgen.tridiag("uniform", 51, inst=2)
+    d = np.concatenate([d1, d2])
+    e = np.concatenate([e1, [0.0], e2])
+    both = np.sort(np.concatenate([oracle.eigvals(d1, e1), oracle.eigvals(d2, e2)]))
+    assert _err(oracle.eigvals(d, e), both, d, e) <= 4.0
+
+
+def test_nonfinite_rejected():
+    d = np.array([1.0, np.nan, 2.0])
+    with pytest.raises(ValueError):
+        oracle.eigvals(d, np.zeros(2))
+    with pytest.raises(ValueError):
+        oracle.eigvals(np.ones(3), np.array([np.inf, 0.0]))
+
+
+# --- the index / count entry points ------------------------------------------
+
+def test_index_matches_full_and_certify():
+    d, e = tdgen.tridiag("uniform", 900)
+    lam = oracle.eigvals(d, e)
+    ks = np.array([0, 1, 17, 450, 898, 899])
+    assert np.array_equal(oracle.eigvals_index(d, e, ks), lam[ks])
+    t = 8 * EPS * tdgen.tnorm1(d, e)
+    assert oracle.certify(d, e, lam, t) == 0
+    bad = lam.copy()
+    bad[123] += 1e-9  # a planted error far above t must be caught
+    assert oracle.certify(d, e, bad, t) >= 1
+    c = oracle.counts(d, e, np.array([-1e9, 1e9, 0.5 * (lam[10] + lam[11])]))
+    assert list(c) == [0, 900, 11]
+
+
+def test_ql_baseline_agrees():
+    for fam in ["uniform", "toeplitz", "wilkinson", "clustered"]:
+        d, e = tdgen.tridiag(fam, 600)
+        assert _err(oracle.ql_eigvals(d, e), oracle.eigvals(d, e), d, e) <= 200.0
+
+
+# --- gradient reference (dense Hellmann-Feynman) ----------------------------
+
+def test_grad_reference_invariants_and_fd():
+    n = 64
+    d, e = tdgen.tridiag("uniform", n, cfg=tdgen.CFG_GRAD)
+    w = tdgen.loss_weights(n)
+    lam, gd, ge = oracle.grad_reference(d, e, w)
+    L = float(np.dot(w, lam))
+    gmax = max(np.abs(gd).max(), np.abs(ge).max())
+    # columns of Q are unit vectors: sum_i g_d,i = sum_k w_k
+    assert abs(gd.sum() - w.sum()) <= 1e-12 * np.abs(w).sum()
+    # lambda(alpha T) = alpha lambda(T): d . g_d + e . g_e = L
+    assert abs(np.dot(d, gd) + np.dot(e, ge) - L) <= 1e-12 * np.abs(w).sum() * tdgen.tnorm1(d, e)
+    # coordinate-wise central differences of the bisection oracle
+    h = 1e-6
+    for i in [0, 5, 31, 63]:
+        dp, dm = d.copy(), d.copy()
+        dp[i] += h
+        dm[i] -= h
+        fd = (np.dot(w, oracle.eigvals(dp, e)) - np.dot(w, oracle.eigvals(dm, e))) / (2 * h)
+        assert abs(fd - gd[i]) <= 1e-7 * gmax
+    for i in [0, 17, 62]:
+        ep, em = e.copy(), e.copy()
+        ep[i] += h
+        em[i] -= h
+        fd = (np.dot(w, oracle.eigvals(d, ep)) - np.dot(w, oracle.eigvals(d, em))) / (2 * h)
+        assert abs(fd - ge[i]) <= 1e-7 * gmax
