@@ -1,0 +1,102 @@
+/*
+ * tde -- eigenvalues of real symmetric tridiagonal matrices by boundary-row
+ * divide and conquer, FP64, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhan & Zhang, "Reducing Internal State in Eigenvalue-Only
+ * Divide-and-Conquer Tridiagonal Eigensolvers".  T (diagonal d, off-diagonal
+ * e) is torn recursively into two children plus a rank-one term (Section 3.1,
+ * Eq. dc-split); each merge solves the secular equation of
+ * diag(D) + rho z z^T with D the children's spectra and z built from the last
+ * row of the left child's eigenvector matrix and the first row of the right
+ * child's (Eq. merge-problem).  Only those boundary rows are propagated up
+ * the tree (Section 3.2, Eq. boundary-state; Algorithm 1), so device memory is
+ * linear in n.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or equivalent) on the
+ *    current HIP device, unless stated otherwise.  The caller owns every buffer;
+ *    the library never frees caller memory.
+ *  - The matrix T of size n has diagonal d[0..n) and off-diagonal e[0..n-1),
+ *    e[i] coupling rows i and i+1.  Output eigenvalues are ascending.
+ *  - Calls are asynchronous on the given HIP stream (hipStream_t passed as
+ *    void*, NULL = default stream).  Argument errors are returned
+ *    synchronously (negative codes).  Errors found on the device (non-finite
+ *    input, non-convergence) are recorded in a status word inside the
+ *    workspace, read back by tde_get_status.
+ *  - The first call for a given problem shape (sizes and leaf size) builds and
+ *    caches a plan: small device tables describing the merge tree, allocated
+ *    once per shape and device and kept until tde_release_plans.  Later calls
+ *    with the same shape allocate nothing.
+ *  - Inputs and outputs must not overlap.  Concurrent calls on different
+ *    streams need distinct workspaces.
+ *  - No exceptions cross this interface and nothing is printed.
+ */
+#ifndef TDE_H
+#define TDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (LAPACK-like: < 0 bad argument or runtime failure, > 0 numerical). */
+#define TDE_OK 0
+#define TDE_EINVAL (-1)     /* bad argument (size, pointer, offsets, option, workspace too small) */
+#define TDE_ENOMEM (-2)     /* plan tables could not be allocated */
+#define TDE_EDEVICE (-3)    /* HIP runtime error while enqueuing */
+#define TDE_ENONFINITE (-4) /* device status: NaN or Inf in d or e */
+#define TDE_ENOCONV 1       /* device status: a leaf QL or secular iteration hit its cap */
+
+/* Options.  Pass NULL for defaults. */
+typedef struct {
+    int leaf;      /* largest leaf size solved directly by QL, 1..64; 0 = default (32) */
+    int flags;     /* reserved, must be 0 */
+    int reserved[6];
+} tde_opts;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int tde_version(void);
+
+/* Bytes of device workspace needed to solve B problems with n_total columns in
+ * total (n_total = n for a single problem).  Linear in n_total (about 200 bytes
+ * per column).  Returns 0 on a bad argument. */
+size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts);
+
+/* All eigenvalues of one n x n symmetric tridiagonal T.
+ *   d      [n]     diagonal (device, read only)
+ *   e      [n-1]   off-diagonal (device, read only; may be NULL when n <= 1)
+ *   n      >= 0; n == 0 is a no-op
+ *   lambda [n]     output eigenvalues, ascending (device)
+ *   ws     workspace of ws_bytes >= tde_workspace_bytes(n, 1, opts) (device)
+ * Returns TDE_OK or a negative code; device-side failures via tde_get_status. */
+int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, void* ws, size_t ws_bytes,
+                void* hip_stream, const tde_opts* opts);
+
+/* All eigenvalues of B independent tridiagonals packed back to back.
+ *   offsets [B+1]  HOST array, offsets[0] = 0, nondecreasing; problem b owns
+ *                  d[offsets[b] .. offsets[b+1]) and e over the same range
+ *                  (its last slot, offsets[b+1]-1, is ignored).
+ *   lambda  [offsets[B]] output, ascending within each problem.
+ * Every merge of one tree height, across all problems, runs in the same
+ * launches (level-aligned schedule). */
+int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                        void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
+
+/* Waits for the stream, then reads the device status word of the last solve
+ * that used ws: TDE_OK, TDE_ENONFINITE or TDE_ENOCONV.  Returns a negative code
+ * if the read itself fails. */
+int tde_get_status(const void* ws, void* hip_stream);
+
+/* Frees every cached plan (device tables).  Not safe while solves are queued. */
+void tde_release_plans(void);
+
+/* Human-readable name of a status code (static string). */
+const char* tde_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDE_H */

@@ -1,0 +1,220 @@
+"""Python binding of libtde: FP64 eigenvalues of symmetric tridiagonal matrices
+by boundary-row divide and conquer on MI355X (gfx950).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  Importing this
+package imports torch first so that libtde binds to the HIP runtime torch has
+already loaded (one runtime per process).  There is no CPU fallback: without
+the built library or a GPU every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "eigvals",
+    "eigvals_batched",
+    "workspace_bytes",
+    "last_status",
+    "TDEError",
+    "lib",
+    "LIB_PATH",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtde.so")
+
+TDE_OK = 0
+TDE_EINVAL = -1
+TDE_ENOMEM = -2
+TDE_EDEVICE = -3
+TDE_ENONFINITE = -4
+TDE_ENOCONV = 1
+
+EXPORTS = (
+    "tde_version",
+    "tde_workspace_bytes",
+    "tde_eigvals",
+    "tde_eigvals_batched",
+    "tde_get_status",
+    "tde_release_plans",
+    "tde_status_string",
+)
+
+
+class TDEError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _status_string(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class tde_opts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def _hip_runtimes_loaded():
+    libs = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    libs.add(line.split()[-1])
+    except OSError:
+        pass
+    return libs
+
+
+def lib():
+    """Load libtde.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2605_26599_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        optp = ctypes.POINTER(tde_opts)
+        L.tde_version.argtypes = []
+        L.tde_version.restype = ctypes.c_int
+        L.tde_workspace_bytes.argtypes = [i64, i64, optp]
+        L.tde_workspace_bytes.restype = sz
+        L.tde_eigvals.argtypes = [vp, vp, i64, vp, vp, sz, vp, optp]
+        L.tde_eigvals.restype = ctypes.c_int
+        L.tde_eigvals_batched.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), i64, vp, vp, sz, vp, optp]
+        L.tde_eigvals_batched.restype = ctypes.c_int
+        L.tde_get_status.argtypes = [vp, vp]
+        L.tde_get_status.restype = ctypes.c_int
+        L.tde_release_plans.argtypes = []
+        L.tde_release_plans.restype = None
+        L.tde_status_string.argtypes = [ctypes.c_int]
+        L.tde_status_string.restype = ctypes.c_char_p
+        _lib = L
+        return L
+
+
+def _status_string(code: int) -> str:
+    try:
+        return lib().tde_status_string(int(code)).decode()
+    except Exception:  # pragma: no cover - only when the library is absent
+        return "status"
+
+
+def _opts(leaf):
+    if leaf is None:
+        return None
+    o = tde_opts()
+    o.leaf = int(leaf)
+    o.flags = 0
+    return ctypes.byref(o)
+
+
+def workspace_bytes(n_total: int, batch: int = 1, leaf=None) -> int:
+    nb = int(lib().tde_workspace_bytes(int(n_total), int(batch), _opts(leaf)))
+    if nb == 0 and n_total >= 0:
+        raise TDEError(TDE_EINVAL, "workspace_bytes")
+    return nb
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device: torch.device) -> torch.Tensor:
+    key = (device.index, torch.cuda.current_stream(device).cuda_stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _check_input(d: torch.Tensor, e: torch.Tensor | None):
+    if not isinstance(d, torch.Tensor) or d.dtype != torch.float64 or not d.is_cuda or d.dim() != 1:
+        raise TypeError("d must be a 1-D float64 CUDA (HIP) tensor")
+    if not d.is_contiguous():
+        raise ValueError("d must be contiguous")
+    if e is not None:
+        if not isinstance(e, torch.Tensor) or e.dtype != torch.float64 or not e.is_cuda or e.dim() != 1:
+            raise TypeError("e must be a 1-D float64 CUDA (HIP) tensor")
+        if not e.is_contiguous():
+            raise ValueError("e must be contiguous")
+        if e.device != d.device:
+            raise ValueError("d and e must be on the same device")
+
+
+def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+    """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
+    off-diagonal e[n-1], on d's device and torch's current stream."""
+    _check_input(d, e)
+    n = d.numel()
+    if e.numel() < max(n - 1, 0):
+        raise ValueError("e must hold n-1 entries")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=d.device)
+    if n == 0:
+        return out
+    nb = workspace_bytes(n, 1, leaf)
+    ws = workspace if workspace is not None else _workspace(nb, d.device)
+    if ws.numel() < nb:
+        raise ValueError("workspace too small")
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
+                               ws.data_ptr(), ws.numel(), stream, _opts(leaf))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals device status")
+    return out
+
+
+def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
+                    workspace: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+    """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
+    and e over the same range (last slot unused).  offsets is a host sequence."""
+    _check_input(d, e)
+    offs = [int(x) for x in offsets]
+    B = len(offs) - 1
+    n = offs[-1] if B >= 0 else 0
+    if d.numel() < n or e.numel() < n:
+        raise ValueError("d and e must hold offsets[-1] entries")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=d.device)
+    if B <= 0 or n == 0:
+        return out
+    nb = workspace_bytes(n, B, leaf)
+    ws = workspace if workspace is not None else _workspace(nb, d.device)
+    if ws.numel() < nb:
+        raise ValueError("workspace too small")
+    arr = (ctypes.c_int64 * (B + 1))(*offs)
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), stream, _opts(leaf))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_batched")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_batched device status")
+    return out
+
+
+def last_status(workspace: torch.Tensor) -> int:
+    """Device status word of the last solve that used this workspace (syncs)."""
+    stream = torch.cuda.current_stream(workspace.device).cuda_stream
+    return int(lib().tde_get_status(workspace.data_ptr(), stream))

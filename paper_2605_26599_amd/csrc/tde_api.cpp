@@ -1,0 +1,182 @@
+// C-ABI of the BR D&C eigenvalue library: argument checks, plan cache and
+// workspace carving.  The numerical work is enqueued by enqueue_solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/tde.h"
+#include "tde_plan.h"
+#include "tde_tree.h"
+
+namespace tde {
+namespace {
+
+using PlanKey = std::tuple<int, int, std::vector<long long>>;
+std::mutex g_mu;
+std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+
+void free_plan(Plan* p) {
+    if (p->d_merges) (void)hipFree(p->d_merges);
+    if (p->d_leaves) (void)hipFree(p->d_leaves);
+    if (p->d_offs) (void)hipFree(p->d_offs);
+    p->d_merges = nullptr;
+    p->d_leaves = nullptr;
+    p->d_offs = nullptr;
+}
+
+int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** out) {
+    PlanKey key{device, leaf, offs};
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return TDE_OK;
+    }
+    auto p = std::make_unique<Plan>();
+    p->device = device;
+    p->leaf = leaf;
+    p->offs = offs;
+    p->B = (int)offs.size() - 1;
+    p->ntot = offs.back();
+    const LevelTables t = build_tree(leaf, offs);
+    const std::vector<MergeRec>& flat = t.merges;
+    int maxM = 1;
+    long long maxN = 1;
+    for (size_t h = 0; h < t.mstart.size(); ++h) {
+        LevelInfo info{};
+        info.mstart = t.mstart[h];
+        info.M = t.mcount[h];
+        info.N = t.ncols[h];
+        maxM = std::max(maxM, info.M);
+        maxN = std::max(maxN, info.N);
+        p->levels.push_back(info);
+    }
+    p->maxM = maxM;
+    p->maxN = maxN;
+    p->nleaves = (int)t.leaves.size();
+    int lmax = 1;
+    for (auto& L : t.leaves) lmax = std::max(lmax, L.size);
+    p->leafmax = lmax;
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 8;
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+        return true;
+    };
+    bool ok = upload((void**)&p->d_merges, flat.empty() ? nullptr : flat.data(), flat.size() * sizeof(MergeRec)) &&
+              upload((void**)&p->d_leaves, t.leaves.empty() ? nullptr : t.leaves.data(),
+                     t.leaves.size() * sizeof(LeafRec)) &&
+              upload((void**)&p->d_offs, offs.data(), offs.size() * sizeof(long long));
+    if (!ok) {
+        free_plan(p.get());
+        return TDE_ENOMEM;
+    }
+    *out = p.get();
+    g_plans.emplace(std::move(key), std::move(p));
+    return TDE_OK;
+}
+
+int resolve_leaf(const tde_opts* opts, int* leaf) {
+    int L = 32;
+    if (opts) {
+        if (opts->flags != 0) return TDE_EINVAL;
+        if (opts->leaf != 0) L = opts->leaf;
+    }
+    if (L < 1 || L > kLeafMax) return TDE_EINVAL;
+    *leaf = L;
+    return TDE_OK;
+}
+
+int solve(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
+          size_t ws_bytes, void* stream, const tde_opts* opts) {
+    int leaf;
+    if (resolve_leaf(opts, &leaf) != TDE_OK) return TDE_EINVAL;
+    const long long ntot = offs.back();
+    const long long B = (long long)offs.size() - 1;
+    if (ntot == 0) return TDE_OK;
+    if (!d || !lambda || !ws) return TDE_EINVAL;
+    bool need_e = false;
+    for (long long b = 0; b < B; ++b)
+        if (offs[b + 1] - offs[b] > 1) need_e = true;
+    if (need_e && !e) return TDE_EINVAL;
+    if (ws_bytes < workspace_layout(ntot, B, ntot / 2 + 1, nullptr, nullptr)) return TDE_EINVAL;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
+    Plan* plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        int rc = make_plan(device, leaf, offs, &plan);
+        if (rc != TDE_OK) return rc;
+    }
+    Work w{};
+    workspace_layout(ntot, B, plan->maxM, (char*)ws, &w);
+    int rc = enqueue_solve(*plan, w, d, e, lambda, stream);
+    return rc == 0 ? TDE_OK : TDE_EDEVICE;
+}
+
+}  // namespace
+}  // namespace tde
+
+extern "C" {
+
+int tde_version(void) { return 100; }
+
+size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts) {
+    int leaf;
+    if (n_total < 0 || batch < 0 || tde::resolve_leaf(opts, &leaf) != TDE_OK) return 0;
+    return tde::workspace_layout(n_total, batch, n_total / 2 + 1, nullptr, nullptr);
+}
+
+int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, void* ws, size_t ws_bytes,
+                void* hip_stream, const tde_opts* opts) {
+    if (n < 0 || n > (int64_t)0x3fffffff) return TDE_EINVAL;
+    std::vector<long long> offs{0, (long long)n};
+    return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts);
+}
+
+int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                        void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts) {
+    if (B < 0 || (B > 0 && !offsets)) return TDE_EINVAL;
+    if (B == 0) return TDE_OK;
+    std::vector<long long> offs((size_t)B + 1);
+    for (int64_t b = 0; b <= B; ++b) offs[b] = offsets[b];
+    if (offs[0] != 0) return TDE_EINVAL;
+    for (int64_t b = 0; b < B; ++b)
+        if (offs[b + 1] < offs[b]) return TDE_EINVAL;
+    if (offs[B] > (long long)0x3fffffff) return TDE_EINVAL;
+    return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts);
+}
+
+int tde_get_status(const void* ws, void* hip_stream) {
+    if (!ws) return TDE_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TDE_EDEVICE;
+    int st = 0;
+    if (hipMemcpy(&st, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return TDE_EDEVICE;
+    if (st & tde::ST_NONFINITE) return TDE_ENONFINITE;
+    if (st & (tde::ST_LEAF_NOCONV | tde::ST_SEC_NOCONV)) return TDE_ENOCONV;
+    return TDE_OK;
+}
+
+void tde_release_plans(void) {
+    std::lock_guard<std::mutex> lk(tde::g_mu);
+    for (auto& kv : tde::g_plans) tde::free_plan(kv.second.get());
+    tde::g_plans.clear();
+}
+
+const char* tde_status_string(int status) {
+    switch (status) {
+        case TDE_OK: return "ok";
+        case TDE_EINVAL: return "invalid argument";
+        case TDE_ENOMEM: return "out of memory";
+        case TDE_EDEVICE: return "HIP runtime error";
+        case TDE_ENONFINITE: return "non-finite input";
+        case TDE_ENOCONV: return "iteration did not converge";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

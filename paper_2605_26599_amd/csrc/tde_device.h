@@ -1,0 +1,628 @@
+// Per-thread bodies of the BR D&C kernels (gfx950).  Every element-parallel
+// kernel in tde_kernels.hip is a thin wrapper that maps its thread index to one
+// call of a body below; the bodies hold all of the method's arithmetic.
+//
+// Notation follows the paper (Section 3.1, merge problem): a merge of children
+// L and R has poles D = Lambda_L (+) Lambda_R, secular vector
+// z = concat(bhi(Q_L), blo(Q_R)) and coupling rho; the parent eigenvalues are
+// the roots of 1 + rho * sum_j z_j^2 / (D_j - lambda) = 0.  We use the
+// normalised tear z~ = z / sqrt(2), rho~ = 2 |beta| (beta the torn
+// off-diagonal), sign(beta) applied to the right half, so that ||z~|| = 1.
+#pragma once
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tde_internal.h"
+
+#ifndef TDE_DEV
+#define TDE_DEV __device__ __forceinline__
+#endif
+#ifndef TDE_ATOMIC_MAX_U64
+#define TDE_ATOMIC_MAX_U64(p, v) atomicMax((p), (v))
+#endif
+#ifndef TDE_ATOMIC_OR
+#define TDE_ATOMIC_OR(p, v) atomicOr((p), (v))
+#endif
+
+namespace tde {
+
+TDE_DEV unsigned long long dbits(double x) {
+    union { double d; unsigned long long u; } c;
+    c.d = x;
+    return c.u;
+}
+TDE_DEV double bitsd(unsigned long long u) {
+    union { double d; unsigned long long u; } c;
+    c.u = u;
+    return c.d;
+}
+
+// Exact power-of-two scale 2^ceil(log2 max|T_ij|) of a problem (driver-level
+// scaling of unreduced blocks, Section 4.2); 1 for the zero matrix.
+TDE_DEV double scale_of(unsigned long long maxbits) {
+    double mx = bitsd(maxbits);
+    if (!(mx > 0.0) || !(mx <= DBL_MAX)) return 1.0;
+    int ex;
+    frexp(mx, &ex);
+    return ldexp(1.0, ex);
+}
+
+// Largest m in [0, M) with key(m) <= t, for nondecreasing keys (merge lookup).
+TDE_DEV int find_merge(const MergeRec* __restrict__ mr, int M, long long t) {
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (mr[mid].pk <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Coupling of a merge: rho~ = 2|beta| / scale and sign(beta), beta the torn
+// off-diagonal e[off + nL - 1] (paper Eq. dc-split; tearing convention of DESIGN).
+TDE_DEV double merge_rho(const MergeRec& R, const double* __restrict__ e,
+                         const unsigned long long* __restrict__ pmax, double* sgn) {
+    double beta = e[R.off + R.nL - 1] * (1.0 / scale_of(pmax[R.prob]));
+    *sgn = (beta < 0.0) ? -1.0 : 1.0;
+    return 2.0 * fabs(beta);
+}
+
+// Deflation tolerance of a merge: 8 eps max(max|D|, max|z~|); the poles are
+// sorted so max|D| is attained at an end.
+TDE_DEV double merge_tol(const double* __restrict__ D, long long pk, int s, unsigned long long zmaxbits) {
+    double dmax = fmax(fabs(D[pk]), fabs(D[pk + s - 1]));
+    return 8.0 * DBL_EPSILON * fmax(dmax, bitsd(zmaxbits));
+}
+
+// Close-pole test for consecutive poles a < b (Section 4.1, deflation): the
+// Givens rotation that zeroes z_a drops an off-diagonal (D_b - D_a) c s.
+TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) {
+    double t = hypot(za, zb);
+    double c = zb / t, s = za / t;
+    return fabs((Db - Da) * c * s) <= tol;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf: implicit QL with a Wilkinson-type shift on one small tridiagonal,
+// accumulating only rows 0 and l-1 of the eigenvector matrix (Algorithm 1,
+// leaf step; rows of Q G are the selected rows of Q times G, Lemma 2).
+// Arrays are strided (stride = lanes sharing the LDS tile).  Returns 0 or
+// ST_LEAF_NOCONV.  On exit d holds the eigenvalues ascending and r0/r1 the
+// first/last eigenvector rows in the same column order.
+// ---------------------------------------------------------------------------
+TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st) {
+#define A_(p, i) p[(i) * st]
+    int status = 0;
+    for (int i = 0; i < nl; ++i) {
+        A_(r0, i) = (i == 0) ? 1.0 : 0.0;
+        A_(r1, i) = (i == nl - 1) ? 1.0 : 0.0;
+    }
+    A_(e, nl - 1) = 0.0;
+    for (int l = 0; l < nl; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m + 1 < nl; ++m) {
+                double dd = fabs(A_(d, m)) + fabs(A_(d, m + 1));
+                if (fabs(A_(e, m)) <= DBL_EPSILON * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 60) { status = ST_LEAF_NOCONV; break; }
+            double g = (A_(d, l + 1) - A_(d, l)) / (2.0 * A_(e, l));
+            double r = hypot(g, 1.0);
+            g = A_(d, m) - A_(d, l) + A_(e, l) / (g + (g >= 0.0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool split = false;
+            for (int i = m - 1; i >= l; --i) {
+                double f = s * A_(e, i);
+                double b = c * A_(e, i);
+                r = hypot(f, g);
+                A_(e, i + 1) = r;
+                if (r == 0.0) {
+                    A_(d, i + 1) -= p;
+                    A_(e, m) = 0.0;
+                    split = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = A_(d, i + 1) - p;
+                r = (A_(d, i) - g) * s + 2.0 * c * b;
+                p = s * r;
+                A_(d, i + 1) = g + p;
+                g = c * r - b;
+                // columns i, i+1 of the two tracked rows
+                double t0 = A_(r0, i + 1);
+                A_(r0, i + 1) = s * A_(r0, i) + c * t0;
+                A_(r0, i) = c * A_(r0, i) - s * t0;
+                double t1 = A_(r1, i + 1);
+                A_(r1, i + 1) = s * A_(r1, i) + c * t1;
+                A_(r1, i) = c * A_(r1, i) - s * t1;
+            }
+            if (split) continue;
+            A_(d, l) -= p;
+            A_(e, l) = g;
+            A_(e, m) = 0.0;
+        }
+    }
+    // ascending order, rows permuted alongside
+    for (int i = 0; i + 1 < nl; ++i) {
+        int k = i;
+        double v = A_(d, i);
+        for (int j = i + 1; j < nl; ++j)
+            if (A_(d, j) < v) { k = j; v = A_(d, j); }
+        if (k != i) {
+            A_(d, k) = A_(d, i);
+            A_(d, i) = v;
+            double t0 = A_(r0, i); A_(r0, i) = A_(r0, k); A_(r0, k) = t0;
+            double t1 = A_(r1, i); A_(r1, i) = A_(r1, k); A_(r1, k) = t1;
+        }
+    }
+    return status;
+#undef A_
+}
+
+// ---------------------------------------------------------------------------
+// Secular equation (Section 2.2, Eq. of the rank-one merge; Section 4.1 root
+// solve; compact roots of the appendix on compact delta reconstruction).
+// Root k (0-based) of f(lambda) = 1 + rho sum_j z_j^2/(D_j - lambda) for
+// strictly ascending poles D[0..K) and nonzero z.  Output: origin pole index
+// org in {k, k+1} and offset tau with lambda_k = D[org] + tau; every
+// denominator is formed as (D_j - D_org) - tau.
+//
+// Iteration: a safeguarded rational model ("middle way"): the poles left of
+// the root (j <= kk) are modelled by one pole at D_kk, the rest by one pole
+// at D_kk+1, each matching value and slope; the model's root in the current
+// bracket is the next iterate, else the bracket midpoint.  Stops when |f| is
+// within its rounding-error bound, when the step is below an ulp of tau, or
+// when the bracket cannot shrink further.  Returns iterations used, negative
+// if the cap was hit.
+// ---------------------------------------------------------------------------
+TDE_DEV double model_step(double f, double d1, double d2, double rdpsi, double rdphi,
+                          double elo, double ehi) {
+    // model g(eta) = c + q/(d1 - eta) + Q/(d2 - eta) with g(0) = f, g'(0) = f'
+    double q = d1 * d1 * rdpsi;
+    double Q = d2 * d2 * rdphi;
+    double c = f - d1 * rdpsi - d2 * rdphi;
+    double a = c * (d1 + d2) + q + Q;
+    double b = d1 * d2 * f;
+    double disc = a * a - 4.0 * b * c;
+    if (!(disc >= 0.0)) disc = 0.0;
+    double sq = sqrt(disc);
+    double den = (a >= 0.0) ? a + sq : a - sq;
+    double r1 = (c != 0.0) ? den / (2.0 * c) : NAN;
+    double r2 = (den != 0.0) ? 2.0 * b / den : NAN;
+    bool in1 = r1 > elo && r1 < ehi;
+    bool in2 = r2 > elo && r2 < ehi;
+    if (in1 && in2) return fabs(r1) < fabs(r2) ? r1 : r2;
+    if (in2) return r2;
+    if (in1) return r1;
+    return NAN;
+}
+
+TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const double* __restrict__ Z,
+                         double rho, int* org_out, double* tau_out) {
+    if (K == 1) {
+        *org_out = 0;
+        *tau_out = rho * Z[0] * Z[0];
+        return 0;
+    }
+    const int kk = (k < K - 1) ? k : K - 2;
+    const double dk = D[kk], dk1 = D[kk + 1];
+    int o;
+    double lo, hi, tau;
+    double psi, dpsi, phi, dphi, err, f;
+    if (k < K - 1) {
+        // Evaluate at the bracket midpoint (origin kk) to pick the nearer pole.
+        const double gap = dk1 - dk;
+        const double mid = 0.5 * gap;
+        psi = dpsi = phi = dphi = err = 0.0;
+        for (int j = 0; j < K; ++j) {
+            double del = (D[j] - dk) - mid;
+            double t = Z[j] / del;
+            double term = Z[j] * t, dterm = t * t;
+            if (j <= kk) { psi += term; dpsi += dterm; }
+            else { phi += term; dphi += dterm; }
+            err += fabs(term);
+        }
+        f = 1.0 + rho * (psi + phi);
+        if (f >= 0.0) { o = k; lo = 0.0; hi = mid; tau = mid; }
+        else { o = k + 1; lo = -mid; hi = 0.0; tau = -mid; }
+        if (f == 0.0) { *org_out = o; *tau_out = tau; return 1; }
+        double eta = model_step(f, -mid, mid, rho * dpsi, rho * dphi, lo - tau, hi - tau);
+        double tn = tau + eta;
+        tau = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+    } else {
+        o = K - 1;
+        double zz = 0.0;
+        for (int j = 0; j < K; ++j) zz += Z[j] * Z[j];
+        lo = 0.0;
+        hi = rho * zz * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
+        tau = 0.5 * hi;
+    }
+    const double Do = D[o];
+    const double d1o = dk - Do, d2o = dk1 - Do;
+    for (int it = 1; it <= kSecMaxIter; ++it) {
+        psi = dpsi = phi = dphi = err = 0.0;
+        for (int j = 0; j < K; ++j) {
+            double del = (D[j] - Do) - tau;
+            double t = Z[j] / del;
+            double term = Z[j] * t, dterm = t * t;
+            if (j <= kk) { psi += term; dpsi += dterm; }
+            else { phi += term; dphi += dterm; }
+            err += fabs(term);
+        }
+        f = 1.0 + rho * (psi + phi);
+        if (fabs(f) <= 8.0 * DBL_EPSILON * (1.0 + rho * err)) {
+            *org_out = o; *tau_out = tau; return it;
+        }
+        if (f < 0.0) lo = tau;
+        else hi = tau;
+        if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) {
+            *org_out = o; *tau_out = tau; return it;
+        }
+        double eta = model_step(f, d1o - tau, d2o - tau, rho * dpsi, rho * dphi, lo - tau, hi - tau);
+        double tn = tau + eta;
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - tau) <= 2.0 * DBL_EPSILON * fabs(tau)) {
+            *org_out = o; *tau_out = tn; return it;
+        }
+        tau = tn;
+    }
+    *org_out = o;
+    *tau_out = tau;
+    return -1;
+}
+
+// lambda_k - D_i from the compact root (org, tau): (D_org - D_i) + tau.
+TDE_DEV double root_minus_pole(const double* __restrict__ D, int org, double tau, int i) {
+    return (D[org] - D[i]) + tau;
+}
+
+// Loewner recomputation of z_i from the computed roots (appendix, WPROD
+// product chains): z_i^2 = prod_k (lambda_k - D_i) / (rho prod_{j!=i}(D_j - D_i)),
+// taken as a chain of ratios of like-signed factors near 1:
+//   k < i: (lambda_k - D_i)/(D_k - D_i);  i <= k < K-1: (lambda_k - D_i)/(D_{k+1} - D_i);
+// times (lambda_{K-1} - D_i).  The sign is that of the input z_i.
+TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double* __restrict__ Z,
+                        const int* __restrict__ org, const double* __restrict__ tau, double rho) {
+    const double di = D[i];
+    double prod = 1.0;
+    for (int k = 0; k < K; ++k) {
+        double num = (D[org[k]] - di) + tau[k];
+        double den;
+        if (k < i) den = D[k] - di;
+        else if (k < K - 1) den = D[k + 1] - di;
+        else den = 1.0;
+        prod *= num / den;
+    }
+    double z2 = prod / rho;
+    double zi = sqrt(fmax(z2, 0.0));
+    return (Z[i] < 0.0) ? -zi : zi;
+}
+
+// Boundary-row propagation for one root (Section 4.1): parent row entries
+// (Q_L (+) Q_R)_sigma y_k with y_k(i) = zhat_i/(D_i - lambda_k), normalised;
+// two streamed dot products, no K x K block.
+TDE_DEV void root_rows(int k, int K, const double* __restrict__ D, const double* __restrict__ zh,
+                       const double* __restrict__ RL, const double* __restrict__ RH, int org, double tau,
+                       double* bl_out, double* bh_out) {
+    const double Do = D[org];
+    double ss = 0.0, bl = 0.0, bh = 0.0;
+    for (int i = 0; i < K; ++i) {
+        double del = (D[i] - Do) - tau;
+        double y = zh[i] / del;
+        ss += y * y;
+        bl += RL[i] * y;
+        bh += RH[i] * y;
+    }
+    double inv = 1.0 / sqrt(ss);
+    *bl_out = bl * inv;
+    *bh_out = bh * inv;
+    (void)k;
+}
+
+// ---------------------------------------------------------------------------
+// Element-parallel level steps.  Packed position t in [0, N) of a level maps
+// to merge m = find_merge(mr, M, t) and local column i = t - mr[m].pk.
+// ---------------------------------------------------------------------------
+
+// (a3/a4) z~, outer rows and merged sorted order of one child column.
+// Left column i: position i + #{right values < x}; right column j:
+// j + #{left values <= x} (ties go left first).  Returns the packed position.
+TDE_DEV long long body_merge(long long t, const MergeRec* __restrict__ mr, int M,
+                             const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
+                             const Work& w, int* m_out, double* absz_out) {
+    const int m = find_merge(mr, M, t);
+    const MergeRec R = mr[m];
+    const int i = (int)(t - R.pk);
+    double sgn;
+    merge_rho(R, e, pmax, &sgn);
+    const double* lamL = w.lam + R.off;
+    const double* lamR = lamL + R.nL;
+    const double rs2 = 0.70710678118654752440;  // 1/sqrt(2)
+    int pos;
+    double x, z, rl, rh;
+    if (i < R.nL) {
+        x = lamL[i];
+        int lo = 0, hi = R.nR;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (lamR[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        pos = i + lo;
+        z = w.bhi[R.off + i] * rs2;
+        rl = w.blo[R.off + i];
+        rh = 0.0;
+    } else {
+        const int j = i - R.nL;
+        x = lamR[j];
+        int lo = 0, hi = R.nL;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (lamL[mid] <= x) lo = mid + 1;
+            else hi = mid;
+        }
+        pos = j + lo;
+        z = sgn * w.blo[R.off + R.nL + j] * rs2;
+        rl = 0.0;
+        rh = w.bhi[R.off + R.nL + j];
+    }
+    const long long P = R.pk + pos;
+    w.D[P] = x;
+    w.Z[P] = z;
+    w.RL[P] = rl;
+    w.RH[P] = rh;
+    *m_out = m;
+    *absz_out = fabs(z);
+    return P;
+}
+
+// (a5) negligible-z test: column stays a candidate iff rho~ |z~_j| > tol.
+TDE_DEV int body_nnflag(long long t, const MergeRec* __restrict__ mr, int M,
+                        const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
+                        const Work& w) {
+    const int m = find_merge(mr, M, t);
+    const MergeRec R = mr[m];
+    double sgn;
+    const double rho = merge_rho(R, e, pmax, &sgn);
+    const double tol = merge_tol(w.D, R.pk, R.nL + R.nR, w.zmax[m]);
+    const int flag = (rho * fabs(w.Z[t]) > tol) ? 1 : 0;
+    w.st[t] = flag;
+    return flag;
+}
+
+// (a5) close poles, step 1: cf[g] = 1 iff non-negligible columns g and g+1
+// of the same merge pass the close-pole test on their unrotated values.
+TDE_DEV void body_closeflag(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
+    const int* __restrict__ nnpos = w.nnpos;
+    const long long t = nnpos[g];
+    const int m = find_merge(mr, M, t);
+    const MergeRec R = mr[m];
+    const int s = R.nL + R.nR;
+    const long long ge = w.scan[R.pk + s];
+    int f = 0;
+    if (g + 1 < ge) {
+        const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
+        const long long u = nnpos[g + 1];
+        f = close_pair(w.D[t], w.Z[t], w.D[u], w.Z[u], tol) ? 1 : 0;
+    }
+    w.cf[g] = f;
+}
+
+// (a5) close poles, step 2.  Candidate g starts a run if it is close to its
+// successor but not to its predecessor; the run extends while cf stays set.
+// The run's owner applies the rotations in order along the run, re-testing
+// each pair on the current (rotated) values, deflating the left column of
+// every rotated pair, then sorts the deflated entries inside the run's span so
+// that each merge's deflated list stays ascending.  Runs are disjoint, so
+// runs proceed in parallel.
+TDE_DEV void body_runs(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
+    const int* __restrict__ nnpos = w.nnpos;
+    const int* __restrict__ cf = w.cf;
+    if (!cf[g]) return;
+    const long long t = nnpos[g];
+    const int m = find_merge(mr, M, t);
+    const MergeRec R = mr[m];
+    const int s = R.nL + R.nR;
+    const long long gs = w.scan[R.pk];
+    if (g > gs && cf[g - 1]) return;
+    long long r = g + 1;
+    while (cf[r]) ++r;  // cf[last column of a merge] == 0 ends every run
+    const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
+    double* D = w.D;
+    double* Z = w.Z;
+    double* RL = w.RL;
+    double* RH = w.RH;
+    long long pc = t;
+    double Dc = D[pc], Zc = Z[pc], Lc = RL[pc], Hc = RH[pc];
+    for (long long j = g + 1; j <= r; ++j) {
+        const long long pj = nnpos[j];
+        const double Dj = D[pj], Zj = Z[pj], Lj = RL[pj], Hj = RH[pj];
+        const double tt = hypot(Zc, Zj);
+        const double c = Zj / tt, sn = Zc / tt;
+        if (fabs((Dj - Dc) * c * sn) <= tol) {
+            // rotate (cur, j): cur deflates with c^2 Dc + s^2 Dj, j keeps z = tt.
+            // Both new diagonal entries are convex combinations of Dc <= Dj;
+            // clamping them into [Dc, Dj] keeps rounding from breaking the
+            // ascending order that the parent assembly merges on.
+            D[pc] = fmin(fmax(c * c * Dc + sn * sn * Dj, Dc), Dj);
+            Z[pc] = 0.0;
+            RL[pc] = c * Lc - sn * Lj;
+            RH[pc] = c * Hc - sn * Hj;
+            w.st[pc] = 2;
+            Dc = fmin(fmax(sn * sn * Dc + c * c * Dj, Dc), Dj);
+            Zc = tt;
+            Lc = sn * Lc + c * Lj;
+            Hc = sn * Hc + c * Hj;
+        } else {
+            D[pc] = Dc;
+            Z[pc] = Zc;
+            RL[pc] = Lc;
+            RH[pc] = Hc;
+            Dc = Dj; Zc = Zj; Lc = Lj; Hc = Hj;
+        }
+        pc = pj;
+    }
+    D[pc] = Dc;
+    Z[pc] = Zc;
+    RL[pc] = Lc;
+    RH[pc] = Hc;
+    // insertion sort of deflated entries (st != 1) within [t, nnpos[r]]
+    const long long p0 = t, p1 = nnpos[r];
+    for (long long p = p0; p <= p1; ++p) {
+        if (w.st[p] == 1) continue;
+        const double kD = D[p], kL = RL[p], kH = RH[p];
+        const int kS = w.st[p];
+        long long h = p;
+        for (long long q = p - 1; q >= p0; --q) {
+            if (w.st[q] == 1) continue;
+            if (D[q] <= kD) break;
+            D[h] = D[q]; RL[h] = RL[q]; RH[h] = RH[q]; w.st[h] = w.st[q];
+            h = q;
+        }
+        D[h] = kD; RL[h] = kL; RH[h] = kH; w.st[h] = kS;
+    }
+}
+
+// Largest m with scan[mr[m].pk] <= g: the merge owning active column g.
+TDE_DEV int find_merge_active(const MergeRec* __restrict__ mr, int M, const int* __restrict__ scan, long long g) {
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (scan[mr[mid].pk] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// (a6) one secular root of the merge owning active column g.
+TDE_DEV int body_secular(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
+                         const unsigned long long* __restrict__ pmax, const Work& w) {
+    const int m = find_merge_active(mr, M, w.scan, g);
+    const MergeRec R = mr[m];
+    const int s = R.nL + R.nR;
+    const long long ks = w.scan[R.pk];
+    const int K = (int)(w.scan[R.pk + s] - ks);
+    double sgn;
+    const double rho = merge_rho(R, e, pmax, &sgn);
+    int o;
+    double tau;
+    int it = secular_root((int)(g - ks), K, w.Da + ks, w.Za + ks, rho, &o, &tau);
+    w.org[g] = o;
+    w.tau[g] = tau;
+    return it;
+}
+
+// (a7) Loewner z-hat for active pole g (non-root merges only).
+TDE_DEV void body_lowner(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
+                         const unsigned long long* __restrict__ pmax, const Work& w) {
+    const int m = find_merge_active(mr, M, w.scan, g);
+    const MergeRec R = mr[m];
+    if (R.flags & MF_ROOT) return;
+    const int s = R.nL + R.nR;
+    const long long ks = w.scan[R.pk];
+    const int K = (int)(w.scan[R.pk + s] - ks);
+    double sgn;
+    const double rho = merge_rho(R, e, pmax, &sgn);
+    w.zhat[g] = lowner_z((int)(g - ks), K, w.Da + ks, w.Za + ks, w.org + ks, w.tau + ks, rho);
+}
+
+// (a7) parent boundary-row entries of active root g (non-root merges only).
+TDE_DEV void body_rows(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
+    const int m = find_merge_active(mr, M, w.scan, g);
+    const MergeRec R = mr[m];
+    if (R.flags & MF_ROOT) return;
+    const int s = R.nL + R.nR;
+    const long long ks = w.scan[R.pk];
+    const int K = (int)(w.scan[R.pk + s] - ks);
+    double bl, bh;
+    root_rows((int)(g - ks), K, w.Da + ks, w.zhat + ks, w.RLa + ks, w.RHa + ks, w.org[g], w.tau[g], &bl, &bh);
+    w.PBL[g] = bl;
+    w.PBH[g] = bh;
+}
+
+// (a9) parent assembly: merge the ascending roots with the ascending deflated
+// values; write the parent's spectrum and boundary rows in place (or the
+// scaled-back eigenvalues for a top merge).
+TDE_DEV void body_assemble(long long t, const MergeRec* __restrict__ mr, int M,
+                           const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
+    const int m = find_merge(mr, M, t);
+    const MergeRec R = mr[m];
+    const int s = R.nL + R.nR;
+    const int i = (int)(t - R.pk);
+    const long long ks = w.scan[R.pk];
+    const int K = (int)(w.scan[R.pk + s] - ks);
+    const long long ds = R.pk - ks;
+    const int nd = s - K;
+    const double* Da = w.Da + ks;
+    const int* og = w.org + ks;
+    const double* ta = w.tau + ks;
+    const double* Dd = w.Dd + ds;
+    const bool root = (R.flags & MF_ROOT) != 0;
+    int pos;
+    double val, bl = 0.0, bh = 0.0;
+    if (i < K) {
+        val = Da[og[i]] + ta[i];
+        int lo = 0, hi = nd;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (Dd[mid] < val) lo = mid + 1;
+            else hi = mid;
+        }
+        pos = i + lo;
+        if (!root) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
+    } else {
+        const int q = i - K;
+        val = Dd[q];
+        int lo = 0, hi = K;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (Da[og[mid]] + ta[mid] <= val) lo = mid + 1;
+            else hi = mid;
+        }
+        pos = q + lo;
+        if (!root) { bl = w.RLd[ds + q]; bh = w.RHd[ds + q]; }
+    }
+    const long long P = R.off + pos;
+    if (root) {
+        out[P] = val * scale_of(pmax[R.prob]);
+    } else {
+        w.lam[P] = val;
+        w.blo[P] = bl;
+        w.bhi[P] = bh;
+    }
+}
+
+// Leaf load + tear + solve for one lane.  The tear subtracts |beta| from the
+// two diagonal entries adjacent to every torn coupling (Eq. dc-split with
+// u = e_m + sign(beta) e_{m+1}, rho = |beta|).
+TDE_DEV int body_leaf(const LeafRec& L, const double* __restrict__ d, const double* __restrict__ e,
+                      const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out,
+                      double* sd, double* se, double* s0, double* s1, int st) {
+    const double inv = 1.0 / scale_of(pmax[L.prob]);
+    const int nl = L.size;
+    for (int i = 0; i < nl; ++i) {
+        double di = d[L.off + i] * inv;
+        if (i == 0 && (L.flags & LF_TEAR_LEFT)) di -= fabs(e[L.off - 1] * inv);
+        if (i == nl - 1 && (L.flags & LF_TEAR_RIGHT)) di -= fabs(e[L.off + nl - 1] * inv);
+        sd[i * st] = di;
+        se[i * st] = (i + 1 < nl) ? e[L.off + i] * inv : 0.0;
+    }
+    int status = leaf_ql(nl, sd, se, s0, s1, st);
+    if (L.flags & LF_WHOLE) {
+        const double sc = 1.0 / inv;
+        for (int i = 0; i < nl; ++i) out[L.off + i] = sd[i * st] * sc;
+    } else {
+        for (int i = 0; i < nl; ++i) {
+            w.lam[L.off + i] = sd[i * st];
+            w.blo[L.off + i] = s0[i * st];
+            w.bhi[L.off + i] = s1[i * st];
+        }
+    }
+    return status;
+}
+
+}  // namespace tde

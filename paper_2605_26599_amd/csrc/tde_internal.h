@@ -1,0 +1,76 @@
+// Internal data layout shared by the host plan and the gfx950 kernels of the
+// boundary-row divide-and-conquer (BR D&C) tridiagonal eigenvalue solver.
+#pragma once
+#include <stdint.h>
+
+namespace tde {
+
+// One rank-one merge of the D&C tree (paper Section 3.1, merge problem).
+// The parent node covers global elements [off, off + nL + nR); its left child
+// is [off, off + nL) and its right child [off + nL, off + nL + nR).  The tear
+// coupling is e[off + nL - 1].  Merges of one tree level are packed back to
+// back: this merge's scratch rows start at packed position pk.
+struct MergeRec {
+    long long off;
+    long long pk;
+    int nL;
+    int nR;
+    int prob;   // problem index within the batch
+    int flags;  // MF_ROOT: top merge of its problem (eigenvalues only, no rows)
+};
+enum { MF_ROOT = 1 };
+
+// One leaf of the D&C tree: global elements [off, off + size) of problem prob.
+struct LeafRec {
+    long long off;
+    int size;
+    int prob;
+    int flags;  // LF_TEAR_LEFT / LF_TEAR_RIGHT: a tear coupling sits on that side;
+                // LF_WHOLE: the leaf is the whole problem (write the output directly)
+    int pad;
+};
+enum { LF_TEAR_LEFT = 1, LF_TEAR_RIGHT = 2, LF_WHOLE = 4 };
+
+// Device status bits (OR-ed into the status word at the start of the workspace).
+enum {
+    ST_NONFINITE = 1,  // NaN or Inf in d or e
+    ST_LEAF_NOCONV = 2,
+    ST_SEC_NOCONV = 4,
+};
+
+constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels
+constexpr int kLeafMax = 64;     // largest leaf the QL leaf kernel accepts
+constexpr int kSecMaxIter = 96;  // secular iteration cap
+
+// Pointers into the caller's workspace for one solve.
+struct Work {
+    int* status;               // [1]
+    unsigned long long* pmax;  // [B]   bits of max |d|,|e| per problem
+    double* lam;               // [n]   node spectra (ascending per node)
+    double* blo;               // [n]   node first eigenvector row
+    double* bhi;               // [n]   node last eigenvector row
+    double* D;                 // [n]   merged, sorted poles (packed per level)
+    double* Z;                 // [n]   secular vector z~ in pole order
+    double* RL;                // [n]   parent-first-row entries per column
+    double* RH;                // [n]   parent-last-row entries per column
+    int* st;                   // [n]   column state: 0 negligible z, 1 active, 2 rotated away
+    int* scan;                 // [n+1] exclusive prefix counts
+    int* bsum;                 // [nb+1] per-block counts
+    int* nnpos;                // [n]   packed positions of non-negligible columns
+    int* cf;                   // [n]   close-pair flag of non-negligible column g and g+1
+    double* Da;                // [n]   active poles
+    double* Za;                // [n]   active z
+    double* RLa;               // [n]
+    double* RHa;               // [n]
+    int* org;                  // [n]   root origin (local active index)
+    double* tau;               // [n]   root offset from its origin pole
+    double* zhat;              // [n]   recomputed (Loewner) secular vector
+    double* PBL;               // [n]   parent first-row entries of active columns
+    double* PBH;               // [n]   parent last-row entries of active columns
+    double* Dd;                // [n]   deflated eigenvalues (sorted per merge)
+    double* RLd;               // [n]
+    double* RHd;               // [n]
+    unsigned long long* zmax;  // [maxM] bits of max |z~| per merge
+};
+
+}  // namespace tde

@@ -1,0 +1,353 @@
+// gfx950 kernels of the boundary-row divide-and-conquer eigenvalue solver and
+// the launch sequence of one solve.  All arithmetic lives in tde_device.h; the
+// kernels here map threads to columns, roots or leaves, aggregate per-merge
+// maxima and prefix counts, and order the steps of each tree level.
+#include <hip/hip_runtime.h>
+
+#include "tde_device.h"
+#include "tde_plan.h"
+
+namespace tde {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, long long n, int v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long u = __shfl_xor(v, o, 64);
+        v = (u > v) ? u : v;
+    }
+    return v;
+}
+
+// Inclusive scan over the workgroup (blockDim.x <= 1024, multiple of 64).
+__device__ __forceinline__ int block_incl_scan(int v, int* wsum) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int d = 1; d < 64; d <<= 1) {
+        int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    if (lane == 63) wsum[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        int x = (lane < nw) ? wsum[lane] : 0;
+        for (int d = 1; d < 16; d <<= 1) {
+            int u = __shfl_up(x, d, 64);
+            if (lane >= d) x += u;
+        }
+        if (lane < nw) wsum[lane] = x;
+    }
+    __syncthreads();
+    if (wid > 0) v += wsum[wid - 1];
+    return v;
+}
+
+// Exclusive scan of the per-block counts bsum[0..nb), total into bsum[nb].
+__global__ __launch_bounds__(1024) void k_scan_blocks(int* bsum, int nb) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = (i < nb) ? bsum[i] : 0;
+        const int incl = block_incl_scan(v, wsum);
+        const int c = carry;
+        if (i < nb) bsum[i] = c + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+// ---------------------------------------------------------------------------
+// Validation and scale: pmax[b] = bits of max(|d|, |e|) over problem b;
+// non-finite entries raise ST_NONFINITE.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_maxabs(const double* __restrict__ d, const double* __restrict__ e,
+                                                const long long* __restrict__ offs, int B, long long ntot,
+                                                unsigned long long* pmax, int* status) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int b = -1;
+    unsigned long long v = 0;
+    if (i < ntot) {
+        int lo = 0, hi = B - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        b = lo;
+        double x = fabs(d[i]);
+        bool fin = x <= DBL_MAX;
+        if (i + 1 < offs[b + 1]) {
+            double y = fabs(e[i]);
+            fin = fin && (y <= DBL_MAX);
+            x = fmax(x, y);
+        }
+        if (!fin) atomicOr(status, ST_NONFINITE);
+        v = dbits(x);
+    }
+    const int b0 = __shfl(b, 0, 64);
+    if (__all(b == b0) && b0 >= 0) {
+        v = wave_max_u64(v);
+        if ((threadIdx.x & 63) == 0) atomicMax(&pmax[b0], v);
+    } else if (b >= 0) {
+        atomicMax(&pmax[b], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaves: one lane per leaf, the leaf's working arrays in LDS (lane-strided).
+// ---------------------------------------------------------------------------
+template <int LMAX>
+__global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves, int nleaves,
+                                             const double* __restrict__ d, const double* __restrict__ e,
+                                             const unsigned long long* __restrict__ pmax, Work w,
+                                             double* __restrict__ out) {
+    __shared__ double sd[LMAX * 64], se[LMAX * 64], s0[LMAX * 64], s1[LMAX * 64];
+    const int lane = threadIdx.x;
+    const int li = blockIdx.x * 64 + lane;
+    if (li >= nleaves) return;
+    const LeafRec L = leaves[li];
+    const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64);
+    if (st) atomicOr(w.status, st);
+}
+
+// ---------------------------------------------------------------------------
+// Level steps
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, int M, long long N,
+                                               const double* __restrict__ e,
+                                               const unsigned long long* __restrict__ pmax, Work w) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int m = -1;
+    double az = 0.0;
+    if (t < N) body_merge(t, mr, M, e, pmax, w, &m, &az);
+    unsigned long long v = dbits(az);
+    const int m0 = __shfl(m, 0, 64);
+    if (__all(m == m0) && m0 >= 0) {
+        v = wave_max_u64(v);
+        if ((threadIdx.x & 63) == 0) atomicMax(&w.zmax[m0], v);
+    } else if (m >= 0) {
+        atomicMax(&w.zmax[m], v);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_nnflag(const MergeRec* __restrict__ mr, int M, long long N,
+                                                const double* __restrict__ e,
+                                                const unsigned long long* __restrict__ pmax, Work w) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int f = 0;
+    if (t < N) f = body_nnflag(t, mr, M, e, pmax, w);
+    const int c = __syncthreads_count(f);
+    if (threadIdx.x == 0) w.bsum[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kWG) void k_stflag(long long N, Work w) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int f = (t < N) ? (w.st[t] == 1) : 0;
+    const int c = __syncthreads_count(f);
+    if (threadIdx.x == 0) w.bsum[blockIdx.x] = c;
+}
+
+// Compaction of candidate (st == 1) columns: scan[t] = exclusive count,
+// nnpos[g] = t for the g-th candidate.
+__global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
+    __shared__ int wsum[16];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int f = (t < N) ? (w.st[t] == 1) : 0;
+    const int incl = block_incl_scan(f, wsum);
+    const int g = w.bsum[blockIdx.x] + incl - f;
+    if (t < N) {
+        w.scan[t] = g;
+        if (f) w.nnpos[g] = (int)t;
+        if (t == N - 1) w.scan[N] = g + f;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_closeflag(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+    const long long total = w.scan[N];
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x)
+        body_closeflag(g, mr, M, w);
+}
+
+__global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+    const long long total = w.scan[N];
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x)
+        body_runs(g, mr, M, w);
+}
+
+// Active/deflated split: active columns to (Da, Za, RLa, RHa) at their active
+// index, deflated ones to (Dd, RLd, RHd) at their deflated index; scan[t] is
+// the exclusive active count.
+__global__ __launch_bounds__(kWG) void k_actcompact(long long N, Work w) {
+    __shared__ int wsum[16];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int f = (t < N) ? (w.st[t] == 1) : 0;
+    const int incl = block_incl_scan(f, wsum);
+    const int g = w.bsum[blockIdx.x] + incl - f;
+    if (t < N) {
+        w.scan[t] = g;
+        if (f) {
+            w.Da[g] = w.D[t];
+            w.Za[g] = w.Z[t];
+            w.RLa[g] = w.RL[t];
+            w.RHa[g] = w.RH[t];
+        } else {
+            const long long q = t - g;
+            w.Dd[q] = w.D[t];
+            w.RLd[q] = w.RL[t];
+            w.RHd[q] = w.RH[t];
+        }
+        if (t == N - 1) w.scan[N] = g + f;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
+                                                 const double* __restrict__ e,
+                                                 const unsigned long long* __restrict__ pmax, Work w) {
+    const long long total = w.scan[N];
+    int bad = 0;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x) {
+        if (body_secular(g, mr, M, e, pmax, w) < 0) bad = 1;
+    }
+    if (bad) atomicOr(w.status, ST_SEC_NOCONV);
+}
+
+__global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
+                                                const double* __restrict__ e,
+                                                const unsigned long long* __restrict__ pmax, Work w) {
+    const long long total = w.scan[N];
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x)
+        body_lowner(g, mr, M, e, pmax, w);
+}
+
+__global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+    const long long total = w.scan[N];
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x)
+        body_rows(g, mr, M, w);
+}
+
+__global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, int M, long long N,
+                                                  const unsigned long long* __restrict__ pmax, Work w,
+                                                  double* __restrict__ out) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < N) body_assemble(t, mr, M, pmax, w, out);
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequence
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+#define TDE_LAUNCH(kern, grid, block, stream, ...)                                   \
+    do {                                                                             \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), \
+                           __VA_ARGS__);                                             \
+    } while (0)
+
+int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream) {
+    if (p.ntot == 0) return 0;
+    TDE_LAUNCH(k_fill_i32, 1, 64, stream, w.status, 1LL, 0);
+    TDE_LAUNCH(k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
+    TDE_LAUNCH(k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B, p.ntot,
+               w.pmax, w.status);
+    if (p.nleaves > 0) {
+        const unsigned g = nblk(p.nleaves, 64);
+        if (p.leafmax <= 8)
+            TDE_LAUNCH(k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+        else if (p.leafmax <= 16)
+            TDE_LAUNCH(k_leaf<16>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+        else if (p.leafmax <= 32)
+            TDE_LAUNCH(k_leaf<32>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+        else
+            TDE_LAUNCH(k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+    }
+    for (const LevelInfo& L : p.levels) {
+        const MergeRec* mr = p.d_merges + L.mstart;
+        const int M = L.M;
+        const long long N = L.N;
+        const unsigned nb = nblk(N, kWG);
+        const unsigned gstride = nb < 4096u ? nb : 4096u;
+        TDE_LAUNCH(k_fill_u64, nblk(M, kWG), kWG, stream, w.zmax, (long long)M, 0ULL);
+        TDE_LAUNCH(k_merge, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+        TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
+        TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, w);
+        TDE_LAUNCH(k_closeflag, gstride, kWG, stream, mr, M, N, w);
+        TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, M, N, w);
+        TDE_LAUNCH(k_stflag, nb, kWG, stream, N, w);
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
+        TDE_LAUNCH(k_actcompact, nb, kWG, stream, N, w);
+        TDE_LAUNCH(k_secular, gstride, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+        TDE_LAUNCH(k_lowner, gstride, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+        TDE_LAUNCH(k_rows, gstride, kWG, stream, mr, M, N, w);
+        TDE_LAUNCH(k_assemble, nb, kWG, stream, mr, M, N, (const unsigned long long*)w.pmax, w, out);
+    }
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (all slices 256-byte aligned)
+// ---------------------------------------------------------------------------
+size_t workspace_layout(long long n, long long B, long long maxM, char* base, Work* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const long long nn = n > 0 ? n : 1;
+    const long long nb = (nn + kWG - 1) / kWG + 2;
+    Work t{};
+    t.status = (int*)take(256);
+    t.pmax = (unsigned long long*)take(sizeof(unsigned long long) * (B > 0 ? B : 1));
+    t.lam = (double*)take(8 * nn);
+    t.blo = (double*)take(8 * nn);
+    t.bhi = (double*)take(8 * nn);
+    t.D = (double*)take(8 * nn);
+    t.Z = (double*)take(8 * nn);
+    t.RL = (double*)take(8 * nn);
+    t.RH = (double*)take(8 * nn);
+    t.st = (int*)take(4 * nn);
+    t.scan = (int*)take(4 * (nn + 1));
+    t.bsum = (int*)take(4 * nb);
+    t.nnpos = (int*)take(4 * nn);
+    t.cf = (int*)take(4 * nn);
+    t.Da = (double*)take(8 * nn);
+    t.Za = (double*)take(8 * nn);
+    t.RLa = (double*)take(8 * nn);
+    t.RHa = (double*)take(8 * nn);
+    t.org = (int*)take(4 * nn);
+    t.tau = (double*)take(8 * nn);
+    t.zhat = (double*)take(8 * nn);
+    t.PBL = (double*)take(8 * nn);
+    t.PBH = (double*)take(8 * nn);
+    t.Dd = (double*)take(8 * nn);
+    t.RLd = (double*)take(8 * nn);
+    t.RHd = (double*)take(8 * nn);
+    t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));
+    if (w) *w = t;
+    return off;
+}
+
+}  // namespace tde

@@ -1,0 +1,44 @@
+// Host-side plan of a (batched) BR D&C solve: the static merge tree of every
+// problem, levelled by height so that all merges of one height run together.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "tde_internal.h"
+
+namespace tde {
+
+struct LevelInfo {
+    int mstart;   // first merge of this level in the flat merge table
+    int M;        // merges in this level
+    long long N;  // packed columns in this level (sum of merge sizes)
+};
+
+struct Plan {
+    int device = 0;
+    long long ntot = 0;
+    int B = 0;
+    int leaf = 32;
+    int nleaves = 0;
+    int leafmax = 1;     // largest leaf size in the plan
+    int maxM = 1;        // most merges in one level
+    long long maxN = 1;  // most packed columns in one level
+    std::vector<long long> offs;  // host copy of the problem offsets [B+1]
+    std::vector<LevelInfo> levels;
+    // device tables owned by the plan
+    MergeRec* d_merges = nullptr;
+    LeafRec* d_leaves = nullptr;
+    long long* d_offs = nullptr;
+};
+
+// Workspace layout for n packed columns, B problems and maxM merges per level.
+// With base == nullptr only the size is computed.
+size_t workspace_layout(long long n, long long B, long long maxM, char* base, Work* w);
+
+// Enqueue one full solve (scale, leaves, every level) on stream.
+int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out,
+                  void* stream);
+
+}  // namespace tde

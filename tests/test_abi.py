@@ -1,0 +1,78 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/tde.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tde.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2605_26599_amd as tde
+
+    if not os.path.exists(tde.LIB_PATH):
+        from paper_2605_26599_amd import build
+
+        build.build()
+    return tde.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tde_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "tde_eigvals" in names and "tde_eigvals_batched" in names
+    for name in names:
+        assert hasattr(L, name), name
+    import paper_2605_26599_amd as tde
+
+    assert set(names) == set(tde.EXPORTS)
+
+
+def test_version_and_strings(L):
+    assert L.tde_version() >= 100
+    assert L.tde_status_string(0) == b"ok"
+    assert L.tde_status_string(-1) == b"invalid argument"
+    assert L.tde_status_string(1) == b"iteration did not converge"
+
+
+def test_workspace_is_linear(L):
+    import paper_2605_26599_amd as tde
+
+    a = tde.workspace_bytes(1 << 16)
+    b = tde.workspace_bytes(1 << 18)
+    assert 100 * (1 << 16) < a < 400 * (1 << 16)
+    assert abs(b / a - 4.0) < 0.01
+    with pytest.raises(tde.TDEError):
+        tde.workspace_bytes(100, 1, leaf=65)
+
+
+def test_argument_errors_are_synchronous(L):
+    import paper_2605_26599_amd as tde
+
+    vp = ctypes.c_void_p
+    dummy = vp(256)  # never dereferenced: every call below fails its checks first
+    assert L.tde_eigvals(dummy, dummy, -1, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals(dummy, dummy, 0, dummy, dummy, 0, None, None) == tde.TDE_OK
+    assert L.tde_eigvals(None, dummy, 10, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals(dummy, None, 10, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 16, None, None) == tde.TDE_EINVAL
+    bad = tde.tde_opts()
+    bad.leaf = 0
+    bad.flags = 1
+    assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(bad)) == tde.TDE_EINVAL
+    offs = (ctypes.c_int64 * 3)(0, 5, 3)  # not monotone
+    assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    offs = (ctypes.c_int64 * 3)(1, 5, 9)  # does not start at 0
+    assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals_batched(dummy, dummy, None, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals_batched(dummy, dummy, None, 0, dummy, dummy, 0, None, None) == tde.TDE_OK

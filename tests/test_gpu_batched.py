@@ -1,0 +1,98 @@
+"""Batched API parity: many packed tridiagonals of uneven size merged level by
+level in shared launches, checked problem by problem against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import tdgen
+
+pytestmark = pytest.mark.gpu
+
+GATE = 2e-11
+
+
+def _step(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def tde():
+    import torch
+
+    import paper_2605_26599_amd as m
+
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _solve_batch(tde, batch, leaf=None):
+    import torch
+
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(batch.d).to(dev)
+    e = torch.from_numpy(batch.e).to(dev)
+    return tde.eigvals_batched(d, e, batch.offsets, leaf=leaf).cpu().numpy()
+
+
+def _check_problem(batch, lam, b, full=True):
+    d, e = batch.problem(b)
+    lo, hi = int(batch.offsets[b]), int(batch.offsets[b + 1])
+    got = lam[lo:hi]
+    if hi == lo:
+        return
+    tn = tdgen.tnorm1(d, e)
+    assert np.all(np.diff(got) >= 0)
+    if full:
+        ref = oracle.eigvals(d, e)
+        assert np.abs(got - ref).max() <= GATE * tn, b
+    else:
+        assert oracle.certify(d, e, got, GATE * tn) == 0, b
+
+
+@pytest.mark.parametrize("leaf", [1, 4, 32])
+def test_mixed_sizes_small(tde, leaf):
+    _step(f"mixed sizes leaf={leaf}")
+    g = np.random.default_rng(5)
+    sizes = [0, 1, 2, 3, 0, 17, 32, 33, 64, 65, 1, 500, 1023, 7, 0]
+    fams = ["uniform", "toeplitz", "wilkinson", "clustered", "normal"]
+    probs = [tdgen.tridiag(fams[i % len(fams)], s, inst=i) for i, s in enumerate(sizes)]
+    probs += [tdgen.tridiag("uniform", int(s), inst=100 + i) for i, s in enumerate(g.integers(1, 300, 40))]
+    batch = tdgen.pack(probs)
+    lam = _solve_batch(tde, batch, leaf)
+    for b in range(batch.count):
+        _check_problem(batch, lam, b)
+
+
+def test_batched_equals_single(tde):
+    import torch
+
+    _step("batched == single, bitwise")
+    batch = tdgen.batched("uniform", count=64, lo=32, hi=2048, inst=3)
+    lam = _solve_batch(tde, batch)
+    dev = torch.device("cuda:0")
+    for b in range(0, batch.count, 7):
+        d, e = batch.problem(b)
+        one = tde.eigvals(torch.from_numpy(d.copy()).to(dev), torch.from_numpy(e.copy()).to(dev)).cpu().numpy()
+        lo, hi = int(batch.offsets[b]), int(batch.offsets[b + 1])
+        assert np.array_equal(one, lam[lo:hi]), b
+
+
+def test_c4_batched_4096(tde):
+    _step("C4: 4096 problems, log-uniform sizes in [32, 4096]")
+    batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
+    lam = _solve_batch(tde, batch)
+    g = np.random.default_rng(11)
+    full = set(g.choice(batch.count, 48, replace=False).tolist())
+    cert = set(g.choice(batch.count, 400, replace=False).tolist())
+    for b in range(batch.count):
+        if b in full:
+            _check_problem(batch, lam, b, full=True)
+        elif b in cert:
+            _check_problem(batch, lam, b, full=False)
+        else:
+            lo, hi = int(batch.offsets[b]), int(batch.offsets[b + 1])
+            assert np.all(np.diff(lam[lo:hi]) >= 0)
+            d, e = batch.problem(b)
+            tn = tdgen.tnorm1(d, e)
+            assert abs(lam[lo:hi].sum() - d.sum()) <= (hi - lo) * GATE * tn

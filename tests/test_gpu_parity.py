@@ -1,0 +1,197 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Gate: max_k |lambda_hat_k - lambda_k| <= 2e-11 * ||T||_1 on the ascending
+vectors (||T||_1 = max_i |e_{i-1}| + |d_i| + |e_i|).  Small and medium sizes
+compare every eigenvalue with Sturm bisection; full-size cases compare sampled
+eigenvalues with bisection and certify all of them with two Sturm counts each
+(count(mu_k - t) <= k < count(mu_k + t) implies |mu_k - lambda_k| <= t).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import tdgen
+
+pytestmark = pytest.mark.gpu
+
+GATE = 2e-11
+
+
+def _step(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def tde():
+    import torch
+
+    import paper_2605_26599_amd as m
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    loaded = m._hip_runtimes_loaded()
+    assert len(loaded) <= 1, f"more than one HIP runtime loaded: {loaded}"
+    return m
+
+
+def _dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def _solve(tde, d, e, leaf=None):
+    import torch
+
+    dv = torch.from_numpy(np.ascontiguousarray(d)).to(_dev())
+    ev = torch.from_numpy(np.ascontiguousarray(e if len(e) else np.zeros(1))).to(_dev())
+    return tde.eigvals(dv, ev, leaf=leaf).cpu().numpy()
+
+
+def _full_check(tde, d, e, leaf=None):
+    lam = _solve(tde, d, e, leaf)
+    ref = oracle.eigvals(d, e)
+    tn = tdgen.tnorm1(d, e)
+    err = float(np.abs(lam - ref).max()) if len(d) else 0.0
+    assert np.all(np.diff(lam) >= 0), "output not ascending"
+    assert err <= GATE * tn, (err, GATE * tn)
+    return err / max(tn, 1e-300)
+
+
+# --- C1: n = 1024, U(-1,1), leaf 32 (QL leaves), 20 seeds --------------------
+
+def test_c1_twenty_seeds(tde):
+    worst = 0.0
+    for inst in range(20):
+        _step(f"C1 inst={inst}")
+        d, e = tdgen.tridiag("uniform", 1024, cfg=tdgen.CFG_SMALL, inst=inst)
+        worst = max(worst, _full_check(tde, d, e, leaf=32))
+    print(f"C1 worst relative error {worst:.3e}")
+
+
+# --- every family, ragged sizes, every leaf kernel ---------------------------
+
+@pytest.mark.parametrize("fam", ["uniform", "normal", "toeplitz", "wilkinson", "clustered",
+                                 "paper_uniform", "paper_toeplitz", "paper_clustered"])
+@pytest.mark.parametrize("leaf", [1, 3, 8, 16, 32, 64])
+def test_families_small(tde, fam, leaf):
+    for n in [1, 2, 3, 5, 31, 32, 33, 63, 64, 65, 127, 200, 1000, 2049]:
+        _step(f"fam={fam} leaf={leaf} n={n}")
+        d, e = tdgen.tridiag(fam, n)
+        _full_check(tde, d, e, leaf=leaf)
+
+
+# --- structured edge cases ---------------------------------------------------
+
+def test_edge_cases(tde):
+    import torch
+
+    _step("edge: n=0")
+    z = torch.zeros(0, dtype=torch.float64, device=_dev())
+    assert tde.eigvals(z, z).numel() == 0
+    _step("edge: zero matrix")
+    assert np.all(_solve(tde, np.zeros(300), np.zeros(299)) == 0.0)
+    _step("edge: diagonal matrix")
+    d, _ = tdgen.tridiag("normal", 777)
+    assert np.array_equal(_solve(tde, d, np.zeros(776)), np.sort(d))
+    _step("edge: exact zeros in e (reducible)")
+    d, e = tdgen.tridiag("uniform", 1500)
+    e[::97] = 0.0
+    _full_check(tde, d, e)
+    _step("edge: huge and tiny scale")
+    d, e = tdgen.tridiag("uniform", 900)
+    for s in [2.0**600, 2.0**-600, 1e300, 3e-300]:
+        _full_check(tde, d * s, e * s)
+    _step("edge: repeated blocks (exact duplicate poles)")
+    d1, e1 = tdgen.tridiag("uniform", 64)
+    d = np.tile(d1, 16)
+    e = np.concatenate([np.concatenate([e1, [1e-3]]) for _ in range(16)])[:-1]
+    _full_check(tde, d, e)
+    _step("edge: constant diagonal, tiny coupling")
+    _full_check(tde, np.ones(1000), np.full(999, 1e-14))
+
+
+def test_nonfinite_status(tde):
+    import torch
+
+    d, e = tdgen.tridiag("uniform", 500)
+    d[123] = np.nan
+    dv = torch.from_numpy(d).to(_dev())
+    ev = torch.from_numpy(e).to(_dev())
+    with pytest.raises(tde.TDEError) as ex:
+        tde.eigvals(dv, ev)
+    assert ex.value.code == tde.TDE_ENONFINITE
+    d[123] = 0.0
+    e[7] = -np.inf
+    with pytest.raises(tde.TDEError) as ex:
+        tde.eigvals(torch.from_numpy(d).to(_dev()), torch.from_numpy(e).to(_dev()))
+    assert ex.value.code == tde.TDE_ENONFINITE
+
+
+def test_deterministic(tde):
+    d, e = tdgen.tridiag("uniform", 20000)
+    a = _solve(tde, d, e)
+    for _ in range(2):
+        assert np.array_equal(_solve(tde, d, e), a)
+
+
+# --- C2: n in {16384, 32768, 65536} x 4 families -----------------------------
+
+def _sampled_and_certified(tde, d, e, nsample=256, ncert=None, seed=0):
+    n = len(d)
+    lam = _solve(tde, d, e)
+    tn = tdgen.tnorm1(d, e)
+    assert np.all(np.diff(lam) >= 0)
+    g = np.random.default_rng(seed)
+    ks = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], g.integers(0, n, nsample)]))
+    ref = oracle.eigvals_index(d, e, ks)
+    err = float(np.abs(lam[ks] - ref).max())
+    assert err <= GATE * tn, (err, GATE * tn)
+    t = GATE * tn
+    if ncert is None or ncert >= n:
+        assert oracle.certify(d, e, lam, t) == 0
+    else:
+        idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, ncert)]))
+        lo = oracle.counts(d, e, lam[idx] - t)
+        hi = oracle.counts(d, e, lam[idx] + t)
+        assert np.all(lo <= idx) and np.all(hi > idx)
+    # invariants that hold at any size
+    assert abs(math.fsum(lam) - math.fsum(d)) <= n * GATE * tn
+    fro = math.fsum(d * d) + 2.0 * math.fsum(e * e)
+    assert abs(math.fsum(lam * lam) - fro) <= 2 * n * tn * GATE * tn
+    return lam
+
+
+@pytest.mark.parametrize("n", [16384, 32768, 65536])
+@pytest.mark.parametrize("fam", ["uniform", "toeplitz", "wilkinson", "clustered"])
+def test_c2_families(tde, fam, n):
+    _step(f"C2 fam={fam} n={n}")
+    d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_FAMILIES)
+    lam = _sampled_and_certified(tde, d, e, ncert=4096)
+    if fam == "toeplitz":
+        k = np.arange(1, n + 1)
+        exact = np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
+        assert np.abs(lam - exact).max() <= GATE * 4.0
+
+
+# --- C3: n in {131072, 262144}, N(0,1); Toeplitz 262144 ----------------------
+
+@pytest.mark.parametrize("n", [131072, 262144])
+def test_c3_large_normal(tde, n):
+    _step(f"C3 normal n={n}")
+    d, e = tdgen.tridiag("normal", n, cfg=tdgen.CFG_LARGE)
+    _sampled_and_certified(tde, d, e, nsample=128, ncert=2048)
+
+
+def test_c3_toeplitz_262144(tde):
+    _step("C3 toeplitz n=262144")
+    n = 262144
+    d, e = tdgen.tridiag("toeplitz", n, cfg=tdgen.CFG_LARGE)
+    lam = _solve(tde, d, e)
+    k = np.arange(1, n + 1)
+    exact = np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
+    assert np.abs(lam - exact).max() <= GATE * 4.0
