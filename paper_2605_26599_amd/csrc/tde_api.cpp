@@ -51,6 +51,7 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
         info.mstart = t.mstart[h];
         info.M = t.mcount[h];
         info.N = t.ncols[h];
+        info.smax = t.smax[h];
         maxM = std::max(maxM, info.M);
         maxN = std::max(maxN, info.N);
         p->levels.push_back(info);

@@ -164,45 +164,62 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
 }
 
 // ---------------------------------------------------------------------------
-// Secular equation (Section 2.2, Eq. of the rank-one merge; Section 4.1 root
-// solve; compact roots of the appendix on compact delta reconstruction).
+// Secular equation (Section 2.2, the rank-one merge; Section 4.1 root solve;
+// compact roots as in the appendix on compact delta reconstruction).
 // Root k (0-based) of f(lambda) = 1 + rho sum_j z_j^2/(D_j - lambda) for
 // strictly ascending poles D[0..K) and nonzero z.  Output: origin pole index
 // org in {k, k+1} and offset tau with lambda_k = D[org] + tau; every
-// denominator is formed as (D_j - D_org) - tau.
+// denominator is formed as (D_j - D_org) - tau, so the near-pole ones carry
+// no cancellation.
 //
-// Iteration: a safeguarded rational model ("middle way"): the poles left of
-// the root (j <= kk) are modelled by one pole at D_kk, the rest by one pole
-// at D_kk+1, each matching value and slope; the model's root in the current
-// bracket is the next iterate, else the bracket midpoint.  Stops when |f| is
-// within its rounding-error bound, when the step is below an ulp of tau, or
-// when the bracket cannot shrink further.  Returns iterations used, negative
-// if the cap was hit.
+// Each step fits a rational model
+//     g(x) = c + q/(d1 - x) + Q/(d2 - x),   d1 = D_kk - D_org, d2 = D_kk+1 - D_org,
+// to the value and slope of f at the current offset and takes its root in the
+// bracket as the next offset x (solved for x directly, not as a correction,
+// which would cancel when the root sits next to its pole).  Two fits are used:
+//  - fixed weight: the origin pole keeps its exact weight rho z_org^2 and the
+//    other model pole absorbs the slope of every other term;
+//  - middle way: each model pole absorbs the slope of all poles on its side.
+// Fixed weight is used first; if an iteration fails to cut |f| tenfold the
+// root switches to the middle way for good.  Safeguard: bisection of the
+// bracket.  The interior roots start from the bracket midpoint, which also
+// picks the nearer pole as origin; the last root starts from the root of the
+// equation truncated to its two nearest poles (a lower bound).
+// Stops when |f| is within its rounding-error bound, when a step moves tau by
+// less than an ulp, or when the bracket cannot shrink.  Returns the number of
+// sweeps after the first, negative if the cap was hit.
 // ---------------------------------------------------------------------------
-TDE_DEV double model_step(double f, double d1, double d2, double rdpsi, double rdphi,
-                          double elo, double ehi) {
-    // model g(eta) = c + q/(d1 - eta) + Q/(d2 - eta) with g(0) = f, g'(0) = f'
-    double q = d1 * d1 * rdpsi;
-    double Q = d2 * d2 * rdphi;
-    double c = f - d1 * rdpsi - d2 * rdphi;
-    double a = c * (d1 + d2) + q + Q;
-    double b = d1 * d2 * f;
-    double disc = a * a - 4.0 * b * c;
+TDE_DEV double model_root(double f, double tau, double d1, double d2, double q, double Q, double lo,
+                          double hi) {
+    // c(d1-x)(d2-x) + q(d2-x) + Q(d1-x) = 0  <=>  c x^2 - A x + C0 = 0
+    const double c = f - q / (d1 - tau) - Q / (d2 - tau);
+    const double A = c * (d1 + d2) + q + Q;
+    const double C0 = c * d1 * d2 + q * d2 + Q * d1;
+    double disc = A * A - 4.0 * C0 * c;
     if (!(disc >= 0.0)) disc = 0.0;
-    double sq = sqrt(disc);
-    double den = (a >= 0.0) ? a + sq : a - sq;
-    double r1 = (c != 0.0) ? den / (2.0 * c) : NAN;
-    double r2 = (den != 0.0) ? 2.0 * b / den : NAN;
-    bool in1 = r1 > elo && r1 < ehi;
-    bool in2 = r2 > elo && r2 < ehi;
-    if (in1 && in2) return fabs(r1) < fabs(r2) ? r1 : r2;
+    const double sq = sqrt(disc);
+    const double den = (A >= 0.0) ? A + sq : A - sq;
+    const double r1 = (c != 0.0) ? den / (2.0 * c) : NAN;
+    const double r2 = (den != 0.0) ? 2.0 * C0 / den : NAN;
+    const bool in1 = r1 > lo && r1 < hi;
+    const bool in2 = r2 > lo && r2 < hi;
+    if (in1 && in2) return 0.5 * (r1 + r2);
     if (in2) return r2;
     if (in1) return r1;
-    return NAN;
+    return 0.5 * (lo + hi);
 }
 
+// Sweeps over the poles are split across a group of G lanes (lane `sub` takes
+// poles sub, sub+G, ...); Red::sum returns the group total, bitwise identical
+// in every lane of the group, so all lanes take the same branches.
+struct RedSerial {
+    TDE_DEV static double sum(double x) { return x; }
+    TDE_DEV static double prod(double x) { return x; }
+};
+
+template <class Red>
 TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const double* __restrict__ Z,
-                         double rho, int* org_out, double* tau_out) {
+                         double rho, int sub, int G, int* org_out, double* tau_out) {
     if (K == 1) {
         *org_out = 0;
         *tau_out = rho * Z[0] * Z[0];
@@ -212,48 +229,80 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
     const double dk = D[kk], dk1 = D[kk + 1];
     int o;
     double lo, hi, tau;
-    double psi, dpsi, phi, dphi, err, f;
     if (k < K - 1) {
-        // Evaluate at the bracket midpoint (origin kk) to pick the nearer pole.
+        // Midpoint sweep (origin kk): picks the nearer pole and seeds the first step.
         const double gap = dk1 - dk;
         const double mid = 0.5 * gap;
-        psi = dpsi = phi = dphi = err = 0.0;
-        for (int j = 0; j < K; ++j) {
-            double del = (D[j] - dk) - mid;
-            double t = Z[j] / del;
-            double term = Z[j] * t, dterm = t * t;
-            if (j <= kk) { psi += term; dpsi += dterm; }
-            else { phi += term; dphi += dterm; }
-            err += fabs(term);
+        double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+        for (int j = sub; j < K; j += G) {
+            const double del = (D[j] - dk) - mid;
+            const double t = Z[j] / del;
+            const bool near = (j == kk) || (j == kk + 1);
+            const bool left = j < kk;
+            const double term = near ? 0.0 : Z[j] * t;
+            const double dterm = near ? 0.0 : t * t;
+            ps += left ? term : 0.0;
+            dps += left ? dterm : 0.0;
+            ph += left ? 0.0 : term;
+            dph += left ? 0.0 : dterm;
         }
-        f = 1.0 + rho * (psi + phi);
+        ps = Red::sum(ps);
+        dps = Red::sum(dps);
+        ph = Red::sum(ph);
+        dph = Red::sum(dph);
+        const double ak = Z[kk] / (-mid), ak1 = Z[kk + 1] / mid;
+        const double f = 1.0 + rho * (ps + ph + Z[kk] * ak + Z[kk + 1] * ak1);
         if (f >= 0.0) { o = k; lo = 0.0; hi = mid; tau = mid; }
         else { o = k + 1; lo = -mid; hi = 0.0; tau = -mid; }
-        if (f == 0.0) { *org_out = o; *tau_out = tau; return 1; }
-        double eta = model_step(f, -mid, mid, rho * dpsi, rho * dphi, lo - tau, hi - tau);
-        double tn = tau + eta;
-        tau = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+        if (f == 0.0) { *org_out = o; *tau_out = tau; return 0; }
+        const double e1 = dk - D[o], e2 = dk1 - D[o];
+        double q, Q;
+        if (o == kk) { q = rho * Z[kk] * Z[kk]; Q = (e2 - tau) * (e2 - tau) * rho * (dps + dph + ak1 * ak1); }
+        else { Q = rho * Z[kk + 1] * Z[kk + 1]; q = (e1 - tau) * (e1 - tau) * rho * (dps + dph + ak * ak); }
+        tau = model_root(f, tau, e1, e2, q, Q, lo, hi);
     } else {
         o = K - 1;
         double zz = 0.0;
-        for (int j = 0; j < K; ++j) zz += Z[j] * Z[j];
+        for (int j = sub; j < K; j += G) zz += Z[j] * Z[j];
+        zz = Red::sum(zz);
         lo = 0.0;
         hi = rho * zz * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
-        tau = 0.5 * hi;
+        // root of 1 = w1/x + w2/(x + g): the two nearest poles only (a lower bound)
+        const double w1 = rho * Z[K - 1] * Z[K - 1], w2 = rho * Z[K - 2] * Z[K - 2], g = dk1 - dk;
+        const double b = g - w1 - w2, sq = sqrt(b * b + 4.0 * w1 * g);
+        const double t2 = (b <= 0.0) ? 0.5 * (sq - b) : 2.0 * w1 * g / (b + sq);
+        tau = (t2 > lo && t2 < hi) ? t2 : 0.5 * hi;
     }
     const double Do = D[o];
-    const double d1o = dk - Do, d2o = dk1 - Do;
+    const double d1 = dk - Do, d2 = dk1 - Do;
+    const double zo = Z[o], wo = rho * zo * zo;
+    const bool orgl = (o == kk);
+    bool fixed_weight = true;
+    double fprev = INFINITY;
     for (int it = 1; it <= kSecMaxIter; ++it) {
-        psi = dpsi = phi = dphi = err = 0.0;
-        for (int j = 0; j < K; ++j) {
-            double del = (D[j] - Do) - tau;
-            double t = Z[j] / del;
-            double term = Z[j] * t, dterm = t * t;
-            if (j <= kk) { psi += term; dpsi += dterm; }
-            else { phi += term; dphi += dterm; }
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, err = 0.0;
+        for (int j = sub; j < K; j += G) {
+            const double del = (D[j] - Do) - tau;
+            const double t = Z[j] / del;
+            const bool own = (j == o);
+            const bool left = j <= kk;
+            const double term = own ? 0.0 : Z[j] * t;
+            const double dterm = own ? 0.0 : t * t;
+            psi += left ? term : 0.0;
+            dpsi += left ? dterm : 0.0;
+            phi += left ? 0.0 : term;
+            dphi += left ? 0.0 : dterm;
             err += fabs(term);
         }
-        f = 1.0 + rho * (psi + phi);
+        psi = Red::sum(psi);
+        dpsi = Red::sum(dpsi);
+        phi = Red::sum(phi);
+        dphi = Red::sum(dphi);
+        err = Red::sum(err);
+        const double to = zo / (-tau);
+        const double termo = zo * to, dto = to * to;
+        const double f = 1.0 + rho * (psi + phi + termo);
+        err += fabs(termo);
         if (fabs(f) <= 8.0 * DBL_EPSILON * (1.0 + rho * err)) {
             *org_out = o; *tau_out = tau; return it;
         }
@@ -262,9 +311,17 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
         if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) {
             *org_out = o; *tau_out = tau; return it;
         }
-        double eta = model_step(f, d1o - tau, d2o - tau, rho * dpsi, rho * dphi, lo - tau, hi - tau);
-        double tn = tau + eta;
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fixed_weight && fabs(f) > 0.1 * fabs(fprev)) fixed_weight = false;
+        fprev = f;
+        double q, Q;
+        if (fixed_weight) {
+            if (orgl) { q = wo; Q = (d2 - tau) * (d2 - tau) * rho * (dpsi + dphi); }
+            else { Q = wo; q = (d1 - tau) * (d1 - tau) * rho * (dpsi + dphi); }
+        } else {
+            q = (d1 - tau) * (d1 - tau) * rho * (dpsi + (orgl ? dto : 0.0));
+            Q = (d2 - tau) * (d2 - tau) * rho * (dphi + (orgl ? 0.0 : dto));
+        }
+        const double tn = model_root(f, tau, d1, d2, q, Q, lo, hi);
         if (fabs(tn - tau) <= 2.0 * DBL_EPSILON * fabs(tau)) {
             *org_out = o; *tau_out = tn; return it;
         }
@@ -285,11 +342,12 @@ TDE_DEV double root_minus_pole(const double* __restrict__ D, int org, double tau
 // taken as a chain of ratios of like-signed factors near 1:
 //   k < i: (lambda_k - D_i)/(D_k - D_i);  i <= k < K-1: (lambda_k - D_i)/(D_{k+1} - D_i);
 // times (lambda_{K-1} - D_i).  The sign is that of the input z_i.
+template <class Red>
 TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double* __restrict__ Z,
-                        const int* __restrict__ org, const double* __restrict__ tau, double rho) {
+                        const int* __restrict__ org, const double* __restrict__ tau, double rho, int sub, int G) {
     const double di = D[i];
     double prod = 1.0;
-    for (int k = 0; k < K; ++k) {
+    for (int k = sub; k < K; k += G) {
         double num = (D[org[k]] - di) + tau[k];
         double den;
         if (k < i) den = D[k] - di;
@@ -297,6 +355,7 @@ TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double
         else den = 1.0;
         prod *= num / den;
     }
+    prod = Red::prod(prod);
     double z2 = prod / rho;
     double zi = sqrt(fmax(z2, 0.0));
     return (Z[i] < 0.0) ? -zi : zi;
@@ -305,22 +364,25 @@ TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double
 // Boundary-row propagation for one root (Section 4.1): parent row entries
 // (Q_L (+) Q_R)_sigma y_k with y_k(i) = zhat_i/(D_i - lambda_k), normalised;
 // two streamed dot products, no K x K block.
-TDE_DEV void root_rows(int k, int K, const double* __restrict__ D, const double* __restrict__ zh,
+template <class Red>
+TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __restrict__ zh,
                        const double* __restrict__ RL, const double* __restrict__ RH, int org, double tau,
-                       double* bl_out, double* bh_out) {
+                       int sub, int G, double* bl_out, double* bh_out) {
     const double Do = D[org];
     double ss = 0.0, bl = 0.0, bh = 0.0;
-    for (int i = 0; i < K; ++i) {
+    for (int i = sub; i < K; i += G) {
         double del = (D[i] - Do) - tau;
         double y = zh[i] / del;
         ss += y * y;
         bl += RL[i] * y;
         bh += RH[i] * y;
     }
+    ss = Red::sum(ss);
+    bl = Red::sum(bl);
+    bh = Red::sum(bh);
     double inv = 1.0 / sqrt(ss);
     *bl_out = bl * inv;
     *bh_out = bh * inv;
-    (void)k;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,20 +532,25 @@ TDE_DEV void body_runs(long long g, const MergeRec* __restrict__ mr, int M, cons
     Z[pc] = Zc;
     RL[pc] = Lc;
     RH[pc] = Hc;
-    // insertion sort of deflated entries (st != 1) within [t, nnpos[r]]
-    const long long p0 = t, p1 = nnpos[r];
-    for (long long p = p0; p <= p1; ++p) {
-        if (w.st[p] == 1) continue;
-        const double kD = D[p], kL = RL[p], kH = RH[p];
-        const int kS = w.st[p];
-        long long h = p;
-        for (long long q = p - 1; q >= p0; --q) {
-            if (w.st[q] == 1) continue;
-            if (D[q] <= kD) break;
-            D[h] = D[q]; RL[h] = RL[q]; RH[h] = RH[q]; w.st[h] = w.st[q];
+    // The rotated-away columns of a run join their own list, ascending in
+    // position order: sort them among the run's rotated positions (only
+    // columns g..r-1 can be rotated away).  Their values lie in [D_g, D_r],
+    // so the lists of different runs stay ordered.
+    for (long long j = g; j < r; ++j) {
+        const long long pj = nnpos[j];
+        if (w.st[pj] != 2) continue;
+        const double kD = D[pj], kL = RL[pj], kH = RH[pj];
+        long long h = j;
+        for (long long q = j - 1; q >= g; --q) {
+            const long long pq = nnpos[q];
+            if (w.st[pq] != 2) continue;
+            if (D[pq] <= kD) break;
+            const long long ph = nnpos[h];
+            D[ph] = D[pq]; RL[ph] = RL[pq]; RH[ph] = RH[pq];
             h = q;
         }
-        D[h] = kD; RL[h] = kL; RH[h] = kH; w.st[h] = kS;
+        const long long ph = nnpos[h];
+        D[ph] = kD; RL[ph] = kL; RH[ph] = kH;
     }
 }
 
@@ -498,9 +565,10 @@ TDE_DEV int find_merge_active(const MergeRec* __restrict__ mr, int M, const int*
     return lo;
 }
 
-// (a6) one secular root of the merge owning active column g.
+// (a6) one secular root of the merge owning active column g (lane sub of G).
+template <class Red>
 TDE_DEV int body_secular(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                         const unsigned long long* __restrict__ pmax, const Work& w) {
+                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G) {
     const int m = find_merge_active(mr, M, w.scan, g);
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
@@ -510,15 +578,18 @@ TDE_DEV int body_secular(long long g, const MergeRec* __restrict__ mr, int M, co
     const double rho = merge_rho(R, e, pmax, &sgn);
     int o;
     double tau;
-    int it = secular_root((int)(g - ks), K, w.Da + ks, w.Za + ks, rho, &o, &tau);
-    w.org[g] = o;
-    w.tau[g] = tau;
+    int it = secular_root<Red>((int)(g - ks), K, w.Da + ks, w.Za + ks, rho, sub, G, &o, &tau);
+    if (sub == 0) {
+        w.org[g] = o;
+        w.tau[g] = tau;
+    }
     return it;
 }
 
 // (a7) Loewner z-hat for active pole g (non-root merges only).
+template <class Red>
 TDE_DEV void body_lowner(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                         const unsigned long long* __restrict__ pmax, const Work& w) {
+                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G) {
     const int m = find_merge_active(mr, M, w.scan, g);
     const MergeRec R = mr[m];
     if (R.flags & MF_ROOT) return;
@@ -527,11 +598,13 @@ TDE_DEV void body_lowner(long long g, const MergeRec* __restrict__ mr, int M, co
     const int K = (int)(w.scan[R.pk + s] - ks);
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
-    w.zhat[g] = lowner_z((int)(g - ks), K, w.Da + ks, w.Za + ks, w.org + ks, w.tau + ks, rho);
+    const double zh = lowner_z<Red>((int)(g - ks), K, w.Da + ks, w.Za + ks, w.org + ks, w.tau + ks, rho, sub, G);
+    if (sub == 0) w.zhat[g] = zh;
 }
 
 // (a7) parent boundary-row entries of active root g (non-root merges only).
-TDE_DEV void body_rows(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
+template <class Red>
+TDE_DEV void body_rows(long long g, const MergeRec* __restrict__ mr, int M, const Work& w, int sub, int G) {
     const int m = find_merge_active(mr, M, w.scan, g);
     const MergeRec R = mr[m];
     if (R.flags & MF_ROOT) return;
@@ -539,14 +612,47 @@ TDE_DEV void body_rows(long long g, const MergeRec* __restrict__ mr, int M, cons
     const long long ks = w.scan[R.pk];
     const int K = (int)(w.scan[R.pk + s] - ks);
     double bl, bh;
-    root_rows((int)(g - ks), K, w.Da + ks, w.zhat + ks, w.RLa + ks, w.RHa + ks, w.org[g], w.tau[g], &bl, &bh);
-    w.PBL[g] = bl;
-    w.PBH[g] = bh;
+    root_rows<Red>(K, w.Da + ks, w.zhat + ks, w.RLa + ks, w.RHa + ks, w.org[g], w.tau[g], sub, G, &bl, &bh);
+    if (sub == 0) {
+        w.PBL[g] = bl;
+        w.PBH[g] = bh;
+    }
 }
 
-// (a9) parent assembly: merge the ascending roots with the ascending deflated
-// values; write the parent's spectrum and boundary rows in place (or the
-// scaled-back eigenvalues for a top merge).
+// (a9) parent assembly: merge three ascending lists -- the roots, the
+// negligible-z columns and the rotated-away columns -- into the parent's
+// spectrum, in place (or the scaled-back eigenvalues for a top merge).  Ties
+// order roots before rotated before negligible columns.
+TDE_DEV int count_lt(const double* __restrict__ v, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (v[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+TDE_DEV int count_le(const double* __restrict__ v, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+TDE_DEV int roots_cmp_count(const double* __restrict__ Da, const int* __restrict__ og,
+                            const double* __restrict__ ta, int K, double x, bool inclusive) {
+    int lo = 0, hi = K;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        const double v = Da[og[mid]] + ta[mid];
+        if (inclusive ? (v <= x) : (v < x)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 TDE_DEV void body_assemble(long long t, const MergeRec* __restrict__ mr, int M,
                            const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
     const int m = find_merge(mr, M, t);
@@ -555,36 +661,32 @@ TDE_DEV void body_assemble(long long t, const MergeRec* __restrict__ mr, int M,
     const int i = (int)(t - R.pk);
     const long long ks = w.scan[R.pk];
     const int K = (int)(w.scan[R.pk + s] - ks);
-    const long long ds = R.pk - ks;
-    const int nd = s - K;
+    const long long rs = w.scanR[R.pk];
+    const int nr = (int)(w.scanR[R.pk + s] - rs);
+    const long long ns = R.pk - ks - rs;
+    const int nn = s - K - nr;
     const double* Da = w.Da + ks;
     const int* og = w.org + ks;
     const double* ta = w.tau + ks;
-    const double* Dd = w.Dd + ds;
+    const double* Dr = w.Dr + rs;
+    const double* Dd = w.Dd + ns;
     const bool root = (R.flags & MF_ROOT) != 0;
     int pos;
     double val, bl = 0.0, bh = 0.0;
     if (i < K) {
         val = Da[og[i]] + ta[i];
-        int lo = 0, hi = nd;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (Dd[mid] < val) lo = mid + 1;
-            else hi = mid;
-        }
-        pos = i + lo;
+        pos = i + count_lt(Dr, nr, val) + count_lt(Dd, nn, val);
         if (!root) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
-    } else {
+    } else if (i < K + nr) {
         const int q = i - K;
+        val = Dr[q];
+        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_lt(Dd, nn, val);
+        if (!root) { bl = w.RLr[rs + q]; bh = w.RHr[rs + q]; }
+    } else {
+        const int q = i - K - nr;
         val = Dd[q];
-        int lo = 0, hi = K;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (Da[og[mid]] + ta[mid] <= val) lo = mid + 1;
-            else hi = mid;
-        }
-        pos = q + lo;
-        if (!root) { bl = w.RLd[ds + q]; bh = w.RHd[ds + q]; }
+        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_le(Dr, nr, val);
+        if (!root) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
     }
     const long long P = R.off + pos;
     if (root) {

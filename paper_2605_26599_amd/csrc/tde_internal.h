@@ -54,8 +54,10 @@ struct Work {
     double* RL;                // [n]   parent-first-row entries per column
     double* RH;                // [n]   parent-last-row entries per column
     int* st;                   // [n]   column state: 0 negligible z, 1 active, 2 rotated away
-    int* scan;                 // [n+1] exclusive prefix counts
+    int* scan;                 // [n+1] exclusive prefix counts (candidates, then active columns)
+    int* scanR;                // [n+1] exclusive prefix counts of rotated-away columns
     int* bsum;                 // [nb+1] per-block counts
+    int* bsumR;                // [nb+1] per-block counts of rotated-away columns
     int* nnpos;                // [n]   packed positions of non-negligible columns
     int* cf;                   // [n]   close-pair flag of non-negligible column g and g+1
     double* Da;                // [n]   active poles
@@ -67,9 +69,12 @@ struct Work {
     double* zhat;              // [n]   recomputed (Loewner) secular vector
     double* PBL;               // [n]   parent first-row entries of active columns
     double* PBH;               // [n]   parent last-row entries of active columns
-    double* Dd;                // [n]   deflated eigenvalues (sorted per merge)
+    double* Dd;                // [n]   negligible-z columns: eigenvalue D_j (ascending per merge)
     double* RLd;               // [n]
     double* RHd;               // [n]
+    double* Dr;                // [n]   rotated-away columns: eigenvalue (ascending per merge)
+    double* RLr;               // [n]
+    double* RHr;               // [n]
     unsigned long long* zmax;  // [maxM] bits of max |z~| per merge
 };
 

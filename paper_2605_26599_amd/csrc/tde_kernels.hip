@@ -159,9 +159,13 @@ __global__ __launch_bounds__(kWG) void k_nnflag(const MergeRec* __restrict__ mr,
 
 __global__ __launch_bounds__(kWG) void k_stflag(long long N, Work w) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int f = (t < N) ? (w.st[t] == 1) : 0;
-    const int c = __syncthreads_count(f);
-    if (threadIdx.x == 0) w.bsum[blockIdx.x] = c;
+    const int s = (t < N) ? w.st[t] : 0;
+    const int c = __syncthreads_count(s == 1);
+    const int r = __syncthreads_count(s == 2);
+    if (threadIdx.x == 0) {
+        w.bsum[blockIdx.x] = c;
+        w.bsumR[blockIdx.x] = r;
+    }
 }
 
 // Compaction of candidate (st == 1) columns: scan[t] = exclusive count,
@@ -193,58 +197,100 @@ __global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, i
         body_runs(g, mr, M, w);
 }
 
-// Active/deflated split: active columns to (Da, Za, RLa, RHa) at their active
-// index, deflated ones to (Dd, RLd, RHd) at their deflated index; scan[t] is
-// the exclusive active count.
+// Three-way split of a level's columns: active ones to (Da, Za, RLa, RHa) at
+// their active index, rotated-away ones to (Dr, RLr, RHr) and negligible-z
+// ones to (Dd, RLd, RHd), each list in column order.  scan / scanR hold the
+// exclusive active / rotated counts.
 __global__ __launch_bounds__(kWG) void k_actcompact(long long N, Work w) {
     __shared__ int wsum[16];
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int f = (t < N) ? (w.st[t] == 1) : 0;
-    const int incl = block_incl_scan(f, wsum);
-    const int g = w.bsum[blockIdx.x] + incl - f;
+    const int s = (t < N) ? w.st[t] : 0;
+    const int fa = (t < N) && (s == 1);
+    const int fr = (t < N) && (s == 2);
+    const int ia = block_incl_scan(fa, wsum);
+    __syncthreads();
+    const int ir = block_incl_scan(fr, wsum);
+    const int g = w.bsum[blockIdx.x] + ia - fa;
+    const int gr = w.bsumR[blockIdx.x] + ir - fr;
     if (t < N) {
         w.scan[t] = g;
-        if (f) {
+        w.scanR[t] = gr;
+        if (fa) {
             w.Da[g] = w.D[t];
             w.Za[g] = w.Z[t];
             w.RLa[g] = w.RL[t];
             w.RHa[g] = w.RH[t];
+        } else if (fr) {
+            w.Dr[gr] = w.D[t];
+            w.RLr[gr] = w.RL[t];
+            w.RHr[gr] = w.RH[t];
         } else {
-            const long long q = t - g;
+            const long long q = t - g - gr;
             w.Dd[q] = w.D[t];
             w.RLd[q] = w.RL[t];
             w.RHd[q] = w.RH[t];
         }
-        if (t == N - 1) w.scan[N] = g + f;
+        if (t == N - 1) {
+            w.scan[N] = g + fa;
+            w.scanR[N] = gr + fr;
+        }
     }
 }
 
+// Group reduction over G consecutive lanes: butterfly, then lane 0 of the
+// group broadcasts, so every lane holds the same bits.
+template <int G>
+struct RedGroup {
+    __device__ __forceinline__ static double sum(double x) {
+        for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+        return __shfl(x, 0, G);
+    }
+    __device__ __forceinline__ static double prod(double x) {
+        for (int o = G / 2; o > 0; o >>= 1) x *= __shfl_xor(x, o, G);
+        return __shfl(x, 0, G);
+    }
+};
+template <>
+struct RedGroup<1> {
+    __device__ __forceinline__ static double sum(double x) { return x; }
+    __device__ __forceinline__ static double prod(double x) { return x; }
+};
+
+// Root-parallel steps: a group of G lanes per root (or per pole for the
+// Loewner step), groups striding over the level's active columns.
+template <int G>
 __global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
                                                  const double* __restrict__ e,
                                                  const unsigned long long* __restrict__ pmax, Work w) {
     const long long total = w.scan[N];
+    const int sub = threadIdx.x % G;
+    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
     int bad = 0;
-    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x) {
-        if (body_secular(g, mr, M, e, pmax, w) < 0) bad = 1;
+    for (long long g = grp; g < total; g += ngrp) {
+        if (body_secular<RedGroup<G>>(g, mr, M, e, pmax, w, sub, G) < 0) bad = 1;
     }
-    if (bad) atomicOr(w.status, ST_SEC_NOCONV);
+    if (bad && sub == 0) atomicOr(w.status, ST_SEC_NOCONV);
 }
 
+template <int G>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w) {
     const long long total = w.scan[N];
-    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x)
-        body_lowner(g, mr, M, e, pmax, w);
+    const int sub = threadIdx.x % G;
+    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
+    for (long long g = grp; g < total; g += ngrp) body_lowner<RedGroup<G>>(g, mr, M, e, pmax, w, sub, G);
 }
 
+template <int G>
 __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
     const long long total = w.scan[N];
-    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x)
-        body_rows(g, mr, M, w);
+    const int sub = threadIdx.x % G;
+    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
+    for (long long g = grp; g < total; g += ngrp) body_rows<RedGroup<G>>(g, mr, M, w, sub, G);
 }
 
 __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, int M, long long N,
@@ -264,6 +310,36 @@ static inline unsigned nblk(long long n, int per) { return (unsigned)((n + per -
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), \
                            __VA_ARGS__);                                             \
     } while (0)
+
+// Lanes per root: grows with the level's largest merge so that small merges
+// keep one lane per root and large ones split each pole sweep.
+static int lanes_per_root(int smax) {
+    int G = 1;
+    while (G < 16 && G * 128 < smax) G <<= 1;
+    return G;
+}
+
+template <int G>
+static void launch_roots_g(long long N, const MergeRec* mr, int M, const double* e, const Work& w, void* stream) {
+    const long long lanes = N * G;
+    long long nb = (lanes + kWG - 1) / kWG;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    TDE_LAUNCH(k_secular<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+    TDE_LAUNCH(k_lowner<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+    TDE_LAUNCH(k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
+}
+
+static void launch_roots(int smax, long long N, const MergeRec* mr, int M, const double* e, const Work& w,
+                         void* stream) {
+    switch (lanes_per_root(smax)) {
+        case 1: launch_roots_g<1>(N, mr, M, e, w, stream); break;
+        case 2: launch_roots_g<2>(N, mr, M, e, w, stream); break;
+        case 4: launch_roots_g<4>(N, mr, M, e, w, stream); break;
+        case 8: launch_roots_g<8>(N, mr, M, e, w, stream); break;
+        default: launch_roots_g<16>(N, mr, M, e, w, stream); break;
+    }
+}
 
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream) {
     if (p.ntot == 0) return 0;
@@ -297,10 +373,9 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, M, N, w);
         TDE_LAUNCH(k_stflag, nb, kWG, stream, N, w);
         TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsumR, (int)nb);
         TDE_LAUNCH(k_actcompact, nb, kWG, stream, N, w);
-        TDE_LAUNCH(k_secular, gstride, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-        TDE_LAUNCH(k_lowner, gstride, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-        TDE_LAUNCH(k_rows, gstride, kWG, stream, mr, M, N, w);
+        launch_roots(L.smax, N, mr, M, e, w, stream);
         TDE_LAUNCH(k_assemble, nb, kWG, stream, mr, M, N, (const unsigned long long*)w.pmax, w, out);
     }
     return (int)hipGetLastError();
@@ -330,7 +405,9 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.RH = (double*)take(8 * nn);
     t.st = (int*)take(4 * nn);
     t.scan = (int*)take(4 * (nn + 1));
+    t.scanR = (int*)take(4 * (nn + 1));
     t.bsum = (int*)take(4 * nb);
+    t.bsumR = (int*)take(4 * nb);
     t.nnpos = (int*)take(4 * nn);
     t.cf = (int*)take(4 * nn);
     t.Da = (double*)take(8 * nn);
@@ -345,6 +422,9 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Dd = (double*)take(8 * nn);
     t.RLd = (double*)take(8 * nn);
     t.RHd = (double*)take(8 * nn);
+    t.Dr = (double*)take(8 * nn);
+    t.RLr = (double*)take(8 * nn);
+    t.RHr = (double*)take(8 * nn);
     t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));
     if (w) *w = t;
     return off;

@@ -14,6 +14,7 @@ struct LevelInfo {
     int mstart;   // first merge of this level in the flat merge table
     int M;        // merges in this level
     long long N;  // packed columns in this level (sum of merge sizes)
+    int smax;     // largest merge (columns) in this level
 };
 
 struct Plan {

@@ -15,6 +15,7 @@ struct LevelTables {
     std::vector<int> mstart;        // first merge of each level
     std::vector<int> mcount;        // merges per level
     std::vector<long long> ncols;   // packed columns per level
+    std::vector<int> smax;          // largest merge per level
     std::vector<LeafRec> leaves;
 };
 
@@ -66,12 +67,15 @@ inline LevelTables build_tree(int leaf, const std::vector<long long>& offs) {
         t.mstart.push_back((int)t.merges.size());
         t.mcount.push_back((int)L.size());
         long long pk = 0;
+        int sm = 0;
         for (auto& R : L) {
             R.pk = pk;
             pk += R.nL + R.nR;
+            sm = std::max(sm, R.nL + R.nR);
             t.merges.push_back(R);
         }
         t.ncols.push_back(pk);
+        t.smax.push_back(sm);
     }
     t.leaves = std::move(tb.leaves);
     return t;
