@@ -1,10 +1,20 @@
 """Benchmark: FP64 tridiagonal eigenvalues/s on one MI355X.
 
-Default workload: one n = 65536 tridiagonal with d, e ~ U(-1, 1) (seeded),
-inputs resident in HBM before the timed region.  A step is one full solve
-(scale, leaves, every merge level) through the C-ABI.  Prints one JSON line.
+Default workload: one n = 65536 symmetric tridiagonal with d, e ~ U(-1, 1)
+(seeded synthetic input), resident in HBM before the timed region.  A step is
+one full solve through the C-ABI: validation/scale, leaves, every merge level
+(sort, z, deflation, secular roots, boundary-row propagation, assembly).
+
+Prints one JSON line.  Besides the headline value it carries:
+  roofline      the dominant kernel (by time in a second, instrumented timed
+                region with HIP events around every launch): algorithmic work
+                from the library's counters / measured duration vs. MI355X peak
+  cpu_baseline  the CPU oracle (Sturm bisection) on a bounded sample of the
+                same matrix, on the host's cores
+  secondary     batched solves/s (4096 problems) and the QL CPU baseline
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -14,6 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+# Algorithmic work per counted unit ("Roofline accounting").
+FLOPS_PER_SEC_TERM = 8      # (D_j - D_o) - tau, z/del, z*t, t*t, 3 accumulations
+FLOPS_PER_LOW_PAIR = 5      # (D_o - D_i) + tau, D_k - D_i, divide, multiply
+FLOPS_PER_ROW_PAIR = 9      # (D_i - D_o) - tau, zhat/del, y*y+ss, 2 fused dot updates
+FLOPS_PER_LEAF_ROT = 26     # one implicit-QL plane rotation incl. the two tracked rows
+BYTES_PER_MERGE_COL = 56    # read lambda, blo, bhi; write D, z, RL, RH
+BYTES_PER_ASSEMBLE_COL = 48  # read value + 2 row entries; write lambda, blo, bhi
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -22,10 +43,123 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--family", default="uniform")
     ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--leaf", type=int, default=0)
-    ap.add_argument("--batched", action="store_true", help="4096 problems, log-uniform sizes in [32, 4096]")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--leaf", type=int, default=0, help="0 = library default")
+    ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("tde_device.h", "tde_kernels.hip", "tde_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_26599_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed(step, steps):
+    import torch
+
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def roofline(tde, kinds, cnt, steps):
+    """Roofline entry for the kernel kind that took the most time."""
+    work = {
+        "secular": ("alu", cnt["secular_terms"] * FLOPS_PER_SEC_TERM),
+        "lowner": ("alu", cnt["lowner_pairs"] * FLOPS_PER_LOW_PAIR),
+        "rows": ("alu", cnt["row_pairs"] * FLOPS_PER_ROW_PAIR),
+        "leaf": ("alu", cnt["leaf_rotations"] * FLOPS_PER_LEAF_ROT),
+        "merge": ("hbm", None),
+        "assemble": ("hbm", None),
+    }
+    ranked = sorted(((ms, k) for k, (ms, n) in kinds.items() if k in work and n > 0), reverse=True)
+    if not ranked:
+        return None
+    ms, kind = ranked[0]
+    launches = kinds[kind][1]
+    per_launch_ms = ms / launches
+    bound, per_solve = work[kind]
+    if bound == "alu":
+        achieved = per_solve * steps / (ms * 1e-3) / 1e12
+        peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+        per_launch = per_solve * steps / launches
+    else:
+        cols = cnt["merge_columns"]
+        per_col = BYTES_PER_MERGE_COL if kind == "merge" else BYTES_PER_ASSEMBLE_COL
+        per_solve = cols * per_col
+        achieved = per_solve * steps / (ms * 1e-3) / 1e9
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+        per_launch = per_solve * steps / launches
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        try:
+            rec = json.load(open(tf)).get(kind)
+            if rec and rec.get("source_hash") == source_hash():
+                traffic = rec["bytes_per_launch"]
+        except (ValueError, KeyError):
+            traffic = None
+    return {
+        "kernel": {"secular": "k_secular", "lowner": "k_lowner", "rows": "k_rows", "leaf": "k_leaf",
+                   "merge": "k_merge", "assemble": "k_assemble"}[kind],
+        "bound": bound,
+        "achieved": achieved,
+        "peak": peak,
+        "unit": unit,
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "launches": launches,
+        "avg_launch_us": per_launch_ms * 1e3,
+        "work_per_launch": per_launch,
+        "time_share": ms / sum(v[0] for v in kinds.values()),
+    }
+
+
+def cpu_baseline(d, e, target_s):
+    import numpy as np
+
+    import oracle
+
+    n = len(d)
+    g = np.random.default_rng(1)
+    probe = np.sort(g.choice(n, 8, replace=False))
+    t0 = time.perf_counter()
+    oracle.eigvals_index(d, e, probe)
+    t_probe = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    per = t_probe / 8 * min(threads, 8)  # CPU-seconds per eigenvalue (probe ran 8 in parallel)
+    m = int(max(threads, min(n, target_s * threads / max(per, 1e-9))))
+    ks = np.sort(g.choice(n, m, replace=False))
+    t0 = time.perf_counter()
+    oracle.eigvals_index(d, e, ks)
+    t = time.perf_counter() - t0
+    return {"value": m / t, "unit": "eigvals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} of the {n} eigenvalues (uniformly drawn indices) of the same matrix, "
+                      f"Sturm bisection, {t:.1f} s wall"}
+
+
+def ql_baseline(d, e, target_s):
+    import oracle
+
+    n = len(d)
+    # implicit QL is sequential and ~n^2: time it on the leading m x m block
+    m = min(n, 8192)
+    t0 = time.perf_counter()
+    oracle.ql_eigvals(d[:m], e[:m - 1])
+    t = time.perf_counter() - t0
+    return {"value": m / t, "unit": "eigvals/s", "cores": 1, "kind": "implicit QL",
+            "sample": f"leading {m} x {m} block of the same matrix, {t:.2f} s"}
 
 
 def main():
@@ -42,47 +176,64 @@ def main():
 
     dev = torch.device("cuda:0")
     leaf = args.leaf or None
-    if args.batched:
-        batch = tdgen.batched(args.family, count=4096, lo=32, hi=4096, inst=0)
+
+    def make_batched():
+        batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
         d = torch.from_numpy(batch.d).to(dev)
         e = torch.from_numpy(batch.e).to(dev)
+        out = torch.empty(int(batch.offsets[-1]), dtype=torch.float64, device=dev)
         offs = batch.offsets
-        n_total = int(offs[-1])
 
         def step():
             tde.eigvals_batched(d, e, offs, leaf=leaf, out=out, check=False)
 
-        out = torch.empty(n_total, dtype=torch.float64, device=dev)
-        workload = {"workload": f"batched 4096 tridiagonals, sizes log-uniform in [32,4096] (total {n_total}), "
-                                f"{args.family}", "problems": 4096, "columns": n_total}
+        return batch, step
+
+    if args.batched:
+        batch, step = make_batched()
+        n_cols = int(batch.offsets[-1])
+        workload = {"workload": f"batched: 4096 tridiagonals, sizes log-uniform in [32,4096] "
+                                f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols}
         metric, unit, per_step = "batched solves/s", "solves/s", 4096
+        dn = en = None
     else:
         n = args.n
         dn, en = tdgen.tridiag(args.family, n, cfg=tdgen.CFG_FAMILIES)
         d = torch.from_numpy(dn).to(dev)
         e = torch.from_numpy(en).to(dev)
         out = torch.empty(n, dtype=torch.float64, device=dev)
+        n_cols = n
 
         def step():
             tde.eigvals(d, e, leaf=leaf, out=out, check=False)
 
-        workload = {"workload": f"single tridiagonal n={n}, {args.family}", "n": n}
+        workload = {"workload": f"single tridiagonal n={n}, family {args.family} (seeded synthetic)", "n": n,
+                    "leaf": args.leaf or "default"}
         metric, unit, per_step = f"FP64 tridiag eigvals/s @n={n}", "eigvals/s", n
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    st = tde.last_status(tde.default_workspace(dev))
+    if st != tde.TDE_OK:
+        raise tde.TDEError(st, "device status after warm-up")
+
+    # timed region: the headline value
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
+    total_ms = timed(step, args.steps)
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop) / args.steps
+    ms = total_ms / args.steps
     value = per_step / (ms / 1e3)
+
+    # second timed region: per-kernel durations from HIP events on the solve's stream
+    tde.timing_read()
+    tde.timing_enable(True)
+    timed(step, args.steps)
+    tde.timing_enable(False)
+    kinds = tde.timing_read()
+    cnt = tde.counters(tde.default_workspace(dev))
+    roof = roofline(tde, kinds, cnt, args.steps)
+
     rec = {
         "metric": metric,
         "value": value,
@@ -91,14 +242,32 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "wall_s": wall,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": workload,
+        "roofline": roof,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kinds.items()},
+        "launches_per_step": sum(v[1] for v in kinds.values()) / args.steps,
+        "work_counters_per_step": cnt,
+        "wall_s": wall,
     }
+    if not args.no_cpu and dn is not None:
+        rec["cpu_baseline"] = cpu_baseline(dn, en, args.cpu_seconds)
+    sec = {}
+    if not args.no_secondary and not args.batched:
+        batch, bstep = make_batched()
+        for _ in range(2):
+            bstep()
+        bms = timed(bstep, 5) / 5
+        sec["batched_solves_per_s"] = 4096 / (bms / 1e3)
+        sec["batched_ms_per_step"] = bms
+    if not args.no_cpu and dn is not None:
+        sec["cpu_ql"] = ql_baseline(dn, en, args.cpu_seconds)
+    if sec:
+        rec["secondary"] = sec
     print(json.dumps(rec), flush=True)
 
 

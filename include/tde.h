@@ -51,7 +51,7 @@ extern "C" {
 
 /* Options.  Pass NULL for defaults. */
 typedef struct {
-    int leaf;      /* largest leaf size solved directly by QL, 1..64; 0 = default (32) */
+    int leaf;      /* largest leaf size solved directly by QL, 1..64; 0 = default (8) */
     int flags;     /* reserved, must be 0 */
     int reserved[6];
 } tde_opts;
@@ -88,6 +88,27 @@ int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets
  * that used ws: TDE_OK, TDE_ENONFINITE or TDE_ENOCONV.  Returns a negative code
  * if the read itself fails. */
 int tde_get_status(const void* ws, void* hip_stream);
+
+/* Measurement aids (not needed to solve).
+ *
+ * tde_get_counters: waits for the stream, then copies n (<= 8) counters of the
+ * algorithmic work of the last solve that used ws:
+ *   [0] pole-term evaluations in secular sweeps, [1] (pole, root) pairs in the
+ *   Loewner products, [2] (root, pole) pairs in the boundary-row dot products,
+ *   [3] secular roots, [4] secular sweeps, [5] columns solved by QL leaves,
+ *   [6] plane rotations applied by the QL leaves, [7] columns passed through
+ *   merges (summed over tree levels).
+ *
+ * tde_timing_enable(1): from then on every launch the library enqueues is
+ * bracketed by two HIP events recorded on the caller's stream (this adds
+ * host work per launch; leave it off when timing whole solves).
+ * tde_timing_read: waits for the recorded events and returns, per launch kind
+ * (0 setup, 1 QL leaves, 2 merge/sort, 3 deflation and compaction, 4 secular
+ * roots, 5 Loewner products, 6 boundary rows, 7 assembly), the summed
+ * milliseconds and launch count since the last read; then forgets them. */
+int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n);
+int tde_timing_enable(int on);
+int tde_timing_read(double* ms, int64_t* launches, int nkinds);
 
 /* Frees every cached plan (device tables).  Not safe while solves are queued. */
 void tde_release_plans(void);

@@ -41,6 +41,9 @@ EXPORTS = (
     "tde_eigvals",
     "tde_eigvals_batched",
     "tde_get_status",
+    "tde_get_counters",
+    "tde_timing_enable",
+    "tde_timing_read",
     "tde_release_plans",
     "tde_status_string",
 )
@@ -96,6 +99,12 @@ def lib():
         L.tde_eigvals_batched.restype = ctypes.c_int
         L.tde_get_status.argtypes = [vp, vp]
         L.tde_get_status.restype = ctypes.c_int
+        L.tde_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+        L.tde_get_counters.restype = ctypes.c_int
+        L.tde_timing_enable.argtypes = [ctypes.c_int]
+        L.tde_timing_enable.restype = ctypes.c_int
+        L.tde_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.tde_timing_read.restype = ctypes.c_int
         L.tde_release_plans.argtypes = []
         L.tde_release_plans.restype = None
         L.tde_status_string.argtypes = [ctypes.c_int]
@@ -212,6 +221,42 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_batched device status")
     return out
+
+
+COUNTER_NAMES = ("secular_terms", "lowner_pairs", "row_pairs", "roots", "sweeps", "leaf_columns", "leaf_rotations", "merge_columns")
+KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble")
+
+
+def counters(workspace: torch.Tensor) -> dict:
+    """Algorithmic work counters of the last solve that used this workspace (syncs)."""
+    buf = (ctypes.c_uint64 * 8)()
+    stream = torch.cuda.current_stream(workspace.device).cuda_stream
+    rc = lib().tde_get_counters(workspace.data_ptr(), stream, buf, 8)
+    if rc != TDE_OK:
+        raise TDEError(rc, "tde_get_counters")
+    return {name: int(buf[i]) for i, name in enumerate(COUNTER_NAMES)}
+
+
+def timing_enable(on: bool = True) -> None:
+    lib().tde_timing_enable(1 if on else 0)
+
+
+def timing_read() -> dict:
+    """Per launch kind: (milliseconds, launches) recorded since the last read."""
+    n = len(KIND_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    rc = lib().tde_timing_read(ms, cnt, n)
+    if rc != TDE_OK:
+        raise TDEError(rc, "tde_timing_read")
+    return {KIND_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def default_workspace(device=None) -> torch.Tensor:
+    """The workspace the convenience functions use on this device and stream."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = (dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    return _ws_cache[key]
 
 
 def last_status(workspace: torch.Tensor) -> int:

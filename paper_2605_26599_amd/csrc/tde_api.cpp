@@ -82,7 +82,7 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
 }
 
 int resolve_leaf(const tde_opts* opts, int* leaf) {
-    int L = 32;
+    int L = kDefaultLeaf;
     if (opts) {
         if (opts->flags != 0) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
@@ -160,6 +160,28 @@ int tde_get_status(const void* ws, void* hip_stream) {
     if (st & tde::ST_NONFINITE) return TDE_ENONFINITE;
     if (st & (tde::ST_LEAF_NOCONV | tde::ST_SEC_NOCONV)) return TDE_ENOCONV;
     return TDE_OK;
+}
+
+int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n) {
+    if (!ws || !out || n < 0) return TDE_EINVAL;
+    if (n > tde::CNT_N) n = tde::CNT_N;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TDE_EDEVICE;
+    if (n && hipMemcpy(out, (const char*)ws + 64, sizeof(uint64_t) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return TDE_EDEVICE;
+    return TDE_OK;
+}
+
+int tde_timing_enable(int on) {
+    tde::timing_enable(on != 0);
+    return TDE_OK;
+}
+
+int tde_timing_read(double* ms, int64_t* launches, int nkinds) {
+    if (!ms || !launches || nkinds < 0) return TDE_EINVAL;
+    std::vector<long long> cnt(nkinds > 0 ? nkinds : 1);
+    int rc = tde::timing_read(ms, cnt.data(), nkinds);
+    for (int k = 0; k < nkinds; ++k) launches[k] = cnt[k];
+    return rc == 0 ? TDE_OK : TDE_EDEVICE;
 }
 
 void tde_release_plans(void) {

@@ -91,9 +91,10 @@ TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) 
 // ST_LEAF_NOCONV.  On exit d holds the eigenvalues ascending and r0/r1 the
 // first/last eigenvector rows in the same column order.
 // ---------------------------------------------------------------------------
-TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st) {
+TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st, unsigned* nrot) {
 #define A_(p, i) p[(i) * st]
     int status = 0;
+    unsigned rot = 0;
     for (int i = 0; i < nl; ++i) {
         A_(r0, i) = (i == 0) ? 1.0 : 0.0;
         A_(r1, i) = (i == nl - 1) ? 1.0 : 0.0;
@@ -132,6 +133,7 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
                 p = s * r;
                 A_(d, i + 1) = g + p;
                 g = c * r - b;
+                ++rot;
                 // columns i, i+1 of the two tracked rows
                 double t0 = A_(r0, i + 1);
                 A_(r0, i + 1) = s * A_(r0, i) + c * t0;
@@ -159,6 +161,7 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
             double t1 = A_(r1, i); A_(r1, i) = A_(r1, k); A_(r1, k) = t1;
         }
     }
+    *nrot = rot;
     return status;
 #undef A_
 }
@@ -234,7 +237,7 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
         const double gap = dk1 - dk;
         const double mid = 0.5 * gap;
         double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
-        for (int j = sub; j < K; j += G) {
+        _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
             const double del = (D[j] - dk) - mid;
             const double t = Z[j] / del;
             const bool near = (j == kk) || (j == kk + 1);
@@ -281,7 +284,7 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
     double fprev = INFINITY;
     for (int it = 1; it <= kSecMaxIter; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, err = 0.0;
-        for (int j = sub; j < K; j += G) {
+        _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
             const double del = (D[j] - Do) - tau;
             const double t = Z[j] / del;
             const bool own = (j == o);
@@ -347,7 +350,7 @@ TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double
                         const int* __restrict__ org, const double* __restrict__ tau, double rho, int sub, int G) {
     const double di = D[i];
     double prod = 1.0;
-    for (int k = sub; k < K; k += G) {
+    _Pragma("unroll 4") for (int k = sub; k < K; k += G) {
         double num = (D[org[k]] - di) + tau[k];
         double den;
         if (k < i) den = D[k] - di;
@@ -370,7 +373,7 @@ TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __rest
                        int sub, int G, double* bl_out, double* bh_out) {
     const double Do = D[org];
     double ss = 0.0, bl = 0.0, bh = 0.0;
-    for (int i = sub; i < K; i += G) {
+    _Pragma("unroll 4") for (int i = sub; i < K; i += G) {
         double del = (D[i] - Do) - tau;
         double y = zh[i] / del;
         ss += y * y;
@@ -565,20 +568,35 @@ TDE_DEV int find_merge_active(const MergeRec* __restrict__ mr, int M, const int*
     return lo;
 }
 
-// (a6) one secular root of the merge owning active column g (lane sub of G).
+// Root-parallel steps.  m is the merge owning active column g (recorded at
+// compaction).  The merge's active arrays are read through views: element
+// ks + j of the level-wide array is view[ks + j - voff], so a caller can pass
+// either the level-wide arrays (voff = 0) or a copy of a window of them staged
+// in LDS (voff = first staged index).
+struct MergeSpan {
+    long long ks;  // first active column of the merge
+    int K;         // active columns
+};
+TDE_DEV MergeSpan merge_span(const MergeRec& R, const int* __restrict__ scan) {
+    MergeSpan sp;
+    sp.ks = scan[R.pk];
+    sp.K = (int)(scan[R.pk + R.nL + R.nR] - sp.ks);
+    return sp;
+}
+
+// (a6) one secular root (lane sub of a G-lane group).
 template <class Red>
-TDE_DEV int body_secular(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G) {
-    const int m = find_merge_active(mr, M, w.scan, g);
+TDE_DEV int body_secular(long long g, int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G,
+                         const double* __restrict__ Dv, const double* __restrict__ Zv, long long voff) {
     const MergeRec R = mr[m];
-    const int s = R.nL + R.nR;
-    const long long ks = w.scan[R.pk];
-    const int K = (int)(w.scan[R.pk + s] - ks);
+    const MergeSpan sp = merge_span(R, w.scan);
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
     int o;
     double tau;
-    int it = secular_root<Red>((int)(g - ks), K, w.Da + ks, w.Za + ks, rho, sub, G, &o, &tau);
+    const long long b = sp.ks - voff;
+    const int it = secular_root<Red>((int)(g - sp.ks), sp.K, Dv + b, Zv + b, rho, sub, G, &o, &tau);
     if (sub == 0) {
         w.org[g] = o;
         w.tau[g] = tau;
@@ -588,31 +606,31 @@ TDE_DEV int body_secular(long long g, const MergeRec* __restrict__ mr, int M, co
 
 // (a7) Loewner z-hat for active pole g (non-root merges only).
 template <class Red>
-TDE_DEV void body_lowner(long long g, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G) {
-    const int m = find_merge_active(mr, M, w.scan, g);
+TDE_DEV void body_lowner(long long g, int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                         const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G,
+                         const double* __restrict__ Dv, const int* __restrict__ orgv,
+                         const double* __restrict__ tauv, long long voff) {
     const MergeRec R = mr[m];
     if (R.flags & MF_ROOT) return;
-    const int s = R.nL + R.nR;
-    const long long ks = w.scan[R.pk];
-    const int K = (int)(w.scan[R.pk + s] - ks);
+    const MergeSpan sp = merge_span(R, w.scan);
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
-    const double zh = lowner_z<Red>((int)(g - ks), K, w.Da + ks, w.Za + ks, w.org + ks, w.tau + ks, rho, sub, G);
+    const long long b = sp.ks - voff;
+    const double zh = lowner_z<Red>((int)(g - sp.ks), sp.K, Dv + b, w.Za + sp.ks, orgv + b, tauv + b, rho, sub, G);
     if (sub == 0) w.zhat[g] = zh;
 }
 
 // (a7) parent boundary-row entries of active root g (non-root merges only).
 template <class Red>
-TDE_DEV void body_rows(long long g, const MergeRec* __restrict__ mr, int M, const Work& w, int sub, int G) {
-    const int m = find_merge_active(mr, M, w.scan, g);
+TDE_DEV void body_rows(long long g, int m, const MergeRec* __restrict__ mr, const Work& w, int sub, int G,
+                       const double* __restrict__ Dv, const double* __restrict__ zhv,
+                       const double* __restrict__ RLv, const double* __restrict__ RHv, long long voff) {
     const MergeRec R = mr[m];
     if (R.flags & MF_ROOT) return;
-    const int s = R.nL + R.nR;
-    const long long ks = w.scan[R.pk];
-    const int K = (int)(w.scan[R.pk + s] - ks);
+    const MergeSpan sp = merge_span(R, w.scan);
+    const long long b = sp.ks - voff;
     double bl, bh;
-    root_rows<Red>(K, w.Da + ks, w.zhat + ks, w.RLa + ks, w.RHa + ks, w.org[g], w.tau[g], sub, G, &bl, &bh);
+    root_rows<Red>(sp.K, Dv + b, zhv + b, RLv + b, RHv + b, w.org[g], w.tau[g], sub, G, &bl, &bh);
     if (sub == 0) {
         w.PBL[g] = bl;
         w.PBH[g] = bh;
@@ -703,7 +721,7 @@ TDE_DEV void body_assemble(long long t, const MergeRec* __restrict__ mr, int M,
 // u = e_m + sign(beta) e_{m+1}, rho = |beta|).
 TDE_DEV int body_leaf(const LeafRec& L, const double* __restrict__ d, const double* __restrict__ e,
                       const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out,
-                      double* sd, double* se, double* s0, double* s1, int st) {
+                      double* sd, double* se, double* s0, double* s1, int st, unsigned* nrot) {
     const double inv = 1.0 / scale_of(pmax[L.prob]);
     const int nl = L.size;
     for (int i = 0; i < nl; ++i) {
@@ -713,7 +731,7 @@ TDE_DEV int body_leaf(const LeafRec& L, const double* __restrict__ d, const doub
         sd[i * st] = di;
         se[i * st] = (i + 1 < nl) ? e[L.off + i] * inv : 0.0;
     }
-    int status = leaf_ql(nl, sd, se, s0, s1, st);
+    int status = leaf_ql(nl, sd, se, s0, s1, st, nrot);
     if (L.flags & LF_WHOLE) {
         const double sc = 1.0 / inv;
         for (int i = 0; i < nl; ++i) out[L.off + i] = sd[i * st] * sc;

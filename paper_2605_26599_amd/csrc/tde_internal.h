@@ -38,13 +38,34 @@ enum {
     ST_SEC_NOCONV = 4,
 };
 
+// Work counters (Work::counters), reset at the start of every solve.
+enum {
+    CNT_SEC_TERMS = 0,   // pole-term evaluations in secular sweeps
+    CNT_LOW_PAIRS = 1,   // (pole, root) pairs in the Loewner products
+    CNT_ROW_PAIRS = 2,   // (root, pole) pairs in the boundary-row dot products
+    CNT_ROOTS = 3,       // secular roots solved
+    CNT_SWEEPS = 4,      // secular sweeps (summed over roots)
+    CNT_LEAF_COLS = 5,   // columns solved by the QL leaf kernel
+    CNT_LEAF_ROT = 6,    // plane rotations applied by the QL leaf kernel
+    CNT_MERGE_COLS = 7,  // columns passed through merges (summed over levels)
+    CNT_N = 8
+};
+
+// Launch kinds for the optional per-kernel timing.
+enum {
+    KIND_SETUP = 0, KIND_LEAF, KIND_MERGE, KIND_DEFLATE, KIND_SECULAR, KIND_LOWNER, KIND_ROWS, KIND_ASSEMBLE,
+    KIND_N
+};
+
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels
 constexpr int kLeafMax = 64;     // largest leaf the QL leaf kernel accepts
+constexpr int kDefaultLeaf = 8;  // leaf size when the caller does not choose one
 constexpr int kSecMaxIter = 96;  // secular iteration cap
 
 // Pointers into the caller's workspace for one solve.
 struct Work {
-    int* status;               // [1]
+    int* status;               // [1]   device status bits
+    unsigned long long* counters;  // [8] algorithmic work of the last solve (CNT_*)
     unsigned long long* pmax;  // [B]   bits of max |d|,|e| per problem
     double* lam;               // [n]   node spectra (ascending per node)
     double* blo;               // [n]   node first eigenvector row
@@ -64,6 +85,7 @@ struct Work {
     double* Za;                // [n]   active z
     double* RLa;               // [n]
     double* RHa;               // [n]
+    int* amerge;               // [n]   merge index (within the level) of active column g
     int* org;                  // [n]   root origin (local active index)
     double* tau;               // [n]   root offset from its origin pole
     double* zhat;              // [n]   recomputed (Loewner) secular vector

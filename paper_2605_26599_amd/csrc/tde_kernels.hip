@@ -7,6 +7,9 @@
 #include "tde_device.h"
 #include "tde_plan.h"
 
+#include <mutex>
+#include <vector>
+
 namespace tde {
 
 // ---------------------------------------------------------------------------
@@ -30,6 +33,17 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
         v = (u > v) ? u : v;
     }
     return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Adds a per-lane count to a work counter with one atomic per wave.
+__device__ __forceinline__ void count_add(unsigned long long* c, unsigned long long v) {
+    v = wave_sum_u64(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(c, v);
 }
 
 // Inclusive scan over the workgroup (blockDim.x <= 1024, multiple of 64).
@@ -123,8 +137,11 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
     const int li = blockIdx.x * 64 + lane;
     if (li >= nleaves) return;
     const LeafRec L = leaves[li];
-    const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64);
+    unsigned nrot = 0;
+    const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64, &nrot);
     if (st) atomicOr(w.status, st);
+    atomicAdd(&w.counters[CNT_LEAF_COLS], (unsigned long long)L.size);
+    atomicAdd(&w.counters[CNT_LEAF_ROT], (unsigned long long)nrot);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,6 +154,7 @@ __global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, 
     int m = -1;
     double az = 0.0;
     if (t < N) body_merge(t, mr, M, e, pmax, w, &m, &az);
+    count_add(&w.counters[CNT_MERGE_COLS], t < N ? 1ULL : 0ULL);
     unsigned long long v = dbits(az);
     const int m0 = __shfl(m, 0, 64);
     if (__all(m == m0) && m0 >= 0) {
@@ -201,7 +219,7 @@ __global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, i
 // their active index, rotated-away ones to (Dr, RLr, RHr) and negligible-z
 // ones to (Dd, RLd, RHd), each list in column order.  scan / scanR hold the
 // exclusive active / rotated counts.
-__global__ __launch_bounds__(kWG) void k_actcompact(long long N, Work w) {
+__global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
     __shared__ int wsum[16];
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int s = (t < N) ? w.st[t] : 0;
@@ -220,6 +238,7 @@ __global__ __launch_bounds__(kWG) void k_actcompact(long long N, Work w) {
             w.Za[g] = w.Z[t];
             w.RLa[g] = w.RL[t];
             w.RHa[g] = w.RH[t];
+            w.amerge[g] = find_merge(mr, M, t);
         } else if (fr) {
             w.Dr[gr] = w.D[t];
             w.RLr[gr] = w.RL[t];
@@ -257,40 +276,159 @@ struct RedGroup<1> {
 };
 
 // Root-parallel steps: a group of G lanes per root (or per pole for the
-// Loewner step), groups striding over the level's active columns.
+// Loewner step).  A workgroup takes tiles of kWG/G consecutive active columns;
+// when the merges covering a tile hold at most kStage active columns, their
+// arrays are first staged in LDS and every sweep reads them from there.
+constexpr int kStage = 2048;
+constexpr int kStageRows = 1024;
+
+struct TileWindow {
+    long long r0, r1;  // staged range of active columns
+    bool staged;
+};
+
+__device__ __forceinline__ TileWindow tile_window(long long g0, long long g1, const MergeRec* __restrict__ mr,
+                                                  const Work& w, int cap) {
+    // g0 <= g1 < total: first and last active column of the tile
+    const int m0 = w.amerge[g0], m1 = w.amerge[g1];
+    TileWindow tw;
+    tw.r0 = w.scan[mr[m0].pk];
+    tw.r1 = w.scan[mr[m1].pk + mr[m1].nL + mr[m1].nR];
+    tw.staged = (tw.r1 - tw.r0) <= cap;
+    return tw;
+}
+
 template <int G>
 __global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
                                                  const double* __restrict__ e,
                                                  const unsigned long long* __restrict__ pmax, Work w) {
+    __shared__ double sD[kStage], sZ[kStage];
+    __shared__ long long s_r0;
+    __shared__ int s_staged;
     const long long total = w.scan[N];
+    const int per = kWG / G;
     const int sub = threadIdx.x % G;
-    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
-    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
     int bad = 0;
-    for (long long g = grp; g < total; g += ngrp) {
-        if (body_secular<RedGroup<G>>(g, mr, M, e, pmax, w, sub, G) < 0) bad = 1;
+    unsigned long long terms = 0, sweeps = 0, roots = 0;
+    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+        const long long g0 = tile * per;
+        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+        if (threadIdx.x == 0) {
+            const TileWindow tw = tile_window(g0, g1, mr, w, kStage);
+            s_r0 = tw.r0;
+            s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+        }
+        __syncthreads();
+        const long long r0 = s_r0;
+        const int ns = s_staged;
+        if (ns >= 0)
+            for (int i = threadIdx.x; i < ns; i += kWG) {
+                sD[i] = w.Da[r0 + i];
+                sZ[i] = w.Za[r0 + i];
+            }
+        __syncthreads();
+        const long long g = g0 + threadIdx.x / G;
+        if (g < total) {
+            const int m = w.amerge[g];
+            const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sZ, r0)
+                                     : body_secular<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.Za, 0);
+            if (it < 0) bad = 1;
+            if (sub == 0) {
+                const MergeSpan sp = merge_span(mr[m], w.scan);
+                const unsigned long long sw = (sp.K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+                sweeps += sw;
+                terms += sw * (unsigned long long)sp.K;
+                roots += 1;
+            }
+        }
+        __syncthreads();
     }
     if (bad && sub == 0) atomicOr(w.status, ST_SEC_NOCONV);
+    count_add(&w.counters[CNT_SEC_TERMS], terms);
+    count_add(&w.counters[CNT_SWEEPS], sweeps);
+    count_add(&w.counters[CNT_ROOTS], roots);
 }
 
 template <int G>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w) {
+    __shared__ double sD[kStage], sT[kStage];
+    __shared__ int sO[kStage];
+    __shared__ long long s_r0;
+    __shared__ int s_staged;
     const long long total = w.scan[N];
+    const int per = kWG / G;
     const int sub = threadIdx.x % G;
-    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
-    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
-    for (long long g = grp; g < total; g += ngrp) body_lowner<RedGroup<G>>(g, mr, M, e, pmax, w, sub, G);
+    unsigned long long pairs = 0;
+    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+        const long long g0 = tile * per;
+        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+        if (threadIdx.x == 0) {
+            const TileWindow tw = tile_window(g0, g1, mr, w, kStage);
+            s_r0 = tw.r0;
+            s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+        }
+        __syncthreads();
+        const long long r0 = s_r0;
+        const int ns = s_staged;
+        if (ns >= 0)
+            for (int i = threadIdx.x; i < ns; i += kWG) {
+                sD[i] = w.Da[r0 + i];
+                sT[i] = w.tau[r0 + i];
+                sO[i] = w.org[r0 + i];
+            }
+        __syncthreads();
+        const long long g = g0 + threadIdx.x / G;
+        if (g < total) {
+            const int m = w.amerge[g];
+            if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0);
+            else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0);
+            if (sub == 0 && !(mr[m].flags & MF_ROOT)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
+        }
+        __syncthreads();
+    }
+    count_add(&w.counters[CNT_LOW_PAIRS], pairs);
 }
 
 template <int G>
 __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+    __shared__ double sD[kStageRows], sH[kStageRows], sL[kStageRows], sR[kStageRows];
+    __shared__ long long s_r0;
+    __shared__ int s_staged;
     const long long total = w.scan[N];
+    const int per = kWG / G;
     const int sub = threadIdx.x % G;
-    const long long grp = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
-    const long long ngrp = ((long long)gridDim.x * blockDim.x) / G;
-    for (long long g = grp; g < total; g += ngrp) body_rows<RedGroup<G>>(g, mr, M, w, sub, G);
+    unsigned long long pairs = 0;
+    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+        const long long g0 = tile * per;
+        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+        if (threadIdx.x == 0) {
+            const TileWindow tw = tile_window(g0, g1, mr, w, kStageRows);
+            s_r0 = tw.r0;
+            s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+        }
+        __syncthreads();
+        const long long r0 = s_r0;
+        const int ns = s_staged;
+        if (ns >= 0)
+            for (int i = threadIdx.x; i < ns; i += kWG) {
+                sD[i] = w.Da[r0 + i];
+                sH[i] = w.zhat[r0 + i];
+                sL[i] = w.RLa[r0 + i];
+                sR[i] = w.RHa[r0 + i];
+            }
+        __syncthreads();
+        const long long g = g0 + threadIdx.x / G;
+        if (g < total) {
+            const int m = w.amerge[g];
+            if (ns >= 0) body_rows<RedGroup<G>>(g, m, mr, w, sub, G, sD, sH, sL, sR, r0);
+            else body_rows<RedGroup<G>>(g, m, mr, w, sub, G, w.Da, w.zhat, w.RLa, w.RHa, 0);
+            if (sub == 0 && !(mr[m].flags & MF_ROOT)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
+        }
+        __syncthreads();
+    }
+    count_add(&w.counters[CNT_ROW_PAIRS], pairs);
 }
 
 __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, int M, long long N,
@@ -301,15 +439,79 @@ __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ m
 }
 
 // ---------------------------------------------------------------------------
+// Optional per-kernel timing: HIP events recorded on the solve's stream
+// around every launch, summed per launch kind on read-back.
+// ---------------------------------------------------------------------------
+namespace {
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+
+struct TimingScope {
+    int kind;
+    void* stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on;
+    TimingScope(int k, void* s) : kind(k), stream(s), on(g_timing) {
+        if (on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, (hipStream_t)stream);
+        else on = false;
+    }
+    ~TimingScope() {
+        if (!on) return;
+        if (hipEventCreate(&b) != hipSuccess) return;
+        (void)hipEventRecord(b, (hipStream_t)stream);
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_timed.push_back(TimedLaunch{kind, a, b});
+    }
+};
+}  // namespace
+
+void timing_enable(bool on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on;
+}
+
+int timing_read(double* ms, long long* count, int nkinds) {
+    std::vector<TimedLaunch> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        recs.swap(g_timed);
+    }
+    for (int k = 0; k < nkinds; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
+    int rc = 0;
+    for (auto& r : recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) rc = -1;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = -1;
+        if (r.kind >= 0 && r.kind < nkinds) {
+            ms[r.kind] += t;
+            count[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Launch sequence
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
-#define TDE_LAUNCH(kern, grid, block, stream, ...)                                   \
+#define TDE_LAUNCH_K(kindv, kern, grid, block, stream, ...)                          \
     do {                                                                             \
+        TimingScope ts_((kindv), (stream));                                          \
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (hipStream_t)(stream), \
                            __VA_ARGS__);                                             \
     } while (0)
+#define TDE_LAUNCH(kern, grid, block, stream, ...) TDE_LAUNCH_K(KIND_DEFLATE, kern, grid, block, stream, __VA_ARGS__)
 
 // Lanes per root: grows with the level's largest merge so that small merges
 // keep one lane per root and large ones split each pole sweep.
@@ -325,9 +527,11 @@ static void launch_roots_g(long long N, const MergeRec* mr, int M, const double*
     long long nb = (lanes + kWG - 1) / kWG;
     if (nb > 8192) nb = 8192;
     if (nb < 1) nb = 1;
-    TDE_LAUNCH(k_secular<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH(k_lowner<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH(k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
+    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)nb, kWG, stream, mr, M, N, e,
+                 (const unsigned long long*)w.pmax, w);
+    TDE_LAUNCH_K(KIND_LOWNER, k_lowner<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax,
+                 w);
+    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
 }
 
 static void launch_roots(int smax, long long N, const MergeRec* mr, int M, const double* e, const Work& w,
@@ -343,20 +547,21 @@ static void launch_roots(int smax, long long N, const MergeRec* mr, int M, const
 
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream) {
     if (p.ntot == 0) return 0;
-    TDE_LAUNCH(k_fill_i32, 1, 64, stream, w.status, 1LL, 0);
-    TDE_LAUNCH(k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
-    TDE_LAUNCH(k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B, p.ntot,
-               w.pmax, w.status);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 1LL, 0);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
+                 p.ntot, w.pmax, w.status);
     if (p.nleaves > 0) {
         const unsigned g = nblk(p.nleaves, 64);
         if (p.leafmax <= 8)
-            TDE_LAUNCH(k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
         else if (p.leafmax <= 16)
-            TDE_LAUNCH(k_leaf<16>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<16>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
         else if (p.leafmax <= 32)
-            TDE_LAUNCH(k_leaf<32>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<32>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
         else
-            TDE_LAUNCH(k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
     }
     for (const LevelInfo& L : p.levels) {
         const MergeRec* mr = p.d_merges + L.mstart;
@@ -365,7 +570,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         const unsigned nb = nblk(N, kWG);
         const unsigned gstride = nb < 4096u ? nb : 4096u;
         TDE_LAUNCH(k_fill_u64, nblk(M, kWG), kWG, stream, w.zmax, (long long)M, 0ULL);
-        TDE_LAUNCH(k_merge, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
+        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
         TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
         TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
         TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, w);
@@ -374,9 +579,10 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         TDE_LAUNCH(k_stflag, nb, kWG, stream, N, w);
         TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
         TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsumR, (int)nb);
-        TDE_LAUNCH(k_actcompact, nb, kWG, stream, N, w);
+        TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, M, N, w);
         launch_roots(L.smax, N, mr, M, e, w, stream);
-        TDE_LAUNCH(k_assemble, nb, kWG, stream, mr, M, N, (const unsigned long long*)w.pmax, w, out);
+        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, M, N, (const unsigned long long*)w.pmax, w,
+                     out);
     }
     return (int)hipGetLastError();
 }
@@ -395,6 +601,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     const long long nb = (nn + kWG - 1) / kWG + 2;
     Work t{};
     t.status = (int*)take(256);
+    t.counters = t.status ? (unsigned long long*)((char*)t.status + 64) : nullptr;
     t.pmax = (unsigned long long*)take(sizeof(unsigned long long) * (B > 0 ? B : 1));
     t.lam = (double*)take(8 * nn);
     t.blo = (double*)take(8 * nn);
@@ -414,6 +621,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Za = (double*)take(8 * nn);
     t.RLa = (double*)take(8 * nn);
     t.RHa = (double*)take(8 * nn);
+    t.amerge = (int*)take(4 * nn);
     t.org = (int*)take(4 * nn);
     t.tau = (double*)take(8 * nn);
     t.zhat = (double*)take(8 * nn);

@@ -38,6 +38,10 @@ struct Plan {
 // With base == nullptr only the size is computed.
 size_t workspace_layout(long long n, long long B, long long maxM, char* base, Work* w);
 
+// Optional per-kernel timing (HIP events around every launch, per kind).
+void timing_enable(bool on);
+int timing_read(double* ms, long long* count, int nkinds);
+
 // Enqueue one full solve (scale, leaves, every level) on stream.
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out,
                   void* stream);
