@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--family", default="uniform")
     ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--leaf", type=int, default=0, help="0 = library default")
+    ap.add_argument("--leaf", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
+    ap.add_argument("--sweep-cols", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-secondary", action="store_true")
@@ -174,8 +176,19 @@ def main():
     import paper_2605_26599_amd as tde
     import tdgen
 
+    from paper_2605_26599_amd import autotune
+
     dev = torch.device("cuda:0")
-    leaf = args.leaf or None
+    tuning = {}
+
+    def choose(d, e, offs, label):
+        """(leaf, sweep_cols): explicit flags, else the autotuner (untimed)."""
+        if args.leaf or args.sweep_cols or args.no_tune:
+            return args.leaf or None, args.sweep_cols or None
+        r = autotune.tune(d, e, offs, reps=3)
+        tuning[label] = {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "best_ms": r["ms"],
+                         "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
+        return r["leaf"], r["sweep_cols"]
 
     def make_batched():
         batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
@@ -183,17 +196,19 @@ def main():
         e = torch.from_numpy(batch.e).to(dev)
         out = torch.empty(int(batch.offsets[-1]), dtype=torch.float64, device=dev)
         offs = batch.offsets
+        bleaf, bcols = choose(d, e, offs, "batched")
 
         def step():
-            tde.eigvals_batched(d, e, offs, leaf=leaf, out=out, check=False)
+            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, out=out, check=False)
 
-        return batch, step
+        return batch, step, (bleaf, bcols)
 
     if args.batched:
-        batch, step = make_batched()
+        batch, step, (leaf, cols) = make_batched()
         n_cols = int(batch.offsets[-1])
         workload = {"workload": f"batched: 4096 tridiagonals, sizes log-uniform in [32,4096] "
-                                f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols}
+                                f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols,
+                    "leaf": leaf or "default", "sweep_cols": cols or "default"}
         metric, unit, per_step = "batched solves/s", "solves/s", 4096
         dn = en = None
     else:
@@ -203,12 +218,13 @@ def main():
         e = torch.from_numpy(en).to(dev)
         out = torch.empty(n, dtype=torch.float64, device=dev)
         n_cols = n
+        leaf, cols = choose(d, e, None, "single")
 
         def step():
-            tde.eigvals(d, e, leaf=leaf, out=out, check=False)
+            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
 
         workload = {"workload": f"single tridiagonal n={n}, family {args.family} (seeded synthetic)", "n": n,
-                    "leaf": args.leaf or "default"}
+                    "leaf": leaf or "default", "sweep_cols": cols or "default"}
         metric, unit, per_step = f"FP64 tridiag eigvals/s @n={n}", "eigvals/s", n
 
     for _ in range(args.warmup):
@@ -258,7 +274,7 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(dn, en, args.cpu_seconds)
     sec = {}
     if not args.no_secondary and not args.batched:
-        batch, bstep = make_batched()
+        batch, bstep, _ = make_batched()
         for _ in range(2):
             bstep()
         bms = timed(bstep, 5) / 5
@@ -268,6 +284,8 @@ def main():
         sec["cpu_ql"] = ql_baseline(dn, en, args.cpu_seconds)
     if sec:
         rec["secondary"] = sec
+    if tuning:
+        rec["autotune"] = tuning
     print(json.dumps(rec), flush=True)
 
 

@@ -25,8 +25,12 @@
  *    workspace, read back by tde_get_status.
  *  - The first call for a given problem shape (sizes and leaf size) builds and
  *    caches a plan: small device tables describing the merge tree, allocated
- *    once per shape and device and kept until tde_release_plans.  Later calls
- *    with the same shape allocate nothing.
+ *    once per shape and device and kept until tde_release_plans.  The first
+ *    call for a given plan and set of buffers (d, e, lambda, workspace) also
+ *    captures the whole solve into a HIP graph on an internal stream; later
+ *    calls with the same plan and buffers replay it with one hipGraphLaunch
+ *    on the caller's stream and allocate nothing.  TDE_FLAG_NO_GRAPH, or
+ *    timing mode, enqueues the kernels one by one instead.
  *  - Inputs and outputs must not overlap.  Concurrent calls on different
  *    streams need distinct workspaces.
  *  - No exceptions cross this interface and nothing is printed.
@@ -50,10 +54,14 @@ extern "C" {
 #define TDE_ENOCONV 1       /* device status: a leaf QL or secular iteration hit its cap */
 
 /* Options.  Pass NULL for defaults. */
+#define TDE_FLAG_NO_GRAPH 1 /* enqueue every kernel eagerly instead of replaying a captured graph */
 typedef struct {
-    int leaf;      /* largest leaf size solved directly by QL, 1..64; 0 = default (8) */
-    int flags;     /* reserved, must be 0 */
-    int reserved[6];
+    int leaf;       /* largest leaf size solved directly by QL, 1..64; 0 = default (8) */
+    int flags;      /* 0 or TDE_FLAG_NO_GRAPH; other bits are rejected */
+    int sweep_cols; /* target poles per lane in the root-parallel sweeps: each root
+                       gets G = min(16, 2^ceil(log2(largest merge / sweep_cols)))
+                       lanes; 0 = default (8) */
+    int reserved[5];
 } tde_opts;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */

@@ -57,7 +57,8 @@ class TDEError(RuntimeError):
 
 
 class tde_opts(ctypes.Structure):
-    _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+    _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 _lib = None
@@ -120,12 +121,16 @@ def _status_string(code: int) -> str:
         return "status"
 
 
-def _opts(leaf):
-    if leaf is None:
+TDE_FLAG_NO_GRAPH = 1
+
+
+def _opts(leaf, graph=True, sweep_cols=None):
+    if leaf is None and graph and sweep_cols is None:
         return None
     o = tde_opts()
-    o.leaf = int(leaf)
-    o.flags = 0
+    o.leaf = int(leaf or 0)
+    o.flags = 0 if graph else TDE_FLAG_NO_GRAPH
+    o.sweep_cols = int(sweep_cols or 0)
     return ctypes.byref(o)
 
 
@@ -163,9 +168,12 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
-            workspace: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+            workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
+            sweep_cols=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
-    off-diagonal e[n-1], on d's device and torch's current stream."""
+    off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
+    replays a captured HIP graph of the whole solve (captured on first use for
+    these buffers); graph=False enqueues the kernels one by one."""
     _check_input(d, e)
     n = d.numel()
     if e.numel() < max(n - 1, 0):
@@ -181,7 +189,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
-                               ws.data_ptr(), ws.numel(), stream, _opts(leaf))
+                               ws.data_ptr(), ws.numel(), stream, _opts(leaf, graph, sweep_cols))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -192,7 +200,8 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 
 
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
-                    workspace: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+                    workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
+                    sweep_cols=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -213,7 +222,7 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
-                                       ws.numel(), stream, _opts(leaf))
+                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:

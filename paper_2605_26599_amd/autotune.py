@@ -1,0 +1,112 @@
+"""Autotuner for the solver's launch shape.
+
+Two knobs change speed but not the method: the leaf size (largest block solved
+directly by QL) and the target number of poles each lane sweeps in the
+root-parallel kernels (which sets the lanes per root, G <= 16, per level).
+`tune` times every combination on the device (graph replay, inputs resident)
+and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
+architecture and a size bucket (log2 of the column count, batch or single),
+so later runs reuse them without re-timing.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+LEAVES = (1, 2, 4, 8, 16, 32)
+SWEEP_COLS = (1, 2, 4, 8, 16, 32, 64)
+
+
+def cache_path() -> str:
+    p = os.environ.get("TDE_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "tde", "tuned.json")
+
+
+def _arch(device) -> str:
+    props = torch.cuda.get_device_properties(device)
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def bucket(n_total: int, batch: int) -> str:
+    kind = "batch" if batch > 1 else "single"
+    return f"{kind}:2^{max(0, int(math.ceil(math.log2(max(n_total, 1)))))}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db: dict) -> None:
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def lookup(n_total: int, batch: int = 1, device=None):
+    """Cached (leaf, sweep_cols) for this size bucket, or None."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    rec = _load().get(_arch(dev), {}).get(bucket(n_total, batch))
+    if rec:
+        return int(rec["leaf"]), int(rec["sweep_cols"])
+    return None
+
+
+def _time(step, reps: int) -> float:
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(d: torch.Tensor, e: torch.Tensor, offsets=None, reps: int = 5, leaves=LEAVES, sweep_cols=SWEEP_COLS,
+         store: bool = True) -> dict:
+    """Time every (leaf, sweep_cols) on this input; return and cache the best.
+
+    d, e are device tensors (single problem: e has n-1 entries; batch: offsets
+    is the host offsets sequence).  Returns {"leaf", "sweep_cols", "ms",
+    "table": [(leaf, cols, ms), ...], "tune_s"}.
+    """
+    import paper_2605_26599_amd as tde
+
+    t0 = time.perf_counter()
+    out = torch.empty(d.numel(), dtype=torch.float64, device=d.device)
+    table = []
+    for leaf in leaves:
+        for cols in sweep_cols:
+            if offsets is None:
+                def step(leaf=leaf, cols=cols):
+                    tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
+            else:
+                def step(leaf=leaf, cols=cols):
+                    tde.eigvals_batched(d, e, offsets, leaf=leaf, sweep_cols=cols, out=out, check=False)
+            step()
+            step()
+            table.append((leaf, cols, _time(step, reps)))
+    best = min(table, key=lambda r: r[2])
+    n_total = int(d.numel()) if offsets is None else int(offsets[-1])
+    batch = 1 if offsets is None else len(offsets) - 1
+    res = {"leaf": best[0], "sweep_cols": best[1], "ms": best[2], "table": table,
+           "tune_s": time.perf_counter() - t0, "bucket": bucket(n_total, batch)}
+    if store:
+        db = _load()
+        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "sweep_cols": best[1], "ms": best[2]}
+        _store(db)
+    return res

@@ -16,21 +16,69 @@
 namespace tde {
 namespace {
 
-using PlanKey = std::tuple<int, int, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, std::vector<long long>>;
 std::mutex g_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+
+// Captured solves: one executable graph per (plan, buffers).  Capture runs on
+// an internal stream per device; replays run on the caller's stream.
+using GraphKey = std::tuple<const Plan*, const void*, const void*, const void*, const void*>;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
+constexpr size_t kMaxGraphs = 64;
+
+void drop_graphs() {
+    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+}
+
+int graph_for(const Plan& plan, const Work& w, const double* d, const double* e, double* out, void* ws,
+              hipGraphExec_t* exec) {
+    GraphKey key{&plan, d, e, out, ws};
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        *exec = it->second;
+        return TDE_OK;
+    }
+    if (g_graphs.size() >= kMaxGraphs) drop_graphs();
+    hipStream_t cs;
+    auto sit = g_capture_streams.find(plan.device);
+    if (sit == g_capture_streams.end()) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TDE_EDEVICE;
+        g_capture_streams[plan.device] = cs;
+    } else {
+        cs = sit->second;
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TDE_EDEVICE;
+    const int rc = enqueue_solve(plan, w, d, e, out, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != 0 || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return TDE_EDEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return TDE_EDEVICE;
+    g_graphs.emplace(key, ge);
+    *exec = ge;
+    return TDE_OK;
+}
 
 void free_plan(Plan* p) {
     if (p->d_merges) (void)hipFree(p->d_merges);
     if (p->d_leaves) (void)hipFree(p->d_leaves);
     if (p->d_offs) (void)hipFree(p->d_offs);
+    if (p->d_blkm) (void)hipFree(p->d_blkm);
+    p->d_blkm = nullptr;
     p->d_merges = nullptr;
     p->d_leaves = nullptr;
     p->d_offs = nullptr;
 }
 
-int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** out) {
-    PlanKey key{device, leaf, offs};
+int make_plan(int device, int leaf, int cols, const std::vector<long long>& offs, Plan** out) {
+    PlanKey key{device, leaf, cols, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second.get();
@@ -39,6 +87,7 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
     auto p = std::make_unique<Plan>();
     p->device = device;
     p->leaf = leaf;
+    p->sweep_cols = cols;
     p->offs = offs;
     p->B = (int)offs.size() - 1;
     p->ntot = offs.back();
@@ -46,18 +95,29 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
     const std::vector<MergeRec>& flat = t.merges;
     int maxM = 1;
     long long maxN = 1;
+    std::vector<int> blkm;
     for (size_t h = 0; h < t.mstart.size(); ++h) {
         LevelInfo info{};
         info.mstart = t.mstart[h];
         info.M = t.mcount[h];
         info.N = t.ncols[h];
         info.smax = t.smax[h];
+        // blkm[b] = merge holding packed column min(b*kWG, N-1), b = 0..nb
+        info.bstart = (int)blkm.size();
+        const long long nb = (info.N + kWG - 1) / kWG;
+        int m = 0;
+        for (long long b = 0; b <= nb; ++b) {
+            const long long c = std::min(b * (long long)kWG, info.N - 1);
+            while (m + 1 < info.M && flat[info.mstart + m + 1].pk <= c) ++m;
+            blkm.push_back(m);
+        }
         maxM = std::max(maxM, info.M);
         maxN = std::max(maxN, info.N);
         p->levels.push_back(info);
     }
     p->maxM = maxM;
     p->maxN = maxN;
+    p->zmax_total = std::max<long long>(1, (long long)flat.size());
     p->nleaves = (int)t.leaves.size();
     int lmax = 1;
     for (auto& L : t.leaves) lmax = std::max(lmax, L.size);
@@ -71,7 +131,8 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
     bool ok = upload((void**)&p->d_merges, flat.empty() ? nullptr : flat.data(), flat.size() * sizeof(MergeRec)) &&
               upload((void**)&p->d_leaves, t.leaves.empty() ? nullptr : t.leaves.data(),
                      t.leaves.size() * sizeof(LeafRec)) &&
-              upload((void**)&p->d_offs, offs.data(), offs.size() * sizeof(long long));
+              upload((void**)&p->d_offs, offs.data(), offs.size() * sizeof(long long)) &&
+              upload((void**)&p->d_blkm, blkm.empty() ? nullptr : blkm.data(), blkm.size() * sizeof(int));
     if (!ok) {
         free_plan(p.get());
         return TDE_ENOMEM;
@@ -81,21 +142,24 @@ int make_plan(int device, int leaf, const std::vector<long long>& offs, Plan** o
     return TDE_OK;
 }
 
-int resolve_leaf(const tde_opts* opts, int* leaf) {
-    int L = kDefaultLeaf;
+int resolve_opts(const tde_opts* opts, int* leaf, int* cols) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols;
     if (opts) {
-        if (opts->flags != 0) return TDE_EINVAL;
+        if (opts->flags & ~TDE_FLAG_NO_GRAPH) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
+        if (opts->sweep_cols != 0) C = opts->sweep_cols;
     }
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
+    if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
     *leaf = L;
+    *cols = C;
     return TDE_OK;
 }
 
 int solve(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
           size_t ws_bytes, void* stream, const tde_opts* opts) {
-    int leaf;
-    if (resolve_leaf(opts, &leaf) != TDE_OK) return TDE_EINVAL;
+    int leaf, cols;
+    if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
     const long long ntot = offs.back();
     const long long B = (long long)offs.size() - 1;
     if (ntot == 0) return TDE_OK;
@@ -104,17 +168,28 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
     for (long long b = 0; b < B; ++b)
         if (offs[b + 1] - offs[b] > 1) need_e = true;
     if (need_e && !e) return TDE_EINVAL;
-    if (ws_bytes < workspace_layout(ntot, B, ntot / 2 + 1, nullptr, nullptr)) return TDE_EINVAL;
+    if (ws_bytes < workspace_layout(ntot, B, ntot, nullptr, nullptr)) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
     Plan* plan = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        int rc = make_plan(device, leaf, offs, &plan);
+        int rc = make_plan(device, leaf, cols, offs, &plan);
         if (rc != TDE_OK) return rc;
     }
     Work w{};
-    workspace_layout(ntot, B, plan->maxM, (char*)ws, &w);
+    workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
+    const bool use_graph = !(opts && (opts->flags & TDE_FLAG_NO_GRAPH)) && !timing_enabled();
+    if (use_graph) {
+        hipGraphExec_t ge = nullptr;
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            rc = graph_for(*plan, w, d, e, lambda, ws, &ge);
+        }
+        if (rc != TDE_OK) return rc;
+        return hipGraphLaunch(ge, (hipStream_t)stream) == hipSuccess ? TDE_OK : TDE_EDEVICE;
+    }
     int rc = enqueue_solve(*plan, w, d, e, lambda, stream);
     return rc == 0 ? TDE_OK : TDE_EDEVICE;
 }
@@ -127,9 +202,9 @@ extern "C" {
 int tde_version(void) { return 100; }
 
 size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts) {
-    int leaf;
-    if (n_total < 0 || batch < 0 || tde::resolve_leaf(opts, &leaf) != TDE_OK) return 0;
-    return tde::workspace_layout(n_total, batch, n_total / 2 + 1, nullptr, nullptr);
+    int leaf, cols;
+    if (n_total < 0 || batch < 0 || tde::resolve_opts(opts, &leaf, &cols) != TDE_OK) return 0;
+    return tde::workspace_layout(n_total, batch, n_total, nullptr, nullptr);
 }
 
 int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, void* ws, size_t ws_bytes,
@@ -186,6 +261,7 @@ int tde_timing_read(double* ms, int64_t* launches, int nkinds) {
 
 void tde_release_plans(void) {
     std::lock_guard<std::mutex> lk(tde::g_mu);
+    tde::drop_graphs();
     for (auto& kv : tde::g_plans) tde::free_plan(kv.second.get());
     tde::g_plans.clear();
 }

@@ -48,6 +48,17 @@ TDE_DEV double scale_of(unsigned long long maxbits) {
     return ldexp(1.0, ex);
 }
 
+// Largest m in [lo, hi] with mr[m].pk <= t (merge lookup within a range known
+// to contain the answer).
+TDE_DEV int find_merge_in(const MergeRec* __restrict__ mr, int lo, int hi, long long t) {
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (mr[mid].pk <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Largest m in [0, M) with key(m) <= t, for nondecreasing keys (merge lookup).
 TDE_DEV int find_merge(const MergeRec* __restrict__ mr, int M, long long t) {
     int lo = 0, hi = M - 1;
@@ -389,17 +400,17 @@ TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Element-parallel level steps.  Packed position t in [0, N) of a level maps
-// to merge m = find_merge(mr, M, t) and local column i = t - mr[m].pk.
+// Element-parallel level steps.  Packed position t in [0, N) of a level
+// belongs to merge m (mr[m].pk <= t < mr[m].pk + size) at local column
+// i = t - mr[m].pk; callers find m (find_merge / find_merge_in).
 // ---------------------------------------------------------------------------
 
 // (a3/a4) z~, outer rows and merged sorted order of one child column.
 // Left column i: position i + #{right values < x}; right column j:
 // j + #{left values <= x} (ties go left first).  Returns the packed position.
-TDE_DEV long long body_merge(long long t, const MergeRec* __restrict__ mr, int M,
+TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr,
                              const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
-                             const Work& w, int* m_out, double* absz_out) {
-    const int m = find_merge(mr, M, t);
+                             const Work& w, double* absz_out) {
     const MergeRec R = mr[m];
     const int i = (int)(t - R.pk);
     double sgn;
@@ -440,16 +451,14 @@ TDE_DEV long long body_merge(long long t, const MergeRec* __restrict__ mr, int M
     w.Z[P] = z;
     w.RL[P] = rl;
     w.RH[P] = rh;
-    *m_out = m;
     *absz_out = fabs(z);
     return P;
 }
 
 // (a5) negligible-z test: column stays a candidate iff rho~ |z~_j| > tol.
-TDE_DEV int body_nnflag(long long t, const MergeRec* __restrict__ mr, int M,
+TDE_DEV int body_nnflag(long long t, int m, const MergeRec* __restrict__ mr,
                         const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
                         const Work& w) {
-    const int m = find_merge(mr, M, t);
     const MergeRec R = mr[m];
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
@@ -459,53 +468,46 @@ TDE_DEV int body_nnflag(long long t, const MergeRec* __restrict__ mr, int M,
     return flag;
 }
 
-// (a5) close poles, step 1: cf[g] = 1 iff non-negligible columns g and g+1
-// of the same merge pass the close-pole test on their unrotated values.
-TDE_DEV void body_closeflag(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
-    const int* __restrict__ nnpos = w.nnpos;
-    const long long t = nnpos[g];
-    const int m = find_merge(mr, M, t);
-    const MergeRec R = mr[m];
-    const int s = R.nL + R.nR;
-    const long long ge = w.scan[R.pk + s];
-    int f = 0;
-    if (g + 1 < ge) {
-        const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
-        const long long u = nnpos[g + 1];
-        f = close_pair(w.D[t], w.Z[t], w.D[u], w.Z[u], tol) ? 1 : 0;
-    }
-    w.cf[g] = f;
+// (a5) close poles.  Candidate g (the g-th non-negligible column of the level)
+// starts a run if it passes the close test with its successor but not with
+// its predecessor, both tested on the unrotated values; the run extends while
+// consecutive candidates keep passing.  The run's owner walks the run left to
+// right, re-testing each pair on the current (rotated) values, and deflates
+// the left column of every rotated pair.  All tests read the unrotated arrays
+// (D, Z, RL, RH) and every candidate's final values go to (D2, Z2, RL2, RH2),
+// so runs proceed in parallel without races; a candidate outside every run is
+// copied through by its own thread.  on_rotate(p) is called for each column
+// rotated away.
+TDE_DEV bool cand_close(const Work& w, long long a, long long b, double tol) {
+    const long long pa = w.nnpos[a], pb = w.nnpos[b];
+    return close_pair(w.D[pa], w.Z[pa], w.D[pb], w.Z[pb], tol);
 }
 
-// (a5) close poles, step 2.  Candidate g starts a run if it is close to its
-// successor but not to its predecessor; the run extends while cf stays set.
-// The run's owner applies the rotations in order along the run, re-testing
-// each pair on the current (rotated) values, deflating the left column of
-// every rotated pair, then sorts the deflated entries inside the run's span so
-// that each merge's deflated list stays ascending.  Runs are disjoint, so
-// runs proceed in parallel.
-TDE_DEV void body_runs(long long g, const MergeRec* __restrict__ mr, int M, const Work& w) {
+template <class OnRotate>
+TDE_DEV void body_runs(long long g, int m, const MergeRec* __restrict__ mr, const Work& w, OnRotate on_rotate) {
     const int* __restrict__ nnpos = w.nnpos;
-    const int* __restrict__ cf = w.cf;
-    if (!cf[g]) return;
     const long long t = nnpos[g];
-    const int m = find_merge(mr, M, t);
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
-    const long long gs = w.scan[R.pk];
-    if (g > gs && cf[g - 1]) return;
-    long long r = g + 1;
-    while (cf[r]) ++r;  // cf[last column of a merge] == 0 ends every run
+    const long long gs = w.scan[R.pk], ge = w.scan[R.pk + s];
     const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
-    double* D = w.D;
-    double* Z = w.Z;
-    double* RL = w.RL;
-    double* RH = w.RH;
+    const bool cl_next = (g + 1 < ge) && cand_close(w, g, g + 1, tol);
+    const bool cl_prev = (g > gs) && cand_close(w, g - 1, g, tol);
+    if (cl_prev) return;  // inside a run owned by an earlier candidate
+    if (!cl_next) {       // not in any run: copy through
+        w.D2[t] = w.D[t];
+        w.Z2[t] = w.Z[t];
+        w.RL2[t] = w.RL[t];
+        w.RH2[t] = w.RH[t];
+        return;
+    }
+    long long r = g + 1;
+    while (r + 1 < ge && cand_close(w, r, r + 1, tol)) ++r;
     long long pc = t;
-    double Dc = D[pc], Zc = Z[pc], Lc = RL[pc], Hc = RH[pc];
+    double Dc = w.D[pc], Zc = w.Z[pc], Lc = w.RL[pc], Hc = w.RH[pc];
     for (long long j = g + 1; j <= r; ++j) {
         const long long pj = nnpos[j];
-        const double Dj = D[pj], Zj = Z[pj], Lj = RL[pj], Hj = RH[pj];
+        const double Dj = w.D[pj], Zj = w.Z[pj], Lj = w.RL[pj], Hj = w.RH[pj];
         const double tt = hypot(Zc, Zj);
         const double c = Zj / tt, sn = Zc / tt;
         if (fabs((Dj - Dc) * c * sn) <= tol) {
@@ -513,28 +515,29 @@ TDE_DEV void body_runs(long long g, const MergeRec* __restrict__ mr, int M, cons
             // Both new diagonal entries are convex combinations of Dc <= Dj;
             // clamping them into [Dc, Dj] keeps rounding from breaking the
             // ascending order that the parent assembly merges on.
-            D[pc] = fmin(fmax(c * c * Dc + sn * sn * Dj, Dc), Dj);
-            Z[pc] = 0.0;
-            RL[pc] = c * Lc - sn * Lj;
-            RH[pc] = c * Hc - sn * Hj;
+            w.D2[pc] = fmin(fmax(c * c * Dc + sn * sn * Dj, Dc), Dj);
+            w.Z2[pc] = 0.0;
+            w.RL2[pc] = c * Lc - sn * Lj;
+            w.RH2[pc] = c * Hc - sn * Hj;
             w.st[pc] = 2;
+            on_rotate(pc);
             Dc = fmin(fmax(sn * sn * Dc + c * c * Dj, Dc), Dj);
             Zc = tt;
             Lc = sn * Lc + c * Lj;
             Hc = sn * Hc + c * Hj;
         } else {
-            D[pc] = Dc;
-            Z[pc] = Zc;
-            RL[pc] = Lc;
-            RH[pc] = Hc;
+            w.D2[pc] = Dc;
+            w.Z2[pc] = Zc;
+            w.RL2[pc] = Lc;
+            w.RH2[pc] = Hc;
             Dc = Dj; Zc = Zj; Lc = Lj; Hc = Hj;
         }
         pc = pj;
     }
-    D[pc] = Dc;
-    Z[pc] = Zc;
-    RL[pc] = Lc;
-    RH[pc] = Hc;
+    w.D2[pc] = Dc;
+    w.Z2[pc] = Zc;
+    w.RL2[pc] = Lc;
+    w.RH2[pc] = Hc;
     // The rotated-away columns of a run join their own list, ascending in
     // position order: sort them among the run's rotated positions (only
     // columns g..r-1 can be rotated away).  Their values lie in [D_g, D_r],
@@ -542,18 +545,18 @@ TDE_DEV void body_runs(long long g, const MergeRec* __restrict__ mr, int M, cons
     for (long long j = g; j < r; ++j) {
         const long long pj = nnpos[j];
         if (w.st[pj] != 2) continue;
-        const double kD = D[pj], kL = RL[pj], kH = RH[pj];
+        const double kD = w.D2[pj], kL = w.RL2[pj], kH = w.RH2[pj];
         long long h = j;
         for (long long q = j - 1; q >= g; --q) {
             const long long pq = nnpos[q];
             if (w.st[pq] != 2) continue;
-            if (D[pq] <= kD) break;
+            if (w.D2[pq] <= kD) break;
             const long long ph = nnpos[h];
-            D[ph] = D[pq]; RL[ph] = RL[pq]; RH[ph] = RH[pq];
+            w.D2[ph] = w.D2[pq]; w.RL2[ph] = w.RL2[pq]; w.RH2[ph] = w.RH2[pq];
             h = q;
         }
         const long long ph = nnpos[h];
-        D[ph] = kD; RL[ph] = kL; RH[ph] = kH;
+        w.D2[ph] = kD; w.RL2[ph] = kL; w.RH2[ph] = kH;
     }
 }
 
@@ -671,9 +674,8 @@ TDE_DEV int roots_cmp_count(const double* __restrict__ Da, const int* __restrict
     return lo;
 }
 
-TDE_DEV void body_assemble(long long t, const MergeRec* __restrict__ mr, int M,
+TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
                            const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
-    const int m = find_merge(mr, M, t);
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
     const int i = (int)(t - R.pk);

@@ -60,6 +60,7 @@ enum {
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels
 constexpr int kLeafMax = 64;     // largest leaf the QL leaf kernel accepts
 constexpr int kDefaultLeaf = 8;  // leaf size when the caller does not choose one
+constexpr int kDefaultSweepCols = 8;  // poles per lane per sweep when the caller does not choose
 constexpr int kSecMaxIter = 96;  // secular iteration cap
 
 // Pointers into the caller's workspace for one solve.
@@ -74,11 +75,19 @@ struct Work {
     double* Z;                 // [n]   secular vector z~ in pole order
     double* RL;                // [n]   parent-first-row entries per column
     double* RH;                // [n]   parent-last-row entries per column
+    double* D2;                // [n]   candidates after close-pole rotations
+    double* Z2;                // [n]
+    double* RL2;               // [n]
+    double* RH2;               // [n]
     int* st;                   // [n]   column state: 0 negligible z, 1 active, 2 rotated away
     int* scan;                 // [n+1] exclusive prefix counts (candidates, then active columns)
     int* scanR;                // [n+1] exclusive prefix counts of rotated-away columns
     int* bsum;                 // [nb+1] per-block counts
     int* bsumR;                // [nb+1] per-block counts of rotated-away columns
+    int* bsumA;                // [nb+1] per-block counts of active columns (raw)
+    int* bsumAs;               // [nb+1] exclusive scan of bsumA
+    int* bsumRs;               // [nb+1] exclusive scan of bsumR
+    unsigned* ticket;          // [1]   last-workgroup ticket (self-resetting)
     int* nnpos;                // [n]   packed positions of non-negligible columns
     int* cf;                   // [n]   close-pair flag of non-negligible column g and g+1
     double* Da;                // [n]   active poles
@@ -97,7 +106,7 @@ struct Work {
     double* Dr;                // [n]   rotated-away columns: eigenvalue (ascending per merge)
     double* RLr;               // [n]
     double* RHr;               // [n]
-    unsigned long long* zmax;  // [maxM] bits of max |z~| per merge
+    unsigned long long* zmax;  // [M] bits of max |z~| per merge (this level's slice)
 };
 
 }  // namespace tde

@@ -68,23 +68,39 @@ __device__ __forceinline__ int block_incl_scan(int v, int* wsum) {
     return v;
 }
 
-// Exclusive scan of the per-block counts bsum[0..nb), total into bsum[nb].
-__global__ __launch_bounds__(1024) void k_scan_blocks(int* bsum, int nb) {
+// Exclusive scans of the per-block counts in[0..nb) into out[0..nb], totals
+// in out[nb]; a second array pair is scanned when in2 is given.
+__global__ __launch_bounds__(1024) void k_scan_blocks(const int* in, int* out, const int* in2, int* out2, int nb) {
     __shared__ int wsum[16];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ int carry, carry2;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        carry2 = 0;
+    }
     __syncthreads();
     for (int base = 0; base < nb; base += 1024) {
         const int i = base + threadIdx.x;
-        const int v = (i < nb) ? bsum[i] : 0;
+        const int v = (i < nb) ? in[i] : 0;
+        const int v2 = (in2 && i < nb) ? in2[i] : 0;
         const int incl = block_incl_scan(v, wsum);
-        const int c = carry;
-        if (i < nb) bsum[i] = c + incl - v;
         __syncthreads();
-        if (threadIdx.x == 1023) carry = c + incl;
+        const int incl2 = block_incl_scan(v2, wsum);
+        const int c = carry, c2 = carry2;
+        if (i < nb) {
+            out[i] = c + incl - v;
+            if (in2) out2[i] = c2 + incl2 - v2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            carry = c + incl;
+            carry2 = c2 + incl2;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) bsum[nb] = carry;
+    if (threadIdx.x == 0) {
+        out[nb] = carry;
+        if (in2) out2[nb] = carry2;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -145,15 +161,25 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
 }
 
 // ---------------------------------------------------------------------------
-// Level steps
+// Level steps.  Element-parallel kernels find the merge of packed position t
+// inside [blkm[t/kWG], blkm[t/kWG + 1]] (a static per-block table of the
+// plan), so each lookup searches only the few merges a block touches.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, int M, long long N,
-                                               const double* __restrict__ e,
+__device__ __forceinline__ int merge_of(const MergeRec* __restrict__ mr, const int* __restrict__ blkm, long long t) {
+    const long long b = t / kWG;
+    return find_merge_in(mr, blkm[b], blkm[b + 1], t);
+}
+
+__global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                               long long N, const double* __restrict__ e,
                                                const unsigned long long* __restrict__ pmax, Work w) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     int m = -1;
     double az = 0.0;
-    if (t < N) body_merge(t, mr, M, e, pmax, w, &m, &az);
+    if (t < N) {
+        m = merge_of(mr, blkm, t);
+        body_merge(t, m, mr, e, pmax, w, &az);
+    }
     count_add(&w.counters[CNT_MERGE_COLS], t < N ? 1ULL : 0ULL);
     unsigned long long v = dbits(az);
     const int m0 = __shfl(m, 0, 64);
@@ -165,35 +191,27 @@ __global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, 
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_nnflag(const MergeRec* __restrict__ mr, int M, long long N,
-                                                const double* __restrict__ e,
+// Negligible-z flags; per-block candidate counts into bsumA.
+__global__ __launch_bounds__(kWG) void k_nnflag(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                long long N, const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     int f = 0;
-    if (t < N) f = body_nnflag(t, mr, M, e, pmax, w);
+    if (t < N) f = body_nnflag(t, merge_of(mr, blkm, t), mr, e, pmax, w);
     const int c = __syncthreads_count(f);
-    if (threadIdx.x == 0) w.bsum[blockIdx.x] = c;
-}
-
-__global__ __launch_bounds__(kWG) void k_stflag(long long N, Work w) {
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int s = (t < N) ? w.st[t] : 0;
-    const int c = __syncthreads_count(s == 1);
-    const int r = __syncthreads_count(s == 2);
-    if (threadIdx.x == 0) {
-        w.bsum[blockIdx.x] = c;
-        w.bsumR[blockIdx.x] = r;
-    }
+    if (threadIdx.x == 0) w.bsumA[blockIdx.x] = c;
 }
 
 // Compaction of candidate (st == 1) columns: scan[t] = exclusive count,
-// nnpos[g] = t for the g-th candidate.
+// nnpos[g] = t for the g-th candidate.  Also clears this block's count of
+// rotated-away columns.
 __global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
     __shared__ int wsum[16];
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int f = (t < N) ? (w.st[t] == 1) : 0;
     const int incl = block_incl_scan(f, wsum);
     const int g = w.bsum[blockIdx.x] + incl - f;
+    if (threadIdx.x == 0) w.bsumR[blockIdx.x] = 0;
     if (t < N) {
         w.scan[t] = g;
         if (f) w.nnpos[g] = (int)t;
@@ -201,25 +219,29 @@ __global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_closeflag(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+// Close-pole runs over the candidates (grid-stride).  Each rotated-away
+// column moves one count from its block's active tally to its rotated tally.
+__global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                              long long N, Work w) {
     const long long total = w.scan[N];
+    int* bA = w.bsumA;
+    int* bR = w.bsumR;
+    auto on_rotate = [bA, bR](long long p) {
+        atomicSub(&bA[p / kWG], 1);
+        atomicAdd(&bR[p / kWG], 1);
+    };
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
          g += (long long)gridDim.x * blockDim.x)
-        body_closeflag(g, mr, M, w);
-}
-
-__global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
-    const long long total = w.scan[N];
-    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x)
-        body_runs(g, mr, M, w);
+        body_runs(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, on_rotate);
 }
 
 // Three-way split of a level's columns: active ones to (Da, Za, RLa, RHa) at
 // their active index, rotated-away ones to (Dr, RLr, RHr) and negligible-z
 // ones to (Dd, RLd, RHd), each list in column order.  scan / scanR hold the
-// exclusive active / rotated counts.
-__global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
+// exclusive active / rotated counts.  Candidates read their post-rotation
+// values (D2, ...), negligible columns the merged ones (D, ...).
+__global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                    long long N, Work w) {
     __shared__ int wsum[16];
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int s = (t < N) ? w.st[t] : 0;
@@ -228,21 +250,21 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
     const int ia = block_incl_scan(fa, wsum);
     __syncthreads();
     const int ir = block_incl_scan(fr, wsum);
-    const int g = w.bsum[blockIdx.x] + ia - fa;
-    const int gr = w.bsumR[blockIdx.x] + ir - fr;
+    const int g = w.bsumAs[blockIdx.x] + ia - fa;
+    const int gr = w.bsumRs[blockIdx.x] + ir - fr;
     if (t < N) {
         w.scan[t] = g;
         w.scanR[t] = gr;
         if (fa) {
-            w.Da[g] = w.D[t];
-            w.Za[g] = w.Z[t];
-            w.RLa[g] = w.RL[t];
-            w.RHa[g] = w.RH[t];
-            w.amerge[g] = find_merge(mr, M, t);
+            w.Da[g] = w.D2[t];
+            w.Za[g] = w.Z2[t];
+            w.RLa[g] = w.RL2[t];
+            w.RHa[g] = w.RH2[t];
+            w.amerge[g] = merge_of(mr, blkm, t);
         } else if (fr) {
-            w.Dr[gr] = w.D[t];
-            w.RLr[gr] = w.RL[t];
-            w.RHr[gr] = w.RH[t];
+            w.Dr[gr] = w.D2[t];
+            w.RLr[gr] = w.RL2[t];
+            w.RHr[gr] = w.RH2[t];
         } else {
             const long long q = t - g - gr;
             w.Dd[q] = w.D[t];
@@ -431,11 +453,11 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
     count_add(&w.counters[CNT_ROW_PAIRS], pairs);
 }
 
-__global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, int M, long long N,
-                                                  const unsigned long long* __restrict__ pmax, Work w,
+__global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                  long long N, const unsigned long long* __restrict__ pmax, Work w,
                                                   double* __restrict__ out) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < N) body_assemble(t, mr, M, pmax, w, out);
+    if (t < N) body_assemble(t, merge_of(mr, blkm, t), mr, pmax, w, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -473,6 +495,11 @@ struct TimingScope {
 void timing_enable(bool on) {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on;
+}
+
+bool timing_enabled() {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return g_timing;
 }
 
 int timing_read(double* ms, long long* count, int nkinds) {
@@ -513,11 +540,11 @@ static inline unsigned nblk(long long n, int per) { return (unsigned)((n + per -
     } while (0)
 #define TDE_LAUNCH(kern, grid, block, stream, ...) TDE_LAUNCH_K(KIND_DEFLATE, kern, grid, block, stream, __VA_ARGS__)
 
-// Lanes per root: grows with the level's largest merge so that small merges
-// keep one lane per root and large ones split each pole sweep.
-static int lanes_per_root(int smax) {
+// Lanes per root: the smallest power of two G <= 16 with G * cols >= smax, so
+// that each lane sweeps about `cols` poles of the level's largest merge.
+static int lanes_per_root(int smax, int cols) {
     int G = 1;
-    while (G < 16 && G * 128 < smax) G <<= 1;
+    while (G < 16 && (long long)G * cols < smax) G <<= 1;
     return G;
 }
 
@@ -534,9 +561,9 @@ static void launch_roots_g(long long N, const MergeRec* mr, int M, const double*
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
 }
 
-static void launch_roots(int smax, long long N, const MergeRec* mr, int M, const double* e, const Work& w,
-                         void* stream) {
-    switch (lanes_per_root(smax)) {
+static void launch_roots(int smax, int cols, long long N, const MergeRec* mr, int M, const double* e,
+                         const Work& w, void* stream) {
+    switch (lanes_per_root(smax, cols)) {
         case 1: launch_roots_g<1>(N, mr, M, e, w, stream); break;
         case 2: launch_roots_g<2>(N, mr, M, e, w, stream); break;
         case 4: launch_roots_g<4>(N, mr, M, e, w, stream); break;
@@ -547,7 +574,7 @@ static void launch_roots(int smax, long long N, const MergeRec* mr, int M, const
 
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream) {
     if (p.ntot == 0) return 0;
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 1LL, 0);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
@@ -563,25 +590,27 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         else
             TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
     }
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.zmax_total, kWG), kWG, stream, w.zmax, p.zmax_total, 0ULL);
     for (const LevelInfo& L : p.levels) {
         const MergeRec* mr = p.d_merges + L.mstart;
+        const int* blkm = p.d_blkm + L.bstart;
         const int M = L.M;
         const long long N = L.N;
         const unsigned nb = nblk(N, kWG);
         const unsigned gstride = nb < 4096u ? nb : 4096u;
-        TDE_LAUNCH(k_fill_u64, nblk(M, kWG), kWG, stream, w.zmax, (long long)M, 0ULL);
-        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-        TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax, w);
-        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
-        TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, w);
-        TDE_LAUNCH(k_closeflag, gstride, kWG, stream, mr, M, N, w);
-        TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, M, N, w);
-        TDE_LAUNCH(k_stflag, nb, kWG, stream, N, w);
-        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsum, (int)nb);
-        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, w.bsumR, (int)nb);
-        TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, M, N, w);
-        launch_roots(L.smax, N, mr, M, e, w, stream);
-        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, M, N, (const unsigned long long*)w.pmax, w,
+        Work wl = w;
+        wl.zmax = w.zmax + L.mstart;
+        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsum, (const int*)nullptr, (int*)nullptr,
+                   (int)nb);
+        TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, wl);
+        TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, blkm, N, wl);
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsumAs, (const int*)wl.bsumR, wl.bsumRs,
+                   (int)nb);
+        TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, blkm, N, wl);
+        launch_roots(L.smax, p.sweep_cols, N, mr, M, e, wl, stream);
+        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
     }
     return (int)hipGetLastError();
@@ -602,6 +631,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     Work t{};
     t.status = (int*)take(256);
     t.counters = t.status ? (unsigned long long*)((char*)t.status + 64) : nullptr;
+    t.ticket = t.status ? (unsigned*)((char*)t.status + 16) : nullptr;
     t.pmax = (unsigned long long*)take(sizeof(unsigned long long) * (B > 0 ? B : 1));
     t.lam = (double*)take(8 * nn);
     t.blo = (double*)take(8 * nn);
@@ -610,11 +640,18 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Z = (double*)take(8 * nn);
     t.RL = (double*)take(8 * nn);
     t.RH = (double*)take(8 * nn);
+    t.D2 = (double*)take(8 * nn);
+    t.Z2 = (double*)take(8 * nn);
+    t.RL2 = (double*)take(8 * nn);
+    t.RH2 = (double*)take(8 * nn);
     t.st = (int*)take(4 * nn);
     t.scan = (int*)take(4 * (nn + 1));
     t.scanR = (int*)take(4 * (nn + 1));
     t.bsum = (int*)take(4 * nb);
     t.bsumR = (int*)take(4 * nb);
+    t.bsumA = (int*)take(4 * nb);
+    t.bsumAs = (int*)take(4 * nb);
+    t.bsumRs = (int*)take(4 * nb);
     t.nnpos = (int*)take(4 * nn);
     t.cf = (int*)take(4 * nn);
     t.Da = (double*)take(8 * nn);
@@ -633,7 +670,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Dr = (double*)take(8 * nn);
     t.RLr = (double*)take(8 * nn);
     t.RHr = (double*)take(8 * nn);
-    t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));
+    t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));  // all levels' merges
     if (w) *w = t;
     return off;
 }

@@ -15,6 +15,7 @@ struct LevelInfo {
     int M;        // merges in this level
     long long N;  // packed columns in this level (sum of merge sizes)
     int smax;     // largest merge (columns) in this level
+    int bstart;   // first entry of this level's per-block merge table
 };
 
 struct Plan {
@@ -22,6 +23,7 @@ struct Plan {
     long long ntot = 0;
     int B = 0;
     int leaf = 32;
+    int sweep_cols = 8;  // target poles per lane in the root-parallel sweeps
     int nleaves = 0;
     int leafmax = 1;     // largest leaf size in the plan
     int maxM = 1;        // most merges in one level
@@ -29,7 +31,9 @@ struct Plan {
     std::vector<long long> offs;  // host copy of the problem offsets [B+1]
     std::vector<LevelInfo> levels;
     // device tables owned by the plan
+    long long zmax_total = 1;  // merges over all levels (one max-|z| slot each)
     MergeRec* d_merges = nullptr;
+    int* d_blkm = nullptr;     // per level, per block of kWG packed columns: first merge touched
     LeafRec* d_leaves = nullptr;
     long long* d_offs = nullptr;
 };
@@ -40,6 +44,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
 
 // Optional per-kernel timing (HIP events around every launch, per kind).
 void timing_enable(bool on);
+bool timing_enabled();
 int timing_read(double* ms, long long* count, int nkinds);
 
 // Enqueue one full solve (scale, leaves, every level) on stream.

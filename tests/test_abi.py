@@ -68,7 +68,7 @@ def test_argument_errors_are_synchronous(L):
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 16, None, None) == tde.TDE_EINVAL
     bad = tde.tde_opts()
     bad.leaf = 0
-    bad.flags = 1
+    bad.flags = 4  # unknown flag bit
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(bad)) == tde.TDE_EINVAL
     offs = (ctypes.c_int64 * 3)(0, 5, 3)  # not monotone
     assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL

@@ -195,3 +195,43 @@ def test_c3_toeplitz_262144(tde):
     k = np.arange(1, n + 1)
     exact = np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
     assert np.abs(lam - exact).max() <= GATE * 4.0
+
+
+# --- captured graphs ---------------------------------------------------------
+
+def test_graph_replays_match_eager(tde):
+    """A captured solve replayed several times, with eager work and syncs in
+    between, must match the eager result bitwise on every replay."""
+    import torch
+
+    for fam, n, leaf in [("uniform", 3000, None), ("toeplitz", 4097, 32), ("clustered", 20000, 4)]:
+        _step(f"graph vs eager fam={fam} n={n} leaf={leaf}")
+        d, e = tdgen.tridiag(fam, n)
+        dv = torch.from_numpy(d).to(_dev())
+        ev = torch.from_numpy(e).to(_dev())
+        eager = tde.eigvals(dv, ev, leaf=leaf, graph=False).cpu().numpy()
+        out = torch.empty(n, dtype=torch.float64, device=_dev())
+        for rep in range(4):
+            tde.eigvals(dv, ev, leaf=leaf, out=out, graph=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), eager), (fam, rep)
+            # unrelated eager work on the same stream between replays
+            junk = tde.eigvals(dv[: n // 2].contiguous(), ev[: n // 2 - 1].contiguous(), graph=False)
+            torch.cuda.synchronize()
+            assert junk.numel() == n // 2
+        ref = oracle.eigvals(d, e)
+        assert np.abs(eager - ref).max() <= GATE * tdgen.tnorm1(d, e)
+
+
+@pytest.mark.parametrize("cols", [1, 2, 4, 16, 64])
+def test_lanes_per_root_variants(tde, cols):
+    """Every lanes-per-root setting (the autotuner's second knob) meets the gate."""
+    import torch
+
+    for fam, n in [("uniform", 5000), ("toeplitz", 3000), ("wilkinson", 2001)]:
+        _step(f"sweep_cols={cols} fam={fam} n={n}")
+        d, e = tdgen.tridiag(fam, n)
+        lam = tde.eigvals(torch.from_numpy(d).to(_dev()), torch.from_numpy(e).to(_dev()), sweep_cols=cols)
+        lam = lam.cpu().numpy()
+        ref = oracle.eigvals(d, e)
+        assert np.abs(lam - ref).max() <= GATE * tdgen.tnorm1(d, e)
