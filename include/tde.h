@@ -92,6 +92,51 @@ int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, voi
 int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
 
+/* Reverse mode (gradients of the eigenvalues).
+ *
+ * The paper computes eigenvalues only; these entry points add the adjoint of
+ * the same computation: for a loss L = sum_k g_k lambda_k they return
+ * dL/dd and dL/de, i.e. g_d[i] = sum_k g_k q_ik^2 and
+ * g_e[i] = 2 sum_k g_k q_ik q_(i+1)k for the unit eigenvectors q_k of T
+ * (ascending order), without forming any eigenvector.  The pass runs the
+ * merge tree top-down: per merge, the implicit-function derivatives of the
+ * secular roots f(lambda) = 1 + rho sum_j z_j^2/(D_j - lambda) = 0 and of the
+ * boundary rows (Section 3.2) with respect to the poles, z, rho and the
+ * children's rows; the deflation rotations and the couplings deflation drops;
+ * the leaves' eigenproblems; and the tear (Section 3.1).
+ *
+ * Problems are given as in tde_eigvals_batched (HOST offsets[B+1]; a single
+ * problem is offsets = {0, n}).  Both calls must use the same d, e, offsets and
+ * options (leaf, sweep_cols), since the checkpoint is tied to the plan.
+ *
+ * tde_checkpoint_bytes: device bytes of the checkpoint, about 36 bytes per
+ * column per tree level (ceil(log2(n / leaf)) levels).  0 on a bad argument.
+ * tde_backward_workspace_bytes: workspace of tde_eigvals_backward (about 480
+ * bytes per column), a superset of the forward's.  0 on a bad argument.
+ *
+ * tde_eigvals_ckpt: as tde_eigvals_batched, and also records in ckpt
+ *   [ckpt_bytes] (device, caller-owned) what the reverse pass needs: per tree
+ *   level the children's spectra and boundary rows read by its merges and the
+ *   secular roots in their (origin pole, offset) form.  ws as for the forward.
+ * tde_eigvals_backward:
+ *   glambda [offsets[B]]  dL/dlambda for each output eigenvalue (device, read only)
+ *   ckpt                  written by tde_eigvals_ckpt on the same inputs; not modified
+ *   gd      [offsets[B]]  output dL/dd (device)
+ *   ge      [offsets[B]]  output dL/de, same layout as e in the batched form; the
+ *                         slot offsets[b+1]-1 of every problem is set to 0
+ *   ws      ws_bytes >= tde_backward_workspace_bytes(...) (device)
+ * Returns TDE_OK or a negative code; device status via tde_get_status(ws).
+ * Gradients of eigenvalues that are (numerically) multiple are not unique: a
+ * loss that weights such a cluster unevenly has no well-defined gradient. */
+size_t tde_checkpoint_bytes(const int64_t* offsets, int64_t B, const tde_opts* opts);
+size_t tde_backward_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts);
+int tde_eigvals_ckpt(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                     void* ckpt, size_t ckpt_bytes, void* ws, size_t ws_bytes, void* hip_stream,
+                     const tde_opts* opts);
+int tde_eigvals_backward(const double* d, const double* e, const int64_t* offsets, int64_t B,
+                         const double* glambda, const void* ckpt, size_t ckpt_bytes, double* gd, double* ge,
+                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
+
 /* Waits for the stream, then reads the device status word of the last solve
  * that used ws: TDE_OK, TDE_ENONFINITE or TDE_ENOCONV.  Returns a negative code
  * if the read itself fails. */
@@ -112,7 +157,7 @@ int tde_get_status(const void* ws, void* hip_stream);
  * host work per launch; leave it off when timing whole solves).
  * tde_timing_read: waits for the recorded events and returns, per launch kind
  * (0 setup, 1 QL leaves, 2 merge/sort, 3 deflation and compaction, 4 secular
- * roots, 5 Loewner products, 6 boundary rows, 7 assembly), the summed
+ * roots, 5 Loewner products, 6 boundary rows, 7 assembly, 8 reverse pass), the summed
  * milliseconds and launch count since the last read; then forgets them. */
 int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n);
 int tde_timing_enable(int on);

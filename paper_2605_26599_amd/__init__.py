@@ -18,6 +18,9 @@ import torch
 __all__ = [
     "eigvals",
     "eigvals_batched",
+    "eigvals_ckpt",
+    "eigvals_backward",
+    "differentiable_eigvals",
     "workspace_bytes",
     "last_status",
     "TDEError",
@@ -40,6 +43,10 @@ EXPORTS = (
     "tde_workspace_bytes",
     "tde_eigvals",
     "tde_eigvals_batched",
+    "tde_checkpoint_bytes",
+    "tde_backward_workspace_bytes",
+    "tde_eigvals_ckpt",
+    "tde_eigvals_backward",
     "tde_get_status",
     "tde_get_counters",
     "tde_timing_enable",
@@ -98,6 +105,15 @@ def lib():
         L.tde_eigvals.restype = ctypes.c_int
         L.tde_eigvals_batched.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), i64, vp, vp, sz, vp, optp]
         L.tde_eigvals_batched.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.tde_checkpoint_bytes.argtypes = [i64p, i64, optp]
+        L.tde_checkpoint_bytes.restype = sz
+        L.tde_backward_workspace_bytes.argtypes = [i64, i64, optp]
+        L.tde_backward_workspace_bytes.restype = sz
+        L.tde_eigvals_ckpt.argtypes = [vp, vp, i64p, i64, vp, vp, sz, vp, sz, vp, optp]
+        L.tde_eigvals_ckpt.restype = ctypes.c_int
+        L.tde_eigvals_backward.argtypes = [vp, vp, i64p, i64, vp, vp, sz, vp, vp, vp, sz, vp, optp]
+        L.tde_eigvals_backward.restype = ctypes.c_int
         L.tde_get_status.argtypes = [vp, vp]
         L.tde_get_status.restype = ctypes.c_int
         L.tde_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
@@ -232,8 +248,121 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     return out
 
 
+# --- reverse mode -------------------------------------------------------------
+
+def _offsets(n: int, offsets):
+    offs = [0, int(n)] if offsets is None else [int(x) for x in offsets]
+    B = len(offs) - 1
+    return offs, B, (ctypes.c_int64 * (B + 1))(*offs)
+
+
+def checkpoint_bytes(n: int, offsets=None, leaf=None, sweep_cols=None) -> int:
+    offs, B, arr = _offsets(n, offsets)
+    nb = int(lib().tde_checkpoint_bytes(arr, B, _opts(leaf, True, sweep_cols)))
+    if nb == 0 and offs[-1] > 0:
+        raise TDEError(TDE_EINVAL, "checkpoint_bytes")
+    return nb
+
+
+def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, out=None,
+                 ckpt=None, workspace=None, check: bool = True, graph: bool = True):
+    """Eigenvalues as eigvals / eigvals_batched (offsets None = one problem with
+    e[n-1]), plus the checkpoint the reverse pass reads.  Returns (lambda, ckpt)."""
+    _check_input(d, e)
+    offs, B, arr = _offsets(d.numel(), offsets)
+    n = offs[-1]
+    if d.numel() < n or (offsets is not None and e.numel() < n) or e.numel() < n - 1:
+        raise ValueError("d and e are shorter than the offsets require")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=d.device)
+    cb = checkpoint_bytes(n, offsets, leaf, sweep_cols) if n else 0
+    if ckpt is None:
+        ckpt = torch.empty(max(cb, 256), dtype=torch.uint8, device=d.device)
+    if B <= 0 or n == 0:
+        return out, ckpt
+    if ckpt.numel() < cb:
+        raise ValueError("checkpoint buffer too small")
+    nb = workspace_bytes(n, B, leaf)
+    ws = workspace if workspace is not None else _workspace(nb, d.device)
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_ckpt(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, out.data_ptr(),
+                                    ckpt.data_ptr(), ckpt.numel(), ws.data_ptr(), ws.numel(), stream,
+                                    _opts(leaf, graph, sweep_cols))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_ckpt")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_ckpt device status")
+    return out, ckpt
+
+
+def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt: torch.Tensor, offsets=None,
+                     leaf=None, sweep_cols=None, workspace=None, check: bool = True, graph: bool = True):
+    """dL/dd and dL/de for L = sum_k glam_k lambda_k, from the checkpoint of
+    eigvals_ckpt on the same inputs and options.  Returns (gd[n], ge[n]) with
+    ge in the batched layout (the last slot of every problem is 0)."""
+    _check_input(d, e)
+    offs, B, arr = _offsets(d.numel(), offsets)
+    n = offs[-1]
+    gd = torch.zeros(n, dtype=torch.float64, device=d.device)
+    ge = torch.zeros(max(n, 1), dtype=torch.float64, device=d.device)
+    if B <= 0 or n == 0:
+        return gd, ge[:n]
+    glam = glam.to(device=d.device, dtype=torch.float64).contiguous()
+    if glam.numel() != n:
+        raise ValueError("glam must hold one entry per eigenvalue")
+    nb = int(lib().tde_backward_workspace_bytes(n, B, _opts(leaf, True, sweep_cols)))
+    ws = workspace if workspace is not None else _workspace(nb, d.device)
+    if ws.numel() < nb:
+        raise ValueError("workspace too small")
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_backward(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B,
+                                        glam.data_ptr(), ckpt.data_ptr(), ckpt.numel(), gd.data_ptr(),
+                                        ge.data_ptr(), ws.data_ptr(), ws.numel(), stream,
+                                        _opts(leaf, graph, sweep_cols))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_backward")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_backward device status")
+    return gd, ge[:n]
+
+
+class _Eigvals(torch.autograd.Function):
+    """lambda(d, e) with the library's reverse pass as its backward."""
+
+    @staticmethod
+    def forward(ctx, d, e, offsets, leaf, sweep_cols):
+        lam, ckpt = eigvals_ckpt(d, e, offsets, leaf=leaf, sweep_cols=sweep_cols)
+        ctx.save_for_backward(d, e, ckpt)
+        ctx.cfg = (offsets, leaf, sweep_cols)
+        return lam
+
+    @staticmethod
+    def backward(ctx, glam):
+        d, e, ckpt = ctx.saved_tensors
+        offsets, leaf, sweep_cols = ctx.cfg
+        gd, ge = eigvals_backward(d, e, glam, ckpt, offsets, leaf=leaf, sweep_cols=sweep_cols)
+        gE = torch.zeros_like(e)
+        m = min(e.numel(), ge.numel())
+        gE[:m] = ge[:m]
+        return gd, gE, None, None, None
+
+
+def differentiable_eigvals(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None):
+    """Eigenvalues (ascending per problem) as a differentiable function of d and
+    e: torch.autograd routes the backward through tde_eigvals_backward.  offsets
+    None = one problem (e holds n-1 entries), else the batched layout."""
+    offs = None if offsets is None else tuple(int(x) for x in offsets)
+    return _Eigvals.apply(d, e, offs, leaf, sweep_cols)
+
+
 COUNTER_NAMES = ("secular_terms", "lowner_pairs", "row_pairs", "roots", "sweeps", "leaf_columns", "leaf_rotations", "merge_columns")
-KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble")
+KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble", "backward")
 
 
 def counters(workspace: torch.Tensor) -> dict:

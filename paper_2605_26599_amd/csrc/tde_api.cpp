@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -20,9 +22,12 @@ using PlanKey = std::tuple<int, int, int, std::vector<long long>>;
 std::mutex g_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
-// Captured solves: one executable graph per (plan, buffers).  Capture runs on
-// an internal stream per device; replays run on the caller's stream.
-using GraphKey = std::tuple<const Plan*, const void*, const void*, const void*, const void*>;
+// Captured passes: one executable graph per (plan, pass kind, buffers).
+// Capture runs on an internal stream per device; replays run on the
+// caller's stream.
+enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2 };
+using Bufs = std::array<const void*, 8>;
+using GraphKey = std::tuple<const Plan*, int, Bufs>;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::map<int, hipStream_t> g_capture_streams;
 constexpr size_t kMaxGraphs = 64;
@@ -32,9 +37,9 @@ void drop_graphs() {
     g_graphs.clear();
 }
 
-int graph_for(const Plan& plan, const Work& w, const double* d, const double* e, double* out, void* ws,
+int graph_for(const Plan& plan, int kind, const Bufs& bufs, const std::function<int(void*)>& enqueue,
               hipGraphExec_t* exec) {
-    GraphKey key{&plan, d, e, out, ws};
+    GraphKey key{&plan, kind, bufs};
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) {
         *exec = it->second;
@@ -50,7 +55,7 @@ int graph_for(const Plan& plan, const Work& w, const double* d, const double* e,
         cs = sit->second;
     }
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return TDE_EDEVICE;
-    const int rc = enqueue_solve(plan, w, d, e, out, cs);
+    const int rc = enqueue(cs);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (rc != 0 || ec != hipSuccess || !graph) {
@@ -64,6 +69,24 @@ int graph_for(const Plan& plan, const Work& w, const double* d, const double* e,
     g_graphs.emplace(key, ge);
     *exec = ge;
     return TDE_OK;
+}
+
+// Runs enqueue either eagerly on the caller's stream or through the graph
+// cache, as the options and timing mode ask.
+int run_pass(const Plan& plan, int kind, const Bufs& bufs, const tde_opts* opts, void* stream,
+             const std::function<int(void*)>& enqueue) {
+    const bool use_graph = !(opts && (opts->flags & TDE_FLAG_NO_GRAPH)) && !timing_enabled();
+    if (use_graph) {
+        hipGraphExec_t ge = nullptr;
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            rc = graph_for(plan, kind, bufs, enqueue, &ge);
+        }
+        if (rc != TDE_OK) return rc;
+        return hipGraphLaunch(ge, (hipStream_t)stream) == hipSuccess ? TDE_OK : TDE_EDEVICE;
+    }
+    return enqueue(stream) == 0 ? TDE_OK : TDE_EDEVICE;
 }
 
 void free_plan(Plan* p) {
@@ -118,6 +141,7 @@ int make_plan(int device, int leaf, int cols, const std::vector<long long>& offs
     p->maxM = maxM;
     p->maxN = maxN;
     p->zmax_total = std::max<long long>(1, (long long)flat.size());
+    p->nmerges = (int)flat.size();
     p->nleaves = (int)t.leaves.size();
     int lmax = 1;
     for (auto& L : t.leaves) lmax = std::max(lmax, L.size);
@@ -156,42 +180,100 @@ int resolve_opts(const tde_opts* opts, int* leaf, int* cols) {
     return TDE_OK;
 }
 
+// Tree height of the largest problem (levels of the plan), host only.
+int tree_levels(int leaf, const std::vector<long long>& offs) {
+    int H = 0;
+    for (size_t b = 0; b + 1 < offs.size(); ++b) {
+        long long sz = offs[b + 1] - offs[b];
+        int h = 0;
+        while (sz > leaf) {
+            sz -= sz / 2;  // the larger child (balanced halving)
+            ++h;
+        }
+        H = std::max(H, h);
+    }
+    return H;
+}
+
+int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* offs) {
+    if (B < 0 || (B > 0 && !offsets)) return TDE_EINVAL;
+    offs->assign((size_t)B + 1, 0);
+    for (int64_t b = 0; b <= B && B > 0; ++b) (*offs)[b] = offsets[b];
+    if (B > 0 && (*offs)[0] != 0) return TDE_EINVAL;
+    for (int64_t b = 0; b < B; ++b)
+        if ((*offs)[b + 1] < (*offs)[b]) return TDE_EINVAL;
+    if ((*offs)[B] > (long long)0x3fffffff) return TDE_EINVAL;
+    return TDE_OK;
+}
+
+int get_plan(int leaf, int cols, const std::vector<long long>& offs, Plan** plan) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return make_plan(device, leaf, cols, offs, plan);
+}
+
+bool needs_e(const std::vector<long long>& offs) {
+    for (size_t b = 0; b + 1 < offs.size(); ++b)
+        if (offs[b + 1] - offs[b] > 1) return true;
+    return false;
+}
+
 int solve(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
-          size_t ws_bytes, void* stream, const tde_opts* opts) {
+          size_t ws_bytes, void* stream, const tde_opts* opts, void* ckpt = nullptr, size_t ckpt_bytes = 0) {
     int leaf, cols;
     if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
     const long long ntot = offs.back();
     const long long B = (long long)offs.size() - 1;
     if (ntot == 0) return TDE_OK;
     if (!d || !lambda || !ws) return TDE_EINVAL;
-    bool need_e = false;
-    for (long long b = 0; b < B; ++b)
-        if (offs[b + 1] - offs[b] > 1) need_e = true;
-    if (need_e && !e) return TDE_EINVAL;
+    if (needs_e(offs) && !e) return TDE_EINVAL;
     if (ws_bytes < workspace_layout(ntot, B, ntot, nullptr, nullptr)) return TDE_EINVAL;
-    int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
+    const int H = tree_levels(leaf, offs);
+    if (ckpt_bytes && (!ckpt || ckpt_bytes < ckpt_layout(ntot, H, nullptr, nullptr))) return TDE_EINVAL;
     Plan* plan = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        int rc = make_plan(device, leaf, cols, offs, &plan);
-        if (rc != TDE_OK) return rc;
-    }
+    int rc = get_plan(leaf, cols, offs, &plan);
+    if (rc != TDE_OK) return rc;
     Work w{};
     workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
-    const bool use_graph = !(opts && (opts->flags & TDE_FLAG_NO_GRAPH)) && !timing_enabled();
-    if (use_graph) {
-        hipGraphExec_t ge = nullptr;
-        int rc;
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            rc = graph_for(*plan, w, d, e, lambda, ws, &ge);
-        }
-        if (rc != TDE_OK) return rc;
-        return hipGraphLaunch(ge, (hipStream_t)stream) == hipSuccess ? TDE_OK : TDE_EDEVICE;
+    if (!ckpt_bytes) {
+        Bufs bufs{d, e, lambda, ws, nullptr, nullptr, nullptr, nullptr};
+        return run_pass(*plan, PASS_SOLVE, bufs, opts, stream,
+                        [&](void* s) { return enqueue_solve(*plan, w, d, e, lambda, s); });
     }
-    int rc = enqueue_solve(*plan, w, d, e, lambda, stream);
-    return rc == 0 ? TDE_OK : TDE_EDEVICE;
+    Ckpt ck{};
+    ckpt_layout(ntot, (int)plan->levels.size(), (char*)ckpt, &ck);
+    Bufs bufs{d, e, lambda, ws, ckpt, nullptr, nullptr, nullptr};
+    return run_pass(*plan, PASS_CKPT, bufs, opts, stream,
+                    [&](void* s) { return enqueue_solve(*plan, w, d, e, lambda, s, &ck); });
+}
+
+int backward(const double* d, const double* e, const std::vector<long long>& offs, const double* gin,
+             const void* ckpt, size_t ckpt_bytes, double* gd, double* ge, void* ws, size_t ws_bytes, void* stream,
+             const tde_opts* opts) {
+    int leaf, cols;
+    if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    const long long ntot = offs.back();
+    const long long B = (long long)offs.size() - 1;
+    if (ntot == 0) return TDE_OK;
+    if (!d || !gin || !ckpt || !gd || !ge || !ws) return TDE_EINVAL;
+    if (needs_e(offs) && !e) return TDE_EINVAL;
+    const int H = tree_levels(leaf, offs);
+    if (ckpt_bytes < ckpt_layout(ntot, H, nullptr, nullptr)) return TDE_EINVAL;
+    const size_t fw = workspace_layout(ntot, B, ntot, nullptr, nullptr);
+    Plan* plan = nullptr;
+    int rc = get_plan(leaf, cols, offs, &plan);
+    if (rc != TDE_OK) return rc;
+    if (ws_bytes < fw + grad_layout(ntot, ntot, nullptr, nullptr)) return TDE_EINVAL;
+    Work w{};
+    workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
+    Grad gr{};
+    grad_layout(ntot, plan->nmerges, (char*)ws + fw, &gr);
+    Ckpt ck{};
+    ckpt_layout(ntot, (int)plan->levels.size(), (char*)const_cast<void*>(ckpt), &ck);
+    Bufs bufs{d, e, gin, ckpt, gd, ge, ws, nullptr};
+    return run_pass(*plan, PASS_BACKWARD, bufs, opts, stream,
+                    [&](void* s) { return enqueue_backward(*plan, w, gr, ck, d, e, gin, gd, ge, s); });
 }
 
 }  // namespace
@@ -199,7 +281,7 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
 
 extern "C" {
 
-int tde_version(void) { return 100; }
+int tde_version(void) { return 200; }
 
 size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts) {
     int leaf, cols;
@@ -216,15 +298,43 @@ int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, voi
 
 int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts) {
-    if (B < 0 || (B > 0 && !offsets)) return TDE_EINVAL;
+    std::vector<long long> offs;
+    if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
     if (B == 0) return TDE_OK;
-    std::vector<long long> offs((size_t)B + 1);
-    for (int64_t b = 0; b <= B; ++b) offs[b] = offsets[b];
-    if (offs[0] != 0) return TDE_EINVAL;
-    for (int64_t b = 0; b < B; ++b)
-        if (offs[b + 1] < offs[b]) return TDE_EINVAL;
-    if (offs[B] > (long long)0x3fffffff) return TDE_EINVAL;
     return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts);
+}
+
+size_t tde_checkpoint_bytes(const int64_t* offsets, int64_t B, const tde_opts* opts) {
+    int leaf, cols;
+    std::vector<long long> offs;
+    if (tde::resolve_opts(opts, &leaf, &cols) != TDE_OK || tde::check_offsets(offsets, B, &offs) != TDE_OK) return 0;
+    return tde::ckpt_layout(offs.back(), tde::tree_levels(leaf, offs), nullptr, nullptr);
+}
+
+size_t tde_backward_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts) {
+    int leaf, cols;
+    if (n_total < 0 || batch < 0 || tde::resolve_opts(opts, &leaf, &cols) != TDE_OK) return 0;
+    return tde::workspace_layout(n_total, batch, n_total, nullptr, nullptr) +
+           tde::grad_layout(n_total, n_total, nullptr, nullptr);
+}
+
+int tde_eigvals_ckpt(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                     void* ckpt, size_t ckpt_bytes, void* ws, size_t ws_bytes, void* hip_stream,
+                     const tde_opts* opts) {
+    std::vector<long long> offs;
+    if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
+    if (B == 0 || offs.back() == 0) return TDE_OK;
+    if (!ckpt || ckpt_bytes == 0) return TDE_EINVAL;
+    return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts, ckpt, ckpt_bytes);
+}
+
+int tde_eigvals_backward(const double* d, const double* e, const int64_t* offsets, int64_t B,
+                         const double* glambda, const void* ckpt, size_t ckpt_bytes, double* gd, double* ge,
+                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts) {
+    std::vector<long long> offs;
+    if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
+    if (B == 0 || offs.back() == 0) return TDE_OK;
+    return tde::backward(d, e, offs, glambda, ckpt, ckpt_bytes, gd, ge, ws, ws_bytes, hip_stream, opts);
 }
 
 int tde_get_status(const void* ws, void* hip_stream) {

@@ -89,6 +89,7 @@ TDE_DEV double merge_tol(const double* __restrict__ D, long long pk, int s, unsi
 // Close-pole test for consecutive poles a < b (Section 4.1, deflation): the
 // Givens rotation that zeroes z_a drops an off-diagonal (D_b - D_a) c s.
 TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) {
+#pragma clang fp contract(off)
     double t = hypot(za, zb);
     double c = zb / t, s = za / t;
     return fabs((Db - Da) * c * s) <= tol;
@@ -96,20 +97,21 @@ TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) 
 
 // ---------------------------------------------------------------------------
 // Leaf: implicit QL with a Wilkinson-type shift on one small tridiagonal,
-// accumulating only rows 0 and l-1 of the eigenvector matrix (Algorithm 1,
+// accumulating only selected rows of the eigenvector matrix (Algorithm 1,
 // leaf step; rows of Q G are the selected rows of Q times G, Lemma 2).
-// Arrays are strided (stride = lanes sharing the LDS tile).  Returns 0 or
-// ST_LEAF_NOCONV.  On exit d holds the eigenvalues ascending and r0/r1 the
-// first/last eigenvector rows in the same column order.
+// `rows` applies each plane rotation to columns i, i+1 of the tracked rows
+// (rot) and mirrors the final ascending sort (swap).  The scalar recurrence is
+// the same for every choice of tracked rows, and contraction is off, so the
+// forward pass (rows 0 and l-1) and the adjoint's recomputation (one row per
+// lane) see bitwise the same eigenvalues and rotations.  Arrays are strided
+// (st = lanes sharing an LDS tile).  Returns 0 or ST_LEAF_NOCONV.
 // ---------------------------------------------------------------------------
-TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st, unsigned* nrot) {
+template <class Rows>
+TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsigned* nrot) {
+#pragma clang fp contract(off)
 #define A_(p, i) p[(i) * st]
     int status = 0;
     unsigned rot = 0;
-    for (int i = 0; i < nl; ++i) {
-        A_(r0, i) = (i == 0) ? 1.0 : 0.0;
-        A_(r1, i) = (i == nl - 1) ? 1.0 : 0.0;
-    }
     A_(e, nl - 1) = 0.0;
     for (int l = 0; l < nl; ++l) {
         int iter = 0;
@@ -145,13 +147,7 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
                 A_(d, i + 1) = g + p;
                 g = c * r - b;
                 ++rot;
-                // columns i, i+1 of the two tracked rows
-                double t0 = A_(r0, i + 1);
-                A_(r0, i + 1) = s * A_(r0, i) + c * t0;
-                A_(r0, i) = c * A_(r0, i) - s * t0;
-                double t1 = A_(r1, i + 1);
-                A_(r1, i + 1) = s * A_(r1, i) + c * t1;
-                A_(r1, i) = c * A_(r1, i) - s * t1;
+                rows.rot(i, c, s);
             }
             if (split) continue;
             A_(d, l) -= p;
@@ -168,13 +164,56 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
         if (k != i) {
             A_(d, k) = A_(d, i);
             A_(d, i) = v;
-            double t0 = A_(r0, i); A_(r0, i) = A_(r0, k); A_(r0, k) = t0;
-            double t1 = A_(r1, i); A_(r1, i) = A_(r1, k); A_(r1, k) = t1;
+            rows.swap(i, k);
         }
     }
     *nrot = rot;
     return status;
 #undef A_
+}
+
+// One tracked row q (row `row` of Q; q starts as that row of the identity).
+struct RowTrack {
+    double* q;
+    int st;
+    TDE_DEV void init(int nl, int row) {
+        for (int i = 0; i < nl; ++i) q[i * st] = (i == row) ? 1.0 : 0.0;
+    }
+    TDE_DEV void rot(int i, double c, double s) {
+#pragma clang fp contract(off)
+        const double t = q[(i + 1) * st];
+        q[(i + 1) * st] = s * q[i * st] + c * t;
+        q[i * st] = c * q[i * st] - s * t;
+    }
+    TDE_DEV void swap(int i, int k) {
+        const double t = q[i * st];
+        q[i * st] = q[k * st];
+        q[k * st] = t;
+    }
+};
+
+struct TwoRows {
+    RowTrack a, b;
+    TDE_DEV void rot(int i, double c, double s) {
+        a.rot(i, c, s);
+        b.rot(i, c, s);
+    }
+    TDE_DEV void swap(int i, int k) {
+        a.swap(i, k);
+        b.swap(i, k);
+    }
+};
+
+// Forward leaf: eigenvalues (ascending, in d) and rows 0 and l-1 (r0, r1).
+TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st, unsigned* nrot) {
+    TwoRows rows;
+    rows.a.q = r0;
+    rows.a.st = st;
+    rows.b.q = r1;
+    rows.b.st = st;
+    rows.a.init(nl, 0);
+    rows.b.init(nl, nl - 1);
+    return leaf_ql_core(nl, d, e, st, rows, nrot);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,6 +490,7 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
     w.Z[P] = z;
     w.RL[P] = rl;
     w.RH[P] = rh;
+    w.src[P] = i;
     *absz_out = fabs(z);
     return P;
 }
@@ -466,6 +506,36 @@ TDE_DEV int body_nnflag(long long t, int m, const MergeRec* __restrict__ mr,
     const int flag = (rho * fabs(w.Z[t]) > tol) ? 1 : 0;
     w.st[t] = flag;
     return flag;
+}
+
+
+// One step of a run: the running column *cur (left) against the next
+// candidate nx.  If the pair passes the close test on the current values it
+// is rotated by the Givens rotation that zeroes cur's z (c = z_nx/t,
+// s = z_cur/t, t = hypot): *def receives the deflated column (pole
+// c^2 D_cur + s^2 D_nx, z = 0, rows c r_cur - s r_nx) and *cur becomes the
+// survivor (pole s^2 D_cur + c^2 D_nx, z = t, rows s r_cur + c r_nx); returns
+// true.  Otherwise returns false and leaves *cur unchanged.  Both new poles
+// are convex combinations of D_cur <= D_nx and are clamped into that interval
+// so rounding cannot break the ascending order the assembly merges on.
+TDE_DEV bool run_step(RunState* cur, const RunState& nx, double tol, RunState* def, double* cc, double* ss) {
+#pragma clang fp contract(off)
+    const double tt = hypot(cur->Z, nx.Z);
+    const double c = nx.Z / tt, sn = cur->Z / tt;
+    *cc = c;
+    *ss = sn;
+    if (!(fabs((nx.D - cur->D) * c * sn) <= tol)) return false;
+    def->D = fmin(fmax(c * c * cur->D + sn * sn * nx.D, cur->D), nx.D);
+    def->Z = 0.0;
+    def->L = c * cur->L - sn * nx.L;
+    def->H = c * cur->H - sn * nx.H;
+    RunState sv;
+    sv.D = fmin(fmax(sn * sn * cur->D + c * c * nx.D, cur->D), nx.D);
+    sv.Z = tt;
+    sv.L = sn * cur->L + c * nx.L;
+    sv.H = sn * cur->H + c * nx.H;
+    *cur = sv;
+    return true;
 }
 
 // (a5) close poles.  Candidate g (the g-th non-negligible column of the level)
@@ -489,7 +559,7 @@ TDE_DEV void body_runs(long long g, int m, const MergeRec* __restrict__ mr, cons
     const long long t = nnpos[g];
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
-    const long long gs = w.scan[R.pk], ge = w.scan[R.pk + s];
+    const long long gs = w.scanC[R.pk], ge = w.scanC[R.pk + s];
     const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
     const bool cl_next = (g + 1 < ge) && cand_close(w, g, g + 1, tol);
     const bool cl_prev = (g > gs) && cand_close(w, g - 1, g, tol);
@@ -504,40 +574,32 @@ TDE_DEV void body_runs(long long g, int m, const MergeRec* __restrict__ mr, cons
     long long r = g + 1;
     while (r + 1 < ge && cand_close(w, r, r + 1, tol)) ++r;
     long long pc = t;
-    double Dc = w.D[pc], Zc = w.Z[pc], Lc = w.RL[pc], Hc = w.RH[pc];
+    RunState cur{w.D[pc], w.Z[pc], w.RL[pc], w.RH[pc]};
     for (long long j = g + 1; j <= r; ++j) {
         const long long pj = nnpos[j];
-        const double Dj = w.D[pj], Zj = w.Z[pj], Lj = w.RL[pj], Hj = w.RH[pj];
-        const double tt = hypot(Zc, Zj);
-        const double c = Zj / tt, sn = Zc / tt;
-        if (fabs((Dj - Dc) * c * sn) <= tol) {
-            // rotate (cur, j): cur deflates with c^2 Dc + s^2 Dj, j keeps z = tt.
-            // Both new diagonal entries are convex combinations of Dc <= Dj;
-            // clamping them into [Dc, Dj] keeps rounding from breaking the
-            // ascending order that the parent assembly merges on.
-            w.D2[pc] = fmin(fmax(c * c * Dc + sn * sn * Dj, Dc), Dj);
+        const RunState nx{w.D[pj], w.Z[pj], w.RL[pj], w.RH[pj]};
+        RunState def;
+        double c, sn;
+        if (run_step(&cur, nx, tol, &def, &c, &sn)) {
+            w.D2[pc] = def.D;
             w.Z2[pc] = 0.0;
-            w.RL2[pc] = c * Lc - sn * Lj;
-            w.RH2[pc] = c * Hc - sn * Hj;
+            w.RL2[pc] = def.L;
+            w.RH2[pc] = def.H;
             w.st[pc] = 2;
             on_rotate(pc);
-            Dc = fmin(fmax(sn * sn * Dc + c * c * Dj, Dc), Dj);
-            Zc = tt;
-            Lc = sn * Lc + c * Lj;
-            Hc = sn * Hc + c * Hj;
         } else {
-            w.D2[pc] = Dc;
-            w.Z2[pc] = Zc;
-            w.RL2[pc] = Lc;
-            w.RH2[pc] = Hc;
-            Dc = Dj; Zc = Zj; Lc = Lj; Hc = Hj;
+            w.D2[pc] = cur.D;
+            w.Z2[pc] = cur.Z;
+            w.RL2[pc] = cur.L;
+            w.RH2[pc] = cur.H;
+            cur = nx;
         }
         pc = pj;
     }
-    w.D2[pc] = Dc;
-    w.Z2[pc] = Zc;
-    w.RL2[pc] = Lc;
-    w.RH2[pc] = Hc;
+    w.D2[pc] = cur.D;
+    w.Z2[pc] = cur.Z;
+    w.RL2[pc] = cur.L;
+    w.RH2[pc] = cur.H;
     // The rotated-away columns of a run join their own list, ascending in
     // position order: sort them among the run's rotated positions (only
     // columns g..r-1 can be rotated away).  Their values lie in [D_g, D_r],
@@ -612,9 +674,9 @@ template <class Red>
 TDE_DEV void body_lowner(long long g, int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
                          const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G,
                          const double* __restrict__ Dv, const int* __restrict__ orgv,
-                         const double* __restrict__ tauv, long long voff) {
+                         const double* __restrict__ tauv, long long voff, bool with_root = false) {
     const MergeRec R = mr[m];
-    if (R.flags & MF_ROOT) return;
+    if ((R.flags & MF_ROOT) && !with_root) return;
     const MergeSpan sp = merge_span(R, w.scan);
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);

@@ -54,7 +54,7 @@ enum {
 // Launch kinds for the optional per-kernel timing.
 enum {
     KIND_SETUP = 0, KIND_LEAF, KIND_MERGE, KIND_DEFLATE, KIND_SECULAR, KIND_LOWNER, KIND_ROWS, KIND_ASSEMBLE,
-    KIND_N
+    KIND_BACKWARD, KIND_N
 };
 
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels
@@ -75,12 +75,14 @@ struct Work {
     double* Z;                 // [n]   secular vector z~ in pole order
     double* RL;                // [n]   parent-first-row entries per column
     double* RH;                // [n]   parent-last-row entries per column
+    int* src;                  // [n]   local child column that landed at each merged position
     double* D2;                // [n]   candidates after close-pole rotations
     double* Z2;                // [n]
     double* RL2;               // [n]
     double* RH2;               // [n]
     int* st;                   // [n]   column state: 0 negligible z, 1 active, 2 rotated away
-    int* scan;                 // [n+1] exclusive prefix counts (candidates, then active columns)
+    int* scan;                 // [n+1] exclusive prefix counts of active columns
+    int* scanC;                // [n+1] exclusive prefix counts of candidate (non-negligible) columns
     int* scanR;                // [n+1] exclusive prefix counts of rotated-away columns
     int* bsum;                 // [nb+1] per-block counts
     int* bsumR;                // [nb+1] per-block counts of rotated-away columns
@@ -95,6 +97,9 @@ struct Work {
     double* RLa;               // [n]
     double* RHa;               // [n]
     int* amerge;               // [n]   merge index (within the level) of active column g
+    int* apos;                 // [n]   packed position of active column g
+    int* rpos;                 // [n]   packed position of rotated-away column gr
+    int* dpos;                 // [n]   packed position of negligible-z column q
     int* org;                  // [n]   root origin (local active index)
     double* tau;               // [n]   root offset from its origin pole
     double* zhat;              // [n]   recomputed (Loewner) secular vector
@@ -107,6 +112,50 @@ struct Work {
     double* RLr;               // [n]
     double* RHr;               // [n]
     unsigned long long* zmax;  // [M] bits of max |z~| per merge (this level's slice)
+};
+
+// Forward checkpoint for the reverse pass: per level h (slot stride n), the
+// node spectra and rows that level's merges read (global positions) and the
+// level's secular roots as (org, tau) by active index.  Everything else of a
+// level (merged order, deflation, Loewner z) is recomputed from these.
+struct Ckpt {
+    double* lam;   // [H][n]
+    double* blo;   // [H][n]
+    double* bhi;   // [H][n]
+    double* tau;   // [H][n]
+    int* org;      // [H][n]
+    long long n;   // slot stride
+};
+
+// One column's state in a close-pole run: pole, z, parent first/last-row entries.
+struct RunState {
+    double D, Z, L, H;
+};
+
+// Reverse-pass scratch: adjoints of one level's quantities (packed like the
+// forward's level arrays) and of the node spectra/rows (global positions).
+struct Grad {
+    double* glam;  // [n] node adjoints: dL/dlambda of each node column (in place across levels)
+    double* gblo;  // [n] dL/dblo
+    double* gbhi;  // [n] dL/dbhi
+    double* gD;    // [n] adjoints of the merged (pre-rotation) columns, packed per level
+    double* gZ;
+    double* gRL;
+    double* gRH;
+    double* gD2;   // [n] adjoints of the post-rotation columns, packed per level
+    double* gZ2;
+    double* gRL2;
+    double* gRH2;
+    double* glr;   // [n] per active root: dL/dlambda_k, dL/dblo_k, dL/dbhi_k
+    double* gbr;
+    double* ghr;
+    double* coef;  // [10 n] per active root: 10 coefficient planes of stride n (see bwd_root_coeffs)
+    RunState* chain;  // [n] run states by candidate index
+    RunState* cdef;   // [n] rotated-away columns of a run, unsorted, by candidate index
+    double* skey;     // [n] rotated-away poles by candidate index (sort keys)
+    int* sidx;        // [n] sorted slot -> candidate index of the rotated-away column
+    double* grho;     // [merges, flat over levels] dL/drho~
+    double* gdp;      // [n] dL/dd' (torn diagonal)
 };
 
 }  // namespace tde

@@ -4,7 +4,7 @@
 // maxima and prefix counts, and order the steps of each tree level.
 #include <hip/hip_runtime.h>
 
-#include "tde_device.h"
+#include "tde_adjoint.h"
 #include "tde_plan.h"
 
 #include <mutex>
@@ -213,9 +213,9 @@ __global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
     const int g = w.bsum[blockIdx.x] + incl - f;
     if (threadIdx.x == 0) w.bsumR[blockIdx.x] = 0;
     if (t < N) {
-        w.scan[t] = g;
+        w.scanC[t] = g;
         if (f) w.nnpos[g] = (int)t;
-        if (t == N - 1) w.scan[N] = g + f;
+        if (t == N - 1) w.scanC[N] = g + f;
     }
 }
 
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
 // column moves one count from its block's active tally to its rotated tally.
 __global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                               long long N, Work w) {
-    const long long total = w.scan[N];
+    const long long total = w.scanC[N];
     int* bA = w.bsumA;
     int* bR = w.bsumR;
     auto on_rotate = [bA, bR](long long p) {
@@ -261,15 +261,18 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
             w.RLa[g] = w.RL2[t];
             w.RHa[g] = w.RH2[t];
             w.amerge[g] = merge_of(mr, blkm, t);
+            w.apos[g] = (int)t;
         } else if (fr) {
             w.Dr[gr] = w.D2[t];
             w.RLr[gr] = w.RL2[t];
             w.RHr[gr] = w.RH2[t];
+            w.rpos[gr] = (int)t;
         } else {
             const long long q = t - g - gr;
             w.Dd[q] = w.D[t];
             w.RLd[q] = w.RL[t];
             w.RHd[q] = w.RH[t];
+            w.dpos[q] = (int)t;
         }
         if (t == N - 1) {
             w.scan[N] = g + fa;
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr
     count_add(&w.counters[CNT_ROOTS], roots);
 }
 
-template <int G>
+template <int G, bool WithRoot>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w) {
@@ -404,8 +407,8 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
         const long long g = g0 + threadIdx.x / G;
         if (g < total) {
             const int m = w.amerge[g];
-            if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0);
-            else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0);
+            if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0, WithRoot);
+            else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0, WithRoot);
             if (sub == 0 && !(mr[m].flags & MF_ROOT)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
         }
         __syncthreads();
@@ -458,6 +461,239 @@ __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ m
                                                   double* __restrict__ out) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < N) body_assemble(t, merge_of(mr, blkm, t), mr, pmax, w, out);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass (adjoint).  Level by level from the top, each level first
+// recomputes its merged order, deflation and Loewner z from the checkpoint,
+// then runs the per-merge VJP steps of tde_adjoint.h; the leaves and the tear
+// couplings close the chain.
+// ---------------------------------------------------------------------------
+
+// Snapshot of the node spectra and rows the level's merges are about to read.
+__global__ __launch_bounds__(kWG) void k_ckpt_save(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                   long long N, Work w, double* __restrict__ sl,
+                                                   double* __restrict__ sb, double* __restrict__ sh) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const MergeRec R = mr[merge_of(mr, blkm, t)];
+    const long long P = R.off + (t - R.pk);
+    sl[P] = w.lam[P];
+    sb[P] = w.blo[P];
+    sh[P] = w.bhi[P];
+}
+
+// Seed: dL/dlambda of every output eigenvalue; no row adjoints above the top.
+__global__ __launch_bounds__(kWG) void k_bwd_init(long long n, const double* __restrict__ gin, Grad gr) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    gr.glam[t] = gin[t];
+    gr.gblo[t] = 0.0;
+    gr.gbhi[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_unassemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                        long long N, Work w, Grad gr) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < N) body_bwd_unassemble(t, merge_of(mr, blkm, t), mr, w, gr);
+}
+
+constexpr int kStageBwd = 1024;
+
+template <int G>
+__global__ __launch_bounds__(kWG) void k_bwd_roots(const MergeRec* __restrict__ mr, long long N, Work w, Grad gr,
+                                                   long long cstride) {
+    __shared__ double sD[kStageBwd], sH[kStageBwd], sL[kStageBwd], sR[kStageBwd];
+    __shared__ long long s_r0;
+    __shared__ int s_staged;
+    const long long total = w.scan[N];
+    const int per = kWG / G;
+    const int sub = threadIdx.x % G;
+    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+        const long long g0 = tile * per;
+        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+        if (threadIdx.x == 0) {
+            const TileWindow tw = tile_window(g0, g1, mr, w, kStageBwd);
+            s_r0 = tw.r0;
+            s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+        }
+        __syncthreads();
+        const long long r0 = s_r0;
+        const int ns = s_staged;
+        if (ns >= 0)
+            for (int i = threadIdx.x; i < ns; i += kWG) {
+                sD[i] = w.Da[r0 + i];
+                sH[i] = w.zhat[r0 + i];
+                sL[i] = w.RLa[r0 + i];
+                sR[i] = w.RHa[r0 + i];
+            }
+        __syncthreads();
+        const long long g = g0 + threadIdx.x / G;
+        if (g < total) {
+            const MergeSpan sp = merge_span(mr[w.amerge[g]], w.scan);
+            const long long b = sp.ks - (ns >= 0 ? r0 : 0);
+            const double* Dv = (ns >= 0 ? sD : w.Da) + b;
+            const double* Hv = (ns >= 0 ? sH : w.zhat) + b;
+            const double* Lv = (ns >= 0 ? sL : w.RLa) + b;
+            const double* Rv = (ns >= 0 ? sR : w.RHa) + b;
+            double cf[10];
+            bwd_root_coeffs<RedGroup<G>>(sp.K, Dv, Hv, Lv, Rv, w.org[g], w.tau[g], gr.glr[g], gr.gbr[g], gr.ghr[g],
+                                         sub, G, cf);
+            if (sub == 0)
+                for (int q = 0; q < 10; ++q) gr.coef[q * cstride + g] = cf[q];
+        }
+        __syncthreads();
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ mr, long long N, Work w, Grad gr,
+                                                   long long cstride) {
+    __shared__ double sD[kStageBwd], sT[kStageBwd], sA[kStageBwd], sB[kStageBwd], sC[kStageBwd], sM[kStageBwd];
+    __shared__ int sO[kStageBwd];
+    __shared__ long long s_r0;
+    __shared__ int s_staged;
+    const long long total = w.scan[N];
+    const int per = kWG / G;
+    const int sub = threadIdx.x % G;
+    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+        const long long g0 = tile * per;
+        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+        if (threadIdx.x == 0) {
+            const TileWindow tw = tile_window(g0, g1, mr, w, kStageBwd);
+            s_r0 = tw.r0;
+            s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+        }
+        __syncthreads();
+        const long long r0 = s_r0;
+        const int ns = s_staged;
+        if (ns >= 0)
+            for (int i = threadIdx.x; i < ns; i += kWG) {
+                sD[i] = w.Da[r0 + i];
+                sT[i] = w.tau[r0 + i];
+                sO[i] = w.org[r0 + i];
+                sA[i] = gr.coef[r0 + i];
+                sB[i] = gr.coef[cstride + r0 + i];
+                sC[i] = gr.coef[2 * cstride + r0 + i];
+                sM[i] = gr.coef[3 * cstride + r0 + i];
+            }
+        __syncthreads();
+        const long long g = g0 + threadIdx.x / G;
+        if (g < total) {
+            const MergeSpan sp = merge_span(mr[w.amerge[g]], w.scan);
+            const bool stg = ns >= 0;
+            const long long b = sp.ks - (stg ? r0 : 0);
+            const double* cg = gr.coef + sp.ks;
+            double o4[4];
+            bwd_pole<RedGroup<G>>((int)(g - sp.ks), sp.K, (stg ? sD : w.Da) + b, (stg ? sO : w.org) + b,
+                                  (stg ? sT : w.tau) + b, stg ? sA + b : cg, stg ? sB + b : cg + cstride,
+                                  stg ? sC + b : cg + 2 * cstride, stg ? sM + b : cg + 3 * cstride, cg, cstride,
+                                  w.zhat[g], w.RLa[g], w.RHa[g], sub, G, o4);
+            if (sub == 0) {
+                const long long t = w.apos[g];
+                gr.gZ2[t] = o4[0];
+                gr.gD2[t] = o4[1];
+                gr.gRL2[t] = o4[2];
+                gr.gRH2[t] = o4[3];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// dL/dz of the negligible-z columns of non-top merges.
+__global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                  long long N, Work w, Grad gr, long long cstride) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= N || w.st[t] != 0) return;
+    const MergeRec R = mr[merge_of(mr, blkm, t)];
+    if (R.flags & MF_ROOT) return;
+    const MergeSpan sp = merge_span(R, w.scan);
+    gr.gZ[t] = bwd_negligible_z<RedSerial>(sp.K, w.Da + sp.ks, w.org + sp.ks, w.tau + sp.ks, gr.coef + sp.ks, cstride,
+                                           w.D[t], w.RL[t], w.RH[t], gr.gRL[t], gr.gRH[t], 0, 1);
+}
+
+// dL/drho~ of each merge: sum_k gtot_k / (rho^2 N_k^2), one workgroup per merge.
+__global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                                  const unsigned long long* __restrict__ pmax, Work w, Grad gr,
+                                                  long long cstride, int mstart) {
+    __shared__ double part[kWG / 64];
+    const MergeRec R = mr[blockIdx.x];
+    const MergeSpan sp = merge_span(R, w.scan);
+    const double* mu = gr.coef + 3 * cstride + sp.ks;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < sp.K; k += kWG) acc += mu[k];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kWG / 64; ++i) s += part[i];
+        double sgn;
+        const double rho = merge_rho(R, e, pmax, &sgn);
+        gr.grho[mstart + blockIdx.x] = sp.K ? s / (rho * rho) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                  long long N, Work w, Grad gr, long long cstride) {
+    const long long total = w.scanC[N];
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x)
+        body_bwd_runs<RedSerial>(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr, cstride);
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                   long long N, const double* __restrict__ e,
+                                                   const unsigned long long* __restrict__ pmax, Work w, Grad gr) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < N) body_bwd_merge(t, merge_of(mr, blkm, t), mr, e, pmax, w, gr);
+}
+
+// Leaves: 64 / LMAX leaves per 64-lane workgroup, one lane per leaf row.
+// Each lane recomputes the QL on its own copy of the leaf (LDS, lane-strided)
+// tracking its row of Q; the leaf's Q and X are shared in LDS.
+template <int LMAX>
+__global__ __launch_bounds__(64) void k_bwd_leaf(const LeafRec* __restrict__ leaves, int nleaves,
+                                                 const double* __restrict__ d, const double* __restrict__ e,
+                                                 const unsigned long long* __restrict__ pmax, Work w, Grad gr,
+                                                 double* __restrict__ gd, double* __restrict__ ge) {
+    constexpr int P = 64 / LMAX;
+    __shared__ double sd[LMAX * 64], se[LMAX * 64];
+    __shared__ double sQ[P * LMAX * LMAX], sX[P * LMAX * LMAX], sL[64];
+    const int lane = threadIdx.x;
+    const int slot = lane / LMAX, r = lane % LMAX;
+    const long long li = (long long)blockIdx.x * P + slot;
+    LeafRec L{};
+    bool act = false;
+    if (li < nleaves) {
+        L = leaves[li];
+        act = r < L.size;
+    }
+    double* Q = sQ + slot * LMAX * LMAX;
+    double* X = sX + slot * LMAX * LMAX;
+    double* lam = sL + slot * LMAX;
+    int st = 0;
+    if (act) st = body_bwd_leaf_q(L, r, d, e, pmax, sd + lane, se + lane, 64, Q, lam);
+    __syncthreads();
+    if (act) body_bwd_leaf_x(L, r, gr, Q, lam, X);
+    __syncthreads();
+    if (act) body_bwd_leaf_out(L, r, gr, Q, X, gd, ge);
+    if (st) atomicOr(w.status, st);
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_tear(const MergeRec* __restrict__ mr, int nm,
+                                                  const double* __restrict__ e,
+                                                  const unsigned long long* __restrict__ pmax, Grad gr,
+                                                  double* __restrict__ ge) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nm) body_bwd_tear(mr[i], gr.grho[i], e, pmax, gr, ge);
+}
+
+// The coupling slot after the last row of every problem does not exist: 0.
+__global__ __launch_bounds__(kWG) void k_bwd_edges(const long long* __restrict__ offs, int B, double* __restrict__ ge) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B && offs[b + 1] > offs[b]) ge[offs[b + 1] - 1] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -556,8 +792,8 @@ static void launch_roots_g(long long N, const MergeRec* mr, int M, const double*
     if (nb < 1) nb = 1;
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)nb, kWG, stream, mr, M, N, e,
                  (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH_K(KIND_LOWNER, k_lowner<G>, (unsigned)nb, kWG, stream, mr, M, N, e, (const unsigned long long*)w.pmax,
-                 w);
+    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), (unsigned)nb, kWG, stream, mr, M, N, e,
+                 (const unsigned long long*)w.pmax, w);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
 }
 
@@ -572,7 +808,24 @@ static void launch_roots(int smax, int cols, long long N, const MergeRec* mr, in
     }
 }
 
-int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream) {
+// Deflation steps of one level (shared by the forward and the reverse pass):
+// negligible-z flags, candidate compaction, close-pole runs, three-way split.
+static void enqueue_deflate(const MergeRec* mr, const int* blkm, long long N, const double* e, const Work& wl,
+                            void* stream) {
+    const unsigned nb = nblk(N, kWG);
+    const unsigned gstride = nb < 4096u ? nb : 4096u;
+    TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)wl.pmax, wl);
+    TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsum, (const int*)nullptr, (int*)nullptr,
+               (int)nb);
+    TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, wl);
+    TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, blkm, N, wl);
+    TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsumAs, (const int*)wl.bsumR, wl.bsumRs,
+               (int)nb);
+    TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, blkm, N, wl);
+}
+
+int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
+                  const Ckpt* ck) {
     if (p.ntot == 0) return 0;
     TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
@@ -591,28 +844,105 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
     }
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.zmax_total, kWG), kWG, stream, w.zmax, p.zmax_total, 0ULL);
-    for (const LevelInfo& L : p.levels) {
+    for (size_t h = 0; h < p.levels.size(); ++h) {
+        const LevelInfo& L = p.levels[h];
+        const MergeRec* mr = p.d_merges + L.mstart;
+        const int* blkm = p.d_blkm + L.bstart;
+        const int M = L.M;
+        const long long N = L.N;
+        const unsigned nb = nblk(N, kWG);
+        Work wl = w;
+        wl.zmax = w.zmax + L.mstart;
+        if (ck) {
+            const long long so = (long long)h * ck->n;
+            TDE_LAUNCH_K(KIND_SETUP, k_ckpt_save, nb, kWG, stream, mr, blkm, N, w, ck->lam + so, ck->blo + so,
+                         ck->bhi + so);
+            wl.org = ck->org + so;
+            wl.tau = ck->tau + so;
+        }
+        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        enqueue_deflate(mr, blkm, N, e, wl, stream);
+        launch_roots(L.smax, p.sweep_cols, N, mr, M, e, wl, stream);
+        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
+                     out);
+    }
+    return (int)hipGetLastError();
+}
+
+template <int G>
+static void launch_bwd_roots_g(long long N, const MergeRec* mr, int M, const double* e, const Work& w,
+                               const Grad& gr, long long cs, void* stream) {
+    long long nb = (N * G + kWG - 1) / kWG;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)nb, kWG, stream, mr, M, N, e,
+                 (const unsigned long long*)w.pmax, w);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nb, kWG, stream, mr, N, w, gr, cs);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nb, kWG, stream, mr, N, w, gr, cs);
+}
+
+int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
+                     const double* e, const double* gin, double* gd, double* ge, void* stream) {
+    if (p.ntot == 0) return 0;
+    const long long cs = p.ntot;  // coefficient plane stride
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
+                 p.ntot, w.pmax, w.status);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.zmax_total, kWG), kWG, stream, w.zmax, p.zmax_total, 0ULL);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_init, nblk(p.ntot, kWG), kWG, stream, p.ntot, gin, gr);
+    for (size_t hh = p.levels.size(); hh-- > 0;) {
+        const LevelInfo& L = p.levels[hh];
         const MergeRec* mr = p.d_merges + L.mstart;
         const int* blkm = p.d_blkm + L.bstart;
         const int M = L.M;
         const long long N = L.N;
         const unsigned nb = nblk(N, kWG);
         const unsigned gstride = nb < 4096u ? nb : 4096u;
+        const long long so = (long long)hh * ck.n;
         Work wl = w;
         wl.zmax = w.zmax + L.mstart;
-        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
-        TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
-        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsum, (const int*)nullptr, (int*)nullptr,
-                   (int)nb);
-        TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, wl);
-        TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, blkm, N, wl);
-        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsumAs, (const int*)wl.bsumR, wl.bsumRs,
-                   (int)nb);
-        TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, blkm, N, wl);
-        launch_roots(L.smax, p.sweep_cols, N, mr, M, e, wl, stream);
-        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
-                     out);
+        wl.lam = ck.lam + so;
+        wl.blo = ck.blo + so;
+        wl.bhi = ck.bhi + so;
+        wl.org = ck.org + so;
+        wl.tau = ck.tau + so;
+        TDE_LAUNCH_K(KIND_BACKWARD, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        enqueue_deflate(mr, blkm, N, e, wl, stream);
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
+        switch (lanes_per_root(L.smax, p.sweep_cols)) {
+            case 1: launch_bwd_roots_g<1>(N, mr, M, e, wl, gr, cs, stream); break;
+            case 2: launch_bwd_roots_g<2>(N, mr, M, e, wl, gr, cs, stream); break;
+            case 4: launch_bwd_roots_g<4>(N, mr, M, e, wl, gr, cs, stream); break;
+            case 8: launch_bwd_roots_g<8>(N, mr, M, e, wl, gr, cs, stream); break;
+            default: launch_bwd_roots_g<16>(N, mr, M, e, wl, gr, cs, stream); break;
+        }
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl, nb, kWG, stream, mr, blkm, N, wl, gr, cs);
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_grho, (unsigned)M, kWG, stream, mr, e, (const unsigned long long*)w.pmax, wl,
+                     gr, cs, L.mstart);
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs, gstride, kWG, stream, mr, blkm, N, wl, gr, cs);
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax,
+                     wl, gr);
     }
+    if (p.nleaves > 0) {
+        if (p.leafmax <= 8)
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<8>, nblk(p.nleaves, 8), 64, stream, p.d_leaves, p.nleaves, d, e,
+                         w.pmax, w, gr, gd, ge);
+        else if (p.leafmax <= 16)
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<16>, nblk(p.nleaves, 4), 64, stream, p.d_leaves, p.nleaves, d, e,
+                         w.pmax, w, gr, gd, ge);
+        else if (p.leafmax <= 32)
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<32>, nblk(p.nleaves, 2), 64, stream, p.d_leaves, p.nleaves, d, e,
+                         w.pmax, w, gr, gd, ge);
+        else
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<64>, (unsigned)p.nleaves, 64, stream, p.d_leaves, p.nleaves, d, e,
+                         w.pmax, w, gr, gd, ge);
+    }
+    if (p.zmax_total > 0 && !p.levels.empty())
+        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_tear, nblk(p.nmerges, kWG), kWG, stream, p.d_merges, p.nmerges, e,
+                     (const unsigned long long*)w.pmax, gr, ge);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_edges, nblk(p.B, kWG), kWG, stream, (const long long*)p.d_offs, p.B, ge);
     return (int)hipGetLastError();
 }
 
@@ -640,12 +970,14 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Z = (double*)take(8 * nn);
     t.RL = (double*)take(8 * nn);
     t.RH = (double*)take(8 * nn);
+    t.src = (int*)take(4 * nn);
     t.D2 = (double*)take(8 * nn);
     t.Z2 = (double*)take(8 * nn);
     t.RL2 = (double*)take(8 * nn);
     t.RH2 = (double*)take(8 * nn);
     t.st = (int*)take(4 * nn);
     t.scan = (int*)take(4 * (nn + 1));
+    t.scanC = (int*)take(4 * (nn + 1));
     t.scanR = (int*)take(4 * (nn + 1));
     t.bsum = (int*)take(4 * nb);
     t.bsumR = (int*)take(4 * nb);
@@ -659,6 +991,9 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.RLa = (double*)take(8 * nn);
     t.RHa = (double*)take(8 * nn);
     t.amerge = (int*)take(4 * nn);
+    t.apos = (int*)take(4 * nn);
+    t.rpos = (int*)take(4 * nn);
+    t.dpos = (int*)take(4 * nn);
     t.org = (int*)take(4 * nn);
     t.tau = (double*)take(8 * nn);
     t.zhat = (double*)take(8 * nn);
@@ -672,6 +1007,61 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.RHr = (double*)take(8 * nn);
     t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));  // all levels' merges
     if (w) *w = t;
+    return off;
+}
+
+size_t grad_layout(long long n, long long nmerges, char* base, Grad* g) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const long long nn = n > 0 ? n : 1;
+    Grad t{};
+    t.glam = (double*)take(8 * nn);
+    t.gblo = (double*)take(8 * nn);
+    t.gbhi = (double*)take(8 * nn);
+    t.gD = (double*)take(8 * nn);
+    t.gZ = (double*)take(8 * nn);
+    t.gRL = (double*)take(8 * nn);
+    t.gRH = (double*)take(8 * nn);
+    t.gD2 = (double*)take(8 * nn);
+    t.gZ2 = (double*)take(8 * nn);
+    t.gRL2 = (double*)take(8 * nn);
+    t.gRH2 = (double*)take(8 * nn);
+    t.glr = (double*)take(8 * nn);
+    t.gbr = (double*)take(8 * nn);
+    t.ghr = (double*)take(8 * nn);
+    t.coef = (double*)take(8 * 10 * nn);
+    t.chain = (RunState*)take(sizeof(RunState) * nn);
+    t.cdef = (RunState*)take(sizeof(RunState) * nn);
+    t.skey = (double*)take(8 * nn);
+    t.sidx = (int*)take(4 * nn);
+    t.grho = (double*)take(8 * (nmerges > 0 ? nmerges : 1));
+    t.gdp = (double*)take(8 * nn);
+    if (g) *g = t;
+    return off;
+}
+
+size_t ckpt_layout(long long n, int levels, char* base, Ckpt* c) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const long long nn = n > 0 ? n : 1;
+    const long long H = levels > 0 ? levels : 0;
+    Ckpt t{};
+    t.n = nn;
+    (void)take(256);  // header slot: the size is never 0, even for a tree with no merges
+    t.lam = (double*)take(8 * nn * H);
+    t.blo = (double*)take(8 * nn * H);
+    t.bhi = (double*)take(8 * nn * H);
+    t.tau = (double*)take(8 * nn * H);
+    t.org = (int*)take(4 * nn * H);
+    if (c) *c = t;
     return off;
 }
 

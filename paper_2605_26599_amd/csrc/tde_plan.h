@@ -32,6 +32,7 @@ struct Plan {
     std::vector<LevelInfo> levels;
     // device tables owned by the plan
     long long zmax_total = 1;  // merges over all levels (one max-|z| slot each)
+    int nmerges = 0;           // merges over all levels
     MergeRec* d_merges = nullptr;
     int* d_blkm = nullptr;     // per level, per block of kWG packed columns: first merge touched
     LeafRec* d_leaves = nullptr;
@@ -47,8 +48,19 @@ void timing_enable(bool on);
 bool timing_enabled();
 int timing_read(double* ms, long long* count, int nkinds);
 
-// Enqueue one full solve (scale, leaves, every level) on stream.
-int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out,
-                  void* stream);
+// Reverse-pass scratch (n columns, nmerges merges) and forward checkpoint
+// (n columns, `levels` tree levels).  With base == nullptr only the size.
+size_t grad_layout(long long n, long long nmerges, char* base, Grad* g);
+size_t ckpt_layout(long long n, int levels, char* base, Ckpt* c);
+
+// Enqueue one full solve (scale, leaves, every level) on stream; with ck, also
+// record the checkpoint the reverse pass reads.
+int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
+                  const Ckpt* ck = nullptr);
+
+// Enqueue the reverse pass: gd, ge = d(sum_k gin_k lambda_k)/d(d, e) from the
+// checkpoint of a forward solve of the same (d, e) under the same plan.
+int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
+                     const double* e, const double* gin, double* gd, double* ge, void* stream);
 
 }  // namespace tde

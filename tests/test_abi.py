@@ -76,3 +76,32 @@ def test_argument_errors_are_synchronous(L):
     assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
     assert L.tde_eigvals_batched(dummy, dummy, None, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
     assert L.tde_eigvals_batched(dummy, dummy, None, 0, dummy, dummy, 0, None, None) == tde.TDE_OK
+
+
+def test_checkpoint_and_backward_sizes(L):
+    """Host-side size queries of the reverse mode: the checkpoint holds about
+    36 bytes per column per tree level, the backward workspace is linear."""
+    import paper_2605_26599_amd as tde
+
+    assert tde.checkpoint_bytes(1, leaf=1) >= 256  # no merges: never 0
+    for n, leaf, levels in [(8192, 8, 10), (8192, 32, 8), (1000, 1, 10), (33, 32, 1)]:
+        nb = tde.checkpoint_bytes(n, leaf=leaf)
+        assert 36 * n * levels <= nb <= 36 * n * levels + 8 * 256 + 256, (n, leaf, nb)
+    offs = [i * 1024 for i in range(257)]
+    assert tde.checkpoint_bytes(offs[-1], offsets=offs, leaf=32) == tde.checkpoint_bytes(
+        offs[-1], offsets=[0] + offs[1:], leaf=32)
+    a = L.tde_backward_workspace_bytes(1 << 16, 1, None)
+    b = L.tde_backward_workspace_bytes(1 << 18, 1, None)
+    assert abs(b / a - 4.0) < 0.01 and a > tde.workspace_bytes(1 << 16)
+    bad = (ctypes.c_int64 * 3)(0, 5, 3)
+    assert L.tde_checkpoint_bytes(bad, 2, None) == 0
+    vp = ctypes.c_void_p
+    dummy = vp(256)
+    offs = (ctypes.c_int64 * 2)(0, 100)
+    # missing checkpoint / too small checkpoint / workspace: rejected before any device work
+    assert L.tde_eigvals_ckpt(dummy, dummy, offs, 1, dummy, None, 0, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals_ckpt(dummy, dummy, offs, 1, dummy, dummy, 16, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
+    assert L.tde_eigvals_backward(dummy, dummy, offs, 1, dummy, dummy, 16, dummy, dummy, dummy, 1 << 30, None,
+                                  None) == tde.TDE_EINVAL
+    assert L.tde_eigvals_backward(dummy, dummy, offs, 1, None, dummy, 1 << 30, dummy, dummy, dummy, 1 << 30,
+                                  None, None) == tde.TDE_EINVAL
