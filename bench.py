@@ -11,7 +11,10 @@ Prints one JSON line.  Besides the headline value it carries:
                 from the library's counters / measured duration vs. MI355X peak
   cpu_baseline  the CPU oracle (Sturm bisection) on a bounded sample of the
                 same matrix, on the host's cores
-  secondary     batched solves/s (4096 problems) and the QL CPU baseline
+  secondary     batched solves/s (4096 problems), the QL CPU baseline, and
+                the reverse mode: (forward with checkpoint + backward) time over
+                plain forward time for L = sum_k w_k lambda_k at n = 8192 and
+                at 256 problems of n = 1024 (d, e ~ U(-1, 1))
 """
 import argparse
 import hashlib
@@ -28,7 +31,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (FMA) x 2.
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
 # Algorithmic work per counted unit ("Roofline accounting").
-FLOPS_PER_SEC_TERM = 8      # (D_j - D_o) - tau, z/del, z*t, t*t, 3 accumulations
+FLOPS_PER_SEC_TERM = 7      # (D_j - D_o) - tau, 1/del, w*r, t*r, 2 accumulations
 FLOPS_PER_LOW_PAIR = 5      # (D_o - D_i) + tau, D_k - D_i, divide, multiply
 FLOPS_PER_ROW_PAIR = 9      # (D_i - D_o) - tau, zhat/del, y*y+ss, 2 fused dot updates
 FLOPS_PER_LEAF_ROT = 26     # one implicit-QL plane rotation incl. the two tracked rows
@@ -164,6 +167,52 @@ def ql_baseline(d, e, target_s):
             "sample": f"leading {m} x {m} block of the same matrix, {t:.2f} s"}
 
 
+def grad_ratio(tde, dev, reps=20):
+    """fwd+bwd / fwd for the two gradient workloads (graph replay, inputs,
+    weights and every output buffer resident before timing)."""
+    import numpy as np
+    import torch
+
+    import tdgen
+    from paper_2605_26599_amd import autotune
+
+    res = {}
+    cases = {"single_n8192": [tdgen.tridiag("uniform", 8192, cfg=tdgen.CFG_GRAD)],
+             "batch_256x1024": [tdgen.tridiag("uniform", 1024, cfg=tdgen.CFG_GRAD, inst=b) for b in range(256)]}
+    for name, probs in cases.items():
+        bt = tdgen.pack(probs)
+        offs = None if len(probs) == 1 else [int(x) for x in bt.offsets]
+        n = int(bt.offsets[-1])
+        d = torch.from_numpy(bt.d).to(dev)
+        e = torch.from_numpy(bt.e if offs else probs[0][1]).to(dev)
+        w = torch.from_numpy(np.concatenate([tdgen.loss_weights(len(p[0]), inst=i) for i, p in enumerate(probs)])).to(dev)
+        r = autotune.tune(d, e, offs, reps=3)
+        leaf, cols = r["leaf"], r["sweep_cols"]
+        out = torch.empty(n, dtype=torch.float64, device=dev)
+        ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
+        gd = torch.empty(n, dtype=torch.float64, device=dev)
+        ge = torch.empty(n, dtype=torch.float64, device=dev)
+
+        def fwd():
+            if offs is None:
+                tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
+            else:
+                tde.eigvals_batched(d, e, offs, leaf=leaf, sweep_cols=cols, out=out, check=False)
+
+        def fwdbwd():
+            tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, out=out, ckpt=ck, check=False)
+            tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, gd=gd, ge=ge, check=False)
+
+        for _ in range(3):
+            fwd()
+            fwdbwd()
+        torch.cuda.synchronize()
+        tf = timed(fwd, reps) / reps
+        tfb = timed(fwdbwd, reps) / reps
+        res[name] = {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf, "leaf": leaf, "sweep_cols": cols}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -280,6 +329,7 @@ def main():
         bms = timed(bstep, 5) / 5
         sec["batched_solves_per_s"] = 4096 / (bms / 1e3)
         sec["batched_ms_per_step"] = bms
+        sec["grad_fwd_bwd_over_fwd"] = grad_ratio(tde, dev)
     if not args.no_cpu and dn is not None:
         sec["cpu_ql"] = ql_baseline(dn, en, args.cpu_seconds)
     if sec:

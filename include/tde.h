@@ -61,7 +61,10 @@ typedef struct {
     int sweep_cols; /* target poles per lane in the root-parallel sweeps: each root
                        gets G = min(16, 2^ceil(log2(largest merge / sweep_cols)))
                        lanes; 0 = default (8) */
-    int reserved[5];
+    int wide_min;   /* merges with at least this many active (non-deflated) roots
+                       solve them with the wide sweep (64 roots per workgroup, the
+                       poles split over 4 waves); >= 2, 0 = default (1024) */
+    int reserved[4];
 } tde_opts;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */

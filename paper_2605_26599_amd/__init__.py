@@ -65,7 +65,7 @@ class TDEError(RuntimeError):
 
 class tde_opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("wide_min", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 _lib = None
@@ -140,13 +140,14 @@ def _status_string(code: int) -> str:
 TDE_FLAG_NO_GRAPH = 1
 
 
-def _opts(leaf, graph=True, sweep_cols=None):
-    if leaf is None and graph and sweep_cols is None:
+def _opts(leaf, graph=True, sweep_cols=None, wide_min=None):
+    if leaf is None and graph and sweep_cols is None and wide_min is None:
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
     o.flags = 0 if graph else TDE_FLAG_NO_GRAPH
     o.sweep_cols = int(sweep_cols or 0)
+    o.wide_min = int(wide_min or 0)
     return ctypes.byref(o)
 
 
@@ -185,7 +186,7 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-            sweep_cols=None) -> torch.Tensor:
+            sweep_cols=None, wide_min=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
     off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
     replays a captured HIP graph of the whole solve (captured on first use for
@@ -205,7 +206,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
-                               ws.data_ptr(), ws.numel(), stream, _opts(leaf, graph, sweep_cols))
+                               ws.data_ptr(), ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -217,7 +218,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-                    sweep_cols=None) -> torch.Tensor:
+                    sweep_cols=None, wide_min=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -238,7 +239,7 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
-                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols))
+                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:
@@ -265,7 +266,7 @@ def checkpoint_bytes(n: int, offsets=None, leaf=None, sweep_cols=None) -> int:
 
 
 def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, out=None,
-                 ckpt=None, workspace=None, check: bool = True, graph: bool = True):
+                 ckpt=None, workspace=None, check: bool = True, graph: bool = True, wide_min=None):
     """Eigenvalues as eigvals / eigvals_batched (offsets None = one problem with
     e[n-1]), plus the checkpoint the reverse pass reads.  Returns (lambda, ckpt)."""
     _check_input(d, e)
@@ -288,7 +289,7 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_ckpt(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, out.data_ptr(),
                                     ckpt.data_ptr(), ckpt.numel(), ws.data_ptr(), ws.numel(), stream,
-                                    _opts(leaf, graph, sweep_cols))
+                                    _opts(leaf, graph, sweep_cols, wide_min))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_ckpt")
         if check:
@@ -299,17 +300,24 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
 
 
 def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt: torch.Tensor, offsets=None,
-                     leaf=None, sweep_cols=None, workspace=None, check: bool = True, graph: bool = True):
+                     leaf=None, sweep_cols=None, workspace=None, check: bool = True, graph: bool = True,
+                     gd: torch.Tensor | None = None, ge: torch.Tensor | None = None, wide_min=None):
     """dL/dd and dL/de for L = sum_k glam_k lambda_k, from the checkpoint of
     eigvals_ckpt on the same inputs and options.  Returns (gd[n], ge[n]) with
-    ge in the batched layout (the last slot of every problem is 0)."""
+    ge in the batched layout (the last slot of every problem is 0); gd and ge
+    may be given as output buffers of at least n entries."""
     _check_input(d, e)
     offs, B, arr = _offsets(d.numel(), offsets)
     n = offs[-1]
-    gd = torch.zeros(n, dtype=torch.float64, device=d.device)
-    ge = torch.zeros(max(n, 1), dtype=torch.float64, device=d.device)
+    if gd is None:
+        gd = torch.zeros(n, dtype=torch.float64, device=d.device)
+    if ge is None:
+        ge = torch.zeros(max(n, 1), dtype=torch.float64, device=d.device)
+    for t in (gd, ge):
+        if t.dtype != torch.float64 or t.device != d.device or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("gd and ge must be contiguous float64 tensors of at least n entries on d's device")
     if B <= 0 or n == 0:
-        return gd, ge[:n]
+        return gd[:n], ge[:n]
     glam = glam.to(device=d.device, dtype=torch.float64).contiguous()
     if glam.numel() != n:
         raise ValueError("glam must hold one entry per eigenvalue")
@@ -322,14 +330,14 @@ def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt:
         rc = lib().tde_eigvals_backward(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B,
                                         glam.data_ptr(), ckpt.data_ptr(), ckpt.numel(), gd.data_ptr(),
                                         ge.data_ptr(), ws.data_ptr(), ws.numel(), stream,
-                                        _opts(leaf, graph, sweep_cols))
+                                        _opts(leaf, graph, sweep_cols, wide_min))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_backward")
         if check:
             st = lib().tde_get_status(ws.data_ptr(), stream)
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_backward device status")
-    return gd, ge[:n]
+    return gd[:n], ge[:n]
 
 
 class _Eigvals(torch.autograd.Function):

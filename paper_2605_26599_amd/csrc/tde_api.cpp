@@ -18,7 +18,7 @@
 namespace tde {
 namespace {
 
-using PlanKey = std::tuple<int, int, int, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, int, std::vector<long long>>;
 std::mutex g_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
@@ -100,8 +100,8 @@ void free_plan(Plan* p) {
     p->d_offs = nullptr;
 }
 
-int make_plan(int device, int leaf, int cols, const std::vector<long long>& offs, Plan** out) {
-    PlanKey key{device, leaf, cols, offs};
+int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long long>& offs, Plan** out) {
+    PlanKey key{device, leaf, cols, wmin, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second.get();
@@ -111,6 +111,7 @@ int make_plan(int device, int leaf, int cols, const std::vector<long long>& offs
     p->device = device;
     p->leaf = leaf;
     p->sweep_cols = cols;
+    p->wide_min = wmin;
     p->offs = offs;
     p->B = (int)offs.size() - 1;
     p->ntot = offs.back();
@@ -166,17 +167,20 @@ int make_plan(int device, int leaf, int cols, const std::vector<long long>& offs
     return TDE_OK;
 }
 
-int resolve_opts(const tde_opts* opts, int* leaf, int* cols) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols;
+int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin;
     if (opts) {
         if (opts->flags & ~TDE_FLAG_NO_GRAPH) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
         if (opts->sweep_cols != 0) C = opts->sweep_cols;
+        if (opts->wide_min != 0) W = opts->wide_min;
     }
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
     if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
+    if (W < 2) return TDE_EINVAL;
     *leaf = L;
     *cols = C;
+    if (wmin) *wmin = W;
     return TDE_OK;
 }
 
@@ -206,11 +210,13 @@ int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* off
     return TDE_OK;
 }
 
-int get_plan(int leaf, int cols, const std::vector<long long>& offs, Plan** plan) {
+int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** plan) {
+    int leaf, cols, wmin;
+    if (resolve_opts(opts, &leaf, &cols, &wmin) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
     std::lock_guard<std::mutex> lk(g_mu);
-    return make_plan(device, leaf, cols, offs, plan);
+    return make_plan(device, leaf, cols, wmin, offs, plan);
 }
 
 bool needs_e(const std::vector<long long>& offs) {
@@ -232,7 +238,7 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
     const int H = tree_levels(leaf, offs);
     if (ckpt_bytes && (!ckpt || ckpt_bytes < ckpt_layout(ntot, H, nullptr, nullptr))) return TDE_EINVAL;
     Plan* plan = nullptr;
-    int rc = get_plan(leaf, cols, offs, &plan);
+    int rc = get_plan(opts, offs, &plan);
     if (rc != TDE_OK) return rc;
     Work w{};
     workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
@@ -262,7 +268,7 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
     if (ckpt_bytes < ckpt_layout(ntot, H, nullptr, nullptr)) return TDE_EINVAL;
     const size_t fw = workspace_layout(ntot, B, ntot, nullptr, nullptr);
     Plan* plan = nullptr;
-    int rc = get_plan(leaf, cols, offs, &plan);
+    int rc = get_plan(opts, offs, &plan);
     if (rc != TDE_OK) return rc;
     if (ws_bytes < fw + grad_layout(ntot, ntot, nullptr, nullptr)) return TDE_EINVAL;
     Work w{};

@@ -24,8 +24,22 @@
 #ifndef TDE_ATOMIC_OR
 #define TDE_ATOMIC_OR(p, v) atomicOr((p), (v))
 #endif
+// Hardware reciprocal estimate (refined by rcp_nr below).
+#ifndef TDE_RCP_ESTIMATE
+#define TDE_RCP_ESTIMATE(x) __builtin_amdgcn_rcp(x)
+#endif
 
 namespace tde {
+
+// 1/x from the hardware estimate and two Newton steps (each squares the
+// relative error), about an ulp: the sweeps' per-term division.
+TDE_DEV double rcp_nr(double x) {
+    double y = TDE_RCP_ESTIMATE(x);
+    double t = fma(-x, y, 1.0);
+    y = fma(y, t, y);
+    t = fma(-x, y, 1.0);
+    return fma(y, t, y);
+}
 
 TDE_DEV unsigned long long dbits(double x) {
     union { double d; unsigned long long u; } c;
@@ -270,118 +284,170 @@ struct RedSerial {
     TDE_DEV static double prod(double x) { return x; }
 };
 
+// State of one secular root between pole sweeps.
+struct SecRoot {
+    int o;                // origin pole
+    double lo, hi, tau;   // bracket and current offset from D_o
+    double d1, d2;        // the bracketing poles D_kk, D_kk+1 relative to D_o
+    double zo, wo;        // z_o and the origin weight rho z_o^2
+    double fprev;
+    bool orgl;            // origin is the left bracketing pole
+    bool fixed_weight;
+};
+
+// Interior root k < K-1 (kk = k): from the sums at the bracket midpoint with
+// origin kk (ps, dps over j < kk; ph, dph over j > kk+1) pick the nearer pole
+// as origin and take the first model step.  Returns true when the midpoint is
+// the root itself (r->tau final).
+TDE_DEV bool sec_start_interior(int k, const double* __restrict__ D, const double* __restrict__ Z, double rho,
+                                double ps, double dps, double ph, double dph, SecRoot* r) {
+    const int kk = k;
+    const double dk = D[kk], dk1 = D[kk + 1];
+    const double mid = 0.5 * (dk1 - dk);
+    const double ak = Z[kk] / (-mid), ak1 = Z[kk + 1] / mid;
+    const double f = 1.0 + rho * (ps + ph + Z[kk] * ak + Z[kk + 1] * ak1);
+    if (f >= 0.0) { r->o = k; r->lo = 0.0; r->hi = mid; r->tau = mid; }
+    else { r->o = k + 1; r->lo = -mid; r->hi = 0.0; r->tau = -mid; }
+    const double Do = D[r->o];
+    r->d1 = dk - Do;
+    r->d2 = dk1 - Do;
+    r->zo = Z[r->o];
+    r->wo = rho * r->zo * r->zo;
+    r->orgl = (r->o == kk);
+    r->fixed_weight = true;
+    r->fprev = INFINITY;
+    if (f == 0.0) return true;
+    double q, Q;
+    if (r->orgl) { q = r->wo; Q = (r->d2 - r->tau) * (r->d2 - r->tau) * rho * (dps + dph + ak1 * ak1); }
+    else { Q = r->wo; q = (r->d1 - r->tau) * (r->d1 - r->tau) * rho * (dps + dph + ak * ak); }
+    r->tau = model_root(f, r->tau, r->d1, r->d2, q, Q, r->lo, r->hi);
+    return false;
+}
+
+// Last root (k = K-1, origin K-1): bracket (0, rho ||z||^2] and the first
+// offset from the equation truncated to the two nearest poles (a lower bound).
+TDE_DEV void sec_start_last(int K, const double* __restrict__ D, const double* __restrict__ Z, double rho, double zz,
+                            SecRoot* r) {
+    const double dk = D[K - 2], dk1 = D[K - 1];
+    r->o = K - 1;
+    r->lo = 0.0;
+    r->hi = rho * zz * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
+    const double w1 = rho * Z[K - 1] * Z[K - 1], w2 = rho * Z[K - 2] * Z[K - 2], g = dk1 - dk;
+    const double b = g - w1 - w2, sq = sqrt(b * b + 4.0 * w1 * g);
+    const double t2 = (b <= 0.0) ? 0.5 * (sq - b) : 2.0 * w1 * g / (b + sq);
+    r->tau = (t2 > r->lo && t2 < r->hi) ? t2 : 0.5 * r->hi;
+    r->d1 = dk - dk1;
+    r->d2 = 0.0;
+    r->zo = Z[K - 1];
+    r->wo = rho * r->zo * r->zo;
+    r->orgl = false;
+    r->fixed_weight = true;
+    r->fprev = INFINITY;
+}
+
+// One iteration from a sweep at r->tau: psi, dpsi over the poles j <= kk and
+// phi, dphi over j > kk (the origin excluded from both), err = sum of |terms|
+// over those poles.  Returns 1 when converged (r->tau final), else 0 with the
+// next offset in r->tau.
+TDE_DEV int sec_update(SecRoot* r, double rho, double psi, double dpsi, double phi, double dphi, double err) {
+    const double tau = r->tau;
+    const double to = r->zo / (-tau);
+    const double termo = r->zo * to, dto = to * to;
+    const double f = 1.0 + rho * (psi + phi + termo);
+    err += fabs(termo);
+    if (fabs(f) <= 8.0 * DBL_EPSILON * (1.0 + rho * err)) return 1;
+    if (f < 0.0) r->lo = tau;
+    else r->hi = tau;
+    if (r->hi - r->lo <= 2.0 * DBL_EPSILON * fmax(fabs(r->lo), fabs(r->hi))) return 1;
+    if (r->fixed_weight && fabs(f) > 0.1 * fabs(r->fprev)) r->fixed_weight = false;
+    r->fprev = f;
+    double q, Q;
+    const double d1 = r->d1, d2 = r->d2;
+    if (r->fixed_weight) {
+        if (r->orgl) { q = r->wo; Q = (d2 - tau) * (d2 - tau) * rho * (dpsi + dphi); }
+        else { Q = r->wo; q = (d1 - tau) * (d1 - tau) * rho * (dpsi + dphi); }
+    } else {
+        q = (d1 - tau) * (d1 - tau) * rho * (dpsi + (r->orgl ? dto : 0.0));
+        Q = (d2 - tau) * (d2 - tau) * rho * (dphi + (r->orgl ? 0.0 : dto));
+    }
+    const double tn = model_root(f, tau, d1, d2, q, Q, r->lo, r->hi);
+    r->tau = tn;
+    if (fabs(tn - tau) <= 2.0 * DBL_EPSILON * fabs(tau)) return 1;
+    return 0;
+}
+
+// Z: the merge's z (global); D, W: views of its poles and weights z_j^2
+// (global or staged).  Per pole term: r = 1/((D_j - D_o) - tau), t = w_j r,
+// t r; the sum of |terms| needed by the stopping test is phi - psi (every
+// left term is negative, every right term positive).
 template <class Red>
 TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const double* __restrict__ Z,
-                         double rho, int sub, int G, int* org_out, double* tau_out) {
+                         const double* __restrict__ W, double rho, int sub, int G, int* org_out, double* tau_out) {
     if (K == 1) {
         *org_out = 0;
         *tau_out = rho * Z[0] * Z[0];
         return 0;
     }
     const int kk = (k < K - 1) ? k : K - 2;
-    const double dk = D[kk], dk1 = D[kk + 1];
-    int o;
-    double lo, hi, tau;
+    SecRoot r;
     if (k < K - 1) {
         // Midpoint sweep (origin kk): picks the nearer pole and seeds the first step.
-        const double gap = dk1 - dk;
-        const double mid = 0.5 * gap;
+        const double dk = D[kk];
+        const double mid = 0.5 * (D[kk + 1] - dk);
         double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
         _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
-            const double del = (D[j] - dk) - mid;
-            const double t = Z[j] / del;
+            const double rr = rcp_nr((D[j] - dk) - mid);
             const bool near = (j == kk) || (j == kk + 1);
+            const double t = near ? 0.0 : W[j] * rr;
+            const double dt = t * rr;
             const bool left = j < kk;
-            const double term = near ? 0.0 : Z[j] * t;
-            const double dterm = near ? 0.0 : t * t;
-            ps += left ? term : 0.0;
-            dps += left ? dterm : 0.0;
-            ph += left ? 0.0 : term;
-            dph += left ? 0.0 : dterm;
+            ps += left ? t : 0.0;
+            dps += left ? dt : 0.0;
+            ph += left ? 0.0 : t;
+            dph += left ? 0.0 : dt;
         }
         ps = Red::sum(ps);
         dps = Red::sum(dps);
         ph = Red::sum(ph);
         dph = Red::sum(dph);
-        const double ak = Z[kk] / (-mid), ak1 = Z[kk + 1] / mid;
-        const double f = 1.0 + rho * (ps + ph + Z[kk] * ak + Z[kk + 1] * ak1);
-        if (f >= 0.0) { o = k; lo = 0.0; hi = mid; tau = mid; }
-        else { o = k + 1; lo = -mid; hi = 0.0; tau = -mid; }
-        if (f == 0.0) { *org_out = o; *tau_out = tau; return 0; }
-        const double e1 = dk - D[o], e2 = dk1 - D[o];
-        double q, Q;
-        if (o == kk) { q = rho * Z[kk] * Z[kk]; Q = (e2 - tau) * (e2 - tau) * rho * (dps + dph + ak1 * ak1); }
-        else { Q = rho * Z[kk + 1] * Z[kk + 1]; q = (e1 - tau) * (e1 - tau) * rho * (dps + dph + ak * ak); }
-        tau = model_root(f, tau, e1, e2, q, Q, lo, hi);
+        if (sec_start_interior(k, D, Z, rho, ps, dps, ph, dph, &r)) {
+            *org_out = r.o;
+            *tau_out = r.tau;
+            return 0;
+        }
     } else {
-        o = K - 1;
         double zz = 0.0;
-        for (int j = sub; j < K; j += G) zz += Z[j] * Z[j];
+        for (int j = sub; j < K; j += G) zz += W[j];
         zz = Red::sum(zz);
-        lo = 0.0;
-        hi = rho * zz * (1.0 + 4.0 * DBL_EPSILON) + DBL_MIN;
-        // root of 1 = w1/x + w2/(x + g): the two nearest poles only (a lower bound)
-        const double w1 = rho * Z[K - 1] * Z[K - 1], w2 = rho * Z[K - 2] * Z[K - 2], g = dk1 - dk;
-        const double b = g - w1 - w2, sq = sqrt(b * b + 4.0 * w1 * g);
-        const double t2 = (b <= 0.0) ? 0.5 * (sq - b) : 2.0 * w1 * g / (b + sq);
-        tau = (t2 > lo && t2 < hi) ? t2 : 0.5 * hi;
+        sec_start_last(K, D, Z, rho, zz, &r);
     }
-    const double Do = D[o];
-    const double d1 = dk - Do, d2 = dk1 - Do;
-    const double zo = Z[o], wo = rho * zo * zo;
-    const bool orgl = (o == kk);
-    bool fixed_weight = true;
-    double fprev = INFINITY;
+    const double Do = D[r.o];
+    const int o = r.o;
     for (int it = 1; it <= kSecMaxIter; ++it) {
-        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, err = 0.0;
+        const double tau = r.tau;
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
         _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
-            const double del = (D[j] - Do) - tau;
-            const double t = Z[j] / del;
-            const bool own = (j == o);
+            const double rr = rcp_nr((D[j] - Do) - tau);
+            const double t = (j == o) ? 0.0 : W[j] * rr;
+            const double dt = t * rr;
             const bool left = j <= kk;
-            const double term = own ? 0.0 : Z[j] * t;
-            const double dterm = own ? 0.0 : t * t;
-            psi += left ? term : 0.0;
-            dpsi += left ? dterm : 0.0;
-            phi += left ? 0.0 : term;
-            dphi += left ? 0.0 : dterm;
-            err += fabs(term);
+            psi += left ? t : 0.0;
+            dpsi += left ? dt : 0.0;
+            phi += left ? 0.0 : t;
+            dphi += left ? 0.0 : dt;
         }
         psi = Red::sum(psi);
         dpsi = Red::sum(dpsi);
         phi = Red::sum(phi);
         dphi = Red::sum(dphi);
-        err = Red::sum(err);
-        const double to = zo / (-tau);
-        const double termo = zo * to, dto = to * to;
-        const double f = 1.0 + rho * (psi + phi + termo);
-        err += fabs(termo);
-        if (fabs(f) <= 8.0 * DBL_EPSILON * (1.0 + rho * err)) {
-            *org_out = o; *tau_out = tau; return it;
+        if (sec_update(&r, rho, psi, dpsi, phi, dphi, phi - psi)) {
+            *org_out = o;
+            *tau_out = r.tau;
+            return it;
         }
-        if (f < 0.0) lo = tau;
-        else hi = tau;
-        if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) {
-            *org_out = o; *tau_out = tau; return it;
-        }
-        if (fixed_weight && fabs(f) > 0.1 * fabs(fprev)) fixed_weight = false;
-        fprev = f;
-        double q, Q;
-        if (fixed_weight) {
-            if (orgl) { q = wo; Q = (d2 - tau) * (d2 - tau) * rho * (dpsi + dphi); }
-            else { Q = wo; q = (d1 - tau) * (d1 - tau) * rho * (dpsi + dphi); }
-        } else {
-            q = (d1 - tau) * (d1 - tau) * rho * (dpsi + (orgl ? dto : 0.0));
-            Q = (d2 - tau) * (d2 - tau) * rho * (dphi + (orgl ? 0.0 : dto));
-        }
-        const double tn = model_root(f, tau, d1, d2, q, Q, lo, hi);
-        if (fabs(tn - tau) <= 2.0 * DBL_EPSILON * fabs(tau)) {
-            *org_out = o; *tau_out = tn; return it;
-        }
-        tau = tn;
     }
     *org_out = o;
-    *tau_out = tau;
+    *tau_out = r.tau;
     return -1;
 }
 
@@ -399,15 +465,26 @@ template <class Red>
 TDE_DEV double lowner_z(int i, int K, const double* __restrict__ D, const double* __restrict__ Z,
                         const int* __restrict__ org, const double* __restrict__ tau, double rho, int sub, int G) {
     const double di = D[i];
-    double prod = 1.0;
+    // numerators and denominators multiplied 8 at a time (8 factors of the
+    // chain cannot leave the exponent range), one division per chunk
+    double prod = 1.0, pn = 1.0, pd = 1.0;
+    int c = 0;
     _Pragma("unroll 4") for (int k = sub; k < K; k += G) {
-        double num = (D[org[k]] - di) + tau[k];
+        const double num = (D[org[k]] - di) + tau[k];
         double den;
         if (k < i) den = D[k] - di;
         else if (k < K - 1) den = D[k + 1] - di;
         else den = 1.0;
-        prod *= num / den;
+        pn *= num;
+        pd *= den;
+        if (++c == 8) {
+            prod *= pn / pd;
+            pn = 1.0;
+            pd = 1.0;
+            c = 0;
+        }
     }
+    prod *= pn / pd;
     prod = Red::prod(prod);
     double z2 = prod / rho;
     double zi = sqrt(fmax(z2, 0.0));
@@ -424,11 +501,10 @@ TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __rest
     const double Do = D[org];
     double ss = 0.0, bl = 0.0, bh = 0.0;
     _Pragma("unroll 4") for (int i = sub; i < K; i += G) {
-        double del = (D[i] - Do) - tau;
-        double y = zh[i] / del;
-        ss += y * y;
-        bl += RL[i] * y;
-        bh += RH[i] * y;
+        const double y = zh[i] * rcp_nr((D[i] - Do) - tau);
+        ss = fma(y, y, ss);
+        bl = fma(RL[i], y, bl);
+        bh = fma(RH[i], y, bh);
     }
     ss = Red::sum(ss);
     bl = Red::sum(bl);
@@ -653,7 +729,7 @@ TDE_DEV MergeSpan merge_span(const MergeRec& R, const int* __restrict__ scan) {
 template <class Red>
 TDE_DEV int body_secular(long long g, int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
                          const unsigned long long* __restrict__ pmax, const Work& w, int sub, int G,
-                         const double* __restrict__ Dv, const double* __restrict__ Zv, long long voff) {
+                         const double* __restrict__ Dv, const double* __restrict__ Wv, long long voff) {
     const MergeRec R = mr[m];
     const MergeSpan sp = merge_span(R, w.scan);
     double sgn;
@@ -661,7 +737,7 @@ TDE_DEV int body_secular(long long g, int m, const MergeRec* __restrict__ mr, co
     int o;
     double tau;
     const long long b = sp.ks - voff;
-    const int it = secular_root<Red>((int)(g - sp.ks), sp.K, Dv + b, Zv + b, rho, sub, G, &o, &tau);
+    const int it = secular_root<Red>((int)(g - sp.ks), sp.K, Dv + b, w.Za + sp.ks, Wv + b, rho, sub, G, &o, &tau);
     if (sub == 0) {
         w.org[g] = o;
         w.tau[g] = tau;

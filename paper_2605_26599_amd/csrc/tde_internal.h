@@ -62,6 +62,8 @@ constexpr int kLeafMax = 64;     // largest leaf the QL leaf kernel accepts
 constexpr int kDefaultLeaf = 8;  // leaf size when the caller does not choose one
 constexpr int kDefaultSweepCols = 8;  // poles per lane per sweep when the caller does not choose
 constexpr int kSecMaxIter = 96;  // secular iteration cap
+constexpr int kWideMin = 1024;   // merges with at least this many active roots use the wide secular sweep
+constexpr int kWideWaves = 4;    // pole segments (waves) per workgroup of the wide secular sweep
 
 // Pointers into the caller's workspace for one solve.
 struct Work {
@@ -94,9 +96,11 @@ struct Work {
     int* cf;                   // [n]   close-pair flag of non-negligible column g and g+1
     double* Da;                // [n]   active poles
     double* Za;                // [n]   active z
+    double* Wa;                // [n]   active z^2 (the weights the wide secular sweep reads)
     double* RLa;               // [n]
     double* RHa;               // [n]
     int* amerge;               // [n]   merge index (within the level) of active column g
+    int* witems;               // [maxM+1] exclusive scan of 64-root blocks per wide merge
     int* apos;                 // [n]   packed position of active column g
     int* rpos;                 // [n]   packed position of rotated-away column gr
     int* dpos;                 // [n]   packed position of negligible-z column q

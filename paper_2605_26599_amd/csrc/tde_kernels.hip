@@ -258,6 +258,7 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
         if (fa) {
             w.Da[g] = w.D2[t];
             w.Za[g] = w.Z2[t];
+            w.Wa[g] = w.Z2[t] * w.Z2[t];
             w.RLa[g] = w.RL2[t];
             w.RHa[g] = w.RH2[t];
             w.amerge[g] = merge_of(mr, blkm, t);
@@ -323,19 +324,355 @@ __device__ __forceinline__ TileWindow tile_window(long long g0, long long g1, co
     return tw;
 }
 
+// ---------------------------------------------------------------------------
+// Wide sweeps for merges with many active roots (K >= wide_min).  A
+// workgroup takes 64 consecutive roots (or poles) of one merge, one per lane;
+// its kWideWaves waves split the other index into segments.  Within a wave
+// that index is uniform, so the per-pole (per-root) operands are scalar loads
+// shared by the 64 lanes, and the left/right split and the origin exclusion
+// of the secular sums become loop bounds: only the window next to the
+// block's own roots needs per-lane selects.  The waves' partial results meet
+// in LDS in a fixed order, so every wave holds the same totals bit for bit.
+// The wide blocks are the trailing blocks of the regular root kernels'
+// grids (block-uniform split), so no extra launch is needed; the work items
+// (64-root blocks of the wide merges) are listed by k_wide_items.
+// ---------------------------------------------------------------------------
+static_assert(64 * kWideWaves == kWG, "wide blocks share the regular kernels' workgroup size");
+
+// Exclusive scan of the number of 64-root blocks of every wide merge of a level.
+__global__ __launch_bounds__(1024) void k_wide_items(const MergeRec* __restrict__ mr, int M, Work w, int wide_min) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < M; base += 1024) {
+        const int m = base + threadIdx.x;
+        int v = 0;
+        if (m < M) {
+            const int K = merge_span(mr[m], w.scan).K;
+            v = (K >= wide_min) ? (K + 63) / 64 : 0;
+        }
+        const int incl = block_incl_scan(v, wsum);
+        const int c = carry;
+        if (m < M) w.witems[m] = c + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) w.witems[M] = carry;
+}
+
+// Values the compiler cannot prove wave-uniform but are (the wave index, a
+// merge's offsets): moved to scalar registers so the loops over them use
+// scalar loads.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long wave_uniform(long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Merge owning wide item `item` (largest m with witems[m] <= item), uniform.
+__device__ __forceinline__ int wide_merge_of(const int* __restrict__ witems, int M, int item) {
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (witems[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+struct WideSums {
+    double ps, dps, ph, dph, zz;
+};
+
+// Read-only views in the constant address space: a wave-uniform index into
+// them is a scalar load (s_load through the scalar data cache; these arrays
+// are written only by earlier launches, and nothing here is ever stored
+// through that cache).
+typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) int cint;
+__device__ __forceinline__ cdouble* as_const(const double* p) { return (cdouble*)p; }
+__device__ __forceinline__ cint* as_const(const int* p) { return (cint*)p; }
+
+// Secular sums over poles j in [a, b) (wave-uniform) for this lane's root:
+// left poles j < L1 into (ps, dps), right poles j >= R0 into (ph, dph); poles
+// in [L1, R0) are skipped.  [w0, w1) (wave-uniform) contains every lane's
+// [L1, R0); below it every pole is left for every lane, above it right.
+template <bool ZZ>
+__device__ __forceinline__ void wide_sweep(cdouble* D, cdouble* W, int a, int b, int w0, int w1, double Do, double tau,
+                                           int L1, int R0, WideSums& s) {
+    const int e1 = min(b, w0);
+    _Pragma("unroll 4") for (int j = a; j < e1; ++j) {
+        const double r = rcp_nr((D[j] - Do) - tau);
+        const double t = W[j] * r;
+        s.ps += t;
+        s.dps = fma(t, r, s.dps);
+        if (ZZ) s.zz += W[j];
+    }
+    const int s2 = max(a, w0), e2 = min(b, w1);
+    for (int j = s2; j < e2; ++j) {
+        const double r = rcp_nr((D[j] - Do) - tau);
+        const double t = W[j] * r;
+        const double dt = t * r;
+        const bool lf = j < L1, rt = j >= R0;
+        s.ps += lf ? t : 0.0;
+        s.dps += lf ? dt : 0.0;
+        s.ph += rt ? t : 0.0;
+        s.dph += rt ? dt : 0.0;
+        if (ZZ) s.zz += W[j];
+    }
+    _Pragma("unroll 4") for (int j = max(a, w1); j < b; ++j) {
+        const double r = rcp_nr((D[j] - Do) - tau);
+        const double t = W[j] * r;
+        s.ph += t;
+        s.dph = fma(t, r, s.dph);
+        if (ZZ) s.zz += W[j];
+    }
+}
+
+// Wide secular roots.  red: 2 x 5 x kWideWaves x 64 doubles of LDS.  The
+// block iterates until all of its 64 roots have converged.
+__device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
+                             const unsigned long long* __restrict__ pmax, const Work& w, double* red) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform((int)(threadIdx.x >> 6));
+    auto R5 = [&](int buf, int q, int v) -> double& { return red[((buf * 5 + q) * kWideWaves + v) * 64 + lane]; };
+    const int total = w.witems[M];
+    int buf = 0;
+    int bad = 0;
+    unsigned long long terms = 0, sweeps = 0, roots = 0;
+    for (int item = bid; item < total; item += nbw) {
+        const int m = wide_merge_of(w.witems, M, item);
+        const MergeRec R = mr[m];
+        const MergeSpan sp = merge_span(R, w.scan);
+        const int K = wave_uniform(sp.K);
+        const long long ks = wave_uniform(sp.ks);
+        const int k0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+        const double* D = w.Da + ks;
+        const double* Z = w.Za + ks;
+        cdouble* Dc = as_const(D);
+        cdouble* Wc = as_const(w.Wa + ks);
+        double sgn;
+        const double rho = merge_rho(R, e, pmax, &sgn);
+        const int k = min(k0 + lane, K - 1);
+        const bool act = (k0 + lane) < K;
+        const int kk = min(k, K - 2);
+        const int klast = min(k0 + 63, K - 1);
+        const int w0 = k0, w1 = min(min(klast, K - 2) + 2, K);
+        const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+        // first sweep: bracket midpoint with origin kk (the last root also needs ||z||^2)
+        WideSums s{0.0, 0.0, 0.0, 0.0, 0.0};
+        wide_sweep<true>(Dc, Wc, a, b, w0, w1, D[kk], 0.5 * (D[kk + 1] - D[kk]), kk, kk + 2, s);
+        double tot[5];
+        R5(buf, 0, wv) = s.ps;
+        R5(buf, 1, wv) = s.dps;
+        R5(buf, 2, wv) = s.ph;
+        R5(buf, 3, wv) = s.dph;
+        R5(buf, 4, wv) = s.zz;
+        __syncthreads();
+        for (int q = 0; q < 5; ++q) {
+            double x = 0.0;
+            for (int v = 0; v < kWideWaves; ++v) x += R5(buf, q, v);
+            tot[q] = x;
+        }
+        buf ^= 1;
+        SecRoot r;
+        bool done;
+        if (k < K - 1) {
+            done = sec_start_interior(k, D, Z, rho, tot[0], tot[1], tot[2], tot[3], &r);
+        } else {
+            sec_start_last(K, D, Z, rho, tot[4], &r);
+            done = false;
+        }
+        int its = 0;
+        for (int it = 1; it <= kSecMaxIter; ++it) {
+            if (__all(done)) break;
+            const int L1 = r.orgl ? kk : kk + 1;
+            const int R0 = r.orgl ? kk + 1 : kk + 2;
+            WideSums u{0.0, 0.0, 0.0, 0.0, 0.0};
+            wide_sweep<false>(Dc, Wc, a, b, w0, w1, D[r.o], r.tau, L1, R0, u);
+            R5(buf, 0, wv) = u.ps;
+            R5(buf, 1, wv) = u.dps;
+            R5(buf, 2, wv) = u.ph;
+            R5(buf, 3, wv) = u.dph;
+            __syncthreads();
+            for (int q = 0; q < 4; ++q) {
+                double x = 0.0;
+                for (int v = 0; v < kWideWaves; ++v) x += R5(buf, q, v);
+                tot[q] = x;
+            }
+            buf ^= 1;
+            if (!done && sec_update(&r, rho, tot[0], tot[1], tot[2], tot[3], tot[2] - tot[0])) {
+                done = true;
+                its = it;
+            }
+        }
+        if (!done) bad = 1;
+        if (wv == 0 && act) {
+            w.org[ks + k] = r.o;
+            w.tau[ks + k] = r.tau;
+            const unsigned long long sw = (unsigned long long)((done ? its : kSecMaxIter) + 1);
+            sweeps += sw;
+            terms += sw * (unsigned long long)K;
+            roots += 1;
+        }
+        __syncthreads();
+    }
+    if (bad && wv == 0 && lane == 0) atomicOr(w.status, ST_SEC_NOCONV);
+    if (wv == 0) {
+        count_add(&w.counters[CNT_SEC_TERMS], terms);
+        count_add(&w.counters[CNT_SWEEPS], sweeps);
+        count_add(&w.counters[CNT_ROOTS], roots);
+    }
+}
+
+// Wide Loewner step: 64 poles per workgroup, the roots split over the waves
+// (root index wave-uniform: D_org, tau and the neighbouring poles are scalar
+// loads).  Factors are multiplied in chunks of 8 numerators and 8
+// denominators, one division per chunk.  red: kWideWaves x 64 doubles.
+__device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
+                            const unsigned long long* __restrict__ pmax, const Work& w, bool with_root, double* red) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform((int)(threadIdx.x >> 6));
+    const int total = w.witems[M];
+    unsigned long long pairs = 0;
+    for (int item = bid; item < total; item += nbw) {
+        const int m = wide_merge_of(w.witems, M, item);
+        const MergeRec R = mr[m];
+        if (!(R.flags & MF_ROOT) || with_root) {
+            const MergeSpan sp = merge_span(R, w.scan);
+            const int K = wave_uniform(sp.K);
+            const long long ks = wave_uniform(sp.ks);
+            const int i0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+            cdouble* D = as_const(w.Da + ks);
+            cint* og = as_const(w.org + ks);
+            cdouble* ta = as_const(w.tau + ks);
+            const int i = min(i0 + lane, K - 1);
+            const double di = w.Da[ks + i];
+            const int ilast = min(i0 + 63, K - 1);
+            const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+            double prod = 1.0, pn = 1.0, pd = 1.0;
+            int c = 0;
+            auto factor = [&](double num, double den) {
+                pn *= num;
+                pd *= den;
+                if (++c == 8) {
+                    prod *= pn / pd;
+                    pn = 1.0;
+                    pd = 1.0;
+                    c = 0;
+                }
+            };
+            // k < i0: every lane has k < i
+            const int e1 = min(b, i0);
+            for (int k = a; k < e1; ++k) factor((D[og[k]] - di) + ta[k], D[k] - di);
+            // window: k in [i0, ilast]
+            const int s2 = max(a, i0), e2 = min(b, ilast + 1);
+            for (int k = s2; k < e2; ++k) {
+                const double num = (D[og[k]] - di) + ta[k];
+                const double den = (k < i) ? D[k] - di : ((k < K - 1) ? D[k + 1] - di : 1.0);
+                factor(num, den);
+            }
+            // ilast < k < K-1: every lane has i <= k
+            const int e3 = min(b, K - 1);
+            for (int k = max(a, ilast + 1); k < e3; ++k) factor((D[og[k]] - di) + ta[k], D[k + 1] - di);
+            if (b == K && ilast + 1 <= K - 1) factor((D[og[K - 1]] - di) + ta[K - 1], 1.0);
+            prod *= pn / pd;
+            red[wv * 64 + lane] = prod;
+            __syncthreads();
+            if (wv == 0 && i0 + lane < K) {
+                double p = 1.0;
+                for (int v = 0; v < kWideWaves; ++v) p *= red[v * 64 + lane];
+                double sgn;
+                const double rho = merge_rho(R, e, pmax, &sgn);
+                const double zi = sqrt(fmax(p / rho, 0.0));
+                w.zhat[ks + i] = (w.Za[ks + i] < 0.0) ? -zi : zi;
+                if (!(R.flags & MF_ROOT)) pairs += (unsigned long long)K;
+            }
+        }
+        __syncthreads();
+    }
+    if (wv == 0) count_add(&w.counters[CNT_LOW_PAIRS], pairs);
+}
+
+// Wide boundary-row step (non-top merges): 64 roots per workgroup, the poles
+// split over the waves, pole index wave-uniform (scalar loads of D_i, zhat_i
+// and both row entries); no pole is excluded, so there is no window.
+// red: 3 x kWideWaves x 64 doubles.
+__device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const Work& w, double* red) {
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform((int)(threadIdx.x >> 6));
+    const int total = w.witems[M];
+    unsigned long long pairs = 0;
+    for (int item = bid; item < total; item += nbw) {
+        const int m = wide_merge_of(w.witems, M, item);
+        const MergeRec R = mr[m];
+        if (!(R.flags & MF_ROOT)) {
+            const MergeSpan sp = merge_span(R, w.scan);
+            const int K = wave_uniform(sp.K);
+            const long long ks = wave_uniform(sp.ks);
+            const int k0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+            cdouble* D = as_const(w.Da + ks);
+            cdouble* H = as_const(w.zhat + ks);
+            cdouble* RL = as_const(w.RLa + ks);
+            cdouble* RH = as_const(w.RHa + ks);
+            const int k = min(k0 + lane, K - 1);
+            const double Do = w.Da[ks + w.org[ks + k]], tau = w.tau[ks + k];
+            const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+            double ss = 0.0, bl = 0.0, bh = 0.0;
+            _Pragma("unroll 4") for (int i = a; i < b; ++i) {
+                const double y = H[i] * rcp_nr((D[i] - Do) - tau);
+                ss = fma(y, y, ss);
+                bl = fma(RL[i], y, bl);
+                bh = fma(RH[i], y, bh);
+            }
+            red[(0 * kWideWaves + wv) * 64 + lane] = ss;
+            red[(1 * kWideWaves + wv) * 64 + lane] = bl;
+            red[(2 * kWideWaves + wv) * 64 + lane] = bh;
+            __syncthreads();
+            if (wv == 0 && k0 + lane < K) {
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+                for (int v = 0; v < kWideWaves; ++v) {
+                    t0 += red[(0 * kWideWaves + v) * 64 + lane];
+                    t1 += red[(1 * kWideWaves + v) * 64 + lane];
+                    t2 += red[(2 * kWideWaves + v) * 64 + lane];
+                }
+                const double inv = 1.0 / sqrt(t0);
+                w.PBL[ks + k] = t1 * inv;
+                w.PBH[ks + k] = t2 * inv;
+                pairs += (unsigned long long)K;
+            }
+        }
+        __syncthreads();
+    }
+    if (wv == 0) count_add(&w.counters[CNT_ROW_PAIRS], pairs);
+}
+
+// Root-parallel kernels.  Blocks [0, nbn) take tiles of kWG / G consecutive
+// active columns of the merges below wide_min (G lanes per root); blocks from
+// nbn on run the wide sweeps.
 template <int G>
-__global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
                                                  const double* __restrict__ e,
-                                                 const unsigned long long* __restrict__ pmax, Work w) {
-    __shared__ double sD[kStage], sZ[kStage];
+                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
+                                                 int nbn) {
+    __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
+    if ((int)blockIdx.x >= nbn) {
+        secular_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, smem);
+        return;
+    }
+    double* sD = smem;
+    double* sW = smem + kStage;
     const long long total = w.scan[N];
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     int bad = 0;
     unsigned long long terms = 0, sweeps = 0, roots = 0;
-    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+    for (long long tile = blockIdx.x; tile * per < total; tile += nbn) {
         const long long g0 = tile * per;
         const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
         if (threadIdx.x == 0) {
@@ -349,17 +686,17 @@ __global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr
         if (ns >= 0)
             for (int i = threadIdx.x; i < ns; i += kWG) {
                 sD[i] = w.Da[r0 + i];
-                sZ[i] = w.Za[r0 + i];
+                sW[i] = w.Wa[r0 + i];
             }
         __syncthreads();
         const long long g = g0 + threadIdx.x / G;
-        if (g < total) {
-            const int m = w.amerge[g];
-            const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sZ, r0)
-                                     : body_secular<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.Za, 0);
+        const int mg = (g < total) ? w.amerge[g] : 0;
+        if (g < total && merge_span(mr[mg], w.scan).K < wide_min) {
+            const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, sD, sW, r0)
+                                     : body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, w.Da, w.Wa, 0);
             if (it < 0) bad = 1;
             if (sub == 0) {
-                const MergeSpan sp = merge_span(mr[m], w.scan);
+                const MergeSpan sp = merge_span(mr[mg], w.scan);
                 const unsigned long long sw = (sp.K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
                 sweeps += sw;
                 terms += sw * (unsigned long long)sp.K;
@@ -377,16 +714,23 @@ __global__ __launch_bounds__(kWG) void k_secular(const MergeRec* __restrict__ mr
 template <int G, bool WithRoot>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
-                                                const unsigned long long* __restrict__ pmax, Work w) {
-    __shared__ double sD[kStage], sT[kStage];
+                                                const unsigned long long* __restrict__ pmax, Work w, int wide_min,
+                                                int nbn) {
+    __shared__ double smem[2 * kStage];
     __shared__ int sO[kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
+    if ((int)blockIdx.x >= nbn) {
+        lowner_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, smem);
+        return;
+    }
+    double* sD = smem;
+    double* sT = smem + kStage;
     const long long total = w.scan[N];
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     unsigned long long pairs = 0;
-    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+    for (long long tile = blockIdx.x; tile * per < total; tile += nbn) {
         const long long g0 = tile * per;
         const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
         if (threadIdx.x == 0) {
@@ -405,7 +749,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
             }
         __syncthreads();
         const long long g = g0 + threadIdx.x / G;
-        if (g < total) {
+        if (g < total && merge_span(mr[w.amerge[g]], w.scan).K < wide_min) {
             const int m = w.amerge[g];
             if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0, WithRoot);
             else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0, WithRoot);
@@ -417,15 +761,24 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
 }
 
 template <int G>
-__global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w) {
-    __shared__ double sD[kStageRows], sH[kStageRows], sL[kStageRows], sR[kStageRows];
+__global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w,
+                                              int wide_min, int nbn) {
+    __shared__ double smem[4 * kStageRows];
     __shared__ long long s_r0;
     __shared__ int s_staged;
+    if ((int)blockIdx.x >= nbn) {
+        rows_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, w, smem);
+        return;
+    }
+    double* sD = smem;
+    double* sH = smem + kStageRows;
+    double* sL = smem + 2 * kStageRows;
+    double* sR = smem + 3 * kStageRows;
     const long long total = w.scan[N];
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     unsigned long long pairs = 0;
-    for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
+    for (long long tile = blockIdx.x; tile * per < total; tile += nbn) {
         const long long g0 = tile * per;
         const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
         if (threadIdx.x == 0) {
@@ -445,7 +798,7 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
             }
         __syncthreads();
         const long long g = g0 + threadIdx.x / G;
-        if (g < total) {
+        if (g < total && merge_span(mr[w.amerge[g]], w.scan).K < wide_min) {
             const int m = w.amerge[g];
             if (ns >= 0) body_rows<RedGroup<G>>(g, m, mr, w, sub, G, sD, sH, sL, sR, r0);
             else body_rows<RedGroup<G>>(g, m, mr, w, sub, G, w.Da, w.zhat, w.RLa, w.RHa, 0);
@@ -784,27 +1137,41 @@ static int lanes_per_root(int smax, int cols) {
     return G;
 }
 
-template <int G>
-static void launch_roots_g(long long N, const MergeRec* mr, int M, const double* e, const Work& w, void* stream) {
-    const long long lanes = N * G;
-    long long nb = (lanes + kWG - 1) / kWG;
+// Grid of a root kernel: the regular tiles plus, when the level has a merge
+// large enough, up to 4096 wide blocks.
+static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw) {
+    long long nb = (N * G + kWG - 1) / kWG;
     if (nb > 8192) nb = 8192;
     if (nb < 1) nb = 1;
-    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)nb, kWG, stream, mr, M, N, e,
-                 (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), (unsigned)nb, kWG, stream, mr, M, N, e,
-                 (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, (unsigned)nb, kWG, stream, mr, M, N, w);
+    long long wb = wide ? (N + 63) / 64 : 0;
+    if (wb > 4096) wb = 4096;
+    *nbn = (int)nb;
+    *nbw = (int)wb;
 }
 
-static void launch_roots(int smax, int cols, long long N, const MergeRec* mr, int M, const double* e,
+template <int G>
+static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
+                           const Work& w, void* stream) {
+    const bool wide = smax >= wmin;
+    const int wide_min = wide ? wmin : 0x7fffffff;
+    int nbn, nbw;
+    root_grid(N, G, wide, &nbn, &nbw);
+    const unsigned grid = (unsigned)(nbn + nbw);
+    const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    if (wide) TDE_LAUNCH_K(KIND_SECULAR, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
+    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
+    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
+    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, nbn);
+}
+
+static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
                          const Work& w, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(N, mr, M, e, w, stream); break;
-        case 2: launch_roots_g<2>(N, mr, M, e, w, stream); break;
-        case 4: launch_roots_g<4>(N, mr, M, e, w, stream); break;
-        case 8: launch_roots_g<8>(N, mr, M, e, w, stream); break;
-        default: launch_roots_g<16>(N, mr, M, e, w, stream); break;
+        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, stream); break;
+        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, stream); break;
+        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, stream); break;
+        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, stream); break;
+        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, stream); break;
     }
 }
 
@@ -862,7 +1229,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         }
         TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
         enqueue_deflate(mr, blkm, N, e, wl, stream);
-        launch_roots(L.smax, p.sweep_cols, N, mr, M, e, wl, stream);
+        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
     }
@@ -870,15 +1237,18 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
 }
 
 template <int G>
-static void launch_bwd_roots_g(long long N, const MergeRec* mr, int M, const double* e, const Work& w,
-                               const Grad& gr, long long cs, void* stream) {
-    long long nb = (N * G + kWG - 1) / kWG;
-    if (nb > 8192) nb = 8192;
-    if (nb < 1) nb = 1;
-    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)nb, kWG, stream, mr, M, N, e,
-                 (const unsigned long long*)w.pmax, w);
-    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nb, kWG, stream, mr, N, w, gr, cs);
-    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nb, kWG, stream, mr, N, w, gr, cs);
+static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
+                               const Work& w, const Grad& gr, long long cs, void* stream) {
+    const bool wide = smax >= wmin;
+    const int wide_min = wide ? wmin : 0x7fffffff;
+    int nbn, nbw;
+    root_grid(N, G, wide, &nbn, &nbw);
+    const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    if (wide) TDE_LAUNCH_K(KIND_BACKWARD, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
+    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
+                 nbn);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
 }
 
 int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
@@ -912,11 +1282,11 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
         enqueue_deflate(mr, blkm, N, e, wl, stream);
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
-            case 1: launch_bwd_roots_g<1>(N, mr, M, e, wl, gr, cs, stream); break;
-            case 2: launch_bwd_roots_g<2>(N, mr, M, e, wl, gr, cs, stream); break;
-            case 4: launch_bwd_roots_g<4>(N, mr, M, e, wl, gr, cs, stream); break;
-            case 8: launch_bwd_roots_g<8>(N, mr, M, e, wl, gr, cs, stream); break;
-            default: launch_bwd_roots_g<16>(N, mr, M, e, wl, gr, cs, stream); break;
+            case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
+            case 2: launch_bwd_roots_g<2>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
+            case 4: launch_bwd_roots_g<4>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
+            case 8: launch_bwd_roots_g<8>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
+            default: launch_bwd_roots_g<16>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
         }
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl, nb, kWG, stream, mr, blkm, N, wl, gr, cs);
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_grho, (unsigned)M, kWG, stream, mr, e, (const unsigned long long*)w.pmax, wl,
@@ -988,9 +1358,11 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.cf = (int*)take(4 * nn);
     t.Da = (double*)take(8 * nn);
     t.Za = (double*)take(8 * nn);
+    t.Wa = (double*)take(8 * nn);
     t.RLa = (double*)take(8 * nn);
     t.RHa = (double*)take(8 * nn);
     t.amerge = (int*)take(4 * nn);
+    t.witems = (int*)take(4 * (nn + 2));
     t.apos = (int*)take(4 * nn);
     t.rpos = (int*)take(4 * nn);
     t.dpos = (int*)take(4 * nn);

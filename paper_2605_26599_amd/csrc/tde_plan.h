@@ -24,6 +24,7 @@ struct Plan {
     int B = 0;
     int leaf = 32;
     int sweep_cols = 8;  // target poles per lane in the root-parallel sweeps
+    int wide_min = kWideMin;  // merges with at least this many active roots use the wide secular sweep
     int nleaves = 0;
     int leafmax = 1;     // largest leaf size in the plan
     int maxM = 1;        // most merges in one level

@@ -251,6 +251,18 @@ def test_backward_graph_replays_match_eager(tde):
             assert junk.numel() == n // 3
 
 
+def test_grad_through_wide_sweep(tde):
+    """Roots found by the wide secular sweep feed the same reverse pass."""
+    for fam, n in [("uniform", 3000), ("toeplitz", 2000), ("clustered", 1500)]:
+        _step(f"wide_min=2 fam={fam} n={n}")
+        d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_GRAD)
+        w = tdgen.loss_weights(n)
+        dv, ev = _t(d), _t(e)
+        lam, ck = tde.eigvals_ckpt(dv, ev, wide_min=2)
+        gd, ge = tde.eigvals_backward(dv, ev, _t(w), ck, wide_min=2)
+        _check_hf(d, e, w, lam.cpu().numpy(), gd.cpu().numpy(), ge.cpu().numpy()[: n - 1])
+
+
 def test_backward_lanes_per_root_variants(tde):
     for cols in [1, 4, 64]:
         for fam, n in [("uniform", 4000), ("toeplitz", 2000)]:

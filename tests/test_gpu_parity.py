@@ -235,3 +235,36 @@ def test_lanes_per_root_variants(tde, cols):
         lam = lam.cpu().numpy()
         ref = oracle.eigvals(d, e)
         assert np.abs(lam - ref).max() <= GATE * tdgen.tnorm1(d, e)
+
+
+# --- wide secular sweep (64 roots per workgroup, poles split over waves) ----
+
+@pytest.mark.parametrize("wide_min", [2, 64])
+def test_wide_secular_sweep(tde, wide_min):
+    """Every merge with at least wide_min active roots solved by the wide
+    sweep (wide_min = 2: all of them) meets the gate on every family."""
+    import torch
+
+    for fam in ["uniform", "normal", "toeplitz", "wilkinson", "clustered", "paper_clustered"]:
+        for n in [2, 3, 5, 33, 64, 65, 129, 200, 1000, 4097]:
+            _step(f"wide_min={wide_min} fam={fam} n={n}")
+            d, e = tdgen.tridiag(fam, n)
+            lam = tde.eigvals(torch.from_numpy(d).to(_dev()), torch.from_numpy(e).to(_dev()), wide_min=wide_min)
+            lam = lam.cpu().numpy()
+            assert np.all(np.diff(lam) >= 0)
+            assert np.abs(lam - oracle.eigvals(d, e)).max() <= GATE * tdgen.tnorm1(d, e)
+
+
+def test_wide_secular_sweep_batched(tde):
+    import torch
+
+    _step("wide_min=2 batched mixed sizes")
+    sizes = [0, 1, 2, 3, 70, 500, 64, 1025]
+    probs = [tdgen.tridiag("uniform", s, inst=i) for i, s in enumerate(sizes)]
+    bt = tdgen.pack(probs)
+    lam = tde.eigvals_batched(torch.from_numpy(bt.d).to(_dev()), torch.from_numpy(bt.e).to(_dev()),
+                              bt.offsets, wide_min=2).cpu().numpy()
+    for b, (d, e) in enumerate(probs):
+        s, t = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        if t > s:
+            assert np.abs(lam[s:t] - oracle.eigvals(d, e)).max() <= GATE * tdgen.tnorm1(d, e)
