@@ -53,14 +53,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, run one plain device-to-device copy of MIB MiB (a kernel of known traffic "
+                         "that hardware-counter runs use to scale FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
 def source_hash():
+    """Hash of the device code (kernels and their headers, not the host-side
+    launch code): hardware-counter figures stay valid while it is unchanged."""
     h = hashlib.sha256()
-    for f in ("tde_device.h", "tde_kernels.hip", "tde_internal.h"):
-        with open(os.path.join(ROOT, "paper_2605_26599_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2605_26599_amd", "csrc")
+    for f in ("tde_internal.h", "tde_device.h", "tde_adjoint.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "tde_kernels.hip"), "rb") as fh:
+        src = fh.read()
+    h.update(src.split(b"// Optional per-kernel timing")[0])
     return h.hexdigest()[:16]
 
 
@@ -319,6 +328,14 @@ def main():
         "work_counters_per_step": cnt,
         "wall_s": wall,
     }
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["calibration_copy_bytes"] = int(src.numel() * 8)
+        del src, dst
     if not args.no_cpu and dn is not None:
         rec["cpu_baseline"] = cpu_baseline(dn, en, args.cpu_seconds)
     sec = {}

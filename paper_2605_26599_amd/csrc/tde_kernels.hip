@@ -1158,7 +1158,7 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     root_grid(N, G, wide, &nbn, &nbw);
     const unsigned grid = (unsigned)(nbn + nbw);
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
-    if (wide) TDE_LAUNCH_K(KIND_SECULAR, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
+    if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, nbn);

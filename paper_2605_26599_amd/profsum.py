@@ -1,0 +1,118 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2605_26599_amd.profsum stats  <kernel_stats.csv> <bench.jsonl> <out.md> <title> <command>
+  python -m paper_2605_26599_amd.profsum traffic <fetch_counter.csv> <write_counter.csv> <copy_bytes> <out.json> <out.md> <command>
+
+`stats` folds the per-instance kernel statistics of a `--kernel-trace --stats`
+run into per-kernel totals and sets them beside the live HIP-event timing of
+the same bench.py line.  `traffic` turns two `--pmc` runs (FETCH_SIZE, then
+WRITE_SIZE; KiB per dispatch) into HBM bytes per launch for each kernel
+family, scaled by the same counters' reading for a plain device copy of
+known size (bench.py --calibrate-copy), and records the hash of the kernel
+sources so bench.py reports the figure only while the kernels are unchanged.
+"""
+import csv
+import json
+import re
+import sys
+from collections import defaultdict
+
+
+def _family(name: str) -> str:
+    short = re.sub(r"\(.*", "", name).replace("void ", "").replace("tde::", "").strip()
+    return re.sub(r"<.*>", "", short)
+
+
+def stats(stats_csv, bench_jsonl, out_md, title, cmd):
+    rows = list(csv.DictReader(open(stats_csv)))
+    agg = {}
+    for r in rows:
+        a = agg.setdefault(_family(r["Name"]), [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    tot = sum(v[1] for v in agg.values())
+    lines = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "", "```", cmd, "```", "",
+             "Per-kernel totals over the whole profiled run (all template instances of a kernel summed):", "",
+             "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {k} | {c} | {t / 1e6:.3f} | {t / c / 1e3:.2f} | {100 * t / tot:.1f}% |")
+    lines += ["", "Instances as reported by rocprofv3 (`--stats`):", "",
+              "| name | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
+        short = re.sub(r"\(.*", "", r["Name"]).replace("void ", "").replace("tde::", "")
+        lines.append(f"| {short} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    b = json.loads([ln for ln in open(bench_jsonl) if ln.startswith("{")][-1])
+    rf = b.get("roofline")
+    if rf:
+        fam = agg.get(rf["kernel"])
+        lines += ["", "The same workload as measured live by bench.py (HIP events, instrumented timed region):", "",
+                  f"- ms per solve (un-instrumented timed region): {b['ms_per_step']:.3f}",
+                  f"- dominant kernel: {rf['kernel']}, {rf['launches']} launches, "
+                  f"average {rf['avg_launch_us']:.2f} us per launch",
+                  (f"- rocprofv3 average for the same kernel family: {fam[1] / fam[0] / 1e3:.2f} us per launch"
+                   if fam else "- (kernel family not in this trace)"),
+                  f"- achieved {rf['achieved']:.4g} {rf['unit']} of {rf['peak']} "
+                  f"({100 * rf['frac']:.2f}% of peak, bound: {rf['bound']})"]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter(path, counter):
+    """Per-dispatch counter values (KiB) by kernel family."""
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        vals[_family(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
+    import os
+
+    f = _counter(fetch_csv, "FETCH_SIZE")
+    w = _counter(write_csv, "WRITE_SIZE")
+    copy_bytes = float(copy_bytes)
+    copy_names = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
+    # the calibration copy is the largest-fetch copy dispatch
+    best = max(((max(f[k]), k) for k in copy_names), default=None)
+    if best is None:
+        raise SystemExit("no copy kernel in the counter run")
+    ck = best[1]
+    kf = copy_bytes / (max(f[ck]) * 1024.0)
+    kw = copy_bytes / (max(w[ck]) * 1024.0) if ck in w and max(w[ck]) > 0 else 1.0
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.dirname(here))
+    import bench
+
+    rec = {"calibration": {"kernel": ck, "copy_bytes": copy_bytes, "fetch_scale": kf, "write_scale": kw}}
+    lines = ["# HBM traffic per launch (rocprofv3 hardware counters)", "", "Commands (repository root, one MI355X):",
+             "", "```", cmd, "```", "",
+             f"Calibration: one plain device copy of {copy_bytes / 2**20:.0f} MiB ({ck}); "
+             f"scale factors fetch {kf:.4f}, write {kw:.4f} (known bytes / counter bytes).", "",
+             "| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) |",
+             "|---|---|---|---|---|"]
+    kinds = {"k_secular": "secular", "k_lowner": "lowner", "k_rows": "rows", "k_leaf": "leaf",
+             "k_merge": "merge", "k_assemble": "assemble"}
+    for k in sorted(f, key=lambda k: -sum(f[k])):
+        if k == ck:
+            continue
+        fm = sum(f[k]) / len(f[k])
+        wm = (sum(w[k]) / len(w[k])) if k in w and w[k] else 0.0
+        b = fm * 1024 * kf + wm * 1024 * kw
+        lines.append(f"| {k} | {len(f[k])} | {fm:.1f} | {wm:.1f} | {b:.4g} |")
+        if k in kinds:
+            rec[kinds[k]] = {"kernel": k, "bytes_per_launch": b, "source_hash": bench.source_hash()}
+    json.dump(rec, open(out_json, "w"), indent=1)
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:7])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:8])
+    else:
+        raise SystemExit(__doc__)
