@@ -71,7 +71,7 @@ typedef struct {
 int tde_version(void);
 
 /* Bytes of device workspace needed to solve B problems with n_total columns in
- * total (n_total = n for a single problem).  Linear in n_total (about 200 bytes
+ * total (n_total = n for a single problem).  Linear in n_total (about 260 bytes
  * per column).  Returns 0 on a bad argument. */
 size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts);
 
@@ -114,7 +114,7 @@ int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets
  *
  * tde_checkpoint_bytes: device bytes of the checkpoint, about 36 bytes per
  * column per tree level (ceil(log2(n / leaf)) levels).  0 on a bad argument.
- * tde_backward_workspace_bytes: workspace of tde_eigvals_backward (about 480
+ * tde_backward_workspace_bytes: workspace of tde_eigvals_backward (about 545
  * bytes per column), a superset of the forward's.  0 on a bad argument.
  *
  * tde_eigvals_ckpt: as tde_eigvals_batched, and also records in ckpt

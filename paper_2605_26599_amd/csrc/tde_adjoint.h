@@ -294,7 +294,7 @@ TDE_DEV void body_bwd_runs(long long g, int m, const MergeRec* __restrict__ mr, 
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
     const long long gs = w.scanC[R.pk], ge = w.scanC[R.pk + s];
-    const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
+    const double tol = merge_tol(w.D, R.pk, s);
     const bool cl_next = (g + 1 < ge) && cand_close(w, g, g + 1, tol);
     const bool cl_prev = (g > gs) && cand_close(w, g - 1, g, tol);
     if (cl_prev) return;

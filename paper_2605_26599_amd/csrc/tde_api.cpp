@@ -141,8 +141,8 @@ int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long l
     }
     p->maxM = maxM;
     p->maxN = maxN;
-    p->zmax_total = std::max<long long>(1, (long long)flat.size());
     p->nmerges = (int)flat.size();
+    if ((int)p->levels.size() > kMaxLevels) return TDE_EINVAL;
     p->nleaves = (int)t.leaves.size();
     int lmax = 1;
     for (auto& L : t.leaves) lmax = std::max(lmax, L.size);
@@ -241,7 +241,7 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
     int rc = get_plan(opts, offs, &plan);
     if (rc != TDE_OK) return rc;
     Work w{};
-    workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
+    workspace_layout(ntot, B, ntot, (char*)ws, &w);
     if (!ckpt_bytes) {
         Bufs bufs{d, e, lambda, ws, nullptr, nullptr, nullptr, nullptr};
         return run_pass(*plan, PASS_SOLVE, bufs, opts, stream,
@@ -272,7 +272,7 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
     if (rc != TDE_OK) return rc;
     if (ws_bytes < fw + grad_layout(ntot, ntot, nullptr, nullptr)) return TDE_EINVAL;
     Work w{};
-    workspace_layout(ntot, B, plan->zmax_total, (char*)ws, &w);
+    workspace_layout(ntot, B, ntot, (char*)ws, &w);
     Grad gr{};
     grad_layout(ntot, plan->nmerges, (char*)ws + fw, &gr);
     Ckpt ck{};

@@ -93,11 +93,13 @@ TDE_DEV double merge_rho(const MergeRec& R, const double* __restrict__ e,
     return 2.0 * fabs(beta);
 }
 
-// Deflation tolerance of a merge: 8 eps max(max|D|, max|z~|); the poles are
-// sorted so max|D| is attained at an end.
-TDE_DEV double merge_tol(const double* __restrict__ D, long long pk, int s, unsigned long long zmaxbits) {
-    double dmax = fmax(fabs(D[pk]), fabs(D[pk + s - 1]));
-    return 8.0 * DBL_EPSILON * fmax(dmax, bitsd(zmaxbits));
+// Deflation tolerance of a merge: 8 eps max(max|D|, 1).  The usual
+// 8 eps max(max|D|, max|z~|) with max|z~| replaced by its bound ||z~|| = 1, so
+// the test needs no reduction over the merge.  The poles are sorted, so
+// max|D| is attained at an end.
+TDE_DEV double merge_tol(const double* __restrict__ D, long long pk, int s) {
+    const double dmax = fmax(fabs(D[pk]), fabs(D[pk + s - 1]));
+    return 8.0 * DBL_EPSILON * fmax(dmax, 1.0);
 }
 
 // Close-pole test for consecutive poles a < b (Section 4.1, deflation): the
@@ -525,13 +527,16 @@ TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __rest
 // j + #{left values <= x} (ties go left first).  Returns the packed position.
 TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr,
                              const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
-                             const Work& w, double* absz_out) {
+                             const Work& w, int* flag_out) {
     const MergeRec R = mr[m];
     const int i = (int)(t - R.pk);
     double sgn;
-    merge_rho(R, e, pmax, &sgn);
+    const double rho = merge_rho(R, e, pmax, &sgn);
     const double* lamL = w.lam + R.off;
     const double* lamR = lamL + R.nL;
+    // the same value as merge_tol on the merged poles (the ends of both sorted children)
+    const double dmax = fmax(fmax(fabs(lamL[0]), fabs(lamL[R.nL - 1])), fmax(fabs(lamR[0]), fabs(lamR[R.nR - 1])));
+    const double tol = 8.0 * DBL_EPSILON * fmax(dmax, 1.0);
     const double rs2 = 0.70710678118654752440;  // 1/sqrt(2)
     int pos;
     double x, z, rl, rh;
@@ -567,22 +572,13 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
     w.RL[P] = rl;
     w.RH[P] = rh;
     w.src[P] = i;
-    *absz_out = fabs(z);
+    // (a5) negligible-z test: the column stays a candidate iff rho~ |z~_j| > tol
+    const int flag = (rho * fabs(z) > tol) ? 1 : 0;
+    w.st[P] = flag;
+    *flag_out = flag;
     return P;
 }
 
-// (a5) negligible-z test: column stays a candidate iff rho~ |z~_j| > tol.
-TDE_DEV int body_nnflag(long long t, int m, const MergeRec* __restrict__ mr,
-                        const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
-                        const Work& w) {
-    const MergeRec R = mr[m];
-    double sgn;
-    const double rho = merge_rho(R, e, pmax, &sgn);
-    const double tol = merge_tol(w.D, R.pk, R.nL + R.nR, w.zmax[m]);
-    const int flag = (rho * fabs(w.Z[t]) > tol) ? 1 : 0;
-    w.st[t] = flag;
-    return flag;
-}
 
 
 // One step of a run: the running column *cur (left) against the next
@@ -636,7 +632,7 @@ TDE_DEV void body_runs(long long g, int m, const MergeRec* __restrict__ mr, cons
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
     const long long gs = w.scanC[R.pk], ge = w.scanC[R.pk + s];
-    const double tol = merge_tol(w.D, R.pk, s, w.zmax[m]);
+    const double tol = merge_tol(w.D, R.pk, s);
     const bool cl_next = (g + 1 < ge) && cand_close(w, g, g + 1, tol);
     const bool cl_prev = (g > gs) && cand_close(w, g - 1, g, tol);
     if (cl_prev) return;  // inside a run owned by an earlier candidate

@@ -64,6 +64,8 @@ constexpr int kDefaultSweepCols = 8;  // poles per lane per sweep when the calle
 constexpr int kSecMaxIter = 96;  // secular iteration cap
 constexpr int kWideMin = 1024;   // merges with at least this many active roots use the wide secular sweep
 constexpr int kWideWaves = 4;    // pole segments (waves) per workgroup of the wide secular sweep
+constexpr int kMaxLevels = 40;   // tree levels the per-level block counters can hold
+constexpr int kSelfScanMax = 2048;  // up to this many blocks per level, blocks sum their own count prefixes
 
 // Pointers into the caller's workspace for one solve.
 struct Work {
@@ -87,8 +89,9 @@ struct Work {
     int* scanC;                // [n+1] exclusive prefix counts of candidate (non-negligible) columns
     int* scanR;                // [n+1] exclusive prefix counts of rotated-away columns
     int* bsum;                 // [nb+1] per-block counts
-    int* bsumR;                // [nb+1] per-block counts of rotated-away columns
-    int* bsumA;                // [nb+1] per-block counts of active columns (raw)
+    int* bsumR;                // [nb+1] per-block counts of rotated-away columns (this level's slice of bcnt)
+    int* bsumA;                // [nb+1] per-block counts of active columns (raw; this level's slice of bcnt)
+    int* bcnt;                 // [kMaxLevels][2][nb+2] per-level block counts, zeroed once per pass
     int* bsumAs;               // [nb+1] exclusive scan of bsumA
     int* bsumRs;               // [nb+1] exclusive scan of bsumR
     unsigned* ticket;          // [1]   last-workgroup ticket (self-resetting)
@@ -115,7 +118,6 @@ struct Work {
     double* Dr;                // [n]   rotated-away columns: eigenvalue (ascending per merge)
     double* RLr;               // [n]
     double* RHr;               // [n]
-    unsigned long long* zmax;  // [M] bits of max |z~| per merge (this level's slice)
 };
 
 // Forward checkpoint for the reverse pass: per level h (slot stride n), the

@@ -46,6 +46,15 @@ __device__ __forceinline__ void count_add(unsigned long long* c, unsigned long l
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(c, v);
 }
 
+// Non-finite input (flagged by k_maxabs, the first kernel of a pass): every
+// later kernel of the pass returns at once.  Sorting NaNs is not a
+// permutation, so the per-level counts could not be trusted; the output is
+// undefined and the status word reports TDE_ENONFINITE.
+__device__ __forceinline__ bool input_nonfinite(const Work& w) {
+    // the bit is set by an earlier launch: a cached scalar read sees it
+    return (*(const __attribute__((address_space(4))) int*)w.status & ST_NONFINITE) != 0;
+}
+
 // Inclusive scan over the workgroup (blockDim.x <= 1024, multiple of 64).
 __device__ __forceinline__ int block_incl_scan(int v, int* wsum) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -148,6 +157,7 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
                                              const double* __restrict__ d, const double* __restrict__ e,
                                              const unsigned long long* __restrict__ pmax, Work w,
                                              double* __restrict__ out) {
+    if (input_nonfinite(w)) return;
     __shared__ double sd[LMAX * 64], se[LMAX * 64], s0[LMAX * 64], s1[LMAX * 64];
     const int lane = threadIdx.x;
     const int li = blockIdx.x * 64 + lane;
@@ -170,51 +180,61 @@ __device__ __forceinline__ int merge_of(const MergeRec* __restrict__ mr, const i
     return find_merge_in(mr, blkm[b], blkm[b + 1], t);
 }
 
+// Sum of in[0..b) over the workgroup (every thread gets it): a block's own
+// exclusive prefix of the per-block counts, when there are few blocks.
+__device__ __forceinline__ int block_prefix(const int* __restrict__ in, int b, int* wsum) {
+    int v = 0;
+    for (int i = threadIdx.x; i < b; i += blockDim.x) v += in[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) wsum[wid] = v;
+    __syncthreads();
+    int t = 0;
+    for (int i = 0; i < nw; ++i) t += wsum[i];
+    __syncthreads();
+    return t;
+}
+
+// Merged order, z~, outer rows and the negligible-z flag of every column;
+// candidates are counted per block of merged positions (bsumA, zeroed once
+// per pass), one atomic per distinct block among a wave's columns.
 __global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                long long N, const double* __restrict__ e,
                                                const unsigned long long* __restrict__ pmax, Work w) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    int m = -1;
-    double az = 0.0;
-    if (t < N) {
-        m = merge_of(mr, blkm, t);
-        body_merge(t, m, mr, e, pmax, w, &az);
-    }
+    int f = 0, pb = -1;
+    if (t < N) pb = (int)(body_merge(t, merge_of(mr, blkm, t), mr, e, pmax, w, &f) / kWG);
     count_add(&w.counters[CNT_MERGE_COLS], t < N ? 1ULL : 0ULL);
-    unsigned long long v = dbits(az);
-    const int m0 = __shfl(m, 0, 64);
-    if (__all(m == m0) && m0 >= 0) {
-        v = wave_max_u64(v);
-        if ((threadIdx.x & 63) == 0) atomicMax(&w.zmax[m0], v);
-    } else if (m >= 0) {
-        atomicMax(&w.zmax[m], v);
+    // one atomic per distinct position block among the wave's columns
+    const int lane = threadIdx.x & 63;
+    bool pending = pb >= 0;
+    for (;;) {
+        const unsigned long long pm = __ballot(pending);
+        if (pm == 0ULL) break;
+        const int leader = __ffsll((long long)pm) - 1;
+        const int lpb = __shfl(pb, leader, 64);
+        const bool mine = pending && (pb == lpb);
+        const unsigned long long fm = __ballot(mine && f);
+        if (lane == leader && fm) atomicAdd(&w.bsumA[lpb], (int)__popcll(fm));
+        pending = pending && !mine;
     }
 }
 
-// Negligible-z flags; per-block candidate counts into bsumA.
-__global__ __launch_bounds__(kWG) void k_nnflag(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
-                                                long long N, const double* __restrict__ e,
-                                                const unsigned long long* __restrict__ pmax, Work w) {
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    int f = 0;
-    if (t < N) f = body_nnflag(t, merge_of(mr, blkm, t), mr, e, pmax, w);
-    const int c = __syncthreads_count(f);
-    if (threadIdx.x == 0) w.bsumA[blockIdx.x] = c;
-}
-
-// Compaction of candidate (st == 1) columns: scan[t] = exclusive count,
-// nnpos[g] = t for the g-th candidate.  Also clears this block's count of
-// rotated-away columns.
-__global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
+// Compaction of candidate (st == 1) columns: scanC[t] = exclusive count,
+// nnpos[g] = t for the g-th candidate.  The block's base is its own prefix of
+// the block counts (selfscan) or the scanned counts in bsum.
+__global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w, int selfscan) {
+    if (input_nonfinite(w)) return;
     __shared__ int wsum[16];
+    const int base = selfscan ? block_prefix(w.bsumA, blockIdx.x, wsum) : w.bsum[blockIdx.x];
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int f = (t < N) ? (w.st[t] == 1) : 0;
     const int incl = block_incl_scan(f, wsum);
-    const int g = w.bsum[blockIdx.x] + incl - f;
-    if (threadIdx.x == 0) w.bsumR[blockIdx.x] = 0;
+    const int g = base + incl - f;
     if (t < N) {
         w.scanC[t] = g;
-        if (f) w.nnpos[g] = (int)t;
+        if (f && g < N) w.nnpos[g] = (int)t;
         if (t == N - 1) w.scanC[N] = g + f;
     }
 }
@@ -223,7 +243,8 @@ __global__ __launch_bounds__(kWG) void k_nncompact(long long N, Work w) {
 // column moves one count from its block's active tally to its rotated tally.
 __global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                               long long N, Work w) {
-    const long long total = w.scanC[N];
+    if (input_nonfinite(w)) return;
+    const long long total = min((long long)w.scanC[N], N);
     int* bA = w.bsumA;
     int* bR = w.bsumR;
     auto on_rotate = [bA, bR](long long p) {
@@ -241,8 +262,17 @@ __global__ __launch_bounds__(kWG) void k_runs(const MergeRec* __restrict__ mr, c
 // exclusive active / rotated counts.  Candidates read their post-rotation
 // values (D2, ...), negligible columns the merged ones (D, ...).
 __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
-                                                    long long N, Work w) {
+                                                    long long N, Work w, int selfscan) {
+    if (input_nonfinite(w)) return;
     __shared__ int wsum[16];
+    int baseA, baseR;
+    if (selfscan) {
+        baseA = block_prefix(w.bsumA, blockIdx.x, wsum);
+        baseR = block_prefix(w.bsumR, blockIdx.x, wsum);
+    } else {
+        baseA = w.bsumAs[blockIdx.x];
+        baseR = w.bsumRs[blockIdx.x];
+    }
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int s = (t < N) ? w.st[t] : 0;
     const int fa = (t < N) && (s == 1);
@@ -250,12 +280,12 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
     const int ia = block_incl_scan(fa, wsum);
     __syncthreads();
     const int ir = block_incl_scan(fr, wsum);
-    const int g = w.bsumAs[blockIdx.x] + ia - fa;
-    const int gr = w.bsumRs[blockIdx.x] + ir - fr;
+    const int g = baseA + ia - fa;
+    const int gr = baseR + ir - fr;
     if (t < N) {
         w.scan[t] = g;
         w.scanR[t] = gr;
-        if (fa) {
+        if (fa && g < N) {
             w.Da[g] = w.D2[t];
             w.Za[g] = w.Z2[t];
             w.Wa[g] = w.Z2[t] * w.Z2[t];
@@ -263,12 +293,12 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
             w.RHa[g] = w.RH2[t];
             w.amerge[g] = merge_of(mr, blkm, t);
             w.apos[g] = (int)t;
-        } else if (fr) {
+        } else if (fr && gr < N) {
             w.Dr[gr] = w.D2[t];
             w.RLr[gr] = w.RL2[t];
             w.RHr[gr] = w.RH2[t];
             w.rpos[gr] = (int)t;
-        } else {
+        } else if (!fa && !fr && t - g - gr >= 0 && t - g - gr < N) {
             const long long q = t - g - gr;
             w.Dd[q] = w.D[t];
             w.RLd[q] = w.RL[t];
@@ -334,13 +364,15 @@ __device__ __forceinline__ TileWindow tile_window(long long g0, long long g1, co
 // block's own roots needs per-lane selects.  The waves' partial results meet
 // in LDS in a fixed order, so every wave holds the same totals bit for bit.
 // The wide blocks are the trailing blocks of the regular root kernels'
-// grids (block-uniform split), so no extra launch is needed; the work items
-// (64-root blocks of the wide merges) are listed by k_wide_items.
+// grids (block-uniform split); the work items (64-root blocks of the wide
+// merges) are listed once per level by k_wide_items.
 // ---------------------------------------------------------------------------
 static_assert(64 * kWideWaves == kWG, "wide blocks share the regular kernels' workgroup size");
+static_assert(2 * 5 * kWideWaves * 64 <= 2 * 2048, "wide reduction buffers fit the regular kernels' LDS staging area");
 
 // Exclusive scan of the number of 64-root blocks of every wide merge of a level.
 __global__ __launch_bounds__(1024) void k_wide_items(const MergeRec* __restrict__ mr, int M, Work w, int wide_min) {
+    if (input_nonfinite(w)) return;
     __shared__ int wsum[16];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -373,7 +405,7 @@ __device__ __forceinline__ long long wave_uniform(long long v) {
 }
 
 // Merge owning wide item `item` (largest m with witems[m] <= item), uniform.
-__device__ __forceinline__ int wide_merge_of(const int* __restrict__ witems, int M, int item) {
+__device__ __forceinline__ int wide_merge_of(const int* witems, int M, int item) {
     int lo = 0, hi = M - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -435,21 +467,22 @@ __device__ __forceinline__ void wide_sweep(cdouble* D, cdouble* W, int a, int b,
 // Wide secular roots.  red: 2 x 5 x kWideWaves x 64 doubles of LDS.  The
 // block iterates until all of its 64 roots have converged.
 __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                             const unsigned long long* __restrict__ pmax, const Work& w, double* red) {
+                             const unsigned long long* __restrict__ pmax, const Work& w, const int* items,
+                             double* red) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform((int)(threadIdx.x >> 6));
     auto R5 = [&](int buf, int q, int v) -> double& { return red[((buf * 5 + q) * kWideWaves + v) * 64 + lane]; };
-    const int total = w.witems[M];
+    const int total = items[M];
     int buf = 0;
     int bad = 0;
     unsigned long long terms = 0, sweeps = 0, roots = 0;
     for (int item = bid; item < total; item += nbw) {
-        const int m = wide_merge_of(w.witems, M, item);
+        const int m = wide_merge_of(items, M, item);
         const MergeRec R = mr[m];
         const MergeSpan sp = merge_span(R, w.scan);
         const int K = wave_uniform(sp.K);
         const long long ks = wave_uniform(sp.ks);
-        const int k0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+        const int k0 = __builtin_amdgcn_readfirstlane((item - items[m]) * 64);
         const double* D = w.Da + ks;
         const double* Z = w.Za + ks;
         cdouble* Dc = as_const(D);
@@ -533,19 +566,20 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
 // loads).  Factors are multiplied in chunks of 8 numerators and 8
 // denominators, one division per chunk.  red: kWideWaves x 64 doubles.
 __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
-                            const unsigned long long* __restrict__ pmax, const Work& w, bool with_root, double* red) {
+                            const unsigned long long* __restrict__ pmax, const Work& w, bool with_root,
+                            const int* items, double* red) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform((int)(threadIdx.x >> 6));
-    const int total = w.witems[M];
+    const int total = items[M];
     unsigned long long pairs = 0;
     for (int item = bid; item < total; item += nbw) {
-        const int m = wide_merge_of(w.witems, M, item);
+        const int m = wide_merge_of(items, M, item);
         const MergeRec R = mr[m];
         if (!(R.flags & MF_ROOT) || with_root) {
             const MergeSpan sp = merge_span(R, w.scan);
             const int K = wave_uniform(sp.K);
             const long long ks = wave_uniform(sp.ks);
-            const int i0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+            const int i0 = __builtin_amdgcn_readfirstlane((item - items[m]) * 64);
             cdouble* D = as_const(w.Da + ks);
             cint* og = as_const(w.org + ks);
             cdouble* ta = as_const(w.tau + ks);
@@ -601,19 +635,20 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
 // split over the waves, pole index wave-uniform (scalar loads of D_i, zhat_i
 // and both row entries); no pole is excluded, so there is no window.
 // red: 3 x kWideWaves x 64 doubles.
-__device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const Work& w, double* red) {
+__device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const Work& w, const int* items,
+                          double* red) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform((int)(threadIdx.x >> 6));
-    const int total = w.witems[M];
+    const int total = items[M];
     unsigned long long pairs = 0;
     for (int item = bid; item < total; item += nbw) {
-        const int m = wide_merge_of(w.witems, M, item);
+        const int m = wide_merge_of(items, M, item);
         const MergeRec R = mr[m];
         if (!(R.flags & MF_ROOT)) {
             const MergeSpan sp = merge_span(R, w.scan);
             const int K = wave_uniform(sp.K);
             const long long ks = wave_uniform(sp.ks);
-            const int k0 = __builtin_amdgcn_readfirstlane((item - w.witems[m]) * 64);
+            const int k0 = __builtin_amdgcn_readfirstlane((item - items[m]) * 64);
             cdouble* D = as_const(w.Da + ks);
             cdouble* H = as_const(w.zhat + ks);
             cdouble* RL = as_const(w.RLa + ks);
@@ -658,16 +693,18 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                  const double* __restrict__ e,
                                                  const unsigned long long* __restrict__ pmax, Work w, int wide_min,
                                                  int nbn) {
+    if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
-        secular_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, smem);
+        const int* items = w.witems;
+        secular_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, items, smem);
         return;
     }
     double* sD = smem;
     double* sW = smem + kStage;
-    const long long total = w.scan[N];
+    const long long total = min((long long)w.scan[N], N);
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     int bad = 0;
@@ -716,17 +753,19 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
                                                 int nbn) {
+    if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ int sO[kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
-        lowner_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, smem);
+        const int* items = w.witems;
+        lowner_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
         return;
     }
     double* sD = smem;
     double* sT = smem + kStage;
-    const long long total = w.scan[N];
+    const long long total = min((long long)w.scan[N], N);
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     unsigned long long pairs = 0;
@@ -763,18 +802,20 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
 template <int G>
 __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w,
                                               int wide_min, int nbn) {
+    if (input_nonfinite(w)) return;
     __shared__ double smem[4 * kStageRows];
     __shared__ long long s_r0;
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
-        rows_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, w, smem);
+        const int* items = w.witems;
+        rows_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, w, items, smem);
         return;
     }
     double* sD = smem;
     double* sH = smem + kStageRows;
     double* sL = smem + 2 * kStageRows;
     double* sR = smem + 3 * kStageRows;
-    const long long total = w.scan[N];
+    const long long total = min((long long)w.scan[N], N);
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     unsigned long long pairs = 0;
@@ -812,6 +853,7 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
 __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, const unsigned long long* __restrict__ pmax, Work w,
                                                   double* __restrict__ out) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < N) body_assemble(t, merge_of(mr, blkm, t), mr, pmax, w, out);
 }
@@ -827,6 +869,7 @@ __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ m
 __global__ __launch_bounds__(kWG) void k_ckpt_save(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                    long long N, Work w, double* __restrict__ sl,
                                                    double* __restrict__ sb, double* __restrict__ sh) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= N) return;
     const MergeRec R = mr[merge_of(mr, blkm, t)];
@@ -847,6 +890,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_init(long long n, const double* __r
 
 __global__ __launch_bounds__(kWG) void k_bwd_unassemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                         long long N, Work w, Grad gr) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < N) body_bwd_unassemble(t, merge_of(mr, blkm, t), mr, w, gr);
 }
@@ -856,10 +900,11 @@ constexpr int kStageBwd = 1024;
 template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_roots(const MergeRec* __restrict__ mr, long long N, Work w, Grad gr,
                                                    long long cstride) {
+    if (input_nonfinite(w)) return;
     __shared__ double sD[kStageBwd], sH[kStageBwd], sL[kStageBwd], sR[kStageBwd];
     __shared__ long long s_r0;
     __shared__ int s_staged;
-    const long long total = w.scan[N];
+    const long long total = min((long long)w.scan[N], N);
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
@@ -902,11 +947,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_roots(const MergeRec* __restrict__ 
 template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ mr, long long N, Work w, Grad gr,
                                                    long long cstride) {
+    if (input_nonfinite(w)) return;
     __shared__ double sD[kStageBwd], sT[kStageBwd], sA[kStageBwd], sB[kStageBwd], sC[kStageBwd], sM[kStageBwd];
     __shared__ int sO[kStageBwd];
     __shared__ long long s_r0;
     __shared__ int s_staged;
-    const long long total = w.scan[N];
+    const long long total = min((long long)w.scan[N], N);
     const int per = kWG / G;
     const int sub = threadIdx.x % G;
     for (long long tile = blockIdx.x; tile * per < total; tile += gridDim.x) {
@@ -957,6 +1003,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ 
 // dL/dz of the negligible-z columns of non-top merges.
 __global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= N || w.st[t] != 0) return;
     const MergeRec R = mr[merge_of(mr, blkm, t)];
@@ -970,6 +1017,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ m
 __global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                   const unsigned long long* __restrict__ pmax, Work w, Grad gr,
                                                   long long cstride, int mstart) {
+    if (input_nonfinite(w)) return;
     __shared__ double part[kWG / 64];
     const MergeRec R = mr[blockIdx.x];
     const MergeSpan sp = merge_span(R, w.scan);
@@ -990,6 +1038,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ m
 
 __global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
+    if (input_nonfinite(w)) return;
     const long long total = w.scanC[N];
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
          g += (long long)gridDim.x * blockDim.x)
@@ -999,6 +1048,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ m
 __global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                    long long N, const double* __restrict__ e,
                                                    const unsigned long long* __restrict__ pmax, Work w, Grad gr) {
+    if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < N) body_bwd_merge(t, merge_of(mr, blkm, t), mr, e, pmax, w, gr);
 }
@@ -1011,6 +1061,7 @@ __global__ __launch_bounds__(64) void k_bwd_leaf(const LeafRec* __restrict__ lea
                                                  const double* __restrict__ d, const double* __restrict__ e,
                                                  const unsigned long long* __restrict__ pmax, Work w, Grad gr,
                                                  double* __restrict__ gd, double* __restrict__ ge) {
+    if (input_nonfinite(w)) return;
     constexpr int P = 64 / LMAX;
     __shared__ double sd[LMAX * 64], se[LMAX * 64];
     __shared__ double sQ[P * LMAX * LMAX], sX[P * LMAX * LMAX], sL[64];
@@ -1158,6 +1209,7 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     root_grid(N, G, wide, &nbn, &nbw);
     const unsigned grid = (unsigned)(nbn + nbw);
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    // one k_wide_items launch serves the three root kernels of the level
     if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
@@ -1177,19 +1229,31 @@ static void launch_roots(int smax, int cols, int wmin, long long N, const MergeR
 
 // Deflation steps of one level (shared by the forward and the reverse pass):
 // negligible-z flags, candidate compaction, close-pole runs, three-way split.
-static void enqueue_deflate(const MergeRec* mr, const int* blkm, long long N, const double* e, const Work& wl,
-                            void* stream) {
+static void enqueue_deflate(const MergeRec* mr, const int* blkm, long long N, const Work& wl, void* stream) {
     const unsigned nb = nblk(N, kWG);
     const unsigned gstride = nb < 4096u ? nb : 4096u;
-    TDE_LAUNCH(k_nnflag, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)wl.pmax, wl);
-    TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsum, (const int*)nullptr, (int*)nullptr,
-               (int)nb);
-    TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, wl);
+    const int selfscan = (nb <= (unsigned)kSelfScanMax) ? 1 : 0;
+    if (!selfscan)
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsum, (const int*)nullptr, (int*)nullptr,
+                   (int)nb);
+    TDE_LAUNCH(k_nncompact, nb, kWG, stream, N, wl, selfscan);
     TDE_LAUNCH(k_runs, gstride, kWG, stream, mr, blkm, N, wl);
-    TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsumAs, (const int*)wl.bsumR, wl.bsumRs,
-               (int)nb);
-    TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, blkm, N, wl);
+    if (!selfscan)
+        TDE_LAUNCH(k_scan_blocks, 1, 1024, stream, (const int*)wl.bsumA, wl.bsumAs, (const int*)wl.bsumR, wl.bsumRs,
+                   (int)nb);
+    TDE_LAUNCH(k_actcompact, nb, kWG, stream, mr, blkm, N, wl, selfscan);
 }
+
+// This level's slice of the per-level block counters.
+static Work level_work(const Work& w, long long ntot, size_t h) {
+    const long long nbs = (ntot + kWG - 1) / kWG + 2;
+    Work wl = w;
+    wl.bsumA = w.bcnt + (long long)h * 2 * nbs;
+    wl.bsumR = wl.bsumA + nbs;
+    return wl;
+}
+
+static long long bcnt_entries(const Plan& p) { return (long long)p.levels.size() * 2 * ((p.ntot + kWG - 1) / kWG + 2); }
 
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck) {
@@ -1210,7 +1274,8 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         else
             TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
     }
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.zmax_total, kWG), kWG, stream, w.zmax, p.zmax_total, 0ULL);
+    if (!p.levels.empty())
+        TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, nblk(bcnt_entries(p), kWG), kWG, stream, w.bcnt, bcnt_entries(p), 0);
     for (size_t h = 0; h < p.levels.size(); ++h) {
         const LevelInfo& L = p.levels[h];
         const MergeRec* mr = p.d_merges + L.mstart;
@@ -1218,8 +1283,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         const int M = L.M;
         const long long N = L.N;
         const unsigned nb = nblk(N, kWG);
-        Work wl = w;
-        wl.zmax = w.zmax + L.mstart;
+        Work wl = level_work(w, p.ntot, h);
         if (ck) {
             const long long so = (long long)h * ck->n;
             TDE_LAUNCH_K(KIND_SETUP, k_ckpt_save, nb, kWG, stream, mr, blkm, N, w, ck->lam + so, ck->blo + so,
@@ -1228,7 +1292,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             wl.tau = ck->tau + so;
         }
         TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
-        enqueue_deflate(mr, blkm, N, e, wl, stream);
+        enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
@@ -1260,7 +1324,8 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.zmax_total, kWG), kWG, stream, w.zmax, p.zmax_total, 0ULL);
+    if (!p.levels.empty())
+        TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, nblk(bcnt_entries(p), kWG), kWG, stream, w.bcnt, bcnt_entries(p), 0);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_init, nblk(p.ntot, kWG), kWG, stream, p.ntot, gin, gr);
     for (size_t hh = p.levels.size(); hh-- > 0;) {
         const LevelInfo& L = p.levels[hh];
@@ -1271,15 +1336,14 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
         const unsigned nb = nblk(N, kWG);
         const unsigned gstride = nb < 4096u ? nb : 4096u;
         const long long so = (long long)hh * ck.n;
-        Work wl = w;
-        wl.zmax = w.zmax + L.mstart;
+        Work wl = level_work(w, p.ntot, hh);
         wl.lam = ck.lam + so;
         wl.blo = ck.blo + so;
         wl.bhi = ck.bhi + so;
         wl.org = ck.org + so;
         wl.tau = ck.tau + so;
         TDE_LAUNCH_K(KIND_BACKWARD, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
-        enqueue_deflate(mr, blkm, N, e, wl, stream);
+        enqueue_deflate(mr, blkm, N, wl, stream);
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
             case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
@@ -1309,7 +1373,7 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
             TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<64>, (unsigned)p.nleaves, 64, stream, p.d_leaves, p.nleaves, d, e,
                          w.pmax, w, gr, gd, ge);
     }
-    if (p.zmax_total > 0 && !p.levels.empty())
+    if (p.nmerges > 0)
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_tear, nblk(p.nmerges, kWG), kWG, stream, p.d_merges, p.nmerges, e,
                      (const unsigned long long*)w.pmax, gr, ge);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_edges, nblk(p.B, kWG), kWG, stream, (const long long*)p.d_offs, p.B, ge);
@@ -1350,8 +1414,9 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.scanC = (int*)take(4 * (nn + 1));
     t.scanR = (int*)take(4 * (nn + 1));
     t.bsum = (int*)take(4 * nb);
-    t.bsumR = (int*)take(4 * nb);
-    t.bsumA = (int*)take(4 * nb);
+    t.bcnt = (int*)take(4 * (size_t)kMaxLevels * 2 * nb);
+    t.bsumA = t.bcnt;
+    t.bsumR = t.bcnt ? t.bcnt + nb : nullptr;
     t.bsumAs = (int*)take(4 * nb);
     t.bsumRs = (int*)take(4 * nb);
     t.nnpos = (int*)take(4 * nn);
@@ -1377,7 +1442,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.Dr = (double*)take(8 * nn);
     t.RLr = (double*)take(8 * nn);
     t.RHr = (double*)take(8 * nn);
-    t.zmax = (unsigned long long*)take(8 * (maxM > 0 ? maxM : 1));  // all levels' merges
+    (void)maxM;
     if (w) *w = t;
     return off;
 }

@@ -32,7 +32,6 @@ struct Plan {
     std::vector<long long> offs;  // host copy of the problem offsets [B+1]
     std::vector<LevelInfo> levels;
     // device tables owned by the plan
-    long long zmax_total = 1;  // merges over all levels (one max-|z| slot each)
     int nmerges = 0;           // merges over all levels
     MergeRec* d_merges = nullptr;
     int* d_blkm = nullptr;     // per level, per block of kWG packed columns: first merge touched
