@@ -378,10 +378,45 @@ TDE_DEV int sec_update(SecRoot* r, double rho, double psi, double dpsi, double p
     return 0;
 }
 
+// One pole sweep for a root at offset tau from pole Do: left poles j < L1 and
+// right poles j >= R0 (those in [L1, R0) are excluded); lane `sub` of a
+// group of G takes j = sub, sub + G, ...  Per pole term: r = 1/((D_j - Do) -
+// tau), t = w_j r, t r.  s[0..3] receive the group totals psi, dpsi, phi,
+// dphi and, with ZZ, s[4] the sum of the weights w_j = z_j^2.
+template <class Red, bool ZZ>
+TDE_DEV void sec_sweep(int K, const double* __restrict__ D, const double* __restrict__ W, double Do, double tau,
+                       int L1, int R0, int sub, int G, double* s) {
+    double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0, zz = 0.0;
+    _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
+        const double rr = rcp_nr((D[j] - Do) - tau);
+        const bool ex = (j >= L1) && (j < R0);
+        const double t = ex ? 0.0 : W[j] * rr;
+        const double dt = t * rr;
+        const bool left = j < L1;
+        ps += left ? t : 0.0;
+        dps += left ? dt : 0.0;
+        ph += left ? 0.0 : t;
+        dph += left ? 0.0 : dt;
+        if (ZZ) zz += W[j];
+    }
+    s[0] = Red::sum(ps);
+    s[1] = Red::sum(dps);
+    s[2] = Red::sum(ph);
+    s[3] = Red::sum(dph);
+    if (ZZ) s[4] = Red::sum(zz);
+}
+
+// The exclusion window and left/right split of a root's sweeps: the midpoint
+// sweep of an interior root excludes both bracketing poles (origin kk), an
+// iteration sweep excludes only the origin.
+TDE_DEV void sec_split(const SecRoot& r, int kk, int* L1, int* R0) {
+    *L1 = r.orgl ? kk : kk + 1;
+    *R0 = r.orgl ? kk + 1 : kk + 2;
+}
+
 // Z: the merge's z (global); D, W: views of its poles and weights z_j^2
-// (global or staged).  Per pole term: r = 1/((D_j - D_o) - tau), t = w_j r,
-// t r; the sum of |terms| needed by the stopping test is phi - psi (every
-// left term is negative, every right term positive).
+// (global or staged).  The sum of |terms| needed by the stopping test is
+// phi - psi (every left term is negative, every right term positive).
 template <class Red>
 TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const double* __restrict__ Z,
                          const double* __restrict__ W, double rho, int sub, int G, int* org_out, double* tau_out) {
@@ -392,27 +427,11 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
     }
     const int kk = (k < K - 1) ? k : K - 2;
     SecRoot r;
+    double s[5];
     if (k < K - 1) {
         // Midpoint sweep (origin kk): picks the nearer pole and seeds the first step.
-        const double dk = D[kk];
-        const double mid = 0.5 * (D[kk + 1] - dk);
-        double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
-        _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
-            const double rr = rcp_nr((D[j] - dk) - mid);
-            const bool near = (j == kk) || (j == kk + 1);
-            const double t = near ? 0.0 : W[j] * rr;
-            const double dt = t * rr;
-            const bool left = j < kk;
-            ps += left ? t : 0.0;
-            dps += left ? dt : 0.0;
-            ph += left ? 0.0 : t;
-            dph += left ? 0.0 : dt;
-        }
-        ps = Red::sum(ps);
-        dps = Red::sum(dps);
-        ph = Red::sum(ph);
-        dph = Red::sum(dph);
-        if (sec_start_interior(k, D, Z, rho, ps, dps, ph, dph, &r)) {
+        sec_sweep<Red, false>(K, D, W, D[kk], 0.5 * (D[kk + 1] - D[kk]), kk, kk + 2, sub, G, s);
+        if (sec_start_interior(k, D, Z, rho, s[0], s[1], s[2], s[3], &r)) {
             *org_out = r.o;
             *tau_out = r.tau;
             return 0;
@@ -423,32 +442,17 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
         zz = Red::sum(zz);
         sec_start_last(K, D, Z, rho, zz, &r);
     }
-    const double Do = D[r.o];
-    const int o = r.o;
     for (int it = 1; it <= kSecMaxIter; ++it) {
-        const double tau = r.tau;
-        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-        _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
-            const double rr = rcp_nr((D[j] - Do) - tau);
-            const double t = (j == o) ? 0.0 : W[j] * rr;
-            const double dt = t * rr;
-            const bool left = j <= kk;
-            psi += left ? t : 0.0;
-            dpsi += left ? dt : 0.0;
-            phi += left ? 0.0 : t;
-            dphi += left ? 0.0 : dt;
-        }
-        psi = Red::sum(psi);
-        dpsi = Red::sum(dpsi);
-        phi = Red::sum(phi);
-        dphi = Red::sum(dphi);
-        if (sec_update(&r, rho, psi, dpsi, phi, dphi, phi - psi)) {
-            *org_out = o;
+        int L1, R0;
+        sec_split(r, kk, &L1, &R0);
+        sec_sweep<Red, false>(K, D, W, D[r.o], r.tau, L1, R0, sub, G, s);
+        if (sec_update(&r, rho, s[0], s[1], s[2], s[3], s[2] - s[0])) {
+            *org_out = r.o;
             *tau_out = r.tau;
             return it;
         }
     }
-    *org_out = o;
+    *org_out = r.o;
     *tau_out = r.tau;
     return -1;
 }

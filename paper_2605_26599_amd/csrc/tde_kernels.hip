@@ -685,18 +685,32 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
     if (wv == 0) count_add(&w.counters[CNT_ROW_PAIRS], pairs);
 }
 
-// Root-parallel kernels.  Blocks [0, nbn) take tiles of kWG / G consecutive
-// active columns of the merges below wide_min (G lanes per root); blocks from
-// nbn on run the wide sweeps.
+// Root-parallel kernels.  Blocks [0, nbn) take tiles of consecutive active
+// columns of the merges below wide_min (G lanes per root); blocks from nbn on
+// run the wide sweeps.
+//
+// Secular roots converge in different numbers of sweeps, so a group of G
+// lanes does not wait for the slowest root of its wave or workgroup: each
+// tile holds kRefill roots per group, and a group takes the next unsolved
+// root of its tile (a workgroup counter in LDS) as soon as its current one
+// has converged.  Every sweep, the bracket-midpoint one included, is the same
+// sec_sweep call with per-group parameters, so groups in different phases
+// still run one instruction stream.  Which group solves which root does not
+// change any result.  The roots per group (refill, 1..4) are chosen per level
+// so that the level still has about kRefillLanes lanes: refill only pays when
+// the level has far more roots than the GPU has lanes (large batches).
+constexpr int kRefillMax = 4;
+constexpr long long kRefillLanes = 1048576;
+
 template <int G>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(const MergeRec* __restrict__ mr, int M, long long N,
-                                                 const double* __restrict__ e,
-                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
-                                                 int nbn) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(
+    const MergeRec* __restrict__ mr, int M, long long N, const double* __restrict__ e,
+    const unsigned long long* __restrict__ pmax, Work w, int wide_min, int nbn, int refill) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
+    __shared__ int s_next;
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
         secular_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, items, smem);
@@ -705,17 +719,55 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     double* sD = smem;
     double* sW = smem + kStage;
     const long long total = min((long long)w.scan[N], N);
-    const int per = kWG / G;
+    const int T = (kWG / G) * refill;
     const int sub = threadIdx.x % G;
     int bad = 0;
     unsigned long long terms = 0, sweeps = 0, roots = 0;
-    for (long long tile = blockIdx.x; tile * per < total; tile += nbn) {
-        const long long g0 = tile * per;
-        const long long g1 = (g0 + per < total ? g0 + per : total) - 1;
+    if (refill == 1) {
+        // one root per group: the plain tile loop
+        for (long long tile = blockIdx.x; tile * T < total; tile += nbn) {
+            const long long g0 = tile * T;
+            const long long g1 = (g0 + T < total ? g0 + T : total) - 1;
+            if (threadIdx.x == 0) {
+                const TileWindow tw = tile_window(g0, g1, mr, w, kStage);
+                s_r0 = tw.r0;
+                s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+            }
+            __syncthreads();
+            const long long r0 = s_r0;
+            const int ns = s_staged;
+            if (ns >= 0)
+                for (int i = threadIdx.x; i < ns; i += kWG) {
+                    sD[i] = w.Da[r0 + i];
+                    sW[i] = w.Wa[r0 + i];
+                }
+            __syncthreads();
+            const long long g = g0 + threadIdx.x / G;
+            const int mg = (g < total) ? w.amerge[g] : 0;
+            if (g < total && merge_span(mr[mg], w.scan).K < wide_min) {
+                const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, sD, sW, r0)
+                                         : body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, w.Da, w.Wa, 0);
+                if (it < 0) bad = 1;
+                if (sub == 0) {
+                    const MergeSpan sp = merge_span(mr[mg], w.scan);
+                    const unsigned long long sw =
+                        (sp.K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+                    sweeps += sw;
+                    terms += sw * (unsigned long long)sp.K;
+                    roots += 1;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (long long tile = blockIdx.x; refill > 1 && tile * T < total; tile += nbn) {
+        const long long g0 = tile * T;
+        const long long g1 = (g0 + T < total ? g0 + T : total) - 1;
         if (threadIdx.x == 0) {
             const TileWindow tw = tile_window(g0, g1, mr, w, kStage);
             s_r0 = tw.r0;
             s_staged = tw.staged ? (int)(tw.r1 - tw.r0) : -1;
+            s_next = 0;
         }
         __syncthreads();
         const long long r0 = s_r0;
@@ -726,18 +778,88 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                 sW[i] = w.Wa[r0 + i];
             }
         __syncthreads();
-        const long long g = g0 + threadIdx.x / G;
-        const int mg = (g < total) ? w.amerge[g] : 0;
-        if (g < total && merge_span(mr[mg], w.scan).K < wide_min) {
-            const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, sD, sW, r0)
-                                     : body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, w.Da, w.Wa, 0);
-            if (it < 0) bad = 1;
-            if (sub == 0) {
-                const MergeSpan sp = merge_span(mr[mg], w.scan);
-                const unsigned long long sw = (sp.K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
-                sweeps += sw;
-                terms += sw * (unsigned long long)sp.K;
-                roots += 1;
+        // per-group state (every lane of a group holds the same copy)
+        long long g = -1, ks = 0;
+        int k = 0, K = 0, kk = 0, it = 0, phase = 0;
+        double rho = 0.0;
+        const double* Dv = nullptr;
+        const double* Wv = nullptr;
+        const double* Zg = nullptr;
+        SecRoot r{};
+        for (;;) {
+            if (g < 0) {
+                int slot = 0;
+                if (sub == 0) slot = atomicAdd(&s_next, 1);
+                slot = __shfl(slot, 0, G);
+                if (g0 + slot > g1) break;
+                g = g0 + slot;
+                const MergeRec R = mr[w.amerge[g]];
+                const MergeSpan sp = merge_span(R, w.scan);
+                if (sp.K >= wide_min) {  // solved by the wide blocks
+                    g = -1;
+                    continue;
+                }
+                K = sp.K;
+                ks = sp.ks;
+                k = (int)(g - ks);
+                kk = (k < K - 1) ? k : K - 2;
+                double sgn;
+                rho = merge_rho(R, e, pmax, &sgn);
+                Dv = (ns >= 0) ? sD + (ks - r0) : w.Da + ks;
+                Wv = (ns >= 0) ? sW + (ks - r0) : w.Wa + ks;
+                Zg = w.Za + ks;
+                if (K == 1) {
+                    if (sub == 0) {
+                        w.org[g] = 0;
+                        w.tau[g] = rho * Zg[0] * Zg[0];
+                        roots += 1;
+                    }
+                    g = -1;
+                    continue;
+                }
+                phase = 1;
+                it = 0;
+            }
+            double Do, tau;
+            int L1, R0;
+            if (phase == 1) {  // bracket midpoint with origin kk (the last root uses only the weight sum)
+                Do = Dv[kk];
+                tau = 0.5 * (Dv[kk + 1] - Dv[kk]);
+                L1 = kk;
+                R0 = kk + 2;
+            } else {
+                Do = Dv[r.o];
+                tau = r.tau;
+                sec_split(r, kk, &L1, &R0);
+            }
+            double sm[5];
+            sec_sweep<RedGroup<G>, true>(K, Dv, Wv, Do, tau, L1, R0, sub, G, sm);
+            bool done = false;
+            int used = 0;
+            if (phase == 1) {
+                if (k < K - 1) done = sec_start_interior(k, Dv, Zg, rho, sm[0], sm[1], sm[2], sm[3], &r);
+                else sec_start_last(K, Dv, Zg, rho, sm[4], &r);
+                phase = 2;
+            } else {
+                ++it;
+                if (sec_update(&r, rho, sm[0], sm[1], sm[2], sm[3], sm[2] - sm[0])) {
+                    done = true;
+                    used = it;
+                } else if (it >= kSecMaxIter) {
+                    done = true;
+                    used = kSecMaxIter;
+                    bad = 1;
+                }
+            }
+            if (done) {
+                if (sub == 0) {
+                    w.org[g] = r.o;
+                    w.tau[g] = r.tau;
+                    sweeps += (unsigned long long)(used + 1);
+                    terms += (unsigned long long)(used + 1) * (unsigned long long)K;
+                    roots += 1;
+                }
+                g = -1;
             }
         }
         __syncthreads();
@@ -1211,7 +1333,11 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     // one k_wide_items launch serves the three root kernels of the level
     if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
-    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
+    long long rf = (N * G) / kRefillLanes;  // roots per group: keep about kRefillLanes lanes busy
+    rf = rf < 1 ? 1 : (rf > kRefillMax ? kRefillMax : rf);
+    const int nbs = (int)((nbn + rf - 1) / rf);
+    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min, nbs,
+                 (int)rf);
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, nbn);
 }
