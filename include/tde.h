@@ -95,6 +95,25 @@ int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, voi
 int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
 
+/* Eigenvalues and the first and last rows of the eigenvector matrix.
+ *
+ * The paper propagates only rows 0 and n-1 of each node's eigenvector matrix
+ * up the tree (Section 3.2) and skips them at the top merge (root-only mode,
+ * Section 3.3).  This entry point keeps them at the top as well (Algorithm 1
+ * with the requested rows sigma = {first, last} at the root), so for every
+ * output eigenvalue lambda_k it also returns q_0k and q_(n-1)k, the first and
+ * last components of its unit eigenvector.  With q_0k, the Golub-Welsch
+ * Gauss-quadrature weights of a Jacobi matrix are mu_0 q_0k^2.
+ *   offsets, B, d, e, lambda, ws: as tde_eigvals_batched (offsets = {0, n} for
+ *                   one problem)
+ *   qfirst [offsets[B]]  output q_0k per eigenvalue (device), or NULL
+ *   qlast  [offsets[B]]  output q_(n-1)k per eigenvalue (device), or NULL
+ *                   (at least one of the two must be given)
+ * Each pair is signed so that q_0k >= 0 (q_(n-1)k >= 0 when q_0k = 0). */
+int tde_eigvals_rows(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                     double* qfirst, double* qlast, void* ws, size_t ws_bytes, void* hip_stream,
+                     const tde_opts* opts);
+
 /* Reverse mode (gradients of the eigenvalues).
  *
  * The paper computes eigenvalues only; these entry points add the adjoint of

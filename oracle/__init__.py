@@ -221,3 +221,24 @@ def grad_reference(d, e, w):
     gd = np.einsum("ik,ik->i", Qw, Q)
     ge = 2.0 * np.einsum("ik,ik->i", Qw[:-1], Q[1:])
     return lam, gd, ge
+
+
+def boundary_rows(d, e):
+    """Eigenvalues and the first and last rows of the eigenvector matrix of T
+    (the rows the method propagates, Section 3.2), from LAPACK eigenvectors
+    (scipy.linalg.eigh_tridiagonal): returns (lam, q0, qlast) in ascending
+    eigenvalue order, each column signed so that q0_k >= 0 (qlast_k >= 0 when
+    q0_k = 0)."""
+    from scipy.linalg import eigh_tridiagonal
+
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    if len(d) == 0:
+        z = np.zeros(0)
+        return z, z, z
+    if len(d) == 1:
+        return d.copy(), np.ones(1), np.ones(1)
+    lam, Q = eigh_tridiagonal(d, e, lapack_driver="stemr")
+    q0, q1 = Q[0].copy(), Q[-1].copy()
+    sg = np.where((q0 < 0) | ((q0 == 0) & (q1 < 0)), -1.0, 1.0)
+    return lam, q0 * sg, q1 * sg

@@ -18,6 +18,7 @@ import torch
 __all__ = [
     "eigvals",
     "eigvals_batched",
+    "eigvals_rows",
     "eigvals_ckpt",
     "eigvals_backward",
     "differentiable_eigvals",
@@ -43,6 +44,7 @@ EXPORTS = (
     "tde_workspace_bytes",
     "tde_eigvals",
     "tde_eigvals_batched",
+    "tde_eigvals_rows",
     "tde_checkpoint_bytes",
     "tde_backward_workspace_bytes",
     "tde_eigvals_ckpt",
@@ -106,6 +108,8 @@ def lib():
         L.tde_eigvals_batched.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), i64, vp, vp, sz, vp, optp]
         L.tde_eigvals_batched.restype = ctypes.c_int
         i64p = ctypes.POINTER(ctypes.c_int64)
+        L.tde_eigvals_rows.argtypes = [vp, vp, i64p, i64, vp, vp, vp, vp, sz, vp, optp]
+        L.tde_eigvals_rows.restype = ctypes.c_int
         L.tde_checkpoint_bytes.argtypes = [i64p, i64, optp]
         L.tde_checkpoint_bytes.restype = sz
         L.tde_backward_workspace_bytes.argtypes = [i64, i64, optp]
@@ -247,6 +251,39 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_batched device status")
     return out
+
+
+# --- boundary rows at the top (NEXT: requested rows, Golub-Welsch) -----------
+
+def eigvals_rows(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, check: bool = True,
+                 graph: bool = True):
+    """Eigenvalues (ascending per problem) and, for each, the first and last
+    components of its unit eigenvector (first >= 0).  offsets None = one
+    problem with e[n-1], else the batched layout.  Returns (lam, qfirst, qlast)."""
+    _check_input(d, e)
+    offs, B, arr = _offsets(d.numel(), offsets)
+    n = offs[-1]
+    lam = torch.empty(n, dtype=torch.float64, device=d.device)
+    q0 = torch.empty(n, dtype=torch.float64, device=d.device)
+    q1 = torch.empty(n, dtype=torch.float64, device=d.device)
+    if B <= 0 or n == 0:
+        return lam, q0, q1
+    if d.numel() < n or (offsets is not None and e.numel() < n) or e.numel() < n - 1:
+        raise ValueError("d and e are shorter than the offsets require")
+    nb = workspace_bytes(n, B, leaf)
+    ws = _workspace(nb, d.device)
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_rows(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, lam.data_ptr(),
+                                    q0.data_ptr(), q1.data_ptr(), ws.data_ptr(), ws.numel(), stream,
+                                    _opts(leaf, graph, sweep_cols))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_rows")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_rows device status")
+    return lam, q0, q1
 
 
 # --- reverse mode -------------------------------------------------------------

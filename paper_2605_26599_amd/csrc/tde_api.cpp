@@ -25,7 +25,7 @@ std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 // Captured passes: one executable graph per (plan, pass kind, buffers).
 // Capture runs on an internal stream per device; replays run on the
 // caller's stream.
-enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2 };
+enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2, PASS_ROWS = 3 };
 using Bufs = std::array<const void*, 8>;
 using GraphKey = std::tuple<const Plan*, int, Bufs>;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
@@ -226,7 +226,8 @@ bool needs_e(const std::vector<long long>& offs) {
 }
 
 int solve(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
-          size_t ws_bytes, void* stream, const tde_opts* opts, void* ckpt = nullptr, size_t ckpt_bytes = 0) {
+          size_t ws_bytes, void* stream, const tde_opts* opts, void* ckpt = nullptr, size_t ckpt_bytes = 0,
+          double* qfirst = nullptr, double* qlast = nullptr) {
     int leaf, cols;
     if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
     const long long ntot = offs.back();
@@ -242,6 +243,14 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
     if (rc != TDE_OK) return rc;
     Work w{};
     workspace_layout(ntot, B, ntot, (char*)ws, &w);
+    if (qfirst || qlast) {
+        w.qfirst = qfirst;
+        w.qlast = qlast;
+        w.rows_out = 1;
+        Bufs bufs{d, e, lambda, ws, qfirst, qlast, nullptr, nullptr};
+        return run_pass(*plan, PASS_ROWS, bufs, opts, stream,
+                        [&](void* s) { return enqueue_solve(*plan, w, d, e, lambda, s); });
+    }
     if (!ckpt_bytes) {
         Bufs bufs{d, e, lambda, ws, nullptr, nullptr, nullptr, nullptr};
         return run_pass(*plan, PASS_SOLVE, bufs, opts, stream,
@@ -308,6 +317,16 @@ int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets
     if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
     if (B == 0) return TDE_OK;
     return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts);
+}
+
+int tde_eigvals_rows(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                     double* qfirst, double* qlast, void* ws, size_t ws_bytes, void* hip_stream,
+                     const tde_opts* opts) {
+    std::vector<long long> offs;
+    if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
+    if (!qfirst && !qlast) return TDE_EINVAL;
+    if (B == 0 || offs.back() == 0) return TDE_OK;
+    return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts, nullptr, 0, qfirst, qlast);
 }
 
 size_t tde_checkpoint_bytes(const int64_t* offsets, int64_t B, const tde_opts* opts) {

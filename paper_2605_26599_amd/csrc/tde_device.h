@@ -752,7 +752,7 @@ TDE_DEV void body_lowner(long long g, int m, const MergeRec* __restrict__ mr, co
                          const double* __restrict__ Dv, const int* __restrict__ orgv,
                          const double* __restrict__ tauv, long long voff, bool with_root = false) {
     const MergeRec R = mr[m];
-    if ((R.flags & MF_ROOT) && !with_root) return;
+    if ((R.flags & MF_ROOT) && !with_root && !w.rows_out) return;
     const MergeSpan sp = merge_span(R, w.scan);
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
@@ -767,7 +767,7 @@ TDE_DEV void body_rows(long long g, int m, const MergeRec* __restrict__ mr, cons
                        const double* __restrict__ Dv, const double* __restrict__ zhv,
                        const double* __restrict__ RLv, const double* __restrict__ RHv, long long voff) {
     const MergeRec R = mr[m];
-    if (R.flags & MF_ROOT) return;
+    if ((R.flags & MF_ROOT) && !w.rows_out) return;
     const MergeSpan sp = merge_span(R, w.scan);
     const long long b = sp.ks - voff;
     double bl, bh;
@@ -812,6 +812,15 @@ TDE_DEV int roots_cmp_count(const double* __restrict__ Da, const int* __restrict
     return lo;
 }
 
+// Rows mode: first and last entries of the unit eigenvector of an output
+// eigenvalue, signed so that the first entry is >= 0 (the last when the first
+// is 0).
+TDE_DEV void store_rows(const Work& w, long long P, double bl, double bh) {
+    const double sg = (bl < 0.0 || (bl == 0.0 && bh < 0.0)) ? -1.0 : 1.0;
+    if (w.qfirst) w.qfirst[P] = sg * bl;
+    if (w.qlast) w.qlast[P] = sg * bh;
+}
+
 TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
                            const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
     const MergeRec R = mr[m];
@@ -829,26 +838,28 @@ TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
     const double* Dr = w.Dr + rs;
     const double* Dd = w.Dd + ns;
     const bool root = (R.flags & MF_ROOT) != 0;
+    const bool rows = !root || w.rows_out;
     int pos;
     double val, bl = 0.0, bh = 0.0;
     if (i < K) {
         val = Da[og[i]] + ta[i];
         pos = i + count_lt(Dr, nr, val) + count_lt(Dd, nn, val);
-        if (!root) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
+        if (rows) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
     } else if (i < K + nr) {
         const int q = i - K;
         val = Dr[q];
         pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_lt(Dd, nn, val);
-        if (!root) { bl = w.RLr[rs + q]; bh = w.RHr[rs + q]; }
+        if (rows) { bl = w.RLr[rs + q]; bh = w.RHr[rs + q]; }
     } else {
         const int q = i - K - nr;
         val = Dd[q];
         pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_le(Dr, nr, val);
-        if (!root) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
+        if (rows) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
     }
     const long long P = R.off + pos;
     if (root) {
         out[P] = val * scale_of(pmax[R.prob]);
+        if (w.rows_out) store_rows(w, P, bl, bh);
     } else {
         w.lam[P] = val;
         w.blo[P] = bl;
@@ -874,7 +885,10 @@ TDE_DEV int body_leaf(const LeafRec& L, const double* __restrict__ d, const doub
     int status = leaf_ql(nl, sd, se, s0, s1, st, nrot);
     if (L.flags & LF_WHOLE) {
         const double sc = 1.0 / inv;
-        for (int i = 0; i < nl; ++i) out[L.off + i] = sd[i * st] * sc;
+        for (int i = 0; i < nl; ++i) {
+            out[L.off + i] = sd[i * st] * sc;
+            if (w.rows_out) store_rows(w, L.off + i, s0[i * st], s1[i * st]);
+        }
     } else {
         for (int i = 0; i < nl; ++i) {
             w.lam[L.off + i] = sd[i * st];

@@ -118,6 +118,9 @@ struct Work {
     double* Dr;                // [n]   rotated-away columns: eigenvalue (ascending per merge)
     double* RLr;               // [n]
     double* RHr;               // [n]
+    double* qfirst;            // [n] or null: first eigenvector row of each output eigenvalue (rows mode)
+    double* qlast;             // [n] or null: last eigenvector row of each output eigenvalue (rows mode)
+    int rows_out;              // 1: the top merges also propagate rows (qfirst / qlast requested)
 };
 
 // Forward checkpoint for the reverse pass: per level h (slot stride n), the

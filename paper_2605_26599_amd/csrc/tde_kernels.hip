@@ -575,7 +575,7 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
     for (int item = bid; item < total; item += nbw) {
         const int m = wide_merge_of(items, M, item);
         const MergeRec R = mr[m];
-        if (!(R.flags & MF_ROOT) || with_root) {
+        if (!(R.flags & MF_ROOT) || with_root || w.rows_out) {
             const MergeSpan sp = merge_span(R, w.scan);
             const int K = wave_uniform(sp.K);
             const long long ks = wave_uniform(sp.ks);
@@ -623,7 +623,7 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
                 const double rho = merge_rho(R, e, pmax, &sgn);
                 const double zi = sqrt(fmax(p / rho, 0.0));
                 w.zhat[ks + i] = (w.Za[ks + i] < 0.0) ? -zi : zi;
-                if (!(R.flags & MF_ROOT)) pairs += (unsigned long long)K;
+                if (!(R.flags & MF_ROOT) || w.rows_out) pairs += (unsigned long long)K;
             }
         }
         __syncthreads();
@@ -644,7 +644,7 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
     for (int item = bid; item < total; item += nbw) {
         const int m = wide_merge_of(items, M, item);
         const MergeRec R = mr[m];
-        if (!(R.flags & MF_ROOT)) {
+        if (!(R.flags & MF_ROOT) || w.rows_out) {
             const MergeSpan sp = merge_span(R, w.scan);
             const int K = wave_uniform(sp.K);
             const long long ks = wave_uniform(sp.ks);
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
             const int m = w.amerge[g];
             if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0, WithRoot);
             else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0, WithRoot);
-            if (sub == 0 && !(mr[m].flags & MF_ROOT)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
+            if (sub == 0 && (!(mr[m].flags & MF_ROOT) || w.rows_out)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
         }
         __syncthreads();
     }
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
             const int m = w.amerge[g];
             if (ns >= 0) body_rows<RedGroup<G>>(g, m, mr, w, sub, G, sD, sH, sL, sR, r0);
             else body_rows<RedGroup<G>>(g, m, mr, w, sub, G, w.Da, w.zhat, w.RLa, w.RHa, 0);
-            if (sub == 0 && !(mr[m].flags & MF_ROOT)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
+            if (sub == 0 && (!(mr[m].flags & MF_ROOT) || w.rows_out)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
         }
         __syncthreads();
     }

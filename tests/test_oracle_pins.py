@@ -224,3 +224,33 @@ def test_grad_reference_invariants_and_fd():
         em[i] -= h
         fd = (np.dot(w, oracle.eigvals(d, ep)) - np.dot(w, oracle.eigvals(d, em))) / (2 * h)
         assert abs(fd - ge[i]) <= 1e-7 * gmax
+
+
+# --- boundary rows (first and last eigenvector rows) -------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 40, 200])
+def test_boundary_rows_gauss_legendre(n):
+    """Golub-Welsch: for the Legendre Jacobi matrix (d = 0, e_k = k/sqrt(4k^2-1))
+    the eigenvalues are the Gauss-Legendre nodes and 2 q_0k^2 the weights."""
+    k = np.arange(1, n, dtype=np.float64)
+    e = k / np.sqrt(4.0 * k * k - 1.0)
+    lam, q0, q1 = oracle.boundary_rows(np.zeros(n), e)
+    x, wgt = np.polynomial.legendre.leggauss(n)
+    assert np.abs(lam - x).max() <= 1e-13
+    assert np.abs(2.0 * q0 * q0 - wgt).max() <= 1e-13
+    assert np.all(q0 >= 0)
+    assert abs(np.sum(q1 * q1) - 1.0) <= 1e-13
+
+
+def test_boundary_rows_identities():
+    """Unit rows, orthogonal rows, and the resolvent identity
+    q_0k q_(n-1)k = prod(e) / prod_{j != k} (lambda_k - lambda_j)."""
+    for fam, n in [("uniform", 7), ("normal", 10), ("toeplitz", 12), ("clustered", 9)]:
+        d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_TEST)
+        lam, q0, q1 = oracle.boundary_rows(d, e)
+        assert abs(np.sum(q0 * q0) - 1.0) <= 1e-14 and abs(np.sum(q1 * q1) - 1.0) <= 1e-14
+        assert abs(np.sum(q0 * q1)) <= 1e-14
+        pe = np.prod(e)
+        for kk in range(n):
+            den = np.prod([lam[kk] - lam[j] for j in range(n) if j != kk])
+            assert abs(q0[kk] * q1[kk] - pe / den) <= 1e-12 * max(1.0, abs(pe / den))
