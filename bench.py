@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
     ap.add_argument("--sweep-cols", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--wide-min", type=int, default=0, help="active roots from which a merge uses the wide "
+                    "secular sweep (0 = library default)")
     ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-secondary", action="store_true")
@@ -196,8 +198,9 @@ def grad_ratio(tde, dev, reps=20):
         e = torch.from_numpy(bt.e if offs else probs[0][1]).to(dev)
         w = torch.from_numpy(np.concatenate([tdgen.loss_weights(len(p[0]), inst=i) for i, p in enumerate(probs)])).to(dev)
         r = autotune.tune(d, e, offs, reps=3)
-        leaf, cols = r["leaf"], r["sweep_cols"]
+        leaf, cols, wide = r["leaf"], r["sweep_cols"], r["wide_min"]
         out = torch.empty(n, dtype=torch.float64, device=dev)
+        tde.set_defaults(wide_min=wide)
         ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
         gd = torch.empty(n, dtype=torch.float64, device=dev)
         ge = torch.empty(n, dtype=torch.float64, device=dev)
@@ -218,7 +221,9 @@ def grad_ratio(tde, dev, reps=20):
         torch.cuda.synchronize()
         tf = timed(fwd, reps) / reps
         tfb = timed(fwdbwd, reps) / reps
-        res[name] = {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf, "leaf": leaf, "sweep_cols": cols}
+        tde.set_defaults(wide_min=None)
+        res[name] = {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf, "leaf": leaf, "sweep_cols": cols,
+                     "wide_min": wide}
     return res
 
 
@@ -238,15 +243,17 @@ def main():
 
     dev = torch.device("cuda:0")
     tuning = {}
+    if args.wide_min:
+        tde.set_defaults(wide_min=args.wide_min)
 
     def choose(d, e, offs, label):
-        """(leaf, sweep_cols): explicit flags, else the autotuner (untimed)."""
+        """(leaf, sweep_cols, wide_min): explicit flags, else the autotuner (untimed)."""
         if args.leaf or args.sweep_cols or args.no_tune:
-            return args.leaf or None, args.sweep_cols or None
+            return args.leaf or None, args.sweep_cols or None, args.wide_min or None
         r = autotune.tune(d, e, offs, reps=3)
-        tuning[label] = {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "best_ms": r["ms"],
-                         "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
-        return r["leaf"], r["sweep_cols"]
+        tuning[label] = {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "wide_min": r["wide_min"],
+                         "best_ms": r["ms"], "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
+        return r["leaf"], r["sweep_cols"], r["wide_min"]
 
     def make_batched():
         batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
@@ -254,19 +261,19 @@ def main():
         e = torch.from_numpy(batch.e).to(dev)
         out = torch.empty(int(batch.offsets[-1]), dtype=torch.float64, device=dev)
         offs = batch.offsets
-        bleaf, bcols = choose(d, e, offs, "batched")
+        bleaf, bcols, bwide = choose(d, e, offs, "batched")
 
         def step():
-            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, out=out, check=False)
+            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, wide_min=bwide, out=out, check=False)
 
-        return batch, step, (bleaf, bcols)
+        return batch, step, (bleaf, bcols, bwide)
 
     if args.batched:
-        batch, step, (leaf, cols) = make_batched()
+        batch, step, (leaf, cols, wide) = make_batched()
         n_cols = int(batch.offsets[-1])
         workload = {"workload": f"batched: 4096 tridiagonals, sizes log-uniform in [32,4096] "
                                 f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols,
-                    "leaf": leaf or "default", "sweep_cols": cols or "default"}
+                    "leaf": leaf or "default", "sweep_cols": cols or "default", "wide_min": wide or "default"}
         metric, unit, per_step = "batched solves/s", "solves/s", 4096
         dn = en = None
     else:
@@ -276,13 +283,13 @@ def main():
         e = torch.from_numpy(en).to(dev)
         out = torch.empty(n, dtype=torch.float64, device=dev)
         n_cols = n
-        leaf, cols = choose(d, e, None, "single")
+        leaf, cols, wide = choose(d, e, None, "single")
 
         def step():
-            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
+            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wide, out=out, check=False)
 
         workload = {"workload": f"single tridiagonal n={n}, family {args.family} (seeded synthetic)", "n": n,
-                    "leaf": leaf or "default", "sweep_cols": cols or "default"}
+                    "leaf": leaf or "default", "sweep_cols": cols or "default", "wide_min": wide or "default"}
         metric, unit, per_step = f"FP64 tridiag eigvals/s @n={n}", "eigvals/s", n
 
     for _ in range(args.warmup):

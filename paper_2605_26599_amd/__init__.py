@@ -144,7 +144,17 @@ def _status_string(code: int) -> str:
 TDE_FLAG_NO_GRAPH = 1
 
 
+# Launch-shape option that does not change the method; set_defaults() changes
+# what every call below uses when it does not pass it (a tuned choice, say).
+_shape_defaults = {"wide_min": None}
+
+
+def set_defaults(wide_min=None):
+    _shape_defaults["wide_min"] = wide_min
+
+
 def _opts(leaf, graph=True, sweep_cols=None, wide_min=None):
+    wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
     if leaf is None and graph and sweep_cols is None and wide_min is None:
         return None
     o = tde_opts()

@@ -1,10 +1,11 @@
 """Autotuner for the solver's launch shape.
 
-Two knobs change speed but not the method: the leaf size (largest block solved
-directly by QL) and the target number of poles each lane sweeps in the
-root-parallel kernels (which sets the lanes per root, G <= 16, per level).
-`tune` times every combination on the device (graph replay, inputs resident)
-and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
+Three knobs change speed but not the method: the leaf size (largest block
+solved directly by QL), the target number of poles each lane sweeps in the
+root-parallel kernels (which sets the lanes per root, G <= 16, per level) and
+the number of active roots from which a merge uses the wide sweeps (64 roots
+per workgroup, poles split over its waves).  `tune` times every combination
+on the device (graph replay, inputs resident) and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
 architecture and a size bucket (log2 of the column count, batch or single),
 so later runs reuse them without re-timing.
 """
@@ -17,8 +18,9 @@ import time
 
 import torch
 
-LEAVES = (1, 2, 4, 8, 16, 32)
-SWEEP_COLS = (1, 2, 4, 8, 16, 32, 64)
+LEAVES = (2, 4, 8, 16, 32)
+SWEEP_COLS = (8, 16, 32, 64)
+WIDE_MIN = (1024, 64, 32)
 
 
 def cache_path() -> str:
@@ -56,11 +58,11 @@ def _store(db: dict) -> None:
 
 
 def lookup(n_total: int, batch: int = 1, device=None):
-    """Cached (leaf, sweep_cols) for this size bucket, or None."""
+    """Cached (leaf, sweep_cols, wide_min) for this size bucket, or None."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     rec = _load().get(_arch(dev), {}).get(bucket(n_total, batch))
-    if rec:
-        return int(rec["leaf"]), int(rec["sweep_cols"])
+    if rec and "wide_min" in rec:
+        return int(rec["leaf"]), int(rec["sweep_cols"]), int(rec["wide_min"])
     return None
 
 
@@ -77,12 +79,13 @@ def _time(step, reps: int) -> float:
 
 
 def tune(d: torch.Tensor, e: torch.Tensor, offsets=None, reps: int = 5, leaves=LEAVES, sweep_cols=SWEEP_COLS,
-         store: bool = True) -> dict:
-    """Time every (leaf, sweep_cols) on this input; return and cache the best.
+         wide_mins=WIDE_MIN, store: bool = True) -> dict:
+    """Time every (leaf, sweep_cols, wide_min) on this input; return and cache
+    the best.
 
     d, e are device tensors (single problem: e has n-1 entries; batch: offsets
-    is the host offsets sequence).  Returns {"leaf", "sweep_cols", "ms",
-    "table": [(leaf, cols, ms), ...], "tune_s"}.
+    is the host offsets sequence).  Returns {"leaf", "sweep_cols", "wide_min",
+    "ms", "table": [(leaf, cols, wide_min, ms), ...], "tune_s"}.
     """
     import paper_2605_26599_amd as tde
 
@@ -91,22 +94,25 @@ def tune(d: torch.Tensor, e: torch.Tensor, offsets=None, reps: int = 5, leaves=L
     table = []
     for leaf in leaves:
         for cols in sweep_cols:
-            if offsets is None:
-                def step(leaf=leaf, cols=cols):
-                    tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
-            else:
-                def step(leaf=leaf, cols=cols):
-                    tde.eigvals_batched(d, e, offsets, leaf=leaf, sweep_cols=cols, out=out, check=False)
-            step()
-            step()
-            table.append((leaf, cols, _time(step, reps)))
-    best = min(table, key=lambda r: r[2])
+            for wm in wide_mins:
+                if offsets is None:
+                    def step(leaf=leaf, cols=cols, wm=wm):
+                        tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wm, out=out, check=False)
+                else:
+                    def step(leaf=leaf, cols=cols, wm=wm):
+                        tde.eigvals_batched(d, e, offsets, leaf=leaf, sweep_cols=cols, wide_min=wm, out=out,
+                                            check=False)
+                step()
+                step()
+                table.append((leaf, cols, wm, _time(step, reps)))
+    best = min(table, key=lambda r: r[3])
     n_total = int(d.numel()) if offsets is None else int(offsets[-1])
     batch = 1 if offsets is None else len(offsets) - 1
-    res = {"leaf": best[0], "sweep_cols": best[1], "ms": best[2], "table": table,
+    res = {"leaf": best[0], "sweep_cols": best[1], "wide_min": best[2], "ms": best[3], "table": table,
            "tune_s": time.perf_counter() - t0, "bucket": bucket(n_total, batch)}
     if store:
         db = _load()
-        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "sweep_cols": best[1], "ms": best[2]}
+        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "sweep_cols": best[1],
+                                                            "wide_min": best[2], "ms": best[3]}
         _store(db)
     return res
