@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
     ap.add_argument("--sweep-cols", type=int, default=0, help="0 = autotuned (or library default with --no-tune)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--leaf-dc", action="store_true", help="with --leaf: solve leaves by divide and conquer "
+                    "inside one wave")
     ap.add_argument("--wide-min", type=int, default=0, help="active roots from which a merge uses the wide "
                     "secular sweep (0 = library default)")
     ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
@@ -95,7 +97,10 @@ def roofline(tde, kinds, cnt, steps):
         "secular": ("alu", cnt["secular_terms"] * FLOPS_PER_SEC_TERM),
         "lowner": ("alu", cnt["lowner_pairs"] * FLOPS_PER_LOW_PAIR),
         "rows": ("alu", cnt["row_pairs"] * FLOPS_PER_ROW_PAIR),
-        "leaf": ("alu", cnt["leaf_rotations"] * FLOPS_PER_LEAF_ROT),
+        # QL leaves: rotations; leaves solved by divide and conquer in one wave:
+        # the secular, Loewner and row work of their merges
+        "leaf": ("alu", cnt["leaf_rotations"] * FLOPS_PER_LEAF_ROT + cnt["dc_secular_terms"] * FLOPS_PER_SEC_TERM
+                 + cnt["dc_lowner_pairs"] * FLOPS_PER_LOW_PAIR + cnt["dc_row_pairs"] * FLOPS_PER_ROW_PAIR),
         "merge": ("hbm", None),
         "assemble": ("hbm", None),
     }
@@ -197,33 +202,61 @@ def grad_ratio(tde, dev, reps=20):
         d = torch.from_numpy(bt.d).to(dev)
         e = torch.from_numpy(bt.e if offs else probs[0][1]).to(dev)
         w = torch.from_numpy(np.concatenate([tdgen.loss_weights(len(p[0]), inst=i) for i, p in enumerate(probs)])).to(dev)
-        r = autotune.tune(d, e, offs, reps=3)
-        leaf, cols, wide = r["leaf"], r["sweep_cols"], r["wide_min"]
         out = torch.empty(n, dtype=torch.float64, device=dev)
-        tde.set_defaults(wide_min=wide)
-        ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
         gd = torch.empty(n, dtype=torch.float64, device=dev)
         ge = torch.empty(n, dtype=torch.float64, device=dev)
+        # the forward alone: its fastest configuration (any leaf solver)
+        r = autotune.tune(d, e, offs, reps=3)
+        fcfg = dict(leaf=r["leaf"], sweep_cols=r["sweep_cols"], wide_min=r["wide_min"], leaf_dc=r["leaf_dc"])
 
         def fwd():
             if offs is None:
-                tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, out=out, check=False)
+                tde.eigvals(d, e, out=out, check=False, **fcfg)
             else:
-                tde.eigvals_batched(d, e, offs, leaf=leaf, sweep_cols=cols, out=out, check=False)
+                tde.eigvals_batched(d, e, offs, out=out, check=False, **fcfg)
 
-        def fwdbwd():
-            tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, out=out, ckpt=ck, check=False)
-            tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, gd=gd, ge=ge, check=False)
+        # forward with checkpoint + reverse pass: its own fastest configuration
+        # (the checkpointing forward always solves leaves by QL)
+        def make_fb(leaf, cols, wide):
+            ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
+
+            def fb():
+                tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, out=out, ckpt=ck,
+                                 check=False)
+                tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, gd=gd, ge=ge,
+                                     check=False)
+            return fb
+
+        best = None
+        for leaf in (4, 8, 16, 32):
+            for cols in (16, 64):
+                for wide in (1024, 64):
+                    fb = make_fb(leaf, cols, wide)
+                    fb()
+                    fb()
+                    t = timed(fb, 3) / 3
+                    if best is None or t < best[0]:
+                        best = (t, leaf, cols, wide)
+        _, bleaf, bcols, bwide = best
+        fwdbwd = make_fb(bleaf, bcols, bwide)
+        qcfg = dict(leaf=bleaf, sweep_cols=bcols, wide_min=bwide)
+
+        def fwd_same():
+            if offs is None:
+                tde.eigvals(d, e, out=out, check=False, **qcfg)
+            else:
+                tde.eigvals_batched(d, e, offs, out=out, check=False, **qcfg)
 
         for _ in range(3):
             fwd()
+            fwd_same()
             fwdbwd()
         torch.cuda.synchronize()
         tf = timed(fwd, reps) / reps
+        tfs = timed(fwd_same, reps) / reps
         tfb = timed(fwdbwd, reps) / reps
-        tde.set_defaults(wide_min=None)
-        res[name] = {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf, "leaf": leaf, "sweep_cols": cols,
-                     "wide_min": wide}
+        res[name] = {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf, "fwd_config": fcfg,
+                     "fwd_bwd_config": qcfg, "fwd_same_config_ms": tfs, "ratio_same_config": tfb / tfs}
     return res
 
 
@@ -247,13 +280,14 @@ def main():
         tde.set_defaults(wide_min=args.wide_min)
 
     def choose(d, e, offs, label):
-        """(leaf, sweep_cols, wide_min): explicit flags, else the autotuner (untimed)."""
+        """(leaf, sweep_cols, wide_min, leaf_dc): explicit flags, else the autotuner (untimed)."""
         if args.leaf or args.sweep_cols or args.no_tune:
-            return args.leaf or None, args.sweep_cols or None, args.wide_min or None
+            return args.leaf or None, args.sweep_cols or None, args.wide_min or None, bool(args.leaf_dc)
         r = autotune.tune(d, e, offs, reps=3)
-        tuning[label] = {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "wide_min": r["wide_min"],
-                         "best_ms": r["ms"], "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
-        return r["leaf"], r["sweep_cols"], r["wide_min"]
+        tuning[label] = {"leaf": r["leaf"], "leaf_dc": r["leaf_dc"], "sweep_cols": r["sweep_cols"],
+                         "wide_min": r["wide_min"], "best_ms": r["ms"], "configs_tried": len(r["table"]),
+                         "tune_s": r["tune_s"]}
+        return r["leaf"], r["sweep_cols"], r["wide_min"], r["leaf_dc"]
 
     def make_batched():
         batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
@@ -261,19 +295,21 @@ def main():
         e = torch.from_numpy(batch.e).to(dev)
         out = torch.empty(int(batch.offsets[-1]), dtype=torch.float64, device=dev)
         offs = batch.offsets
-        bleaf, bcols, bwide = choose(d, e, offs, "batched")
+        bleaf, bcols, bwide, bdc = choose(d, e, offs, "batched")
 
         def step():
-            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, wide_min=bwide, out=out, check=False)
+            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, wide_min=bwide, leaf_dc=bdc, out=out,
+                                check=False)
 
-        return batch, step, (bleaf, bcols, bwide)
+        return batch, step, (bleaf, bcols, bwide, bdc)
 
     if args.batched:
-        batch, step, (leaf, cols, wide) = make_batched()
+        batch, step, (leaf, cols, wide, dc) = make_batched()
         n_cols = int(batch.offsets[-1])
         workload = {"workload": f"batched: 4096 tridiagonals, sizes log-uniform in [32,4096] "
                                 f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols,
-                    "leaf": leaf or "default", "sweep_cols": cols or "default", "wide_min": wide or "default"}
+                    "leaf": leaf or "default", "leaf_solver": "dc" if dc else "ql",
+                    "sweep_cols": cols or "default", "wide_min": wide or "default"}
         metric, unit, per_step = "batched solves/s", "solves/s", 4096
         dn = en = None
     else:
@@ -283,13 +319,14 @@ def main():
         e = torch.from_numpy(en).to(dev)
         out = torch.empty(n, dtype=torch.float64, device=dev)
         n_cols = n
-        leaf, cols, wide = choose(d, e, None, "single")
+        leaf, cols, wide, dc = choose(d, e, None, "single")
 
         def step():
-            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wide, out=out, check=False)
+            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wide, leaf_dc=dc, out=out, check=False)
 
         workload = {"workload": f"single tridiagonal n={n}, family {args.family} (seeded synthetic)", "n": n,
-                    "leaf": leaf or "default", "sweep_cols": cols or "default", "wide_min": wide or "default"}
+                    "leaf": leaf or "default", "leaf_solver": "dc" if dc else "ql",
+                    "sweep_cols": cols or "default", "wide_min": wide or "default"}
         metric, unit, per_step = f"FP64 tridiag eigvals/s @n={n}", "eigvals/s", n
 
     for _ in range(args.warmup):

@@ -55,9 +55,13 @@ extern "C" {
 
 /* Options.  Pass NULL for defaults. */
 #define TDE_FLAG_NO_GRAPH 1 /* enqueue every kernel eagerly instead of replaying a captured graph */
+#define TDE_FLAG_LEAF_DC 2  /* forward passes (tde_eigvals, tde_eigvals_batched, tde_eigvals_rows) solve
+                               each leaf by running its own divide-and-conquer tree (halving down to
+                               single columns) inside one 64-lane wave instead of by QL; the
+                               checkpointing forward of reverse mode always uses QL leaves */
 typedef struct {
-    int leaf;       /* largest leaf size solved directly by QL, 1..64; 0 = default (8) */
-    int flags;      /* 0 or TDE_FLAG_NO_GRAPH; other bits are rejected */
+    int leaf;       /* largest leaf size of the merge tree, 1..64; 0 = default (8) */
+    int flags;      /* TDE_FLAG_* bits; other bits are rejected */
     int sweep_cols; /* target poles per lane in the root-parallel sweeps: each root
                        gets G = min(16, 2^ceil(log2(largest merge / sweep_cols)))
                        lanes; 0 = default (8) */
@@ -166,13 +170,15 @@ int tde_get_status(const void* ws, void* hip_stream);
 
 /* Measurement aids (not needed to solve).
  *
- * tde_get_counters: waits for the stream, then copies n (<= 8) counters of the
+ * tde_get_counters: waits for the stream, then copies n (<= 12) counters of the
  * algorithmic work of the last solve that used ws:
  *   [0] pole-term evaluations in secular sweeps, [1] (pole, root) pairs in the
  *   Loewner products, [2] (root, pole) pairs in the boundary-row dot products,
- *   [3] secular roots, [4] secular sweeps, [5] columns solved by QL leaves,
- *   [6] plane rotations applied by the QL leaves, [7] columns passed through
- *   merges (summed over tree levels).
+ *   [3] secular roots, [4] secular sweeps, [5] columns solved by leaves,
+ *   [6] plane rotations applied by QL leaves, [7] columns passed through
+ *   merges (summed over tree levels, in-wave leaf merges included);
+ *   [8..11] as [0..3] for the merges run inside leaves solved by divide and
+ *   conquer in one wave (TDE_FLAG_LEAF_DC), which [0..4] do not include.
  *
  * tde_timing_enable(1): from then on every launch the library enqueues is
  * bracketed by two HIP events recorded on the caller's stream (this adds

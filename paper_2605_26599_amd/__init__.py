@@ -142,24 +142,29 @@ def _status_string(code: int) -> str:
 
 
 TDE_FLAG_NO_GRAPH = 1
+TDE_FLAG_LEAF_DC = 2
 
 
-# Launch-shape option that does not change the method; set_defaults() changes
-# what every call below uses when it does not pass it (a tuned choice, say).
-_shape_defaults = {"wide_min": None}
+# Schedule options that do not change the method; set_defaults() changes what
+# every call below uses when it does not pass them (a tuned choice, say).
+# leaf_dc: forward passes solve each leaf by its own divide and conquer inside
+# one wave (the reverse mode's checkpointing forward keeps QL leaves).
+_shape_defaults = {"wide_min": None, "leaf_dc": None}
 
 
-def set_defaults(wide_min=None):
+def set_defaults(wide_min=None, leaf_dc=None):
     _shape_defaults["wide_min"] = wide_min
+    _shape_defaults["leaf_dc"] = leaf_dc
 
 
-def _opts(leaf, graph=True, sweep_cols=None, wide_min=None):
+def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None):
     wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
-    if leaf is None and graph and sweep_cols is None and wide_min is None:
+    leaf_dc = _shape_defaults["leaf_dc"] if leaf_dc is None else leaf_dc
+    if leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc:
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
-    o.flags = 0 if graph else TDE_FLAG_NO_GRAPH
+    o.flags = (0 if graph else TDE_FLAG_NO_GRAPH) | (TDE_FLAG_LEAF_DC if leaf_dc else 0)
     o.sweep_cols = int(sweep_cols or 0)
     o.wide_min = int(wide_min or 0)
     return ctypes.byref(o)
@@ -200,11 +205,12 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-            sweep_cols=None, wide_min=None) -> torch.Tensor:
+            sweep_cols=None, wide_min=None, leaf_dc=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
     off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
     replays a captured HIP graph of the whole solve (captured on first use for
-    these buffers); graph=False enqueues the kernels one by one."""
+    these buffers); graph=False enqueues the kernels one by one.  leaf_dc=True
+    solves the leaves by divide and conquer inside one wave each."""
     _check_input(d, e)
     n = d.numel()
     if e.numel() < max(n - 1, 0):
@@ -220,7 +226,8 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
-                               ws.data_ptr(), ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min))
+                               ws.data_ptr(), ws.numel(), stream,
+                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -232,7 +239,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-                    sweep_cols=None, wide_min=None) -> torch.Tensor:
+                    sweep_cols=None, wide_min=None, leaf_dc=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -253,7 +260,7 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
-                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min))
+                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min, leaf_dc))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:
@@ -266,7 +273,7 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
 # --- boundary rows at the top (NEXT: requested rows, Golub-Welsch) -----------
 
 def eigvals_rows(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, check: bool = True,
-                 graph: bool = True):
+                 graph: bool = True, leaf_dc=None):
     """Eigenvalues (ascending per problem) and, for each, the first and last
     components of its unit eigenvector (first >= 0).  offsets None = one
     problem with e[n-1], else the batched layout.  Returns (lam, qfirst, qlast)."""
@@ -286,7 +293,7 @@ def eigvals_rows(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_rows(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, lam.data_ptr(),
                                     q0.data_ptr(), q1.data_ptr(), ws.data_ptr(), ws.numel(), stream,
-                                    _opts(leaf, graph, sweep_cols))
+                                    _opts(leaf, graph, sweep_cols, None, leaf_dc))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_rows")
         if check:
@@ -416,15 +423,16 @@ def differentiable_eigvals(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=
     return _Eigvals.apply(d, e, offs, leaf, sweep_cols)
 
 
-COUNTER_NAMES = ("secular_terms", "lowner_pairs", "row_pairs", "roots", "sweeps", "leaf_columns", "leaf_rotations", "merge_columns")
+COUNTER_NAMES = ("secular_terms", "lowner_pairs", "row_pairs", "roots", "sweeps", "leaf_columns", "leaf_rotations",
+                 "merge_columns", "dc_secular_terms", "dc_lowner_pairs", "dc_row_pairs", "dc_roots")
 KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble", "backward")
 
 
 def counters(workspace: torch.Tensor) -> dict:
     """Algorithmic work counters of the last solve that used this workspace (syncs)."""
-    buf = (ctypes.c_uint64 * 8)()
+    buf = (ctypes.c_uint64 * len(COUNTER_NAMES))()
     stream = torch.cuda.current_stream(workspace.device).cuda_stream
-    rc = lib().tde_get_counters(workspace.data_ptr(), stream, buf, 8)
+    rc = lib().tde_get_counters(workspace.data_ptr(), stream, buf, len(COUNTER_NAMES))
     if rc != TDE_OK:
         raise TDEError(rc, "tde_get_counters")
     return {name: int(buf[i]) for i, name in enumerate(COUNTER_NAMES)}

@@ -1,7 +1,8 @@
 """Autotuner for the solver's launch shape.
 
-Three knobs change speed but not the method: the leaf size (largest block
-solved directly by QL), the target number of poles each lane sweeps in the
+Four knobs change speed but not the method: the leaf size (largest block of
+the merge tree), how leaves are solved (QL, or their own divide and conquer
+inside one wave), the target number of poles each lane sweeps in the
 root-parallel kernels (which sets the lanes per root, G <= 16, per level) and
 the number of active roots from which a merge uses the wide sweeps (64 roots
 per workgroup, poles split over its waves).  `tune` times every combination
@@ -18,7 +19,8 @@ import time
 
 import torch
 
-LEAVES = (2, 4, 8, 16, 32)
+LEAVES = (2, 4, 8, 16, 32)     # QL leaves
+DC_LEAVES = (32, 64)           # leaves solved by divide and conquer inside one wave
 SWEEP_COLS = (8, 16, 32, 64)
 WIDE_MIN = (1024, 64, 32)
 
@@ -58,11 +60,11 @@ def _store(db: dict) -> None:
 
 
 def lookup(n_total: int, batch: int = 1, device=None):
-    """Cached (leaf, sweep_cols, wide_min) for this size bucket, or None."""
+    """Cached (leaf, sweep_cols, wide_min, leaf_dc) for this size bucket, or None."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     rec = _load().get(_arch(dev), {}).get(bucket(n_total, batch))
-    if rec and "wide_min" in rec:
-        return int(rec["leaf"]), int(rec["sweep_cols"]), int(rec["wide_min"])
+    if rec and "leaf_dc" in rec:
+        return int(rec["leaf"]), int(rec["sweep_cols"]), int(rec["wide_min"]), bool(rec["leaf_dc"])
     return None
 
 
@@ -79,40 +81,44 @@ def _time(step, reps: int) -> float:
 
 
 def tune(d: torch.Tensor, e: torch.Tensor, offsets=None, reps: int = 5, leaves=LEAVES, sweep_cols=SWEEP_COLS,
-         wide_mins=WIDE_MIN, store: bool = True) -> dict:
-    """Time every (leaf, sweep_cols, wide_min) on this input; return and cache
-    the best.
+         wide_mins=WIDE_MIN, dc_leaves=DC_LEAVES, store: bool = True) -> dict:
+    """Time every (leaf, leaf solver, sweep_cols, wide_min) on this input;
+    return and cache the best.
 
     d, e are device tensors (single problem: e has n-1 entries; batch: offsets
-    is the host offsets sequence).  Returns {"leaf", "sweep_cols", "wide_min",
-    "ms", "table": [(leaf, cols, wide_min, ms), ...], "tune_s"}.
+    is the host offsets sequence).  Returns {"leaf", "leaf_dc", "sweep_cols",
+    "wide_min", "ms", "table": [(leaf, leaf_dc, cols, wide_min, ms), ...],
+    "tune_s"}.
     """
     import paper_2605_26599_amd as tde
 
     t0 = time.perf_counter()
     out = torch.empty(d.numel(), dtype=torch.float64, device=d.device)
     table = []
-    for leaf in leaves:
+    cands = [(leaf, False) for leaf in leaves] + [(leaf, True) for leaf in dc_leaves]
+    for leaf, dc in cands:
         for cols in sweep_cols:
             for wm in wide_mins:
                 if offsets is None:
-                    def step(leaf=leaf, cols=cols, wm=wm):
-                        tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wm, out=out, check=False)
+                    def step(leaf=leaf, dc=dc, cols=cols, wm=wm):
+                        tde.eigvals(d, e, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm, out=out,
+                                    check=False)
                 else:
-                    def step(leaf=leaf, cols=cols, wm=wm):
-                        tde.eigvals_batched(d, e, offsets, leaf=leaf, sweep_cols=cols, wide_min=wm, out=out,
-                                            check=False)
+                    def step(leaf=leaf, dc=dc, cols=cols, wm=wm):
+                        tde.eigvals_batched(d, e, offsets, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm,
+                                            out=out, check=False)
                 step()
                 step()
-                table.append((leaf, cols, wm, _time(step, reps)))
-    best = min(table, key=lambda r: r[3])
+                table.append((leaf, dc, cols, wm, _time(step, reps)))
+    best = min(table, key=lambda r: r[4])
     n_total = int(d.numel()) if offsets is None else int(offsets[-1])
     batch = 1 if offsets is None else len(offsets) - 1
-    res = {"leaf": best[0], "sweep_cols": best[1], "wide_min": best[2], "ms": best[3], "table": table,
-           "tune_s": time.perf_counter() - t0, "bucket": bucket(n_total, batch)}
+    res = {"leaf": best[0], "leaf_dc": best[1], "sweep_cols": best[2], "wide_min": best[3], "ms": best[4],
+           "table": table, "tune_s": time.perf_counter() - t0, "bucket": bucket(n_total, batch)}
     if store:
         db = _load()
-        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "sweep_cols": best[1],
-                                                            "wide_min": best[2], "ms": best[3]}
+        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "leaf_dc": best[1],
+                                                            "sweep_cols": best[2], "wide_min": best[3],
+                                                            "ms": best[4]}
         _store(db)
     return res

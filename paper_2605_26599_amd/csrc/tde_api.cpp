@@ -18,7 +18,7 @@
 namespace tde {
 namespace {
 
-using PlanKey = std::tuple<int, int, int, int, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, int, bool, std::vector<long long>>;
 std::mutex g_mu;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
@@ -94,14 +94,34 @@ void free_plan(Plan* p) {
     if (p->d_leaves) (void)hipFree(p->d_leaves);
     if (p->d_offs) (void)hipFree(p->d_offs);
     if (p->d_blkm) (void)hipFree(p->d_blkm);
+    if (p->d_shdr) (void)hipFree(p->d_shdr);
+    if (p->d_smer) (void)hipFree(p->d_smer);
+    p->d_shdr = nullptr;
+    p->d_smer = nullptr;
     p->d_blkm = nullptr;
     p->d_merges = nullptr;
     p->d_leaves = nullptr;
     p->d_offs = nullptr;
 }
 
-int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long long>& offs, Plan** out) {
-    PlanKey key{device, leaf, cols, wmin, offs};
+// In-wave merge trees of every leaf size 1..kLeafMax (leaf-local offsets).
+void sub_trees(std::vector<SubHdr>* hdr, std::vector<SubMerge>* mer) {
+    hdr->assign(kLeafMax + 1, SubHdr{});
+    mer->clear();
+    for (int l = 1; l <= kLeafMax; ++l) {
+        const LevelTables t = build_tree(1, {0, (long long)l});
+        SubHdr& h = (*hdr)[l];
+        h.mbase = (int)mer->size();
+        h.H = (int)t.mstart.size();
+        for (int k = 0; k < h.H; ++k) h.lv[k] = (unsigned char)t.mstart[k];
+        h.lv[h.H] = (unsigned char)t.merges.size();
+        for (const MergeRec& R : t.merges)
+            mer->push_back(SubMerge{(unsigned char)R.off, (unsigned char)R.nL, (unsigned char)R.nR, (unsigned char)R.pk});
+    }
+}
+
+int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vector<long long>& offs, Plan** out) {
+    PlanKey key{device, leaf, cols, wmin, dc, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         *out = it->second.get();
@@ -112,6 +132,7 @@ int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long l
     p->leaf = leaf;
     p->sweep_cols = cols;
     p->wide_min = wmin;
+    p->leaf_dc = dc;
     p->offs = offs;
     p->B = (int)offs.size() - 1;
     p->ntot = offs.back();
@@ -158,6 +179,13 @@ int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long l
                      t.leaves.size() * sizeof(LeafRec)) &&
               upload((void**)&p->d_offs, offs.data(), offs.size() * sizeof(long long)) &&
               upload((void**)&p->d_blkm, blkm.empty() ? nullptr : blkm.data(), blkm.size() * sizeof(int));
+    if (ok && dc) {
+        std::vector<SubHdr> sh;
+        std::vector<SubMerge> sm;
+        sub_trees(&sh, &sm);
+        ok = upload((void**)&p->d_shdr, sh.data(), sh.size() * sizeof(SubHdr)) &&
+             upload((void**)&p->d_smer, sm.data(), sm.size() * sizeof(SubMerge));
+    }
     if (!ok) {
         free_plan(p.get());
         return TDE_ENOMEM;
@@ -167,10 +195,10 @@ int make_plan(int device, int leaf, int cols, int wmin, const std::vector<long l
     return TDE_OK;
 }
 
-int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr) {
+int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr) {
     int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin;
     if (opts) {
-        if (opts->flags & ~TDE_FLAG_NO_GRAPH) return TDE_EINVAL;
+        if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
         if (opts->sweep_cols != 0) C = opts->sweep_cols;
         if (opts->wide_min != 0) W = opts->wide_min;
@@ -181,6 +209,7 @@ int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr
     *leaf = L;
     *cols = C;
     if (wmin) *wmin = W;
+    if (dc) *dc = opts && (opts->flags & TDE_FLAG_LEAF_DC);
     return TDE_OK;
 }
 
@@ -212,11 +241,12 @@ int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* off
 
 int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** plan) {
     int leaf, cols, wmin;
-    if (resolve_opts(opts, &leaf, &cols, &wmin) != TDE_OK) return TDE_EINVAL;
+    bool dc;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
     std::lock_guard<std::mutex> lk(g_mu);
-    return make_plan(device, leaf, cols, wmin, offs, plan);
+    return make_plan(device, leaf, cols, wmin, dc, offs, plan);
 }
 
 bool needs_e(const std::vector<long long>& offs) {

@@ -383,20 +383,24 @@ TDE_DEV int sec_update(SecRoot* r, double rho, double psi, double dpsi, double p
 // group of G takes j = sub, sub + G, ...  Per pole term: r = 1/((D_j - Do) -
 // tau), t = w_j r, t r.  s[0..3] receive the group totals psi, dpsi, phi,
 // dphi and, with ZZ, s[4] the sum of the weights w_j = z_j^2.
+// The root lies strictly between the poles L1 - 1 and R0 (its offset never
+// reaches a bracketing pole, and a difference of distinct doubles is never
+// 0), so every left term is <= 0 and every right term >= 0: the split is
+// taken by sign (min / max) rather than by index.
 template <class Red, bool ZZ>
 TDE_DEV void sec_sweep(int K, const double* __restrict__ D, const double* __restrict__ W, double Do, double tau,
                        int L1, int R0, int sub, int G, double* s) {
     double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0, zz = 0.0;
+    const unsigned exw = (unsigned)(R0 - L1);
     _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
         const double rr = rcp_nr((D[j] - Do) - tau);
-        const bool ex = (j >= L1) && (j < R0);
-        const double t = ex ? 0.0 : W[j] * rr;
-        const double dt = t * rr;
-        const bool left = j < L1;
-        ps += left ? t : 0.0;
-        dps += left ? dt : 0.0;
-        ph += left ? 0.0 : t;
-        dph += left ? 0.0 : dt;
+        const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : W[j];
+        const double t = wj * rr;
+        const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
+        ps += tl;
+        dps = fma(tl, rr, dps);
+        ph += th;
+        dph = fma(th, rr, dph);
         if (ZZ) zz += W[j];
     }
     s[0] = Red::sum(ps);

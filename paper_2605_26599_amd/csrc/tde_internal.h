@@ -31,6 +31,20 @@ struct LeafRec {
 };
 enum { LF_TEAR_LEFT = 1, LF_TEAR_RIGHT = 2, LF_WHOLE = 4 };
 
+// Merge tree of a leaf solved by divide and conquer inside one wave (the
+// leaf's own balanced halving down to single columns, levelled by height, the
+// same shape the global tree has below that node).  Offsets are local to the
+// leaf.  Per leaf size l: SubHdr[l] gives the first SubMerge of the size and,
+// for local level h < H, the merges [lv[h], lv[h+1]) of that level.
+struct SubMerge {
+    unsigned char off, nL, nR, pk;
+};
+struct SubHdr {
+    int mbase;
+    int H;
+    unsigned char lv[8];
+};
+
 // Device status bits (OR-ed into the status word at the start of the workspace).
 enum {
     ST_NONFINITE = 1,  // NaN or Inf in d or e
@@ -48,7 +62,12 @@ enum {
     CNT_LEAF_COLS = 5,   // columns solved by the QL leaf kernel
     CNT_LEAF_ROT = 6,    // plane rotations applied by the QL leaf kernel
     CNT_MERGE_COLS = 7,  // columns passed through merges (summed over levels)
-    CNT_N = 8
+    // the same work done inside leaves solved by divide and conquer in one wave
+    CNT_DC_TERMS = 8,      // pole-term evaluations in secular sweeps
+    CNT_DC_LOW_PAIRS = 9,  // (pole, root) pairs in the Loewner products
+    CNT_DC_ROW_PAIRS = 10, // (root, pole) pairs in the boundary-row dot products
+    CNT_DC_ROOTS = 11,     // secular roots solved
+    CNT_N = 12
 };
 
 // Launch kinds for the optional per-kernel timing.

@@ -171,6 +171,197 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
 }
 
 // ---------------------------------------------------------------------------
+// Leaves solved by divide and conquer inside one wave (one workgroup of 64
+// lanes per leaf of at most 64 columns).  The leaf's own merge tree (balanced
+// halving down to single columns, Section 3.1; levelled by height) runs level
+// by level with every level array in LDS, one lane per column or per root.
+// Each merge runs the same per-column and per-root steps as the global levels
+// (merged order and z~, negligible-z and close-pole deflation, secular roots,
+// Loewner z, boundary rows, three-list assembly); only the level-wide
+// compactions differ: a wave ballot replaces the block scans.  The leaf's top
+// merge writes its node's spectrum and rows to the global arrays (or the
+// scaled eigenvalues when the leaf is a whole problem).
+// ---------------------------------------------------------------------------
+constexpr int kDcCols = kLeafMax;  // columns of one in-wave leaf
+static_assert(kDcCols == 64, "one lane per column of an in-wave leaf");
+
+__global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leaves,
+                                               const SubHdr* __restrict__ shdr,
+                                               const SubMerge* __restrict__ smer,
+                                               const double* __restrict__ d, const double* __restrict__ e,
+                                               const unsigned long long* __restrict__ pmax, Work w,
+                                               double* __restrict__ out) {
+    if (input_nonfinite(w)) return;
+    constexpr int C = kDcCols;
+    __shared__ double sb[26 * C];
+    __shared__ int sbi[4 * C + 4 * (C + 1)];
+    __shared__ MergeRec smr[C / 2];
+    const LeafRec L = leaves[blockIdx.x];
+    const int l = L.size;
+    const int lane = threadIdx.x;
+    const double inv = 1.0 / scale_of(pmax[L.prob]);
+    const double* eL = e + L.off;  // merge records below carry leaf-local offsets
+
+    // level arrays in LDS
+    Work wl = w;
+    {
+        double* p = sb;
+        wl.lam = p; p += C;  wl.blo = p; p += C;  wl.bhi = p; p += C;
+        wl.D = p; p += C;    wl.Z = p; p += C;    wl.RL = p; p += C;   wl.RH = p; p += C;
+        wl.D2 = p; p += C;   wl.Z2 = p; p += C;   wl.RL2 = p; p += C;  wl.RH2 = p; p += C;
+        wl.Da = p; p += C;   wl.Za = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;
+        wl.RHa = p; p += C;  wl.tau = p; p += C;  wl.zhat = p; p += C; wl.PBL = p; p += C;
+        wl.PBH = p; p += C;  wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
+        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;
+        int* q = sbi;
+        wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = q; q += C;
+        wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
+    }
+    // destinations of the leaf's top merge
+    Work wt = wl;
+    wt.lam = w.lam + L.off;
+    wt.blo = w.blo + L.off;
+    wt.bhi = w.bhi + L.off;
+    wt.qfirst = w.qfirst ? w.qfirst + L.off : nullptr;
+    wt.qlast = w.qlast ? w.qlast + L.off : nullptr;
+    double* outL = out + L.off;
+
+    // single-column nodes: the torn diagonal (every coupling inside the leaf is
+    // torn, plus the leaf's own torn ends), first and last row 1
+    if (lane < l) {
+        double di = d[L.off + lane] * inv;
+        if (lane > 0 || (L.flags & LF_TEAR_LEFT)) di -= fabs(eL[lane - 1] * inv);
+        if (lane < l - 1 || (L.flags & LF_TEAR_RIGHT)) di -= fabs(eL[lane] * inv);
+        if (l == 1) {
+            if (L.flags & LF_WHOLE) {
+                outL[0] = di / inv;
+                if (w.rows_out) store_rows(wt, 0, 1.0, 1.0);
+            } else {
+                wt.lam[0] = di;
+                wt.blo[0] = 1.0;
+                wt.bhi[0] = 1.0;
+            }
+        }
+        wl.lam[lane] = di;
+        wl.blo[lane] = 1.0;
+        wl.bhi[lane] = 1.0;
+    }
+    if (lane == 0) {
+        atomicAdd(&w.counters[CNT_LEAF_COLS], (unsigned long long)l);
+    }
+    if (l <= 1) return;
+    const SubHdr* hd = shdr + l;  // read in place: a local copy of lv[] would live in scratch
+    const int H = hd->H, mbase = hd->mbase;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    unsigned long long terms = 0, roots = 0, lpairs = 0, rpairs = 0, mcols = 0;
+    int bad = 0;
+    for (int h = 0; h < H; ++h) {
+        const int m0 = hd->lv[h];
+        const int M = hd->lv[h + 1] - m0;
+        const bool top = (h == H - 1);
+        if (lane < M) {
+            const SubMerge s = smer[mbase + m0 + lane];
+            MergeRec R;
+            R.off = s.off;
+            R.pk = s.pk;
+            R.nL = s.nL;
+            R.nR = s.nR;
+            R.prob = L.prob;
+            R.flags = (top && (L.flags & LF_WHOLE)) ? MF_ROOT : 0;
+            smr[lane] = R;
+        }
+        __syncthreads();
+        const int N = (int)smr[M - 1].pk + smr[M - 1].nL + smr[M - 1].nR;
+        mcols += (lane == 0) ? (unsigned long long)N : 0ULL;
+        // merged order, z~, negligible-z flags (lane = child column; its flag
+        // lands with it at the merged position)
+        if (lane < N) {
+            int fl;
+            body_merge(lane, find_merge(smr, M, lane), smr, eL, pmax, wl, &fl);
+        }
+        __syncthreads();
+        const int f = (lane < N) ? wl.st[lane] : 0;
+        const unsigned long long cm = __ballot(f != 0);
+        if (lane < N) {
+            const int gc = (int)__popcll(cm & below);
+            wl.scanC[lane] = gc;
+            if (f) wl.nnpos[gc] = lane;
+        }
+        if (lane == 0) wl.scanC[N] = (int)__popcll(cm);
+        __syncthreads();
+        // close-pole runs
+        if (lane < (int)__popcll(cm)) body_runs(lane, find_merge(smr, M, wl.nnpos[lane]), smr, wl, [](long long) {});
+        __syncthreads();
+        // three-way split
+        const int s = (lane < N) ? wl.st[lane] : 0;
+        const unsigned long long am = __ballot(lane < N && s == 1);
+        const unsigned long long rm = __ballot(lane < N && s == 2);
+        const int g = (int)__popcll(am & below), gr = (int)__popcll(rm & below);
+        if (lane < N) {
+            wl.scan[lane] = g;
+            wl.scanR[lane] = gr;
+            if (s == 1) {
+                const double z = wl.Z2[lane];
+                wl.Da[g] = wl.D2[lane];
+                wl.Za[g] = z;
+                wl.Wa[g] = z * z;
+                wl.RLa[g] = wl.RL2[lane];
+                wl.RHa[g] = wl.RH2[lane];
+                wl.amerge[g] = find_merge(smr, M, lane);
+            } else if (s == 2) {
+                wl.Dr[gr] = wl.D2[lane];
+                wl.RLr[gr] = wl.RL2[lane];
+                wl.RHr[gr] = wl.RH2[lane];
+            } else {
+                const int q = lane - g - gr;
+                wl.Dd[q] = wl.D[lane];
+                wl.RLd[q] = wl.RL[lane];
+                wl.RHd[q] = wl.RH[lane];
+            }
+        }
+        if (lane == 0) {
+            wl.scan[N] = (int)__popcll(am);
+            wl.scanR[N] = (int)__popcll(rm);
+        }
+        __syncthreads();
+        // secular roots, Loewner z, boundary rows: one lane per active root
+        const int K = (int)__popcll(am);
+        const int m = (lane < K) ? wl.amerge[lane] : 0;
+        const bool rowsm = (lane < K) && (!(smr[m].flags & MF_ROOT) || w.rows_out);
+        int Km = 0;
+        if (lane < K) {
+            Km = merge_span(smr[m], wl.scan).K;
+            const int it = body_secular<RedSerial>(lane, m, smr, eL, pmax, wl, 0, 1, wl.Da, wl.Wa, 0);
+            if (it < 0) bad = 1;
+            const unsigned long long sw = (Km > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+            terms += sw * (unsigned long long)Km;
+            roots += 1;
+        }
+        __syncthreads();
+        if (lane < K) body_lowner<RedSerial>(lane, m, smr, eL, pmax, wl, 0, 1, wl.Da, wl.org, wl.tau, 0);
+        __syncthreads();
+        if (lane < K) body_rows<RedSerial>(lane, m, smr, wl, 0, 1, wl.Da, wl.zhat, wl.RLa, wl.RHa, 0);
+        if (rowsm) {
+            lpairs += (unsigned long long)Km;
+            rpairs += (unsigned long long)Km;
+        }
+        __syncthreads();
+        // parent spectra and rows (in place), or the leaf's outputs
+        if (lane < N) {
+            if (top) body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wt, outL);
+            else body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wl, outL);
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(w.status, ST_SEC_NOCONV);
+    count_add(&w.counters[CNT_DC_TERMS], terms);
+    count_add(&w.counters[CNT_DC_ROOTS], roots);
+    count_add(&w.counters[CNT_DC_LOW_PAIRS], lpairs);
+    count_add(&w.counters[CNT_DC_ROW_PAIRS], rpairs);
+    count_add(&w.counters[CNT_MERGE_COLS], mcols);
+}
+
+// ---------------------------------------------------------------------------
 // Level steps.  Element-parallel kernels find the merge of packed position t
 // inside [blkm[t/kWG], blkm[t/kWG + 1]] (a static per-block table of the
 // plan), so each lookup searches only the few merges a block touches.
@@ -1389,7 +1580,11 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
-    if (p.nleaves > 0) {
+    if (p.nleaves > 0 && p.leaf_dc && !ck) {
+        // the checkpointing forward keeps the QL leaves the reverse pass differentiates
+        TDE_LAUNCH_K(KIND_LEAF, k_leaf_dc, (unsigned)p.nleaves, 64, stream, p.d_leaves, p.d_shdr, p.d_smer, d, e,
+                     (const unsigned long long*)w.pmax, w, out);
+    } else if (p.nleaves > 0) {
         const unsigned g = nblk(p.nleaves, 64);
         if (p.leafmax <= 8)
             TDE_LAUNCH_K(KIND_LEAF, k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);

@@ -25,6 +25,7 @@ struct Plan {
     int leaf = 32;
     int sweep_cols = 8;  // target poles per lane in the root-parallel sweeps
     int wide_min = kWideMin;  // merges with at least this many active roots use the wide secular sweep
+    bool leaf_dc = false;     // forward passes solve the leaves by divide and conquer inside one wave
     int nleaves = 0;
     int leafmax = 1;     // largest leaf size in the plan
     int maxM = 1;        // most merges in one level
@@ -37,6 +38,8 @@ struct Plan {
     int* d_blkm = nullptr;     // per level, per block of kWG packed columns: first merge touched
     LeafRec* d_leaves = nullptr;
     long long* d_offs = nullptr;
+    SubHdr* d_shdr = nullptr;      // [kLeafMax+1] in-wave merge trees by leaf size (leaf_dc)
+    SubMerge* d_smer = nullptr;
 };
 
 // Workspace layout for n packed columns, B problems and maxM merges per level.
