@@ -392,17 +392,48 @@ TDE_DEV void sec_sweep(int K, const double* __restrict__ D, const double* __rest
                        int L1, int R0, int sub, int G, double* s) {
     double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0, zz = 0.0;
     const unsigned exw = (unsigned)(R0 - L1);
-    _Pragma("unroll 4") for (int j = sub; j < K; j += G) {
-        const double rr = rcp_nr((D[j] - Do) - tau);
-        const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : W[j];
+    auto term = [&](int j, double dj, double wr) {
+        const double rr = rcp_nr((dj - Do) - tau);
+        const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : wr;
         const double t = wj * rr;
         const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
         ps += tl;
         dps = fma(tl, rr, dps);
         ph += th;
         dph = fma(th, rr, dph);
-        if (ZZ) zz += W[j];
+        if (ZZ) zz += wr;
+    };
+    int j = sub;
+    // four terms per step; the next step's poles and weights are loaded
+    // before this step's terms are evaluated, so the loads overlap the math
+    if (j + 3 * G < K) {
+        double a0 = D[j], a1 = D[j + G], a2 = D[j + 2 * G], a3 = D[j + 3 * G];
+        double b0 = W[j], b1 = W[j + G], b2 = W[j + 2 * G], b3 = W[j + 3 * G];
+        for (;;) {
+            const int jn = j + 4 * G;
+            const bool more = jn + 3 * G < K;
+            double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, e0 = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+            if (more) {
+                c0 = D[jn];
+                c1 = D[jn + G];
+                c2 = D[jn + 2 * G];
+                c3 = D[jn + 3 * G];
+                e0 = W[jn];
+                e1 = W[jn + G];
+                e2 = W[jn + 2 * G];
+                e3 = W[jn + 3 * G];
+            }
+            term(j, a0, b0);
+            term(j + G, a1, b1);
+            term(j + 2 * G, a2, b2);
+            term(j + 3 * G, a3, b3);
+            j = jn;
+            if (!more) break;
+            a0 = c0; a1 = c1; a2 = c2; a3 = c3;
+            b0 = e0; b1 = e1; b2 = e2; b3 = e3;
+        }
     }
+    for (; j < K; j += G) term(j, D[j], W[j]);
     s[0] = Red::sum(ps);
     s[1] = Red::sum(dps);
     s[2] = Red::sum(ph);
