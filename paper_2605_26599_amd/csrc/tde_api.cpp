@@ -406,8 +406,16 @@ int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n) {
     if (!ws || !out || n < 0) return TDE_EINVAL;
     if (n > tde::CNT_N) n = tde::CNT_N;
     if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return TDE_EDEVICE;
-    if (n && hipMemcpy(out, (const char*)ws + 64, sizeof(uint64_t) * n, hipMemcpyDeviceToHost) != hipSuccess)
+    if (n == 0) return TDE_OK;
+    std::vector<uint64_t> slots((size_t)n * tde::kCntSlots);
+    if (hipMemcpy(slots.data(), (const char*)ws + tde::kCntOffset, sizeof(uint64_t) * slots.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
         return TDE_EDEVICE;
+    for (int c = 0; c < n; ++c) {
+        uint64_t v = 0;
+        for (int k = 0; k < tde::kCntSlots; ++k) v += slots[(size_t)c * tde::kCntSlots + k];
+        out[c] = v;
+    }
     return TDE_OK;
 }
 

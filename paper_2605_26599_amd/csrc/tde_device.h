@@ -564,6 +564,41 @@ TDE_DEV void root_rows(int K, const double* __restrict__ D, const double* __rest
 // (a3/a4) z~, outer rows and merged sorted order of one child column.
 // Left column i: position i + #{right values < x}; right column j:
 // j + #{left values <= x} (ties go left first).  Returns the packed position.
+// The deflation tolerance of merge R from its children's spectra (the same
+// value as merge_tol on the merged poles: the ends of both sorted children).
+TDE_DEV double merge_tol_children(const MergeRec& R, const Work& w) {
+    const double* lamL = w.lam + R.off;
+    const double* lamR = lamL + R.nL;
+    const double dmax = fmax(fmax(fabs(lamL[0]), fabs(lamL[R.nL - 1])), fmax(fabs(lamR[0]), fabs(lamR[R.nR - 1])));
+    return 8.0 * DBL_EPSILON * fmax(dmax, 1.0);
+}
+
+// Writes merged position P: child column c (local index in the parent, left
+// child first) with eigenvalue x; z~ and the outer rows from that child's
+// boundary rows; (a5) the negligible-z flag, a candidate iff rho~ |z~| > tol.
+TDE_DEV int merge_emit(const MergeRec& R, int c, double x, double rho, double sgn, double tol, const Work& w,
+                       long long P) {
+    const double rs2 = 0.70710678118654752440;  // 1/sqrt(2)
+    double z, rl, rh;
+    if (c < R.nL) {
+        z = w.bhi[R.off + c] * rs2;
+        rl = w.blo[R.off + c];
+        rh = 0.0;
+    } else {
+        z = sgn * w.blo[R.off + c] * rs2;
+        rl = 0.0;
+        rh = w.bhi[R.off + c];
+    }
+    w.D[P] = x;
+    w.Z[P] = z;
+    w.RL[P] = rl;
+    w.RH[P] = rh;
+    w.src[P] = c;
+    const int flag = (rho * fabs(z) > tol) ? 1 : 0;
+    w.st[P] = flag;
+    return flag;
+}
+
 TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr,
                              const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
                              const Work& w, int* flag_out) {
@@ -573,12 +608,9 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
     const double rho = merge_rho(R, e, pmax, &sgn);
     const double* lamL = w.lam + R.off;
     const double* lamR = lamL + R.nL;
-    // the same value as merge_tol on the merged poles (the ends of both sorted children)
-    const double dmax = fmax(fmax(fabs(lamL[0]), fabs(lamL[R.nL - 1])), fmax(fabs(lamR[0]), fabs(lamR[R.nR - 1])));
-    const double tol = 8.0 * DBL_EPSILON * fmax(dmax, 1.0);
-    const double rs2 = 0.70710678118654752440;  // 1/sqrt(2)
+    const double tol = merge_tol_children(R, w);
     int pos;
-    double x, z, rl, rh;
+    double x;
     if (i < R.nL) {
         x = lamL[i];
         int lo = 0, hi = R.nR;
@@ -588,9 +620,6 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
             else hi = mid;
         }
         pos = i + lo;
-        z = w.bhi[R.off + i] * rs2;
-        rl = w.blo[R.off + i];
-        rh = 0.0;
     } else {
         const int j = i - R.nL;
         x = lamR[j];
@@ -601,20 +630,9 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
             else hi = mid;
         }
         pos = j + lo;
-        z = sgn * w.blo[R.off + R.nL + j] * rs2;
-        rl = 0.0;
-        rh = w.bhi[R.off + R.nL + j];
     }
     const long long P = R.pk + pos;
-    w.D[P] = x;
-    w.Z[P] = z;
-    w.RL[P] = rl;
-    w.RH[P] = rh;
-    w.src[P] = i;
-    // (a5) negligible-z test: the column stays a candidate iff rho~ |z~_j| > tol
-    const int flag = (rho * fabs(z) > tol) ? 1 : 0;
-    w.st[P] = flag;
-    *flag_out = flag;
+    *flag_out = merge_emit(R, i, x, rho, sgn, tol, w, P);
     return P;
 }
 

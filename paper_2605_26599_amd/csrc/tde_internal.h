@@ -69,6 +69,11 @@ enum {
     CNT_DC_ROOTS = 11,     // secular roots solved
     CNT_N = 12
 };
+// Each counter is spread over kCntSlots words (a launch's waves add into
+// different slots, so their atomics do not queue on one address); readers sum
+// the slots.  The slots sit at byte kCntOffset of the workspace.
+constexpr int kCntSlots = 64;
+constexpr int kCntOffset = 256;
 
 // Launch kinds for the optional per-kernel timing.
 enum {
@@ -89,7 +94,7 @@ constexpr int kSelfScanMax = 2048;  // up to this many blocks per level, blocks 
 // Pointers into the caller's workspace for one solve.
 struct Work {
     int* status;               // [1]   device status bits
-    unsigned long long* counters;  // [8] algorithmic work of the last solve (CNT_*)
+    unsigned long long* counters;  // [CNT_N][kCntSlots] algorithmic work of the last solve (CNT_*)
     unsigned long long* pmax;  // [B]   bits of max |d|,|e| per problem
     double* lam;               // [n]   node spectra (ascending per node)
     double* blo;               // [n]   node first eigenvector row

@@ -40,10 +40,18 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Adds a per-lane count to a work counter with one atomic per wave.
-__device__ __forceinline__ void count_add(unsigned long long* c, unsigned long long v) {
+// Adds a per-lane count to work counter `which` with one atomic per wave,
+// into the slot of this wave.
+__device__ __forceinline__ unsigned long long* count_slot(unsigned long long* c, int which) {
+    return c + which * kCntSlots + (((blockIdx.x << 2) + (threadIdx.x >> 6)) & (kCntSlots - 1));
+}
+__device__ __forceinline__ void count_add(unsigned long long* c, int which, unsigned long long v) {
     v = wave_sum_u64(v);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(c, v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(count_slot(c, which), v);
+}
+// The same for a count held by one lane.
+__device__ __forceinline__ void count_add1(unsigned long long* c, int which, unsigned long long v) {
+    if (v) atomicAdd(count_slot(c, which), v);
 }
 
 // Non-finite input (flagged by k_maxabs, the first kernel of a pass): every
@@ -166,8 +174,8 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
     unsigned nrot = 0;
     const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64, &nrot);
     if (st) atomicOr(w.status, st);
-    atomicAdd(&w.counters[CNT_LEAF_COLS], (unsigned long long)L.size);
-    atomicAdd(&w.counters[CNT_LEAF_ROT], (unsigned long long)nrot);
+    count_add1(w.counters, CNT_LEAF_COLS, (unsigned long long)L.size);
+    count_add1(w.counters, CNT_LEAF_ROT, (unsigned long long)nrot);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
         wl.bhi[lane] = 1.0;
     }
     if (lane == 0) {
-        atomicAdd(&w.counters[CNT_LEAF_COLS], (unsigned long long)l);
+        count_add1(w.counters, CNT_LEAF_COLS, (unsigned long long)l);
     }
     if (l <= 1) return;
     const SubHdr* hd = shdr + l;  // read in place: a local copy of lv[] would live in scratch
@@ -354,11 +362,11 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
         __syncthreads();
     }
     if (bad) atomicOr(w.status, ST_SEC_NOCONV);
-    count_add(&w.counters[CNT_DC_TERMS], terms);
-    count_add(&w.counters[CNT_DC_ROOTS], roots);
-    count_add(&w.counters[CNT_DC_LOW_PAIRS], lpairs);
-    count_add(&w.counters[CNT_DC_ROW_PAIRS], rpairs);
-    count_add(&w.counters[CNT_MERGE_COLS], mcols);
+    count_add(w.counters, CNT_DC_TERMS, terms);
+    count_add(w.counters, CNT_DC_ROOTS, roots);
+    count_add(w.counters, CNT_DC_LOW_PAIRS, lpairs);
+    count_add(w.counters, CNT_DC_ROW_PAIRS, rpairs);
+    count_add(w.counters, CNT_MERGE_COLS, mcols);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +404,7 @@ __global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, 
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     int f = 0, pb = -1;
     if (t < N) pb = (int)(body_merge(t, merge_of(mr, blkm, t), mr, e, pmax, w, &f) / kWG);
-    count_add(&w.counters[CNT_MERGE_COLS], t < N ? 1ULL : 0ULL);
+    if (t == 0) count_add1(w.counters, CNT_MERGE_COLS, (unsigned long long)N);
     // one atomic per distinct position block among the wave's columns
     const int lane = threadIdx.x & 63;
     bool pending = pb >= 0;
@@ -410,6 +418,103 @@ __global__ __launch_bounds__(kWG) void k_merge(const MergeRec* __restrict__ mr, 
         if (lane == leader && fm) atomicAdd(&w.bsumA[lpb], (int)__popcll(fm));
         pending = pending && !mine;
     }
+}
+
+// The same by output position (merge path), for levels of large merges: block b writes packed positions
+// [b kWG, (b+1) kWG).  For each merge piece the block covers, the co-ranks
+// of the piece's two ends (how many left-child values precede them) are found
+// cooperatively, half the block per end, 128 probes a round, so a merge of
+// s columns needs about log_128(s) dependent global reads instead of log2(s)
+// per column; the two child slices are then staged in LDS and every thread
+// places its own position with a search inside them.  Ties go left first, as
+// in body_merge.  The block's candidate count is added to bsumA[b].
+//
+// co-rank(p) = smallest i in [max(0, p - nR), min(p, nL)] with
+// i == min(p, nL) or lamL[i] > lamR[p - i - 1].
+__device__ __forceinline__ bool corank_pred(const double* __restrict__ lamL, const double* __restrict__ lamR,
+                                            int p, int i, int hi) {
+    return (i >= hi) || (lamL[i] > lamR[p - i - 1]);
+}
+
+__global__ __launch_bounds__(kWG) void k_merge_path(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                    long long N, const double* __restrict__ e,
+                                                    const unsigned long long* __restrict__ pmax, Work w) {
+    if (input_nonfinite(w)) return;
+    __shared__ double sL[kWG], sR[kWG];
+    __shared__ int s_k[4];
+    __shared__ int s_co[2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, half = tid >> 7, kt = tid & 127;
+    const long long p0 = (long long)blockIdx.x * kWG;
+    const long long p1 = (p0 + kWG < N) ? p0 + kWG : N;
+    const long long P = p0 + tid;
+    int f = 0;
+    const int mfirst = blkm[blockIdx.x], mlast = blkm[blockIdx.x + 1];
+    for (int m = mfirst; m <= mlast; ++m) {
+        const MergeRec R = mr[m];
+        const int s = R.nL + R.nR;
+        const long long ga = (p0 > R.pk) ? p0 : R.pk;
+        const long long gb = (p1 < R.pk + s) ? p1 : R.pk + s;
+        if (ga >= gb) continue;  // block-uniform
+        const int a = (int)(ga - R.pk), bnd = (int)(gb - R.pk);
+        const double* lamL = w.lam + R.off;
+        const double* lamR = lamL + R.nL;
+        // co-ranks of a (first half) and bnd (second half)
+        const int pe = half ? bnd : a;
+        int lo = (pe - R.nR > 0) ? pe - R.nR : 0;
+        int hi = (pe < R.nL) ? pe : R.nL;
+        const int hi0 = hi;
+        for (int round = 0; round < 8; ++round) {
+            const bool active = hi > lo;
+            if (!__syncthreads_or(active)) break;
+            const int r = hi - lo;
+            const int step = (r + 127) / 128;
+            if (active) {
+                const long long i = (long long)lo + (long long)kt * step;
+                const bool t = (i >= hi) || corank_pred(lamL, lamR, pe, (int)i, hi0);
+                const unsigned long long bm = __ballot(t);
+                if (lane == 0) s_k[wv] = bm ? (wv & 1) * 64 + __ffsll((long long)bm) - 1 : 128;
+            }
+            __syncthreads();
+            if (active) {
+                const int k = min(s_k[2 * half], s_k[2 * half + 1]);
+                const int nhi = (k < 128) ? lo + k * step : hi;
+                const int nlo = (k == 0) ? lo : lo + (k - 1) * step + 1;
+                lo = nlo;
+                hi = nhi < hi ? nhi : hi;
+            }
+        }
+        if (kt == 0) s_co[half] = lo;
+        __syncthreads();
+        const int ia = s_co[0], ib = s_co[1];
+        const int ja = a - ia, jb = bnd - ib;
+        // stage the two slices
+        if (tid < ib - ia && ia + tid < R.nL) sL[tid] = lamL[ia + tid];
+        if (tid < jb - ja && ja + tid < R.nR) sR[tid] = lamR[ja + tid];
+        __syncthreads();
+        const int p = (int)(P - R.pk);
+        if (P >= ga && P < gb) {
+            // co-rank of p inside the slices
+            int l2 = (p - jb > ia) ? p - jb : ia;
+            int h2 = (p - ja < ib) ? p - ja : ib;
+            const int h20 = h2;
+            while (l2 < h2) {
+                const int mid = (l2 + h2) >> 1;
+                if (mid >= h20 || sL[mid - ia] > sR[p - mid - 1 - ja]) h2 = mid;
+                else l2 = mid + 1;
+            }
+            const int i = l2, j = p - i;
+            const bool left = (i < ib) && (j >= jb || sL[i - ia] <= sR[j - ja]);
+            double sgn;
+            const double rho = merge_rho(R, e, pmax, &sgn);
+            const double tol = merge_tol_children(R, w);
+            const double x = left ? sL[i - ia] : sR[j - ja];
+            f = merge_emit(R, left ? i : R.nL + j, x, rho, sgn, tol, w, P);
+        }
+        __syncthreads();  // slices and s_co are reused by the next piece
+    }
+    const int cnt = __syncthreads_count(f);
+    if (tid == 0 && cnt) atomicAdd(&w.bsumA[blockIdx.x], cnt);
+    if (P == 0) count_add1(w.counters, CNT_MERGE_COLS, (unsigned long long)N);
 }
 
 // Compaction of candidate (st == 1) columns: scanC[t] = exclusive count,
@@ -746,9 +851,9 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
     }
     if (bad && wv == 0 && lane == 0) atomicOr(w.status, ST_SEC_NOCONV);
     if (wv == 0) {
-        count_add(&w.counters[CNT_SEC_TERMS], terms);
-        count_add(&w.counters[CNT_SWEEPS], sweeps);
-        count_add(&w.counters[CNT_ROOTS], roots);
+        count_add(w.counters, CNT_SEC_TERMS, terms);
+        count_add(w.counters, CNT_SWEEPS, sweeps);
+        count_add(w.counters, CNT_ROOTS, roots);
     }
 }
 
@@ -819,7 +924,7 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
         }
         __syncthreads();
     }
-    if (wv == 0) count_add(&w.counters[CNT_LOW_PAIRS], pairs);
+    if (wv == 0) count_add(w.counters, CNT_LOW_PAIRS, pairs);
 }
 
 // Wide boundary-row step (non-top merges): 64 roots per workgroup, the poles
@@ -873,7 +978,7 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
         }
         __syncthreads();
     }
-    if (wv == 0) count_add(&w.counters[CNT_ROW_PAIRS], pairs);
+    if (wv == 0) count_add(w.counters, CNT_ROW_PAIRS, pairs);
 }
 
 // Root-parallel kernels.  Blocks [0, nbn) take tiles of consecutive active
@@ -1056,9 +1161,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
     }
     if (bad && sub == 0) atomicOr(w.status, ST_SEC_NOCONV);
-    count_add(&w.counters[CNT_SEC_TERMS], terms);
-    count_add(&w.counters[CNT_SWEEPS], sweeps);
-    count_add(&w.counters[CNT_ROOTS], roots);
+    count_add(w.counters, CNT_SEC_TERMS, terms);
+    count_add(w.counters, CNT_SWEEPS, sweeps);
+    count_add(w.counters, CNT_ROOTS, roots);
 }
 
 template <int G, bool WithRoot>
@@ -1109,7 +1214,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
         }
         __syncthreads();
     }
-    count_add(&w.counters[CNT_LOW_PAIRS], pairs);
+    count_add(w.counters, CNT_LOW_PAIRS, pairs);
 }
 
 template <int G>
@@ -1160,7 +1265,7 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
         }
         __syncthreads();
     }
-    count_add(&w.counters[CNT_ROW_PAIRS], pairs);
+    count_add(w.counters, CNT_ROW_PAIRS, pairs);
 }
 
 __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
@@ -1544,6 +1649,20 @@ static void launch_roots(int smax, int cols, int wmin, long long N, const MergeR
     }
 }
 
+// Merged order of one level: by output position (merge path) when the level's
+// merges average at least kMergePathMin columns, else one thread per input
+// column with its own binary search (few steps for small merges).
+constexpr long long kMergePathMin = 1024;
+static void launch_merge(int kind, const LevelInfo& L, const MergeRec* mr, const int* blkm, const double* e,
+                         const Work& wl, void* stream) {
+    const unsigned nb = nblk(L.N, kWG);
+    const unsigned long long* pm = (const unsigned long long*)wl.pmax;
+    if (L.N >= kMergePathMin * (long long)L.M)
+        TDE_LAUNCH_K(kind, k_merge_path, nb, kWG, stream, mr, blkm, L.N, e, pm, wl);
+    else
+        TDE_LAUNCH_K(kind, k_merge, nb, kWG, stream, mr, blkm, L.N, e, pm, wl);
+}
+
 // Deflation steps of one level (shared by the forward and the reverse pass):
 // negligible-z flags, candidate compaction, close-pole runs, three-way split.
 static void enqueue_deflate(const MergeRec* mr, const int* blkm, long long N, const Work& wl, void* stream) {
@@ -1576,7 +1695,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
                   const Ckpt* ck) {
     if (p.ntot == 0) return 0;
     TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 256, stream, w.counters, (long long)CNT_N * kCntSlots, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
@@ -1612,7 +1731,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             wl.org = ck->org + so;
             wl.tau = ck->tau + so;
         }
-        TDE_LAUNCH_K(KIND_MERGE, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
@@ -1641,7 +1760,7 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
     if (p.ntot == 0) return 0;
     const long long cs = p.ntot;  // coefficient plane stride
     TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 64, stream, w.counters, (long long)CNT_N, 0ULL);
+    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 256, stream, w.counters, (long long)CNT_N * kCntSlots, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
@@ -1663,7 +1782,7 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
         wl.bhi = ck.bhi + so;
         wl.org = ck.org + so;
         wl.tau = ck.tau + so;
-        TDE_LAUNCH_K(KIND_BACKWARD, k_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax, wl);
+        launch_merge(KIND_BACKWARD, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
@@ -1714,9 +1833,9 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     const long long nn = n > 0 ? n : 1;
     const long long nb = (nn + kWG - 1) / kWG + 2;
     Work t{};
-    t.status = (int*)take(256);
-    t.counters = t.status ? (unsigned long long*)((char*)t.status + 64) : nullptr;
+    t.status = (int*)take(kCntOffset);
     t.ticket = t.status ? (unsigned*)((char*)t.status + 16) : nullptr;
+    t.counters = (unsigned long long*)take(sizeof(unsigned long long) * CNT_N * kCntSlots);
     t.pmax = (unsigned long long*)take(sizeof(unsigned long long) * (B > 0 ? B : 1));
     t.lam = (double*)take(8 * nn);
     t.blo = (double*)take(8 * nn);
