@@ -667,7 +667,8 @@ static_assert(64 * kWideWaves == kWG, "wide blocks share the regular kernels' wo
 static_assert(2 * 5 * kWideWaves * 64 <= 2 * 2048, "wide reduction buffers fit the regular kernels' LDS staging area");
 
 // Exclusive scan of the number of 64-root blocks of every wide merge of a level.
-__global__ __launch_bounds__(1024) void k_wide_items(const MergeRec* __restrict__ mr, int M, Work w, int wide_min) {
+__global__ __launch_bounds__(1024) void k_wide_items(const MergeRec* __restrict__ mr, int M, Work w, int wide_min,
+                                                     int fuse_max) {
     if (input_nonfinite(w)) return;
     __shared__ int wsum[16];
     __shared__ int carry;
@@ -678,7 +679,7 @@ __global__ __launch_bounds__(1024) void k_wide_items(const MergeRec* __restrict_
         int v = 0;
         if (m < M) {
             const int K = merge_span(mr[m], w.scan).K;
-            v = (K >= wide_min) ? (K + 63) / 64 : 0;
+            v = (K >= wide_min && K > fuse_max) ? (K + 63) / 64 : 0;
         }
         const int incl = block_incl_scan(v, wsum);
         const int c = carry;
@@ -1001,7 +1002,7 @@ constexpr long long kRefillLanes = 1048576;
 template <int G>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(
     const MergeRec* __restrict__ mr, int M, long long N, const double* __restrict__ e,
-    const unsigned long long* __restrict__ pmax, Work w, int wide_min, int nbn, int refill) {
+    const unsigned long long* __restrict__ pmax, Work w, int wide_min, int fuse_max, int nbn, int refill) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
@@ -1040,7 +1041,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
             __syncthreads();
             const long long g = g0 + threadIdx.x / G;
             const int mg = (g < total) ? w.amerge[g] : 0;
-            if (g < total && merge_span(mr[mg], w.scan).K < wide_min) {
+            const int Kg = (g < total) ? merge_span(mr[mg], w.scan).K : 0;
+            if (g < total && Kg < wide_min && Kg > fuse_max) {
                 const int it = (ns >= 0) ? body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, sD, sW, r0)
                                          : body_secular<RedGroup<G>>(g, mg, mr, e, pmax, w, sub, G, w.Da, w.Wa, 0);
                 if (it < 0) bad = 1;
@@ -1091,7 +1093,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                 g = g0 + slot;
                 const MergeRec R = mr[w.amerge[g]];
                 const MergeSpan sp = merge_span(R, w.scan);
-                if (sp.K >= wide_min) {  // solved by the wide blocks
+                if (sp.K >= wide_min || sp.K <= fuse_max) {  // solved by the wide blocks or k_small_merge
                     g = -1;
                     continue;
                 }
@@ -1166,11 +1168,107 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     count_add(w.counters, CNT_ROOTS, roots);
 }
 
+// ---------------------------------------------------------------------------
+// Merges with at most kFuseMax active roots (after deflation): one workgroup
+// of kFuseThreads per merge runs the secular roots, the Loewner z and the
+// boundary rows with the merge's active arrays staged in LDS once, with
+// G = min(16, kFuseThreads / K) lanes per root or pole rounded down to a power
+// of two (the same device functions as the level-wide kernels, which skip
+// these merges).  G depends on K alone, so a merge's arithmetic does not
+// depend on the rest of its level (a batched solve matches the single ones
+// bit for bit).  On random spectra nearly every merge is of this kind (a
+// hundred or so roots survive deflation).
+// ---------------------------------------------------------------------------
+constexpr int kFuseMax = 512;
+constexpr int kFuseThreads = 512;
+
+template <int NT, int G>
+__device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long long ks, double rho, const Work& w,
+                                                 double* sD, double* sW, double* sZ, double* sT, double* sH,
+                                                 double* sL, double* sR, int* sO) {
+    const int sub = threadIdx.x % G, grp = threadIdx.x / G, ng = NT / G;
+    int bad = 0;
+    unsigned long long terms = 0, sweeps = 0, roots = 0, pairs = 0;
+    for (int k = grp; k < K; k += ng) {
+        int o;
+        double tau;
+        const int it = secular_root<RedGroup<G>>(k, K, sD, sZ, sW, rho, sub, G, &o, &tau);
+        if (it < 0) bad = 1;
+        if (sub == 0) {
+            sO[k] = o;
+            sT[k] = tau;
+            const unsigned long long sw = (K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+            sweeps += sw;
+            terms += sw * (unsigned long long)K;
+            roots += 1;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < K; i += NT) {
+        w.org[ks + i] = sO[i];
+        w.tau[ks + i] = sT[i];
+    }
+    if (!(R.flags & MF_ROOT) || w.rows_out) {
+        for (int i = grp; i < K; i += ng) {
+            const double zh = lowner_z<RedGroup<G>>(i, K, sD, sZ, sO, sT, rho, sub, G);
+            if (sub == 0) {
+                sH[i] = zh;
+                w.zhat[ks + i] = zh;
+                pairs += (unsigned long long)K;
+            }
+        }
+        __syncthreads();
+        for (int k = grp; k < K; k += ng) {
+            double bl, bh;
+            root_rows<RedGroup<G>>(K, sD, sH, sL, sR, sO[k], sT[k], sub, G, &bl, &bh);
+            if (sub == 0) {
+                w.PBL[ks + k] = bl;
+                w.PBH[ks + k] = bh;
+            }
+        }
+    }
+    if (bad && sub == 0) atomicOr(w.status, ST_SEC_NOCONV);
+    count_add(w.counters, CNT_SEC_TERMS, terms);
+    count_add(w.counters, CNT_SWEEPS, sweeps);
+    count_add(w.counters, CNT_ROOTS, roots);
+    count_add(w.counters, CNT_LOW_PAIRS, pairs);
+    count_add(w.counters, CNT_ROW_PAIRS, pairs);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                                    const unsigned long long* __restrict__ pmax, Work w) {
+    if (input_nonfinite(w)) return;
+    const MergeRec R = mr[blockIdx.x];
+    const MergeSpan sp = merge_span(R, w.scan);
+    const int K = sp.K;
+    if (K < 1 || K > kFuseMax) return;  // block-uniform
+    __shared__ double sD[kFuseMax], sW[kFuseMax], sZ[kFuseMax], sT[kFuseMax], sH[kFuseMax], sL[kFuseMax],
+        sR[kFuseMax];
+    __shared__ int sO[kFuseMax];
+    const long long ks = sp.ks;
+    for (int i = threadIdx.x; i < K; i += NT) {
+        sD[i] = w.Da[ks + i];
+        sW[i] = w.Wa[ks + i];
+        sZ[i] = w.Za[ks + i];
+        sL[i] = w.RLa[ks + i];
+        sR[i] = w.RHa[ks + i];
+    }
+    double sgn;
+    const double rho = merge_rho(R, e, pmax, &sgn);
+    __syncthreads();
+    if (K <= NT / 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+    else if (K <= NT / 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+    else if (K <= NT / 4) small_merge_body<NT, 4>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+    else if (K <= NT / 2) small_merge_body<NT, 2>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+    else small_merge_body<NT, 1>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+}
+
 template <int G, bool WithRoot>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
-                                                int nbn) {
+                                                int fuse_max, int nbn) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ int sO[kStage];
@@ -1206,7 +1304,8 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
             }
         __syncthreads();
         const long long g = g0 + threadIdx.x / G;
-        if (g < total && merge_span(mr[w.amerge[g]], w.scan).K < wide_min) {
+        const int Kg = (g < total) ? merge_span(mr[w.amerge[g]], w.scan).K : 0;
+        if (g < total && Kg < wide_min && Kg > fuse_max) {
             const int m = w.amerge[g];
             if (ns >= 0) body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, sD, sO, sT, r0, WithRoot);
             else body_lowner<RedGroup<G>>(g, m, mr, e, pmax, w, sub, G, w.Da, w.org, w.tau, 0, WithRoot);
@@ -1219,7 +1318,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
 
 template <int G>
 __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w,
-                                              int wide_min, int nbn) {
+                                              int wide_min, int fuse_max, int nbn) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[4 * kStageRows];
     __shared__ long long s_r0;
@@ -1257,7 +1356,8 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
             }
         __syncthreads();
         const long long g = g0 + threadIdx.x / G;
-        if (g < total && merge_span(mr[w.amerge[g]], w.scan).K < wide_min) {
+        const int Kg = (g < total) ? merge_span(mr[w.amerge[g]], w.scan).K : 0;
+        if (g < total && Kg < wide_min && Kg > fuse_max) {
             const int m = w.amerge[g];
             if (ns >= 0) body_rows<RedGroup<G>>(g, m, mr, w, sub, G, sD, sH, sL, sR, r0);
             else body_rows<RedGroup<G>>(g, m, mr, w, sub, G, w.Da, w.zhat, w.RLa, w.RHa, 0);
@@ -1621,21 +1721,27 @@ static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw) {
 template <int G>
 static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
                            const Work& w, void* stream) {
+    const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    const int fuse_max = kFuseMax;
+    // merges with at most kFuseMax active roots: one workgroup each
+    TDE_LAUNCH_K(KIND_SECULAR, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
+    if (smax <= kFuseMax) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
     int nbn, nbw;
     root_grid(N, G, wide, &nbn, &nbw);
+    // every merge too large for k_small_merge is wide: no regular tiles
+    if (wide_min <= fuse_max + 1) nbn = 0;
     const unsigned grid = (unsigned)(nbn + nbw);
-    const unsigned long long* pm = (const unsigned long long*)w.pmax;
     // one k_wide_items launch serves the three root kernels of the level
-    if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
+    if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, fuse_max);
     long long rf = (N * G) / kRefillLanes;  // roots per group: keep about kRefillLanes lanes busy
     rf = rf < 1 ? 1 : (rf > kRefillMax ? kRefillMax : rf);
     const int nbs = (int)((nbn + rf - 1) / rf);
-    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min, nbs,
-                 (int)rf);
-    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, nbn);
-    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, nbn);
+    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
+                 fuse_max, nbs, (int)rf);
+    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn);
+    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn);
 }
 
 static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
@@ -1748,8 +1854,8 @@ static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* 
     int nbn, nbw;
     root_grid(N, G, wide, &nbn, &nbw);
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
-    if (wide) TDE_LAUNCH_K(KIND_BACKWARD, k_wide_items, 1, 1024, stream, mr, M, w, wide_min);
-    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
+    if (wide) TDE_LAUNCH_K(KIND_BACKWARD, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, 0);
+    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min, 0,
                  nbn);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
