@@ -93,10 +93,14 @@ def timed(step, steps):
 
 def roofline(tde, kinds, cnt, steps):
     """Roofline entry for the kernel kind that took the most time."""
+    # the level-wide kernels' share of the work (the fused small-merge kernel
+    # counts its own part separately)
     work = {
-        "secular": ("alu", cnt["secular_terms"] * FLOPS_PER_SEC_TERM),
-        "lowner": ("alu", cnt["lowner_pairs"] * FLOPS_PER_LOW_PAIR),
-        "rows": ("alu", cnt["row_pairs"] * FLOPS_PER_ROW_PAIR),
+        "secular": ("alu", (cnt["secular_terms"] - cnt["small_secular_terms"]) * FLOPS_PER_SEC_TERM),
+        "lowner": ("alu", (cnt["lowner_pairs"] - cnt["small_lowner_pairs"]) * FLOPS_PER_LOW_PAIR),
+        "rows": ("alu", (cnt["row_pairs"] - cnt["small_row_pairs"]) * FLOPS_PER_ROW_PAIR),
+        "small": ("alu", cnt["small_secular_terms"] * FLOPS_PER_SEC_TERM + cnt["small_lowner_pairs"] * FLOPS_PER_LOW_PAIR
+                  + cnt["small_row_pairs"] * FLOPS_PER_ROW_PAIR),
         # QL leaves: rotations; leaves solved by divide and conquer in one wave:
         # the secular, Loewner and row work of their merges
         "leaf": ("alu", cnt["leaf_rotations"] * FLOPS_PER_LEAF_ROT + cnt["dc_secular_terms"] * FLOPS_PER_SEC_TERM
@@ -132,7 +136,8 @@ def roofline(tde, kinds, cnt, steps):
         except (ValueError, KeyError):
             traffic = None
     return {
-        "kernel": {"secular": "k_secular", "lowner": "k_lowner", "rows": "k_rows", "leaf": "k_leaf",
+        "kernel": {"secular": "k_secular", "lowner": "k_lowner", "rows": "k_rows",
+                   "leaf": "k_leaf_dc" if cnt["leaf_rotations"] == 0 else "k_leaf", "small": "k_small_merge",
                    "merge": "k_merge", "assemble": "k_assemble"}[kind],
         "bound": bound,
         "achieved": achieved,

@@ -170,7 +170,7 @@ int tde_get_status(const void* ws, void* hip_stream);
 
 /* Measurement aids (not needed to solve).
  *
- * tde_get_counters: waits for the stream, then copies n (<= 12) counters of the
+ * tde_get_counters: waits for the stream, then copies n (<= 16) counters of the
  * algorithmic work of the last solve that used ws:
  *   [0] pole-term evaluations in secular sweeps, [1] (pole, root) pairs in the
  *   Loewner products, [2] (root, pole) pairs in the boundary-row dot products,
@@ -178,14 +178,17 @@ int tde_get_status(const void* ws, void* hip_stream);
  *   [6] plane rotations applied by QL leaves, [7] columns passed through
  *   merges (summed over tree levels, in-wave leaf merges included);
  *   [8..11] as [0..3] for the merges run inside leaves solved by divide and
- *   conquer in one wave (TDE_FLAG_LEAF_DC), which [0..4] do not include.
+ *   conquer in one wave (TDE_FLAG_LEAF_DC), which [0..4] do not include;
+ *   [12..15] the part of [0..3] done by the fused kernel for merges with at
+ *   most 512 active roots (one workgroup per merge).
  *
  * tde_timing_enable(1): from then on every launch the library enqueues is
  * bracketed by two HIP events recorded on the caller's stream (this adds
  * host work per launch; leave it off when timing whole solves).
  * tde_timing_read: waits for the recorded events and returns, per launch kind
- * (0 setup, 1 QL leaves, 2 merge/sort, 3 deflation and compaction, 4 secular
- * roots, 5 Loewner products, 6 boundary rows, 7 assembly, 8 reverse pass), the summed
+ * (0 setup, 1 leaves, 2 merge/sort, 3 deflation and compaction, 4 secular
+ * roots, 5 Loewner products, 6 boundary rows, 7 assembly, 8 reverse pass,
+ * 9 fused roots + Loewner + rows of merges with few active roots), the summed
  * milliseconds and launch count since the last read; then forgets them. */
 int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n);
 int tde_timing_enable(int on);

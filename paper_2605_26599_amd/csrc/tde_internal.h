@@ -67,7 +67,12 @@ enum {
     CNT_DC_LOW_PAIRS = 9,  // (pole, root) pairs in the Loewner products
     CNT_DC_ROW_PAIRS = 10, // (root, pole) pairs in the boundary-row dot products
     CNT_DC_ROOTS = 11,     // secular roots solved
-    CNT_N = 12
+    // the part of [0..3] done by the fused kernel of merges with few active roots
+    CNT_SM_TERMS = 12,
+    CNT_SM_LOW_PAIRS = 13,
+    CNT_SM_ROW_PAIRS = 14,
+    CNT_SM_ROOTS = 15,
+    CNT_N = 16
 };
 // Each counter is spread over kCntSlots words (a launch's waves add into
 // different slots, so their atomics do not queue on one address); readers sum
@@ -78,7 +83,7 @@ constexpr int kCntOffset = 256;
 // Launch kinds for the optional per-kernel timing.
 enum {
     KIND_SETUP = 0, KIND_LEAF, KIND_MERGE, KIND_DEFLATE, KIND_SECULAR, KIND_LOWNER, KIND_ROWS, KIND_ASSEMBLE,
-    KIND_BACKWARD, KIND_N
+    KIND_BACKWARD, KIND_SMALL, KIND_N
 };
 
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels

@@ -1233,6 +1233,10 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     count_add(w.counters, CNT_ROOTS, roots);
     count_add(w.counters, CNT_LOW_PAIRS, pairs);
     count_add(w.counters, CNT_ROW_PAIRS, pairs);
+    count_add(w.counters, CNT_SM_TERMS, terms);
+    count_add(w.counters, CNT_SM_ROOTS, roots);
+    count_add(w.counters, CNT_SM_LOW_PAIRS, pairs);
+    count_add(w.counters, CNT_SM_ROW_PAIRS, pairs);
 }
 
 template <int NT>
@@ -1724,7 +1728,7 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = kFuseMax;
     // merges with at most kFuseMax active roots: one workgroup each
-    TDE_LAUNCH_K(KIND_SECULAR, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
+    TDE_LAUNCH_K(KIND_SMALL, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
     if (smax <= kFuseMax) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
