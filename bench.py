@@ -265,6 +265,41 @@ def grad_ratio(tde, dev, reps=20):
     return res
 
 
+def split_prepass(tde, dev, reps=10):
+    """Driver pre-pass on a reducible input: n = 65536 uniform with every 97th
+    coupling zeroed (676 unreduced blocks), split solve against the plain one
+    (both include everything they do; the split one reads back the block
+    boundaries once per call)."""
+    import torch
+
+    import tdgen
+
+    n = 65536
+    d, e = tdgen.tridiag("uniform", n, cfg=tdgen.CFG_FAMILIES)
+    e = e.copy()
+    e[96::97] = 0.0
+    dv = torch.from_numpy(d).to(dev)
+    ev = torch.from_numpy(e).to(dev)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    kw = dict(leaf=64, leaf_dc=True)
+    nb = tde.eigvals_split(dv, ev, **kw)[1]
+
+    def plain():
+        tde.eigvals(dv, ev, out=out, check=False, **kw)
+
+    def split():
+        tde.eigvals_split(dv, ev, check=False, **kw)
+
+    for _ in range(2):
+        plain()
+        split()
+    torch.cuda.synchronize()
+    tp = timed(plain, reps) / reps
+    ts = timed(split, reps) / reps
+    return {"workload": "uniform n=65536, every 97th coupling zero", "blocks": nb, "plain_ms": tp,
+            "split_ms": ts}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -396,6 +431,7 @@ def main():
         sec["batched_solves_per_s"] = 4096 / (bms / 1e3)
         sec["batched_ms_per_step"] = bms
         sec["grad_fwd_bwd_over_fwd"] = grad_ratio(tde, dev)
+        sec["split_prepass"] = split_prepass(tde, dev)
     if not args.no_cpu and dn is not None:
         sec["cpu_ql"] = ql_baseline(dn, en, args.cpu_seconds)
     if sec:

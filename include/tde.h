@@ -99,6 +99,27 @@ int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, voi
 int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
                         void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
 
+/* Driver pre-pass: split at negligible couplings, then solve the blocks.
+ *
+ * The outer structure of a tridiagonal eigensolver driver (the paper's CPU
+ * driver validates, splits at negligible off-diagonal entries and scales each
+ * unreduced block before the D&C, Section 4.2): every coupling with
+ * |e_i| <= eps sqrt|d_i| sqrt|d_(i+1)| is dropped (no eigenvalue moves by more
+ * than eps ||T||), each resulting block is solved as a problem of its own
+ * (own power-of-two scale, own merge tree, all blocks of all problems in the
+ * level-aligned batched schedule), and the blocks' ascending spectra are
+ * merged back into each problem's ascending output.  Reducible and graded
+ * matrices become many small problems.
+ *   d, e, offsets, B, lambda: as tde_eigvals_batched (offsets = {0, n} for one
+ *                   problem; e of a single problem needs only n-1 entries)
+ *   ws            workspace of ws_bytes >= tde_workspace_bytes(offsets[B],
+ *                   offsets[B], opts) (room for every column being a block)
+ *   nblocks       HOST, may be NULL: receives the number of blocks solved
+ * Unlike the other entry points this one waits for the stream once (the block
+ * boundaries are read back to plan the solve); the rest is asynchronous. */
+int tde_eigvals_split(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                      void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts, int64_t* nblocks);
+
 /* Eigenvalues and the first and last rows of the eigenvector matrix.
  *
  * The paper propagates only rows 0 and n-1 of each node's eigenvector matrix

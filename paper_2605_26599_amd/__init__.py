@@ -45,6 +45,7 @@ EXPORTS = (
     "tde_eigvals",
     "tde_eigvals_batched",
     "tde_eigvals_rows",
+    "tde_eigvals_split",
     "tde_checkpoint_bytes",
     "tde_backward_workspace_bytes",
     "tde_eigvals_ckpt",
@@ -110,6 +111,8 @@ def lib():
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.tde_eigvals_rows.argtypes = [vp, vp, i64p, i64, vp, vp, vp, vp, sz, vp, optp]
         L.tde_eigvals_rows.restype = ctypes.c_int
+        L.tde_eigvals_split.argtypes = [vp, vp, i64p, i64, vp, vp, sz, vp, optp, i64p]
+        L.tde_eigvals_split.restype = ctypes.c_int
         L.tde_checkpoint_bytes.argtypes = [i64p, i64, optp]
         L.tde_checkpoint_bytes.restype = sz
         L.tde_backward_workspace_bytes.argtypes = [i64, i64, optp]
@@ -268,6 +271,39 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_batched device status")
     return out
+
+
+# --- driver pre-pass: split at negligible couplings ----------------------------
+
+def eigvals_split(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, check: bool = True,
+                  graph: bool = True, wide_min=None, leaf_dc=None):
+    """Eigenvalues (ascending per problem) after splitting every problem at its
+    negligible couplings (|e_i| <= eps sqrt|d_i d_i+1|) into independently
+    scaled blocks.  offsets None = one problem with e[n-1], else the batched
+    layout.  Waits for the stream once.  Returns (lam, number of blocks)."""
+    _check_input(d, e)
+    offs, B, arr = _offsets(d.numel(), offsets)
+    n = offs[-1]
+    lam = torch.empty(n, dtype=torch.float64, device=d.device)
+    if B <= 0 or n == 0:
+        return lam, 0
+    if d.numel() < n or (offsets is not None and e.numel() < n) or e.numel() < n - 1:
+        raise ValueError("d and e are shorter than the offsets require")
+    nb = workspace_bytes(n, n, leaf)
+    ws = _workspace(nb, d.device)
+    nblocks = ctypes.c_int64(0)
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_split(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, lam.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), stream,
+                                     _opts(leaf, graph, sweep_cols, wide_min, leaf_dc), ctypes.byref(nblocks))
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_split")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_split device status")
+    return lam, int(nblocks.value)
 
 
 # --- boundary rows at the top (NEXT: requested rows, Golub-Welsch) -----------

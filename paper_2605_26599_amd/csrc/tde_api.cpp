@@ -321,6 +321,117 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
                     [&](void* s) { return enqueue_backward(*plan, w, gr, ck, d, e, gin, gd, ge, s); });
 }
 
+// Driver pre-pass: pairwise merge schedule of the blocks of every problem
+// (balanced over the blocks, levelled by height), cached per split.
+struct RunMerges {
+    std::vector<std::pair<int, int>> levels;  // (first record, count) per pass
+    MergeRec* d_recs = nullptr;
+};
+using RunKey = std::tuple<int, std::vector<long long>, std::vector<long long>>;
+std::map<RunKey, RunMerges> g_runs;
+constexpr size_t kMaxRunSchedules = 64;
+
+int run_merge_build(const std::vector<long long>& nb, int bs, int be, std::vector<std::vector<MergeRec>>* lv) {
+    if (be - bs <= 1) return 0;
+    const int mid = bs + (be - bs) / 2;
+    const int h = std::max(run_merge_build(nb, bs, mid, lv), run_merge_build(nb, mid, be, lv)) + 1;
+    if ((int)lv->size() < h) lv->resize(h);
+    MergeRec R{};
+    R.off = nb[bs];
+    R.nL = (int)(nb[mid] - nb[bs]);
+    R.nR = (int)(nb[be] - nb[mid]);
+    (*lv)[h - 1].push_back(R);
+    return h;
+}
+
+int get_run_merges(int device, const std::vector<long long>& offs, const std::vector<long long>& nb,
+                   const RunMerges** out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    RunKey key{device, offs, nb};
+    auto it = g_runs.find(key);
+    if (it != g_runs.end()) {
+        *out = &it->second;
+        return TDE_OK;
+    }
+    if (g_runs.size() >= kMaxRunSchedules) {
+        for (auto& kv : g_runs)
+            if (kv.second.d_recs) (void)hipFree(kv.second.d_recs);
+        g_runs.clear();
+    }
+    std::vector<std::vector<MergeRec>> lv;
+    size_t bi = 0;  // first block of problem b
+    for (size_t b = 0; b + 1 < offs.size(); ++b) {
+        size_t be = bi;
+        while (be + 1 < nb.size() && nb[be] < offs[b + 1]) ++be;
+        run_merge_build(nb, (int)bi, (int)be, &lv);
+        bi = be;
+    }
+    RunMerges rm;
+    std::vector<MergeRec> flat;
+    for (auto& L : lv) {
+        std::sort(L.begin(), L.end(), [](const MergeRec& a, const MergeRec& b) { return a.off < b.off; });
+        rm.levels.emplace_back((int)flat.size(), (int)L.size());
+        flat.insert(flat.end(), L.begin(), L.end());
+    }
+    if (!flat.empty()) {
+        if (hipMalloc(&rm.d_recs, flat.size() * sizeof(MergeRec)) != hipSuccess) return TDE_ENOMEM;
+        if (hipMemcpy(rm.d_recs, flat.data(), flat.size() * sizeof(MergeRec), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(rm.d_recs);
+            return TDE_EDEVICE;
+        }
+    }
+    *out = &g_runs.emplace(std::move(key), std::move(rm)).first->second;
+    return TDE_OK;
+}
+
+int solve_split(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
+                size_t ws_bytes, void* stream, const tde_opts* opts, int64_t* nblocks) {
+    int leaf, cols;
+    if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    const long long ntot = offs.back();
+    if (nblocks) *nblocks = 0;
+    if (ntot == 0) return TDE_OK;
+    if (!d || !lambda || !ws) return TDE_EINVAL;
+    if (needs_e(offs) && !e) return TDE_EINVAL;
+    // room for the worst case, every column its own block
+    if (ws_bytes < workspace_layout(ntot, ntot, ntot, nullptr, nullptr)) return TDE_EINVAL;
+    Work w{};
+    workspace_layout(ntot, ntot, ntot, (char*)ws, &w);
+    if (enqueue_split_flags(d, e, ntot, w.st, stream) != 0) return TDE_EDEVICE;
+    std::vector<int> flags((size_t)ntot);
+    if (hipMemcpyAsync(flags.data(), w.st, sizeof(int) * (size_t)ntot, hipMemcpyDeviceToHost,
+                       (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return TDE_EDEVICE;
+    std::vector<long long> nb;
+    for (size_t b = 0; b + 1 < offs.size(); ++b)
+        for (long long i = offs[b]; i < offs[b + 1]; ++i)
+            if (i == offs[b] || flags[(size_t)i]) nb.push_back(i);
+    nb.push_back(ntot);
+    if (nblocks) *nblocks = (int64_t)nb.size() - 1;
+    int rc = solve(d, e, nb, lambda, ws, ws_bytes, stream, opts);
+    if (rc != TDE_OK) return rc;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
+    const RunMerges* rm = nullptr;
+    rc = get_run_merges(device, offs, nb, &rm);
+    if (rc != TDE_OK) return rc;
+    if (rm->levels.empty()) return TDE_OK;
+    Work ws2{};
+    workspace_layout(ntot, (long long)nb.size() - 1, ntot, (char*)ws, &ws2);
+    double* src = lambda;
+    double* dst = ws2.D;  // free once the solve is done (same stream)
+    for (const auto& L : rm->levels) {
+        if (enqueue_merge_runs(rm->d_recs + L.first, L.second, src, dst, ntot, stream) != 0) return TDE_EDEVICE;
+        std::swap(src, dst);
+    }
+    if (src != lambda &&
+        hipMemcpyAsync(lambda, src, sizeof(double) * (size_t)ntot, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+            hipSuccess)
+        return TDE_EDEVICE;
+    return TDE_OK;
+}
+
 }  // namespace
 }  // namespace tde
 
@@ -339,6 +450,13 @@ int tde_eigvals(const double* d, const double* e, int64_t n, double* lambda, voi
     if (n < 0 || n > (int64_t)0x3fffffff) return TDE_EINVAL;
     std::vector<long long> offs{0, (long long)n};
     return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts);
+}
+
+int tde_eigvals_split(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
+                      void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts, int64_t* nblocks) {
+    std::vector<long long> offs;
+    if (tde::check_offsets(offsets, B, &offs) != TDE_OK) return TDE_EINVAL;
+    return tde::solve_split(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts, nblocks);
 }
 
 int tde_eigvals_batched(const double* d, const double* e, const int64_t* offsets, int64_t B, double* lambda,
@@ -437,6 +555,9 @@ void tde_release_plans(void) {
     tde::drop_graphs();
     for (auto& kv : tde::g_plans) tde::free_plan(kv.second.get());
     tde::g_plans.clear();
+    for (auto& kv : tde::g_runs)
+        if (kv.second.d_recs) (void)hipFree(kv.second.d_recs);
+    tde::g_runs.clear();
 }
 
 const char* tde_status_string(int status) {

@@ -1931,6 +1931,69 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
 }
 
 // ---------------------------------------------------------------------------
+// Driver pre-pass: split at negligible couplings (the outer structure of a
+// tridiagonal eigensolver driver: independent unreduced blocks, each scaled
+// on its own), and the merge of the blocks' ascending spectra afterwards.
+// ---------------------------------------------------------------------------
+
+// flags[i] = 1 when the coupling e[i-1] is negligible beside its diagonal
+// neighbours, |e| <= eps sqrt|d_{i-1}| sqrt|d_i| (setting it to zero moves no
+// eigenvalue by more than eps ||T||), for 1 <= i < n; flags[0] = 1.  Problem
+// starts are added by the host, so the unused slot e[off_b - 1] of the
+// batched layout is read but never decides anything.
+__global__ __launch_bounds__(kWG) void k_split_flags(const double* __restrict__ d, const double* __restrict__ e,
+                                                     long long n, int* __restrict__ flags) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0) {
+        flags[0] = 1;
+        return;
+    }
+    const double tiny = DBL_EPSILON * sqrt(fabs(d[i - 1])) * sqrt(fabs(d[i]));
+    flags[i] = (fabs(e[i - 1]) <= tiny) ? 1 : 0;
+}
+
+// One pass of the pairwise merges of ascending runs: merge m combines the
+// adjacent runs [off, off + nL) and [off + nL, off + nL + nR) of src into the
+// same range of dst (ties: left run first); columns in no merge of this pass
+// are copied.  recs are sorted by off.
+__global__ __launch_bounds__(kWG) void k_merge_runs(const MergeRec* __restrict__ recs, int M,
+                                                    const double* __restrict__ src, double* __restrict__ dst,
+                                                    long long n) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (recs[mid].off <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const MergeRec R = recs[lo];
+    const double x = src[t];
+    if (t < R.off || t >= R.off + R.nL + R.nR) {
+        dst[t] = x;
+        return;
+    }
+    const int i = (int)(t - R.off);
+    int pos;
+    if (i < R.nL) pos = i + count_lt(src + R.off + R.nL, R.nR, x);
+    else pos = (i - R.nL) + count_le(src + R.off, R.nL, x);
+    dst[R.off + pos] = x;
+}
+
+int enqueue_split_flags(const double* d, const double* e, long long n, int* flags, void* stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_split_flags, dim3(nblk(n, kWG)), dim3(kWG), 0, (hipStream_t)stream, d, e, n, flags);
+    return (int)hipGetLastError();
+}
+
+int enqueue_merge_runs(const MergeRec* recs, int M, const double* src, double* dst, long long n, void* stream) {
+    if (n <= 0 || M <= 0) return 0;
+    hipLaunchKernelGGL(k_merge_runs, dim3(nblk(n, kWG)), dim3(kWG), 0, (hipStream_t)stream, recs, M, src, dst, n);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Workspace layout (all slices 256-byte aligned)
 // ---------------------------------------------------------------------------
 size_t workspace_layout(long long n, long long B, long long maxM, char* base, Work* w) {

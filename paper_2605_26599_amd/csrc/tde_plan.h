@@ -61,6 +61,11 @@ size_t ckpt_layout(long long n, int levels, char* base, Ckpt* c);
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck = nullptr);
 
+// Driver pre-pass: negligible-coupling flags (flags[i] = 1: a block starts at
+// column i), and one pass of pairwise merges of ascending runs (src -> dst).
+int enqueue_split_flags(const double* d, const double* e, long long n, int* flags, void* stream);
+int enqueue_merge_runs(const MergeRec* recs, int M, const double* src, double* dst, long long n, void* stream);
+
 // Enqueue the reverse pass: gd, ge = d(sum_k gin_k lambda_k)/d(d, e) from the
 // checkpoint of a forward solve of the same (d, e) under the same plan.
 int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
