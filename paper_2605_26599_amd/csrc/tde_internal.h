@@ -114,9 +114,9 @@ struct Work {
     double* RL2;               // [n]
     double* RH2;               // [n]
     int* st;                   // [n]   column state: 0 negligible z, 1 active, 2 rotated away
-    int* scan;                 // [n+1] exclusive prefix counts of active columns
-    int* scanC;                // [n+1] exclusive prefix counts of candidate (non-negligible) columns
-    int* scanR;                // [n+1] exclusive prefix counts of rotated-away columns
+    int* scan;                 // [n + n/2 + 2] exclusive prefix counts of active columns (level-wide, or per merge)
+    int* scanC;                // [n + n/2 + 2] the same for candidate (non-negligible) columns
+    int* scanR;                // [n + n/2 + 2] the same for rotated-away columns
     int* bsum;                 // [nb+1] per-block counts
     int* bsumR;                // [nb+1] per-block counts of rotated-away columns (this level's slice of bcnt)
     int* bsumA;                // [nb+1] per-block counts of active columns (raw; this level's slice of bcnt)

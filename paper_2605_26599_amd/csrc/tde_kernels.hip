@@ -1239,6 +1239,35 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     count_add(w.counters, CNT_SM_ROW_PAIRS, pairs);
 }
 
+// LDS staging of one merge's active arrays for the fused root steps.
+struct SmallStage {
+    double D[kFuseMax], W[kFuseMax], Z[kFuseMax], T[kFuseMax], H[kFuseMax], L[kFuseMax], R[kFuseMax];
+    int O[kFuseMax];
+};
+
+// Roots, Loewner z and rows of one merge with 1 <= K <= kFuseMax active
+// columns at active index ks (the whole workgroup; block-uniform arguments).
+template <int NT>
+__device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long long ks, const double* e,
+                                                  const unsigned long long* __restrict__ pmax, const Work& w,
+                                                  SmallStage& sg) {
+    for (int i = threadIdx.x; i < K; i += NT) {
+        sg.D[i] = w.Da[ks + i];
+        sg.W[i] = w.Wa[ks + i];
+        sg.Z[i] = w.Za[ks + i];
+        sg.L[i] = w.RLa[ks + i];
+        sg.R[i] = w.RHa[ks + i];
+    }
+    double sgn;
+    const double rho = merge_rho(R, e, pmax, &sgn);
+    __syncthreads();
+    if (K <= NT / 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K <= NT / 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K <= NT / 4) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K <= NT / 2) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else small_merge_body<NT, 1>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                     const unsigned long long* __restrict__ pmax, Work w) {
@@ -1247,25 +1276,135 @@ __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__
     const MergeSpan sp = merge_span(R, w.scan);
     const int K = sp.K;
     if (K < 1 || K > kFuseMax) return;  // block-uniform
-    __shared__ double sD[kFuseMax], sW[kFuseMax], sZ[kFuseMax], sT[kFuseMax], sH[kFuseMax], sL[kFuseMax],
-        sR[kFuseMax];
-    __shared__ int sO[kFuseMax];
-    const long long ks = sp.ks;
-    for (int i = threadIdx.x; i < K; i += NT) {
-        sD[i] = w.Da[ks + i];
-        sW[i] = w.Wa[ks + i];
-        sZ[i] = w.Za[ks + i];
-        sL[i] = w.RLa[ks + i];
-        sR[i] = w.RHa[ks + i];
-    }
-    double sgn;
-    const double rho = merge_rho(R, e, pmax, &sgn);
+    __shared__ SmallStage sg;
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg);
+}
+
+// ---------------------------------------------------------------------------
+// Levels whose merges all have at most kFuseMax columns (outside checkpoint
+// mode): one workgroup per merge runs the whole merge -- merged order and z~,
+// negligible-z flags, close-pole runs, the three-way split, roots, Loewner z,
+// rows and the assembly -- with barriers between the steps instead of kernel
+// boundaries and merge-local prefix counts instead of level-wide scans: one
+// launch per level instead of six.  The per-column and per-root device
+// functions are those of the level-wide kernels; they see the merge's active
+// and rotated lists and its candidate list through views that start at the
+// merge's packed position pk (a merge's lists never outgrow its own range),
+// while the negligible list is indexed by pk itself, as body_assemble reads it
+// with local counts.  The prefix arrays are shifted by one slot per merge so
+// that neighbouring merges' counts (s + 1 entries each) do not overlap.
+// ---------------------------------------------------------------------------
+// Above this many merges a level keeps the level-wide kernels: they stream the
+// columns with all lanes busy, while a workgroup per merge would queue
+// thousands of mostly idle 512-thread groups (a merge's result is the same
+// either way).
+constexpr int kLevelBlockMaxMerges = 1024;
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                                    const unsigned long long* __restrict__ pmax, Work w,
+                                                    double* __restrict__ out) {
+    if (input_nonfinite(w)) return;
+    __shared__ MergeRec sm[1];
+    __shared__ int wsum[16];
+    __shared__ SmallStage sg;
+    const MergeRec R = mr[blockIdx.x];
+    if (threadIdx.x == 0) sm[0] = R;
+    const int s = R.nL + R.nR;
+    const long long pk = R.pk;
+    Work v = w;
+    // merge b's counts live at [pk + b, pk + b + s]: its total (index pk + s of
+    // the view) must not land on the next merge's first count
+    v.scan = w.scan + blockIdx.x;
+    v.scanC = w.scanC + blockIdx.x;
+    v.scanR = w.scanR + blockIdx.x;
+    v.nnpos = w.nnpos + pk;
+    v.Da = w.Da + pk;
+    v.Za = w.Za + pk;
+    v.Wa = w.Wa + pk;
+    v.RLa = w.RLa + pk;
+    v.RHa = w.RHa + pk;
+    v.org = w.org + pk;
+    v.tau = w.tau + pk;
+    v.zhat = w.zhat + pk;
+    v.PBL = w.PBL + pk;
+    v.PBH = w.PBH + pk;
+    v.Dr = w.Dr + pk;
+    v.RLr = w.RLr + pk;
+    v.RHr = w.RHr + pk;
     __syncthreads();
-    if (K <= NT / 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
-    else if (K <= NT / 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
-    else if (K <= NT / 4) small_merge_body<NT, 4>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
-    else if (K <= NT / 2) small_merge_body<NT, 2>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
-    else small_merge_body<NT, 1>(R, K, ks, rho, w, sD, sW, sZ, sT, sH, sL, sR, sO);
+    // merged order, z~, negligible-z flags
+    for (int i = threadIdx.x; i < s; i += NT) {
+        int f;
+        body_merge(pk + i, 0, sm, e, pmax, v, &f);
+    }
+    __syncthreads();
+    // candidates: merge-local prefix counts and positions (each thread a run
+    // of consecutive columns)
+    const int cs = (s + NT - 1) / NT;
+    const int c0 = min(s, (int)threadIdx.x * cs), c1 = min(s, c0 + cs);
+    int cnt = 0;
+    for (int i = c0; i < c1; ++i) cnt += (v.st[pk + i] == 1) ? 1 : 0;
+    const int incl = block_incl_scan(cnt, wsum);
+    int g = incl - cnt;
+    for (int i = c0; i < c1; ++i) {
+        v.scanC[pk + i] = g;
+        if (v.st[pk + i] == 1) v.nnpos[g++] = (int)(pk + i);
+    }
+    if (threadIdx.x == NT - 1) v.scanC[pk + s] = incl;
+    __syncthreads();
+    // close-pole runs
+    const int nc = v.scanC[pk + s];
+    for (int q = threadIdx.x; q < nc; q += NT) body_runs(q, 0, sm, v, [](long long) {});
+    __syncthreads();
+    // three-way split
+    int ca = 0, cr = 0;
+    for (int i = c0; i < c1; ++i) {
+        const int st = v.st[pk + i];
+        ca += (st == 1) ? 1 : 0;
+        cr += (st == 2) ? 1 : 0;
+    }
+    const int ia = block_incl_scan(ca, wsum);
+    __syncthreads();
+    const int ir = block_incl_scan(cr, wsum);
+    int ga = ia - ca, gr = ir - cr;
+    for (int i = c0; i < c1; ++i) {
+        const long long t = pk + i;
+        const int st = v.st[t];
+        v.scan[t] = ga;
+        v.scanR[t] = gr;
+        if (st == 1) {
+            const double z = v.Z2[t];
+            v.Da[ga] = v.D2[t];
+            v.Za[ga] = z;
+            v.Wa[ga] = z * z;
+            v.RLa[ga] = v.RL2[t];
+            v.RHa[ga] = v.RH2[t];
+            ++ga;
+        } else if (st == 2) {
+            v.Dr[gr] = v.D2[t];
+            v.RLr[gr] = v.RL2[t];
+            v.RHr[gr] = v.RH2[t];
+            ++gr;
+        } else {
+            const long long q = pk + (i - ga - gr);
+            v.Dd[q] = v.D[t];
+            v.RLd[q] = v.RL[t];
+            v.RHd[q] = v.RH[t];
+        }
+    }
+    if (threadIdx.x == NT - 1) {
+        v.scan[pk + s] = ia;
+        v.scanR[pk + s] = ir;
+    }
+    __syncthreads();
+    // roots, Loewner z, rows
+    const int K = v.scan[pk + s];
+    if (K >= 1) small_merge_solve<NT>(R, K, 0, e, pmax, v, sg);
+    __syncthreads();
+    // the parent's spectrum and rows, or the problem's eigenvalues
+    for (int i = threadIdx.x; i < s; i += NT) body_assemble(pk + i, 0, sm, pmax, v, out);
+    if (threadIdx.x == 0) count_add1(w.counters, CNT_MERGE_COLS, (unsigned long long)s);
 }
 
 template <int G, bool WithRoot>
@@ -1841,6 +1980,12 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             wl.org = ck->org + so;
             wl.tau = ck->tau + so;
         }
+        if (!ck && L.smax <= kFuseMax && M <= kLevelBlockMaxMerges) {
+            // every merge of the level fits one workgroup: the whole merge in one launch
+            TDE_LAUNCH_K(KIND_SMALL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
+                         (const unsigned long long*)w.pmax, wl, out);
+            continue;
+        }
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, stream);
@@ -2023,9 +2168,11 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.RL2 = (double*)take(8 * nn);
     t.RH2 = (double*)take(8 * nn);
     t.st = (int*)take(4 * nn);
-    t.scan = (int*)take(4 * (nn + 1));
-    t.scanC = (int*)take(4 * (nn + 1));
-    t.scanR = (int*)take(4 * (nn + 1));
+    // prefix arrays: n + 1 entries for the level-wide scans, plus one per merge
+    // (at most n/2 + 1) for k_level_block's merge-local counts
+    t.scan = (int*)take(4 * (nn + nn / 2 + 2));
+    t.scanC = (int*)take(4 * (nn + nn / 2 + 2));
+    t.scanR = (int*)take(4 * (nn + nn / 2 + 2));
     t.bsum = (int*)take(4 * nb);
     t.bcnt = (int*)take(4 * (size_t)kMaxLevels * 2 * nb);
     t.bsumA = t.bcnt;
