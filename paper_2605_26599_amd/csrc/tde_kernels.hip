@@ -1181,6 +1181,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ---------------------------------------------------------------------------
 constexpr int kFuseMax = 512;
 constexpr int kFuseThreads = 512;
+constexpr int kFuseWideS = 2048;
 
 template <int NT, int G>
 __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long long ks, double rho, const Work& w,
@@ -1261,10 +1262,14 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
     __syncthreads();
-    if (K <= NT / 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K <= NT / 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K <= NT / 4) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K <= NT / 2) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    // lanes per root from the merge alone: G = min(16, ref / K), ref twice as
+    // large for merges of kFuseWideS columns or more (few such merges share a
+    // level, so their roots get more lanes); NT >= G K is one pass
+    const int ref = (R.nL + R.nR >= kFuseWideS) ? 2 * kFuseThreads : kFuseThreads;
+    if (K * 16 <= ref) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K * 8 <= ref) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K * 4 <= ref) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    else if (K * 2 <= ref) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
     else small_merge_body<NT, 1>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
 }
 
@@ -1867,7 +1872,11 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = kFuseMax;
     // merges with at most kFuseMax active roots: one workgroup each
-    TDE_LAUNCH_K(KIND_SMALL, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
+    if (smax >= kFuseWideS)
+        TDE_LAUNCH_K(KIND_SMALL, k_small_merge<2 * kFuseThreads>, (unsigned)M, 2 * kFuseThreads, stream, mr, e, pm,
+                     w);
+    else
+        TDE_LAUNCH_K(KIND_SMALL, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
     if (smax <= kFuseMax) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
