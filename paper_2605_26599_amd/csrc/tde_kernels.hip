@@ -1305,6 +1305,10 @@ __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__
 // either way).
 constexpr int kLevelBlockMaxMerges = 1024;
 
+// Levels run by k_level_block (forward; the reverse pass reads their
+// checkpointed roots from the merges' packed positions).
+static bool level_blocked(const LevelInfo& L) { return L.smax <= kFuseMax && L.M <= kLevelBlockMaxMerges; }
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                     const unsigned long long* __restrict__ pmax, Work w,
@@ -1552,6 +1556,23 @@ __global__ __launch_bounds__(kWG) void k_bwd_init(long long n, const double* __r
     gr.glam[t] = gin[t];
     gr.gblo[t] = 0.0;
     gr.gbhi[t] = 0.0;
+}
+
+// Roots of a level the forward ran with k_level_block: the checkpoint holds
+// them at the merges' packed positions (pk + local index); gather them into
+// active-index order for the reverse steps.
+__global__ __launch_bounds__(kWG) void k_bwd_roots_gather(const MergeRec* __restrict__ mr, long long N, Work w,
+                                                          const int* __restrict__ corg,
+                                                          const double* __restrict__ ctau) {
+    if (input_nonfinite(w)) return;
+    const long long total = min((long long)w.scan[N], N);
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+         g += (long long)gridDim.x * blockDim.x) {
+        const MergeRec R = mr[w.amerge[g]];
+        const long long src = R.pk + (g - w.scan[R.pk]);
+        w.org[g] = corg[src];
+        w.tau[g] = ctau[src];
+    }
 }
 
 __global__ __launch_bounds__(kWG) void k_bwd_unassemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
@@ -1989,8 +2010,9 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             wl.org = ck->org + so;
             wl.tau = ck->tau + so;
         }
-        if (!ck && L.smax <= kFuseMax && M <= kLevelBlockMaxMerges) {
+        if (level_blocked(L)) {
             // every merge of the level fits one workgroup: the whole merge in one launch
+            // (with a checkpoint, its roots land at the merge's packed positions)
             TDE_LAUNCH_K(KIND_SMALL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
                          (const unsigned long long*)w.pmax, wl, out);
             continue;
@@ -2048,6 +2070,12 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
         wl.tau = ck.tau + so;
         launch_merge(KIND_BACKWARD, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
+        if (level_blocked(L)) {
+            wl.org = w.org;
+            wl.tau = w.tau;
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots_gather, nb < 4096u ? nb : 4096u, kWG, stream, mr, N, wl,
+                         (const int*)(ck.org + so), (const double*)(ck.tau + so));
+        }
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
             case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
