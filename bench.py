@@ -95,12 +95,18 @@ def roofline(tde, kinds, cnt, steps):
     """Roofline entry for the kernel kind that took the most time."""
     # the level-wide kernels' share of the work (the fused small-merge kernel
     # counts its own part separately)
+    def fused(p):
+        return (cnt[p + "secular_terms"] * FLOPS_PER_SEC_TERM + cnt[p + "lowner_pairs"] * FLOPS_PER_LOW_PAIR
+                + cnt[p + "row_pairs"] * FLOPS_PER_ROW_PAIR)
+
     work = {
-        "secular": ("alu", (cnt["secular_terms"] - cnt["small_secular_terms"]) * FLOPS_PER_SEC_TERM),
-        "lowner": ("alu", (cnt["lowner_pairs"] - cnt["small_lowner_pairs"]) * FLOPS_PER_LOW_PAIR),
-        "rows": ("alu", (cnt["row_pairs"] - cnt["small_row_pairs"]) * FLOPS_PER_ROW_PAIR),
-        "small": ("alu", cnt["small_secular_terms"] * FLOPS_PER_SEC_TERM + cnt["small_lowner_pairs"] * FLOPS_PER_LOW_PAIR
-                  + cnt["small_row_pairs"] * FLOPS_PER_ROW_PAIR),
+        "secular": ("alu", (cnt["secular_terms"] - cnt["small_secular_terms"] - cnt["level_secular_terms"])
+                    * FLOPS_PER_SEC_TERM),
+        "lowner": ("alu", (cnt["lowner_pairs"] - cnt["small_lowner_pairs"] - cnt["level_lowner_pairs"])
+                   * FLOPS_PER_LOW_PAIR),
+        "rows": ("alu", (cnt["row_pairs"] - cnt["small_row_pairs"] - cnt["level_row_pairs"]) * FLOPS_PER_ROW_PAIR),
+        "small": ("alu", fused("small_")),
+        "level": ("alu", fused("level_")),
         # QL leaves: rotations; leaves solved by divide and conquer in one wave:
         # the secular, Loewner and row work of their merges
         "leaf": ("alu", cnt["leaf_rotations"] * FLOPS_PER_LEAF_ROT + cnt["dc_secular_terms"] * FLOPS_PER_SEC_TERM
@@ -138,6 +144,7 @@ def roofline(tde, kinds, cnt, steps):
     return {
         "kernel": {"secular": "k_secular", "lowner": "k_lowner", "rows": "k_rows",
                    "leaf": "k_leaf_dc" if cnt["leaf_rotations"] == 0 else "k_leaf", "small": "k_small_merge",
+                   "level": "k_level_block",
                    "merge": "k_merge", "assemble": "k_assemble"}[kind],
         "bound": bound,
         "achieved": achieved,

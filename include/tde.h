@@ -191,7 +191,7 @@ int tde_get_status(const void* ws, void* hip_stream);
 
 /* Measurement aids (not needed to solve).
  *
- * tde_get_counters: waits for the stream, then copies n (<= 16) counters of the
+ * tde_get_counters: waits for the stream, then copies n (<= 20) counters of the
  * algorithmic work of the last solve that used ws:
  *   [0] pole-term evaluations in secular sweeps, [1] (pole, root) pairs in the
  *   Loewner products, [2] (root, pole) pairs in the boundary-row dot products,
@@ -201,7 +201,9 @@ int tde_get_status(const void* ws, void* hip_stream);
  *   [8..11] as [0..3] for the merges run inside leaves solved by divide and
  *   conquer in one wave (TDE_FLAG_LEAF_DC), which [0..4] do not include;
  *   [12..15] the part of [0..3] done by the fused kernel for merges with at
- *   most 512 active roots (one workgroup per merge).
+ *   most 512 active roots (one workgroup per merge; terms, Loewner pairs, row
+ *   pairs, roots); [16..19] the same for the workgroups that run whole merges
+ *   of levels of small merges.
  *
  * tde_timing_enable(1): from then on every launch the library enqueues is
  * bracketed by two HIP events recorded on the caller's stream (this adds
@@ -209,7 +211,8 @@ int tde_get_status(const void* ws, void* hip_stream);
  * tde_timing_read: waits for the recorded events and returns, per launch kind
  * (0 setup, 1 leaves, 2 merge/sort, 3 deflation and compaction, 4 secular
  * roots, 5 Loewner products, 6 boundary rows, 7 assembly, 8 reverse pass,
- * 9 fused roots + Loewner + rows of merges with few active roots), the summed
+ * 9 fused roots + Loewner + rows of merges with few active roots, 10 whole
+ * merges of levels of small merges), the summed
  * milliseconds and launch count since the last read; then forgets them. */
 int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n);
 int tde_timing_enable(int on);

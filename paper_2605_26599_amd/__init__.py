@@ -461,8 +461,10 @@ def differentiable_eigvals(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=
 
 COUNTER_NAMES = ("secular_terms", "lowner_pairs", "row_pairs", "roots", "sweeps", "leaf_columns", "leaf_rotations",
                  "merge_columns", "dc_secular_terms", "dc_lowner_pairs", "dc_row_pairs", "dc_roots",
-                 "small_secular_terms", "small_lowner_pairs", "small_row_pairs", "small_roots")
-KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble", "backward", "small")
+                 "small_secular_terms", "small_lowner_pairs", "small_row_pairs", "small_roots",
+                 "level_secular_terms", "level_lowner_pairs", "level_row_pairs", "level_roots")
+KIND_NAMES = ("setup", "leaf", "merge", "deflate", "secular", "lowner", "rows", "assemble", "backward", "small",
+              "level")
 
 
 def counters(workspace: torch.Tensor) -> dict:

@@ -72,7 +72,12 @@ enum {
     CNT_SM_LOW_PAIRS = 13,
     CNT_SM_ROW_PAIRS = 14,
     CNT_SM_ROOTS = 15,
-    CNT_N = 16
+    // the same for the whole-merge workgroups of small levels (k_level_block)
+    CNT_LB_TERMS = 16,
+    CNT_LB_LOW_PAIRS = 17,
+    CNT_LB_ROW_PAIRS = 18,
+    CNT_LB_ROOTS = 19,
+    CNT_N = 20
 };
 // Each counter is spread over kCntSlots words (a launch's waves add into
 // different slots, so their atomics do not queue on one address); readers sum
@@ -83,7 +88,7 @@ constexpr int kCntOffset = 256;
 // Launch kinds for the optional per-kernel timing.
 enum {
     KIND_SETUP = 0, KIND_LEAF, KIND_MERGE, KIND_DEFLATE, KIND_SECULAR, KIND_LOWNER, KIND_ROWS, KIND_ASSEMBLE,
-    KIND_BACKWARD, KIND_SMALL, KIND_N
+    KIND_BACKWARD, KIND_SMALL, KIND_LEVEL, KIND_N
 };
 
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels

@@ -1183,10 +1183,12 @@ constexpr int kFuseMax = 512;
 constexpr int kFuseThreads = 512;
 constexpr int kFuseWideS = 2048;
 
+// cbase: the first of the four counters (terms, Loewner pairs, row pairs,
+// roots) that single out this kernel's share of the work.
 template <int NT, int G>
 __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long long ks, double rho, const Work& w,
                                                  double* sD, double* sW, double* sZ, double* sT, double* sH,
-                                                 double* sL, double* sR, int* sO) {
+                                                 double* sL, double* sR, int* sO, int cbase) {
     const int sub = threadIdx.x % G, grp = threadIdx.x / G, ng = NT / G;
     int bad = 0;
     unsigned long long terms = 0, sweeps = 0, roots = 0, pairs = 0;
@@ -1234,10 +1236,10 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     count_add(w.counters, CNT_ROOTS, roots);
     count_add(w.counters, CNT_LOW_PAIRS, pairs);
     count_add(w.counters, CNT_ROW_PAIRS, pairs);
-    count_add(w.counters, CNT_SM_TERMS, terms);
-    count_add(w.counters, CNT_SM_ROOTS, roots);
-    count_add(w.counters, CNT_SM_LOW_PAIRS, pairs);
-    count_add(w.counters, CNT_SM_ROW_PAIRS, pairs);
+    count_add(w.counters, cbase, terms);
+    count_add(w.counters, cbase + 1, pairs);
+    count_add(w.counters, cbase + 2, pairs);
+    count_add(w.counters, cbase + 3, roots);
 }
 
 // LDS staging of one merge's active arrays for the fused root steps.
@@ -1251,7 +1253,7 @@ struct SmallStage {
 template <int NT>
 __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long long ks, const double* e,
                                                   const unsigned long long* __restrict__ pmax, const Work& w,
-                                                  SmallStage& sg) {
+                                                  SmallStage& sg, int cbase) {
     for (int i = threadIdx.x; i < K; i += NT) {
         sg.D[i] = w.Da[ks + i];
         sg.W[i] = w.Wa[ks + i];
@@ -1266,11 +1268,11 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     // large for merges of kFuseWideS columns or more (few such merges share a
     // level, so their roots get more lanes); NT >= G K is one pass
     const int ref = (R.nL + R.nR >= kFuseWideS) ? 2 * kFuseThreads : kFuseThreads;
-    if (K * 16 <= ref) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K * 8 <= ref) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K * 4 <= ref) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else if (K * 2 <= ref) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
-    else small_merge_body<NT, 1>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O);
+    if (K * 16 <= ref) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else if (K * 8 <= ref) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else if (K * 4 <= ref) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else if (K * 2 <= ref) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else small_merge_body<NT, 1>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
 }
 
 template <int NT>
@@ -1282,7 +1284,7 @@ __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__
     const int K = sp.K;
     if (K < 1 || K > kFuseMax) return;  // block-uniform
     __shared__ SmallStage sg;
-    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg);
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS);
 }
 
 // ---------------------------------------------------------------------------
@@ -1409,7 +1411,7 @@ __global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__
     __syncthreads();
     // roots, Loewner z, rows
     const int K = v.scan[pk + s];
-    if (K >= 1) small_merge_solve<NT>(R, K, 0, e, pmax, v, sg);
+    if (K >= 1) small_merge_solve<NT>(R, K, 0, e, pmax, v, sg, CNT_LB_TERMS);
     __syncthreads();
     // the parent's spectrum and rows, or the problem's eigenvalues
     for (int i = threadIdx.x; i < s; i += NT) body_assemble(pk + i, 0, sm, pmax, v, out);
@@ -2013,7 +2015,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         if (level_blocked(L)) {
             // every merge of the level fits one workgroup: the whole merge in one launch
             // (with a checkpoint, its roots land at the merge's packed positions)
-            TDE_LAUNCH_K(KIND_SMALL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
+            TDE_LAUNCH_K(KIND_LEVEL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
                          (const unsigned long long*)w.pmax, wl, out);
             continue;
         }

@@ -94,7 +94,7 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
              "| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) |",
              "|---|---|---|---|---|"]
     kinds = {"k_secular": "secular", "k_lowner": "lowner", "k_rows": "rows", "k_leaf": "leaf", "k_leaf_dc": "leaf",
-             "k_small_merge": "small", "k_merge": "merge", "k_assemble": "assemble"}
+             "k_small_merge": "small", "k_level_block": "level", "k_merge": "merge", "k_assemble": "assemble"}
     for k in sorted(f, key=lambda k: -sum(f[k])):
         if k == ck:
             continue

@@ -159,6 +159,11 @@ def test_counters(tde):
     # six levels inside the 64-column leaves, six global ones: both did work
     assert c["dc_roots"] > 0 and c["roots"] > 0
     assert c["dc_secular_terms"] >= c["dc_roots"]
+    # the global levels' roots: whole-merge workgroups (merges of at most 512
+    # columns) plus the fused root kernel make up all of them here
+    assert c["level_roots"] > 0
+    assert c["level_roots"] + c["small_roots"] == c["roots"]
+    assert c["level_secular_terms"] + c["small_secular_terms"] == c["secular_terms"]
     # the global path alone counts no in-wave work
     tde.eigvals(_t(d), _t(e), leaf=64, leaf_dc=False, workspace=ws)
     torch.cuda.synchronize()
