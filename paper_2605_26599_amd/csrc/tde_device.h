@@ -261,15 +261,15 @@ TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st
 TDE_DEV double model_root(double f, double tau, double d1, double d2, double q, double Q, double lo,
                           double hi) {
     // c(d1-x)(d2-x) + q(d2-x) + Q(d1-x) = 0  <=>  c x^2 - A x + C0 = 0
-    const double c = f - q / (d1 - tau) - Q / (d2 - tau);
+    const double c = f - q * rcp_nr(d1 - tau) - Q * rcp_nr(d2 - tau);
     const double A = c * (d1 + d2) + q + Q;
     const double C0 = c * d1 * d2 + q * d2 + Q * d1;
     double disc = A * A - 4.0 * C0 * c;
     if (!(disc >= 0.0)) disc = 0.0;
     const double sq = sqrt(disc);
     const double den = (A >= 0.0) ? A + sq : A - sq;
-    const double r1 = (c != 0.0) ? den / (2.0 * c) : NAN;
-    const double r2 = (den != 0.0) ? 2.0 * C0 / den : NAN;
+    const double r1 = (c != 0.0) ? den * rcp_nr(2.0 * c) : NAN;
+    const double r2 = (den != 0.0) ? 2.0 * C0 * rcp_nr(den) : NAN;
     const bool in1 = r1 > lo && r1 < hi;
     const bool in2 = r2 > lo && r2 < hi;
     if (in1 && in2) return 0.5 * (r1 + r2);
@@ -353,7 +353,7 @@ TDE_DEV void sec_start_last(int K, const double* __restrict__ D, const double* _
 // next offset in r->tau.
 TDE_DEV int sec_update(SecRoot* r, double rho, double psi, double dpsi, double phi, double dphi, double err) {
     const double tau = r->tau;
-    const double to = r->zo / (-tau);
+    const double to = -r->zo * rcp_nr(tau);
     const double termo = r->zo * to, dto = to * to;
     const double f = 1.0 + rho * (psi + phi + termo);
     err += fabs(termo);
@@ -794,6 +794,7 @@ TDE_DEV int body_secular(long long g, int m, const MergeRec* __restrict__ mr, co
     if (sub == 0) {
         w.org[g] = o;
         w.tau[g] = tau;
+        w.rootval[g] = Dv[b + o] + tau;
     }
     return it;
 }
@@ -885,9 +886,7 @@ TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
     const int nr = (int)(w.scanR[R.pk + s] - rs);
     const long long ns = R.pk - ks - rs;
     const int nn = s - K - nr;
-    const double* Da = w.Da + ks;
-    const int* og = w.org + ks;
-    const double* ta = w.tau + ks;
+    const double* rv = w.rootval + ks;  // D_org + tau of each root, ascending
     const double* Dr = w.Dr + rs;
     const double* Dd = w.Dd + ns;
     const bool root = (R.flags & MF_ROOT) != 0;
@@ -895,18 +894,18 @@ TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
     int pos;
     double val, bl = 0.0, bh = 0.0;
     if (i < K) {
-        val = Da[og[i]] + ta[i];
+        val = rv[i];
         pos = i + count_lt(Dr, nr, val) + count_lt(Dd, nn, val);
         if (rows) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
     } else if (i < K + nr) {
         const int q = i - K;
         val = Dr[q];
-        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_lt(Dd, nn, val);
+        pos = q + count_le(rv, K, val) + count_lt(Dd, nn, val);
         if (rows) { bl = w.RLr[rs + q]; bh = w.RHr[rs + q]; }
     } else {
         const int q = i - K - nr;
         val = Dd[q];
-        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_le(Dr, nr, val);
+        pos = q + count_le(rv, K, val) + count_le(Dr, nr, val);
         if (rows) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
     }
     const long long P = R.off + pos;

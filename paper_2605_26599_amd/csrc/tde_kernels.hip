@@ -201,7 +201,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
                                                double* __restrict__ out) {
     if (input_nonfinite(w)) return;
     constexpr int C = kDcCols;
-    __shared__ double sb[26 * C];
+    __shared__ double sb[27 * C];
     __shared__ int sbi[4 * C + 4 * (C + 1)];
     __shared__ MergeRec smr[C / 2];
     const LeafRec L = leaves[blockIdx.x];
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
         wl.Da = p; p += C;   wl.Za = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;
         wl.RHa = p; p += C;  wl.tau = p; p += C;  wl.zhat = p; p += C; wl.PBL = p; p += C;
         wl.PBH = p; p += C;  wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
-        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;
+        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;  wl.rootval = p; p += C;
         int* q = sbi;
         wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = q; q += C;
         wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
@@ -843,6 +843,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
         if (wv == 0 && act) {
             w.org[ks + k] = r.o;
             w.tau[ks + k] = r.tau;
+            w.rootval[ks + k] = D[r.o] + r.tau;
             const unsigned long long sw = (unsigned long long)((done ? its : kSecMaxIter) + 1);
             sweeps += sw;
             terms += sw * (unsigned long long)K;
@@ -1110,6 +1111,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                     if (sub == 0) {
                         w.org[g] = 0;
                         w.tau[g] = rho * Zg[0] * Zg[0];
+                        w.rootval[g] = Dv[0] + w.tau[g];
                         roots += 1;
                     }
                     g = -1;
@@ -1153,6 +1155,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (sub == 0) {
                     w.org[g] = r.o;
                     w.tau[g] = r.tau;
+                    w.rootval[g] = Dv[r.o] + r.tau;
                     sweeps += (unsigned long long)(used + 1);
                     terms += (unsigned long long)(used + 1) * (unsigned long long)K;
                     roots += 1;
@@ -1210,6 +1213,7 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     for (int i = threadIdx.x; i < K; i += NT) {
         w.org[ks + i] = sO[i];
         w.tau[ks + i] = sT[i];
+        w.rootval[ks + i] = sD[sO[i]] + sT[i];
     }
     if (!(R.flags & MF_ROOT) || w.rows_out) {
         for (int i = grp; i < K; i += ng) {
@@ -1337,6 +1341,7 @@ __global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__
     v.RHa = w.RHa + pk;
     v.org = w.org + pk;
     v.tau = w.tau + pk;
+    v.rootval = w.rootval + pk;
     v.zhat = w.zhat + pk;
     v.PBL = w.PBL + pk;
     v.PBH = w.PBH + pk;
@@ -2232,6 +2237,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.dpos = (int*)take(4 * nn);
     t.org = (int*)take(4 * nn);
     t.tau = (double*)take(8 * nn);
+    t.rootval = (double*)take(8 * nn);
     t.zhat = (double*)take(8 * nn);
     t.PBL = (double*)take(8 * nn);
     t.PBH = (double*)take(8 * nn);
