@@ -268,3 +268,28 @@ def test_wide_secular_sweep_batched(tde):
         s, t = int(bt.offsets[b]), int(bt.offsets[b + 1])
         if t > s:
             assert np.abs(lam[s:t] - oracle.eigvals(d, e)).max() <= GATE * tdgen.tnorm1(d, e)
+
+
+def test_golden_exact_small(tde):
+    """The stored exact eigenvalues (tests/golden/exact_small.txt) of the tiny
+    classic cases, one solve at a time in every leaf mode and all in one batch."""
+    import torch
+
+    from conftest import load_exact_small
+
+    cases = load_exact_small()
+    for name, d, e, lam in cases:
+        tn = tdgen.tnorm1(d, e)
+        for kw in [{}, {"leaf": 1}, {"leaf": 4}, {"leaf": 64, "leaf_dc": True}]:
+            _step(f"golden {name} {kw}")
+            dv = torch.from_numpy(d).to(_dev())
+            ev = torch.from_numpy(e if len(e) else np.zeros(1)).to(_dev())
+            got = tde.eigvals(dv, ev, **kw).cpu().numpy()
+            assert np.abs(got - lam).max() <= GATE * tn, (name, kw)
+    _step("golden batched")
+    bt = tdgen.pack([(d, e) for _, d, e, _ in cases])
+    got = tde.eigvals_batched(torch.from_numpy(bt.d).to(_dev()), torch.from_numpy(bt.e).to(_dev()),
+                              bt.offsets).cpu().numpy()
+    for b, (name, d, e, lam) in enumerate(cases):
+        s, t = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        assert np.abs(got[s:t] - lam).max() <= GATE * tdgen.tnorm1(d, e), name

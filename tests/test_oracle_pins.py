@@ -85,6 +85,27 @@ def test_wilkinson21_exact():
     assert abs(exact[-1] - 10.746194182903393) < 1e-12  # largest eigenvalue of W+_21
 
 
+def test_golden_exact_small():
+    # Stored exact eigenvalues (tests/golden/make_exact_small.py): the oracle's
+    # bisection within a few ulps of ||T||, and facts that pin the fixture itself.
+    from conftest import load_exact_small
+
+    cases = {name: (d, e, lam) for name, d, e, lam in load_exact_small()}
+    assert len(cases) >= 10
+    for name, (d, e, lam) in cases.items():
+        assert np.all(np.diff(lam) >= 0), name
+        assert _err(oracle.eigvals(d, e), lam, d, e) <= 4.0, name
+        assert abs(lam.sum() - d.sum()) <= 1e-12 * max(1.0, np.abs(d).sum()), name  # trace
+    assert cases["wilkinson_plus_21"][2][-1] == 10.746194182903393  # largest eigenvalue of W+_21
+    wm = cases["wilkinson_minus_21"][2]
+    assert np.array_equal(wm, -wm[::-1]) and wm[10] == 0.0  # W-_21 is similar to -W-_21
+    k = np.arange(1, 17)
+    assert np.abs(cases["toeplitz_121_n16"][2] - (2 - 2 * np.cos(k * np.pi / 17))).max() <= 8 * EPS
+    d, e, lam = cases["n2"]
+    m, r = 0.5 * (d[0] + d[1]), math.hypot(0.5 * (d[0] - d[1]), e[0])
+    assert np.abs(lam - [m - r, m + r]).max() <= 4 * EPS
+
+
 @pytest.mark.parametrize("fam", ["uniform", "wilkinson", "paper_clustered"])
 def test_dense_high_precision(fam):
     # An independent dense symmetric eigensolver (mpmath Jacobi, 40 digits).
