@@ -608,17 +608,39 @@ __global__ __launch_bounds__(kWG) void k_actcompact(const MergeRec* __restrict__
     }
 }
 
-// Group reduction over G consecutive lanes: butterfly, then lane 0 of the
-// group broadcasts, so every lane holds the same bits.
+// Group reduction over G <= 16 consecutive lanes with DPP lane moves (no LDS
+// crossbar): swap within pairs, then within quads, then mirror the
+// eight-lane half rows, then the sixteen-lane rows.  Each step pairs lane i
+// with a partner that takes lane i as its own partner, and x + y == y + x
+// bit for bit, so every lane of the group ends with the same bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+constexpr int kDppSwap1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within eight lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within sixteen lanes
+
 template <int G>
 struct RedGroup {
+    static_assert(G == 2 || G == 4 || G == 8 || G == 16, "group of 2..16 lanes");
     __device__ __forceinline__ static double sum(double x) {
-        for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
-        return __shfl(x, 0, G);
+        x += dpp_move<kDppSwap1>(x);
+        if (G >= 4) x += dpp_move<kDppSwap2>(x);
+        if (G >= 8) x += dpp_move<kDppHalfMirror>(x);
+        if (G >= 16) x += dpp_move<kDppMirror>(x);
+        return x;
     }
     __device__ __forceinline__ static double prod(double x) {
-        for (int o = G / 2; o > 0; o >>= 1) x *= __shfl_xor(x, o, G);
-        return __shfl(x, 0, G);
+        x *= dpp_move<kDppSwap1>(x);
+        if (G >= 4) x *= dpp_move<kDppSwap2>(x);
+        if (G >= 8) x *= dpp_move<kDppHalfMirror>(x);
+        if (G >= 16) x *= dpp_move<kDppMirror>(x);
+        return x;
     }
 };
 template <>
