@@ -783,14 +783,15 @@ __device__ __forceinline__ void wide_sweep(cdouble* D, cdouble* W, int a, int b,
     }
 }
 
-// Wide secular roots.  red: 2 x 5 x kWideWaves x 64 doubles of LDS.  The
-// block iterates until all of its 64 roots have converged.
+// Wide secular roots with NW waves per block.  red: 2 x 5 x NW x 64 doubles
+// of LDS.  The block iterates until all of its 64 roots have converged.
+template <int NW>
 __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
                              const unsigned long long* __restrict__ pmax, const Work& w, const int* items,
                              double* red) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform((int)(threadIdx.x >> 6));
-    auto R5 = [&](int buf, int q, int v) -> double& { return red[((buf * 5 + q) * kWideWaves + v) * 64 + lane]; };
+    auto R5 = [&](int buf, int q, int v) -> double& { return red[((buf * 5 + q) * NW + v) * 64 + lane]; };
     const int total = items[M];
     int buf = 0;
     int bad = 0;
@@ -813,7 +814,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
         const int kk = min(k, K - 2);
         const int klast = min(k0 + 63, K - 1);
         const int w0 = k0, w1 = min(min(klast, K - 2) + 2, K);
-        const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+        const int a = (int)((long long)K * wv / NW), b = (int)((long long)K * (wv + 1) / NW);
         // first sweep: bracket midpoint with origin kk (the last root also needs ||z||^2)
         WideSums s{0.0, 0.0, 0.0, 0.0, 0.0};
         wide_sweep<true>(Dc, Wc, a, b, w0, w1, D[kk], 0.5 * (D[kk + 1] - D[kk]), kk, kk + 2, s);
@@ -826,7 +827,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
         __syncthreads();
         for (int q = 0; q < 5; ++q) {
             double x = 0.0;
-            for (int v = 0; v < kWideWaves; ++v) x += R5(buf, q, v);
+            for (int v = 0; v < NW; ++v) x += R5(buf, q, v);
             tot[q] = x;
         }
         buf ^= 1;
@@ -852,7 +853,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
             __syncthreads();
             for (int q = 0; q < 4; ++q) {
                 double x = 0.0;
-                for (int v = 0; v < kWideWaves; ++v) x += R5(buf, q, v);
+                for (int v = 0; v < NW; ++v) x += R5(buf, q, v);
                 tot[q] = x;
             }
             buf ^= 1;
@@ -884,7 +885,8 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
 // Wide Loewner step: 64 poles per workgroup, the roots split over the waves
 // (root index wave-uniform: D_org, tau and the neighbouring poles are scalar
 // loads).  Factors are multiplied in chunks of 8 numerators and 8
-// denominators, one division per chunk.  red: kWideWaves x 64 doubles.
+// denominators, one division per chunk.  red: NW x 64 doubles.
+template <int NW>
 __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
                             const unsigned long long* __restrict__ pmax, const Work& w, bool with_root,
                             const int* items, double* red) {
@@ -906,7 +908,7 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
             const int i = min(i0 + lane, K - 1);
             const double di = w.Da[ks + i];
             const int ilast = min(i0 + 63, K - 1);
-            const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+            const int a = (int)((long long)K * wv / NW), b = (int)((long long)K * (wv + 1) / NW);
             double prod = 1.0, pn = 1.0, pd = 1.0;
             int c = 0;
             auto factor = [&](double num, double den) {
@@ -938,7 +940,7 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
             __syncthreads();
             if (wv == 0 && i0 + lane < K) {
                 double p = 1.0;
-                for (int v = 0; v < kWideWaves; ++v) p *= red[v * 64 + lane];
+                for (int v = 0; v < NW; ++v) p *= red[v * 64 + lane];
                 double sgn;
                 const double rho = merge_rho(R, e, pmax, &sgn);
                 const double zi = sqrt(fmax(p / rho, 0.0));
@@ -954,7 +956,8 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
 // Wide boundary-row step (non-top merges): 64 roots per workgroup, the poles
 // split over the waves, pole index wave-uniform (scalar loads of D_i, zhat_i
 // and both row entries); no pole is excluded, so there is no window.
-// red: 3 x kWideWaves x 64 doubles.
+// red: 3 x NW x 64 doubles.
+template <int NW>
 __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const Work& w, const int* items,
                           double* red) {
     const int lane = threadIdx.x & 63;
@@ -975,7 +978,7 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
             cdouble* RH = as_const(w.RHa + ks);
             const int k = min(k0 + lane, K - 1);
             const double Do = w.Da[ks + w.org[ks + k]], tau = w.tau[ks + k];
-            const int a = (int)((long long)K * wv / kWideWaves), b = (int)((long long)K * (wv + 1) / kWideWaves);
+            const int a = (int)((long long)K * wv / NW), b = (int)((long long)K * (wv + 1) / NW);
             double ss = 0.0, bl = 0.0, bh = 0.0;
             _Pragma("unroll 4") for (int i = a; i < b; ++i) {
                 const double y = H[i] * rcp_nr((D[i] - Do) - tau);
@@ -983,16 +986,16 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
                 bl = fma(RL[i], y, bl);
                 bh = fma(RH[i], y, bh);
             }
-            red[(0 * kWideWaves + wv) * 64 + lane] = ss;
-            red[(1 * kWideWaves + wv) * 64 + lane] = bl;
-            red[(2 * kWideWaves + wv) * 64 + lane] = bh;
+            red[(0 * NW + wv) * 64 + lane] = ss;
+            red[(1 * NW + wv) * 64 + lane] = bl;
+            red[(2 * NW + wv) * 64 + lane] = bh;
             __syncthreads();
             if (wv == 0 && k0 + lane < K) {
                 double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-                for (int v = 0; v < kWideWaves; ++v) {
-                    t0 += red[(0 * kWideWaves + v) * 64 + lane];
-                    t1 += red[(1 * kWideWaves + v) * 64 + lane];
-                    t2 += red[(2 * kWideWaves + v) * 64 + lane];
+                for (int v = 0; v < NW; ++v) {
+                    t0 += red[(0 * NW + v) * 64 + lane];
+                    t1 += red[(1 * NW + v) * 64 + lane];
+                    t2 += red[(2 * NW + v) * 64 + lane];
                 }
                 const double inv = 1.0 / sqrt(t0);
                 w.PBL[ks + k] = t1 * inv;
@@ -1033,7 +1036,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ int s_next;
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        secular_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, items, smem);
+        secular_wide<kWideWaves>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, items, smem);
         return;
     }
     double* sD = smem;
@@ -1191,6 +1194,36 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     count_add(w.counters, CNT_SEC_TERMS, terms);
     count_add(w.counters, CNT_SWEEPS, sweeps);
     count_add(w.counters, CNT_ROOTS, roots);
+}
+
+// Wide roots of a level on which every merge too large for k_small_merge is
+// wide (no regular tiles): eight waves per 64-root block instead of four, so
+// each wave sweeps an eighth of the poles and twice as many waves per SIMD
+// hide the latency of the per-term chains.
+constexpr int kWideWavesOnly = 8;
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_secular_wide(const MergeRec* __restrict__ mr, int M,
+                                                          const double* __restrict__ e,
+                                                          const unsigned long long* __restrict__ pmax, Work w) {
+    if (input_nonfinite(w)) return;
+    __shared__ double red[2 * 5 * NW * 64];
+    secular_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, w.witems, red);
+}
+
+// The same for the Loewner step and the rows (forward pass).
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_lowner_wide(const MergeRec* __restrict__ mr, int M,
+                                                         const double* __restrict__ e,
+                                                         const unsigned long long* __restrict__ pmax, Work w) {
+    if (input_nonfinite(w)) return;
+    __shared__ double red[NW * 64];
+    lowner_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, false, w.witems, red);
+}
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_rows_wide(const MergeRec* __restrict__ mr, int M, Work w) {
+    if (input_nonfinite(w)) return;
+    __shared__ double red[3 * NW * 64];
+    rows_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, w, w.witems, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1457,7 +1490,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        lowner_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
+        lowner_wide<kWideWaves>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
         return;
     }
     double* sD = smem;
@@ -1506,7 +1539,7 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        rows_wide((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, w, items, smem);
+        rows_wide<kWideWaves>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, w, items, smem);
         return;
     }
     double* sD = smem;
@@ -1940,6 +1973,13 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     long long rf = (N * G) / kRefillLanes;  // roots per group: keep about kRefillLanes lanes busy
     rf = rf < 1 ? 1 : (rf > kRefillMax ? kRefillMax : rf);
     const int nbs = (int)((nbn + rf - 1) / rf);
+    if (nbn == 0) {  // wide blocks only
+        const unsigned bw = kWideWavesOnly * 64;
+        TDE_LAUNCH_K(KIND_SECULAR, k_secular_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
+        TDE_LAUNCH_K(KIND_LOWNER, k_lowner_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
+        TDE_LAUNCH_K(KIND_ROWS, k_rows_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, w);
+        return;
+    }
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
                  fuse_max, nbs, (int)rf);
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn);
