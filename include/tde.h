@@ -75,7 +75,7 @@ typedef struct {
 int tde_version(void);
 
 /* Bytes of device workspace needed to solve B problems with n_total columns in
- * total (n_total = n for a single problem).  Linear in n_total (about 260 bytes
+ * total (n_total = n for a single problem).  Linear in n_total (about 285 bytes
  * per column).  Returns 0 on a bad argument. */
 size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts);
 

@@ -144,6 +144,7 @@ struct Work {
     int* org;                  // [n]   root origin (local active index)
     double* tau;               // [n]   root offset from its origin pole
     double* rootval;           // [n]   the root itself, D_org + tau (what the assembly sorts by)
+    double* dorg;              // [n]   D_org of the roots of wide merges (forward; read by their Loewner step)
     double* zhat;              // [n]   recomputed (Loewner) secular vector
     double* PBL;               // [n]   parent first-row entries of active columns
     double* PBH;               // [n]   parent last-row entries of active columns

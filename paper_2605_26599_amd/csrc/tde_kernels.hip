@@ -866,7 +866,9 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
         if (wv == 0 && act) {
             w.org[ks + k] = r.o;
             w.tau[ks + k] = r.tau;
-            w.rootval[ks + k] = D[r.o] + r.tau;
+            const double dor = D[r.o];
+            w.dorg[ks + k] = dor;
+            w.rootval[ks + k] = dor + r.tau;
             const unsigned long long sw = (unsigned long long)((done ? its : kSecMaxIter) + 1);
             sweeps += sw;
             terms += sw * (unsigned long long)K;
@@ -885,8 +887,11 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
 // Wide Loewner step: 64 poles per workgroup, the roots split over the waves
 // (root index wave-uniform: D_org, tau and the neighbouring poles are scalar
 // loads).  Factors are multiplied in chunks of 8 numerators and 8
-// denominators, one division per chunk.  red: NW x 64 doubles.
-template <int NW>
+// denominators, one division per chunk.  red: NW x 64 doubles.  DORG: take
+// D_org of each root from w.dorg (written by secular_wide in the same
+// forward level) instead of gathering D[org[k]], so the scalar loads of one
+// factor do not wait on each other.
+template <int NW, bool DORG>
 __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int M, const double* __restrict__ e,
                             const unsigned long long* __restrict__ pmax, const Work& w, bool with_root,
                             const int* items, double* red) {
@@ -904,7 +909,9 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
             const int i0 = __builtin_amdgcn_readfirstlane((item - items[m]) * 64);
             cdouble* D = as_const(w.Da + ks);
             cint* og = as_const(w.org + ks);
+            cdouble* dg = as_const(w.dorg + ks);
             cdouble* ta = as_const(w.tau + ks);
+            auto dorg = [&](int k) -> double { return DORG ? dg[k] : D[og[k]]; };
             const int i = min(i0 + lane, K - 1);
             const double di = w.Da[ks + i];
             const int ilast = min(i0 + 63, K - 1);
@@ -923,18 +930,18 @@ __device__ void lowner_wide(int bid, int nbw, const MergeRec* __restrict__ mr, i
             };
             // k < i0: every lane has k < i
             const int e1 = min(b, i0);
-            for (int k = a; k < e1; ++k) factor((D[og[k]] - di) + ta[k], D[k] - di);
+            for (int k = a; k < e1; ++k) factor((dorg(k) - di) + ta[k], D[k] - di);
             // window: k in [i0, ilast]
             const int s2 = max(a, i0), e2 = min(b, ilast + 1);
             for (int k = s2; k < e2; ++k) {
-                const double num = (D[og[k]] - di) + ta[k];
+                const double num = (dorg(k) - di) + ta[k];
                 const double den = (k < i) ? D[k] - di : ((k < K - 1) ? D[k + 1] - di : 1.0);
                 factor(num, den);
             }
             // ilast < k < K-1: every lane has i <= k
             const int e3 = min(b, K - 1);
-            for (int k = max(a, ilast + 1); k < e3; ++k) factor((D[og[k]] - di) + ta[k], D[k + 1] - di);
-            if (b == K && ilast + 1 <= K - 1) factor((D[og[K - 1]] - di) + ta[K - 1], 1.0);
+            for (int k = max(a, ilast + 1); k < e3; ++k) factor((dorg(k) - di) + ta[k], D[k + 1] - di);
+            if (b == K && ilast + 1 <= K - 1) factor((dorg(K - 1) - di) + ta[K - 1], 1.0);
             prod *= pn / pd;
             red[wv * 64 + lane] = prod;
             __syncthreads();
@@ -1217,7 +1224,7 @@ __global__ __launch_bounds__(NW * 64) void k_lowner_wide(const MergeRec* __restr
                                                          const unsigned long long* __restrict__ pmax, Work w) {
     if (input_nonfinite(w)) return;
     __shared__ double red[NW * 64];
-    lowner_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, false, w.witems, red);
+    lowner_wide<NW, true>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, false, w.witems, red);
 }
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_rows_wide(const MergeRec* __restrict__ mr, int M, Work w) {
@@ -1490,7 +1497,7 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
     __shared__ int s_staged;
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        lowner_wide<kWideWaves>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
+        lowner_wide<kWideWaves, false>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
         return;
     }
     double* sD = smem;
@@ -2300,6 +2307,7 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
     t.org = (int*)take(4 * nn);
     t.tau = (double*)take(8 * nn);
     t.rootval = (double*)take(8 * nn);
+    t.dorg = (double*)take(8 * nn);
     t.zhat = (double*)take(8 * nn);
     t.PBL = (double*)take(8 * nn);
     t.PBH = (double*)take(8 * nn);
