@@ -15,16 +15,15 @@ namespace tde {
 // ---------------------------------------------------------------------------
 // Small helpers
 // ---------------------------------------------------------------------------
-__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void k_fill_i32(int* p, long long n, int v) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
+// Start of a pass: zero the status words, the work counters, the per-problem
+// maxima and the per-level block counts in one launch.
+__global__ void k_setup(int* status, long long nst, unsigned long long* counters, long long ncnt,
+                        unsigned long long* pmax, long long B, int* bcnt, long long nbc) {
+    const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x, st = (long long)gridDim.x * blockDim.x;
+    for (long long i = t0; i < nst; i += st) status[i] = 0;
+    for (long long i = t0; i < ncnt; i += st) counters[i] = 0ULL;
+    for (long long i = t0; i < B; i += st) pmax[i] = 0ULL;
+    for (long long i = t0; i < nbc; i += st) bcnt[i] = 0;
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
@@ -1207,14 +1206,46 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // wide (no regular tiles): eight waves per 64-root block instead of four, so
 // each wave sweeps an eighth of the poles and twice as many waves per SIMD
 // hide the latency of the per-term chains.
+// On levels of at most kWideOwnItems merges every block scans the merges' wide
+// item counts itself (the work of k_wide_items, one launch less per level)
+// and block 0 stores the table for the Loewner and row steps.
 constexpr int kWideWavesOnly = 8;
+constexpr int kWideOwnItems = 1024;
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_secular_wide(const MergeRec* __restrict__ mr, int M,
                                                           const double* __restrict__ e,
-                                                          const unsigned long long* __restrict__ pmax, Work w) {
+                                                          const unsigned long long* __restrict__ pmax, Work w,
+                                                          int wide_min, int fuse_max, int own_items) {
     if (input_nonfinite(w)) return;
     __shared__ double red[2 * 5 * NW * 64];
-    secular_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, w.witems, red);
+    __shared__ int sitems[kWideOwnItems + 1];
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    const int* items = w.witems;
+    if (own_items) {  // M <= kWideOwnItems (block-uniform)
+        if (threadIdx.x == 0) carry = 0;
+        __syncthreads();
+        for (int base = 0; base < M; base += NW * 64) {
+            const int m = base + (int)threadIdx.x;
+            int v = 0;
+            if (m < M) {
+                const int K = merge_span(mr[m], w.scan).K;
+                v = (K >= wide_min && K > fuse_max) ? (K + 63) / 64 : 0;
+            }
+            const int incl = block_incl_scan(v, wsum);
+            const int c = carry;
+            if (m < M) sitems[m] = c + incl - v;
+            __syncthreads();
+            if (threadIdx.x == NW * 64 - 1) carry = c + incl;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sitems[M] = carry;
+        __syncthreads();
+        if (blockIdx.x == 0)
+            for (int m = threadIdx.x; m <= M; m += NW * 64) w.witems[m] = sitems[m];
+        items = sitems;
+    }
+    secular_wide<NW>((int)blockIdx.x, (int)gridDim.x, mr, M, e, pmax, w, items, red);
 }
 
 // The same for the Loewner step and the rows (forward pass).
@@ -1975,14 +2006,17 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     // every merge too large for k_small_merge is wide: no regular tiles
     if (wide_min <= fuse_max + 1) nbn = 0;
     const unsigned grid = (unsigned)(nbn + nbw);
-    // one k_wide_items launch serves the three root kernels of the level
-    if (wide) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, fuse_max);
+    // one k_wide_items launch serves the three root kernels of the level (on
+    // wide-only levels of few merges the secular kernel builds the table)
+    const int own_items = (nbn == 0 && M <= kWideOwnItems) ? 1 : 0;
+    if (wide && !own_items) TDE_LAUNCH_K(KIND_DEFLATE, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, fuse_max);
     long long rf = (N * G) / kRefillLanes;  // roots per group: keep about kRefillLanes lanes busy
     rf = rf < 1 ? 1 : (rf > kRefillMax ? kRefillMax : rf);
     const int nbs = (int)((nbn + rf - 1) / rf);
     if (nbn == 0) {  // wide blocks only
         const unsigned bw = kWideWavesOnly * 64;
-        TDE_LAUNCH_K(KIND_SECULAR, k_secular_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
+        TDE_LAUNCH_K(KIND_SECULAR, k_secular_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w,
+                     wide_min, fuse_max, own_items);
         TDE_LAUNCH_K(KIND_LOWNER, k_lowner_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
         TDE_LAUNCH_K(KIND_ROWS, k_rows_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, w);
         return;
@@ -2046,12 +2080,21 @@ static Work level_work(const Work& w, long long ntot, size_t h) {
 
 static long long bcnt_entries(const Plan& p) { return (long long)p.levels.size() * 2 * ((p.ntot + kWG - 1) / kWG + 2); }
 
+static void enqueue_setup(const Plan& p, const Work& w, void* stream) {
+    const long long nbc = p.levels.empty() ? 0 : bcnt_entries(p);
+    const long long ncnt = (long long)CNT_N * kCntSlots;
+    long long most = nbc > p.B ? nbc : p.B;
+    if (most < ncnt) most = ncnt;
+    unsigned g = nblk(most, kWG);
+    if (g > 64) g = 64;
+    TDE_LAUNCH_K(KIND_SETUP, k_setup, g, kWG, stream, w.status, 16LL, w.counters, ncnt, w.pmax, (long long)p.B,
+                 w.bcnt, nbc);
+}
+
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck) {
     if (p.ntot == 0) return 0;
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 256, stream, w.counters, (long long)CNT_N * kCntSlots, 0ULL);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
+    enqueue_setup(p, w, stream);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
     if (p.nleaves > 0 && p.leaf_dc && !ck) {
@@ -2069,8 +2112,6 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         else
             TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
     }
-    if (!p.levels.empty())
-        TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, nblk(bcnt_entries(p), kWG), kWG, stream, w.bcnt, bcnt_entries(p), 0);
     for (size_t h = 0; h < p.levels.size(); ++h) {
         const LevelInfo& L = p.levels[h];
         const MergeRec* mr = p.d_merges + L.mstart;
@@ -2121,13 +2162,9 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
                      const double* e, const double* gin, double* gd, double* ge, void* stream) {
     if (p.ntot == 0) return 0;
     const long long cs = p.ntot;  // coefficient plane stride
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, 1, 64, stream, w.status, 16LL, 0);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, 1, 256, stream, w.counters, (long long)CNT_N * kCntSlots, 0ULL);
-    TDE_LAUNCH_K(KIND_SETUP, k_fill_u64, nblk(p.B, kWG), kWG, stream, w.pmax, (long long)p.B, 0ULL);
+    enqueue_setup(p, w, stream);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
-    if (!p.levels.empty())
-        TDE_LAUNCH_K(KIND_SETUP, k_fill_i32, nblk(bcnt_entries(p), kWG), kWG, stream, w.bcnt, bcnt_entries(p), 0);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_init, nblk(p.ntot, kWG), kWG, stream, p.ntot, gin, gr);
     for (size_t hh = p.levels.size(); hh-- > 0;) {
         const LevelInfo& L = p.levels[hh];
