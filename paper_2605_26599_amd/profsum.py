@@ -45,7 +45,9 @@ def stats(stats_csv, bench_jsonl, out_md, title, cmd):
     b = json.loads([ln for ln in open(bench_jsonl) if ln.startswith("{")][-1])
     rf = b.get("roofline")
     if rf:
-        fam = agg.get(rf["kernel"])
+        # the eight-wave launches of wide-only levels belong to the same step
+        parts = [agg[k] for k in (rf["kernel"], rf["kernel"] + "_wide") if k in agg]
+        fam = [sum(p[0] for p in parts), sum(p[1] for p in parts)] if parts else None
         lines += ["", "The same workload as measured live by bench.py (HIP events, instrumented timed region):", "",
                   f"- ms per solve (un-instrumented timed region): {b['ms_per_step']:.3f}",
                   f"- dominant kernel: {rf['kernel']}, {rf['launches']} launches, "
@@ -93,7 +95,8 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
              f"scale factors fetch {kf:.4f}, write {kw:.4f} (known bytes / counter bytes).", "",
              "| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) |",
              "|---|---|---|---|---|"]
-    kinds = {"k_secular": "secular", "k_lowner": "lowner", "k_rows": "rows", "k_leaf": "leaf", "k_leaf_dc": "leaf",
+    kinds = {"k_secular": "secular", "k_lowner": "lowner", "k_rows": "rows", "k_secular_wide": "secular",
+             "k_lowner_wide": "lowner", "k_rows_wide": "rows", "k_leaf": "leaf", "k_leaf_dc": "leaf",
              "k_small_merge": "small", "k_level_block": "level", "k_merge": "merge", "k_assemble": "assemble"}
     for k in sorted(f, key=lambda k: -sum(f[k])):
         if k == ck:
