@@ -44,12 +44,12 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _solve(tde, d, e, leaf=None):
+def _solve(tde, d, e, leaf=None, **kw):
     import torch
 
     dv = torch.from_numpy(np.ascontiguousarray(d)).to(_dev())
     ev = torch.from_numpy(np.ascontiguousarray(e if len(e) else np.zeros(1))).to(_dev())
-    return tde.eigvals(dv, ev, leaf=leaf).cpu().numpy()
+    return tde.eigvals(dv, ev, leaf=leaf, **kw).cpu().numpy()
 
 
 def _full_check(tde, d, e, leaf=None):
@@ -141,9 +141,9 @@ def test_deterministic(tde):
 
 # --- C2: n in {16384, 32768, 65536} x 4 families -----------------------------
 
-def _sampled_and_certified(tde, d, e, nsample=256, ncert=None, seed=0):
+def _sampled_and_certified(tde, d, e, nsample=256, ncert=None, seed=0, **kw):
     n = len(d)
-    lam = _solve(tde, d, e)
+    lam = _solve(tde, d, e, **kw) if kw else _solve(tde, d, e)
     tn = tdgen.tnorm1(d, e)
     assert np.all(np.diff(lam) >= 0)
     g = np.random.default_rng(seed)
@@ -176,6 +176,30 @@ def test_c2_families(tde, fam, n):
         k = np.arange(1, n + 1)
         exact = np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
         assert np.abs(lam - exact).max() <= GATE * 4.0
+
+
+TUNED = {"leaf": 64, "leaf_dc": True, "sweep_cols": 64, "wide_min": 32}
+
+
+@pytest.mark.parametrize("n", [65536, 262144])
+@pytest.mark.parametrize("fam", ["uniform", "toeplitz", "clustered"])
+def test_full_size_tuned_launch(tde, fam, n):
+    """The launch configuration the benchmark times (in-wave leaves of 64,
+    every merge above the fused limit on the eight-wave wide-only path):
+    Toeplitz against its closed form everywhere, and the same bits on a
+    second solve; the others sampled against bisection and certified by
+    Sturm counts."""
+    _step(f"tuned launch fam={fam} n={n}")
+    d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_FAMILIES)
+    if fam == "toeplitz":
+        lam = _solve(tde, d, e, **TUNED)
+        k = np.arange(1, n + 1)
+        exact = np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
+        assert np.abs(lam - exact).max() <= GATE * 4.0
+        lam2 = _solve(tde, d, e, **TUNED)
+        assert np.array_equal(lam, lam2), "replays differ"
+    else:
+        _sampled_and_certified(tde, d, e, nsample=128, ncert=2048, **TUNED)
 
 
 # --- C3: n in {131072, 262144}, N(0,1); Toeplitz 262144 ----------------------
