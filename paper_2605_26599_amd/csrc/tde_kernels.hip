@@ -1266,11 +1266,12 @@ __global__ __launch_bounds__(NW * 64) void k_rows_wide(const MergeRec* __restric
 
 // ---------------------------------------------------------------------------
 // Merges with at most kFuseMax active roots (after deflation): one workgroup
-// of kFuseThreads per merge runs the secular roots, the Loewner z and the
-// boundary rows with the merge's active arrays staged in LDS once, with
-// G = min(16, kFuseThreads / K) lanes per root or pole rounded down to a power
-// of two (the same device functions as the level-wide kernels, which skip
-// these merges).  G depends on K alone, so a merge's arithmetic does not
+// of kFuseThreads (2 kFuseThreads on levels of merges of kFuseWideS columns
+// or more) per merge runs the secular roots, the Loewner z and the boundary
+// rows with the merge's active arrays staged in LDS once, with
+// G = min(16, 2 kFuseThreads / K) lanes per root or pole rounded down to a
+// power of two (the same device functions as the level-wide kernels, which
+// skip these merges).  G depends on K alone, so a merge's arithmetic does not
 // depend on the rest of its level (a batched solve matches the single ones
 // bit for bit).  On random spectra nearly every merge is of this kind (a
 // hundred or so roots survive deflation).
@@ -1361,10 +1362,11 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
     __syncthreads();
-    // lanes per root from the merge alone: G = min(16, ref / K), ref twice as
-    // large for merges of kFuseWideS columns or more (few such merges share a
-    // level, so their roots get more lanes); NT >= G K is one pass
-    const int ref = (R.nL + R.nR >= kFuseWideS) ? 2 * kFuseThreads : kFuseThreads;
+    // lanes per root from the merge alone: G = min(16, 1024 / K) (a root's
+    // sweeps are latency-bound chains, so more lanes per root pay even when a
+    // 512-thread workgroup then takes two passes over the roots: measured on
+    // single solves and large batches against 512 / K and 2048 / K)
+    const int ref = 2 * kFuseThreads;
     if (K * 16 <= ref) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else if (K * 8 <= ref) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else if (K * 4 <= ref) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
