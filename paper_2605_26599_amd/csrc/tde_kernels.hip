@@ -200,7 +200,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
                                                double* __restrict__ out) {
     if (input_nonfinite(w)) return;
     constexpr int C = kDcCols;
-    __shared__ double sb[27 * C];
+    __shared__ double sb[21 * C];
     __shared__ int sbi[4 * C + 4 * (C + 1)];
     __shared__ MergeRec smr[C / 2];
     const LeafRec L = leaves[blockIdx.x];
@@ -209,17 +209,25 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
     const double inv = 1.0 / scale_of(pmax[L.prob]);
     const double* eL = e + L.off;  // merge records below carry leaf-local offsets
 
-    // level arrays in LDS
+    // level arrays in LDS.  A level runs merge | flags | runs | three-way
+    // split | roots | Loewner | rows | assembly; the merged and rotated
+    // columns (D, Z, RL, RH, D2, Z2) are last read by the split, so the later
+    // steps' arrays live in them: active z (split to Loewner) in Z, tau in D,
+    // the root values in D2, z-hat in Z2, the parent rows in RL and RH.  (The
+    // node state lam, blo, bhi keeps its own storage: nodes that no merge of
+    // this level touches carry their values to a higher level.)  Fewer arrays
+    // let more leaves share a compute unit.
     Work wl = w;
     {
         double* p = sb;
         wl.lam = p; p += C;  wl.blo = p; p += C;  wl.bhi = p; p += C;
         wl.D = p; p += C;    wl.Z = p; p += C;    wl.RL = p; p += C;   wl.RH = p; p += C;
         wl.D2 = p; p += C;   wl.Z2 = p; p += C;   wl.RL2 = p; p += C;  wl.RH2 = p; p += C;
-        wl.Da = p; p += C;   wl.Za = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;
-        wl.RHa = p; p += C;  wl.tau = p; p += C;  wl.zhat = p; p += C; wl.PBL = p; p += C;
-        wl.PBH = p; p += C;  wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
-        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;  wl.rootval = p; p += C;
+        wl.Da = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;  wl.RHa = p; p += C;
+        wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
+        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;
+        wl.Za = wl.Z;        wl.tau = wl.D;       wl.rootval = wl.D2;  wl.zhat = wl.Z2;
+        wl.PBL = wl.RL;      wl.PBH = wl.RH;
         int* q = sbi;
         wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = q; q += C;
         wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
