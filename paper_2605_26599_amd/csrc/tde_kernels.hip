@@ -201,7 +201,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
     if (input_nonfinite(w)) return;
     constexpr int C = kDcCols;
     __shared__ double sb[21 * C];
-    __shared__ int sbi[4 * C + 4 * (C + 1)];
+    __shared__ int sbi[3 * C + 4 * (C + 1)];
     __shared__ MergeRec smr[C / 2];
     const LeafRec L = leaves[blockIdx.x];
     const int l = L.size;
@@ -213,7 +213,8 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
     // split | roots | Loewner | rows | assembly; the merged and rotated
     // columns (D, Z, RL, RH, D2, Z2) are last read by the split, so the later
     // steps' arrays live in them: active z (split to Loewner) in Z, tau in D,
-    // the root values in D2, z-hat in Z2, the parent rows in RL and RH.  (The
+    // the root values in D2, z-hat in Z2, the parent rows in RL and RH; the
+    // roots' origins reuse the candidate positions, last read by the runs.  (The
     // node state lam, blo, bhi keeps its own storage: nodes that no merge of
     // this level touches carry their values to a higher level.)  Fewer arrays
     // let more leaves share a compute unit.
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
         wl.Za = wl.Z;        wl.tau = wl.D;       wl.rootval = wl.D2;  wl.zhat = wl.Z2;
         wl.PBL = wl.RL;      wl.PBH = wl.RH;
         int* q = sbi;
-        wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = q; q += C;
+        wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = wl.nnpos;
         wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
     }
     // destinations of the leaf's top merge
