@@ -57,6 +57,8 @@ def _load():
         lib.oracle_eigvals_index.restype = ctypes.c_int
         lib.oracle_counts.argtypes = [i64, dp, dp, i64, dp, ip]
         lib.oracle_counts.restype = ctypes.c_int
+        lib.oracle_counts_scalar.argtypes = [i64, dp, dp, i64, dp, ip]
+        lib.oracle_counts_scalar.restype = ctypes.c_int
         lib.ql_eigvals.argtypes = [i64, dp, dp, dp]
         lib.ql_eigvals.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
@@ -125,6 +127,16 @@ def counts(d, e, x) -> np.ndarray:
     out = np.empty(x.size, dtype=np.int64)
     if x.size:
         _check(_load().oracle_counts(n, _dp(d), _dp(e), x.size, _dp(x), _ip(out)))
+    return out
+
+
+def counts_scalar(d, e, x) -> np.ndarray:
+    """As counts, one point at a time (checks the grouped evaluation)."""
+    d, e, n = _prep(d, e)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty(x.size, dtype=np.int64)
+    if x.size:
+        _check(_load().oracle_counts_scalar(n, _dp(d), _dp(e), x.size, _dp(x), _ip(out)))
     return out
 
 

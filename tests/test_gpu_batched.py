@@ -79,20 +79,14 @@ def test_batched_equals_single(tde):
 
 
 def test_c4_batched_4096(tde):
+    """Every problem of the batch: 48 bisected in full, all 4096 certified
+    eigenvalue by eigenvalue with two Sturm counts each."""
     _step("C4: 4096 problems, log-uniform sizes in [32, 4096]")
     batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
     lam = _solve_batch(tde, batch)
     g = np.random.default_rng(11)
     full = set(g.choice(batch.count, 48, replace=False).tolist())
-    cert = set(g.choice(batch.count, 400, replace=False).tolist())
     for b in range(batch.count):
+        _check_problem(batch, lam, b, full=b in full)
         if b in full:
-            _check_problem(batch, lam, b, full=True)
-        elif b in cert:
             _check_problem(batch, lam, b, full=False)
-        else:
-            lo, hi = int(batch.offsets[b]), int(batch.offsets[b + 1])
-            assert np.all(np.diff(lam[lo:hi]) >= 0)
-            d, e = batch.problem(b)
-            tn = tdgen.tnorm1(d, e)
-            assert abs(lam[lo:hi].sum() - d.sum()) <= (hi - lo) * GATE * tn

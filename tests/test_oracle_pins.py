@@ -212,6 +212,22 @@ def test_index_matches_full_and_certify():
     assert list(c) == [0, 900, 11]
 
 
+def test_grouped_counts_equal_scalar_counts():
+    """The grouped Sturm counts (eight points sharing one loop) return exactly
+    the one-point-at-a-time counts, at every point, including points on and
+    next to eigenvalues, tails of the group and an empty group."""
+    for fam, n in [("uniform", 1000), ("clustered", 777), ("wilkinson", 21), ("toeplitz", 64)]:
+        d, e = tdgen.tridiag(fam, n)
+        lam = oracle.eigvals(d, e)
+        g = np.random.default_rng(n)
+        x = np.concatenate([lam, np.nextafter(lam, np.inf), np.nextafter(lam, -np.inf),
+                            g.uniform(lam[0] - 1, lam[-1] + 1, 1003)])
+        for m in (x.size, 7, 8, 9, 1):
+            assert np.array_equal(oracle.counts(d, e, x[:m]), oracle.counts_scalar(d, e, x[:m])), (fam, m)
+        c = oracle.counts(d, e, np.sort(x))
+        assert np.all(np.diff(c) >= 0) and c[0] >= 0 and c[-1] <= n
+
+
 def test_ql_baseline_agrees():
     for fam in ["uniform", "toeplitz", "wilkinson", "clustered"]:
         d, e = tdgen.tridiag(fam, 600)
