@@ -25,12 +25,16 @@
  *    workspace, read back by tde_get_status.
  *  - The first call for a given problem shape (sizes and leaf size) builds and
  *    caches a plan: small device tables describing the merge tree, allocated
- *    once per shape and device and kept until tde_release_plans.  The first
- *    call for a given plan and set of buffers (d, e, lambda, workspace) also
- *    captures the whole solve into a HIP graph on an internal stream; later
- *    calls with the same plan and buffers replay it with one hipGraphLaunch
- *    on the caller's stream and allocate nothing.  TDE_FLAG_NO_GRAPH, or
- *    timing mode, enqueues the kernels one by one instead.
+ *    once per shape and device.  The first call for a given plan and set of
+ *    buffers (d, e, lambda, workspace) also captures the whole solve into a
+ *    HIP graph on an internal stream; later calls with the same plan and
+ *    buffers replay it with one hipGraphLaunch on the caller's stream and
+ *    allocate nothing.  TDE_FLAG_NO_GRAPH, or timing mode, enqueues the
+ *    kernels one by one instead.  Both caches are bounded (32 plans, 64
+ *    graphs, least recently used out): a graph is destroyed only after its
+ *    last launch has completed, a plan's tables only after the device is
+ *    idle; tde_release_plans empties them.  The caches are guarded by one
+ *    lock held for the duration of each call.
  *  - Inputs and outputs must not overlap.  Concurrent calls on different
  *    streams need distinct workspaces.
  *  - No exceptions cross this interface and nothing is printed.
@@ -68,7 +72,10 @@ typedef struct {
     int wide_min;   /* merges with at least this many active (non-deflated) roots
                        solve them with the wide sweep (64 roots per workgroup, the
                        poles split over 4 waves); >= 2, 0 = default (1024) */
-    int reserved[4];
+    int max_sweeps; /* secular iterations allowed per root, 1..96; 0 = default (96).
+                       A root still unconverged at the cap sets TDE_ENOCONV (a
+                       small cap forces that path from the host, for tests) */
+    int reserved[3]; /* must be 0 */
 } tde_opts;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -218,8 +225,13 @@ int tde_get_counters(const void* ws, void* hip_stream, uint64_t* out, int n);
 int tde_timing_enable(int on);
 int tde_timing_read(double* ms, int64_t* launches, int nkinds);
 
-/* Frees every cached plan (device tables).  Not safe while solves are queued. */
+/* Frees every cached plan (device tables), captured graph and split
+ * schedule, after waiting for the launches that may still use them. */
 void tde_release_plans(void);
+
+/* Current sizes of the library's caches: out[0] plans, out[1] captured graphs,
+ * out[2] split merge schedules (the first n of them).  TDE_OK or TDE_EINVAL. */
+int tde_cache_sizes(int64_t* out, int n);
 
 /* Human-readable name of a status code (static string). */
 const char* tde_status_string(int status);

@@ -1,18 +1,31 @@
 /*
  * CPU BASELINE -- test/benchmark infrastructure only (never on the product path).
  *
- * Plain eigenvalue-only implicit QL with a Wilkinson-type shift for a real
+ * Plain eigenvalue-only implicit QL with a Wilkinson shift for a real
  * symmetric tridiagonal matrix: the sequential QR/QL family the paper compares
  * boundary-row D&C against (Section 2.1 and the QR/QL baseline of Section 5.2).
- * This is the textbook implicit-shift QL iteration (Bowdler, Martin, Reinsch
- * and Wilkinson, 1968), written out plainly; no square-root-free tricks.
  *
- *   For the active block [l, m]: pick the shift from the leading 2x2 block,
- *   chase the bulge upward with plane rotations from row m-1 to row l,
- *   and shrink the block once e[l] is negligible.
+ * Written from the mathematics of the implicit symmetric QR step with a
+ * Wilkinson shift as Golub and Van Loan state it (Matrix Computations, 4th ed.,
+ * Section 8.3, Algorithm 8.3.2), mirrored into its QL form: the shift comes
+ * from the top 2x2 block of the active block, the first plane rotation from
+ * the shifted last column, and the bulge it creates is chased upward; the top
+ * coupling converges and the block shrinks from the top.
+ *
+ * Rotation in plane (k, k+1) with cosine c and sine s: rows k and k+1 become
+ * c r_k - s r_(k+1) and s r_k + c r_(k+1); applied from both sides,
+ *   d_k'     = c^2 d_k - 2 c s e_k + s^2 d_(k+1)
+ *   d_(k+1)' = s^2 d_k + 2 c s e_k + c^2 d_(k+1)
+ *   e_k'     = c s (d_k - d_(k+1)) + (c^2 - s^2) e_k
+ *   e_(k-1)' = c e_(k-1), and a bulge s e_(k-1) appears at (k-1, k+1).
+ * With c^2 + s^2 = 1 the first three are evaluated in difference form,
+ * w = s (d_k - d_(k+1)) + 2 c e_k: d_k' = d_k - s w, d_(k+1)' = d_(k+1) + s w,
+ * e_k' = c w - e_k (the trace is kept exactly, no c^2 / s^2 cancellation).
+ * The rotation of the chase that removes a bulge b at (k, k+2) has
+ * c = e_(k+1)/r, s = b/r, r = hypot(b, e_(k+1)), and leaves e_(k+1)' = r.
  *
  * Output eigenvalues are sorted ascending.  Returns 0, -1 on non-finite input,
- * 1 if some eigenvalue did not converge in 60 sweeps.
+ * -2 when out of memory, 1 if some eigenvalue did not converge in 60 steps.
  */
 #include <float.h>
 #include <math.h>
@@ -23,6 +36,47 @@
 static int cmp_double(const void* a, const void* b) {
     double x = *(const double*)a, y = *(const double*)b;
     return (x > y) - (x < y);
+}
+
+/* Eigenvalue of [a f; f g] nearer to a (Wilkinson shift), overflow-safe. */
+static double wilkinson_shift(double a, double f, double g) {
+    if (f == 0.0) return a;
+    double h = (g - a) / (2.0 * f);
+    double r = hypot(h, 1.0);
+    return a - f / (h + (h >= 0.0 ? r : -r));
+}
+
+/* One implicit QL step with shift mu on the unreduced block [l, m]. */
+static void ql_step(double* d, double* e, int64_t l, int64_t m, double mu) {
+    double c, s, r;
+    /* first rotation: annihilates the (m-1, m) entry of T - mu I */
+    {
+        double x = d[m] - mu, y = e[m - 1];
+        r = hypot(x, y);
+        c = (r == 0.0) ? 1.0 : x / r;
+        s = (r == 0.0) ? 0.0 : y / r;
+    }
+    double bulge = 0.0;
+    for (int64_t k = m - 1; k >= l; --k) {
+        if (k < m - 1) {
+            /* rotation that removes the bulge at (k, k+2) */
+            r = hypot(bulge, e[k + 1]);
+            c = (r == 0.0) ? 1.0 : e[k + 1] / r;
+            s = (r == 0.0) ? 0.0 : bulge / r;
+            e[k + 1] = r;
+        }
+        /* the 2x2 update in difference form (trace kept exactly):
+         * w = s (a - g) + 2 c f, d_k' = a - s w, d_(k+1)' = g + s w, e_k' = c w - f */
+        double a = d[k], g = d[k + 1], f = e[k];
+        double w = s * (a - g) + 2.0 * c * f;
+        d[k] = a - s * w;
+        d[k + 1] = g + s * w;
+        e[k] = c * w - f;
+        if (k > l) {
+            bulge = s * e[k - 1];
+            e[k - 1] = c * e[k - 1];
+        }
+    }
 }
 
 int ql_eigvals(int64_t n, const double* d_in, const double* e_in, double* lam) {
@@ -38,44 +92,18 @@ int ql_eigvals(int64_t n, const double* d_in, const double* e_in, double* lam) {
     for (int64_t i = 0; i + 1 < n; ++i) e[i] = e_in[i];
     int status = 0;
     for (int64_t l = 0; l < n; ++l) {
-        int iter = 0;
+        int steps = 0;
         for (;;) {
-            /* Smallest m >= l with a negligible coupling e[m] (or m = n-1). */
+            /* end m of the unreduced block starting at l: first negligible coupling */
             int64_t m = l;
-            for (; m + 1 < n; ++m) {
-                double dd = fabs(d[m]) + fabs(d[m + 1]);
-                if (fabs(e[m]) <= DBL_EPSILON * dd) break;
+            while (m + 1 < n && fabs(e[m]) > DBL_EPSILON * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
+            if (m + 1 < n) e[m] = 0.0;
+            if (m == l) break; /* d[l] has converged */
+            if (++steps > 60) {
+                status = 1;
+                break;
             }
-            if (m == l) break;
-            if (++iter > 60) { status = 1; break; }
-            /* Shift: eigenvalue of the leading 2x2 block [d_l e_l; e_l d_{l+1}] nearer d_l. */
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int64_t i;
-            for (i = m - 1; i >= l; --i) {
-                double f = s * e[i];
-                double b = c * e[i];
-                r = hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) { /* exact deflation inside the sweep */
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-            }
-            if (r == 0.0 && i >= l) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+            ql_step(d, e, l, m, wilkinson_shift(d[l], e[l], d[l + 1]));
         }
     }
     free(e);

@@ -55,6 +55,7 @@ EXPORTS = (
     "tde_timing_enable",
     "tde_timing_read",
     "tde_release_plans",
+    "tde_cache_sizes",
     "tde_status_string",
 )
 
@@ -68,7 +69,7 @@ class TDEError(RuntimeError):
 
 class tde_opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
-                ("wide_min", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("wide_min", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 _lib = None
@@ -131,6 +132,8 @@ def lib():
         L.tde_timing_read.restype = ctypes.c_int
         L.tde_release_plans.argtypes = []
         L.tde_release_plans.restype = None
+        L.tde_cache_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.tde_cache_sizes.restype = ctypes.c_int
         L.tde_status_string.argtypes = [ctypes.c_int]
         L.tde_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -152,24 +155,30 @@ TDE_FLAG_LEAF_DC = 2
 # every call below uses when it does not pass them (a tuned choice, say).
 # leaf_dc: forward passes solve each leaf by its own divide and conquer inside
 # one wave (the reverse mode's checkpointing forward keeps QL leaves).
-_shape_defaults = {"wide_min": None, "leaf_dc": None}
+# max_sweeps: secular iterations allowed per root (a small value forces the
+# non-convergence status, for tests).
+_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None}
 
 
-def set_defaults(wide_min=None, leaf_dc=None):
+def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None):
     _shape_defaults["wide_min"] = wide_min
     _shape_defaults["leaf_dc"] = leaf_dc
+    _shape_defaults["max_sweeps"] = max_sweeps
 
 
 def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None):
     wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
     leaf_dc = _shape_defaults["leaf_dc"] if leaf_dc is None else leaf_dc
-    if leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc:
+    max_sweeps = _shape_defaults["max_sweeps"]
+    if (leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc
+            and max_sweeps is None):
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
     o.flags = (0 if graph else TDE_FLAG_NO_GRAPH) | (TDE_FLAG_LEAF_DC if leaf_dc else 0)
     o.sweep_cols = int(sweep_cols or 0)
     o.wide_min = int(wide_min or 0)
+    o.max_sweeps = int(max_sweeps or 0)
     return ctypes.byref(o)
 
 
@@ -497,6 +506,20 @@ def default_workspace(device=None) -> torch.Tensor:
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     key = (dev.index, torch.cuda.current_stream(dev).cuda_stream)
     return _ws_cache[key]
+
+
+def cache_sizes() -> dict:
+    """Entries in the library's caches: plans, captured graphs, split schedules."""
+    buf = (ctypes.c_int64 * 3)()
+    rc = lib().tde_cache_sizes(buf, 3)
+    if rc != TDE_OK:
+        raise TDEError(rc, "tde_cache_sizes")
+    return {"plans": int(buf[0]), "graphs": int(buf[1]), "split_schedules": int(buf[2])}
+
+
+def release_plans() -> None:
+    """Free every cached plan, graph and split schedule (waits for their launches)."""
+    lib().tde_release_plans()
 
 
 def last_status(workspace: torch.Tensor) -> int:

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtde.so")
 ARCH = os.environ.get("TDE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tde_kernels.hip", "tde_api.cpp"]
+SOURCES = ["tde_kernels.hip", "tde_api.cpp", "tde_planner.cpp"]
 
 HIPCC_FLAGS = [
     "-O3",

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <array>
 #include <functional>
+#include <iterator>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -18,9 +20,28 @@
 namespace tde {
 namespace {
 
+// ---------------------------------------------------------------------------
+// Caches.  One (recursive) mutex guards them all; every entry point holds it
+// from the plan lookup to the last launch it enqueues, so no other thread can
+// evict a plan or an executable graph that a call is still using.
+//
+// Plans: bounded, least recently used first out.  Graph executables: bounded,
+// least recently used first out; an event recorded after every launch of an
+// executable is waited for before it is destroyed, so an executable still
+// queued on a caller's stream is never freed.  Evicting a plan first drops its
+// graphs, then waits for the device before freeing its tables (eager launches
+// may still read them).
+// ---------------------------------------------------------------------------
+std::recursive_mutex g_mu;
+
 using PlanKey = std::tuple<int, int, int, int, bool, std::vector<long long>>;
-std::mutex g_mu;
-std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+constexpr size_t kMaxPlans = 32;
+struct PlanEntry {
+    PlanKey key;
+    std::unique_ptr<Plan> plan;
+};
+std::list<PlanEntry> g_plan_lru;  // front = most recently used
+std::map<PlanKey, std::list<PlanEntry>::iterator> g_plans;
 
 // Captured passes: one executable graph per (plan, pass kind, buffers).
 // Capture runs on an internal stream per device; replays run on the
@@ -28,24 +49,89 @@ std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2, PASS_ROWS = 3 };
 using Bufs = std::array<const void*, 8>;
 using GraphKey = std::tuple<const Plan*, int, Bufs>;
-std::map<GraphKey, hipGraphExec_t> g_graphs;
-std::map<int, hipStream_t> g_capture_streams;
 constexpr size_t kMaxGraphs = 64;
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    hipEvent_t done;  // recorded after every launch of exec
+    int device;
+};
+std::list<GraphEntry> g_graph_lru;  // front = most recently used
+std::map<GraphKey, std::list<GraphEntry>::iterator> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
 
-void drop_graphs() {
-    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
-    g_graphs.clear();
+// Scoped switch to another device (restored on exit).
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+void destroy_graph(GraphEntry& ge) {
+    DeviceScope ds(ge.device);
+    (void)hipEventSynchronize(ge.done);  // the last launch has finished
+    (void)hipGraphExecDestroy(ge.exec);
+    (void)hipEventDestroy(ge.done);
 }
 
+void drop_graphs_if(const std::function<bool(const GraphEntry&)>& pred) {
+    for (auto it = g_graph_lru.begin(); it != g_graph_lru.end();) {
+        if (pred(*it)) {
+            destroy_graph(*it);
+            g_graphs.erase(it->key);
+            it = g_graph_lru.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+void free_plan(Plan* p) {
+    DeviceScope ds(p->device);
+    (void)hipDeviceSynchronize();  // eager launches may still read the tables
+    if (p->d_merges) (void)hipFree(p->d_merges);
+    if (p->d_leaves) (void)hipFree(p->d_leaves);
+    if (p->d_offs) (void)hipFree(p->d_offs);
+    if (p->d_blkm) (void)hipFree(p->d_blkm);
+    if (p->d_shdr) (void)hipFree(p->d_shdr);
+    if (p->d_smer) (void)hipFree(p->d_smer);
+    p->d_shdr = nullptr;
+    p->d_smer = nullptr;
+    p->d_blkm = nullptr;
+    p->d_merges = nullptr;
+    p->d_leaves = nullptr;
+    p->d_offs = nullptr;
+}
+
+void evict_plan(std::list<PlanEntry>::iterator it) {
+    const Plan* p = it->plan.get();
+    drop_graphs_if([p](const GraphEntry& g) { return std::get<0>(g.key) == p; });
+    free_plan(it->plan.get());
+    g_plans.erase(it->key);
+    g_plan_lru.erase(it);
+}
+
+// Caller holds g_mu.
 int graph_for(const Plan& plan, int kind, const Bufs& bufs, const std::function<int(void*)>& enqueue,
-              hipGraphExec_t* exec) {
+              GraphEntry** out) {
     GraphKey key{&plan, kind, bufs};
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) {
-        *exec = it->second;
+        g_graph_lru.splice(g_graph_lru.begin(), g_graph_lru, it->second);
+        *out = &*it->second;
         return TDE_OK;
     }
-    if (g_graphs.size() >= kMaxGraphs) drop_graphs();
+    if (g_graph_lru.size() >= kMaxGraphs) {  // least recently used out
+        auto last = std::prev(g_graph_lru.end());
+        destroy_graph(*last);
+        g_graphs.erase(last->key);
+        g_graph_lru.erase(last);
+    }
     hipStream_t cs;
     auto sit = g_capture_streams.find(plan.device);
     if (sit == g_capture_streams.end()) {
@@ -66,8 +152,14 @@ int graph_for(const Plan& plan, int kind, const Bufs& bufs, const std::function<
     const hipError_t ei = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return TDE_EDEVICE;
-    g_graphs.emplace(key, ge);
-    *exec = ge;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(ge);
+        return TDE_EDEVICE;
+    }
+    g_graph_lru.push_front(GraphEntry{key, ge, ev, plan.device});
+    g_graphs.emplace(key, g_graph_lru.begin());
+    *out = &g_graph_lru.front();
     return TDE_OK;
 }
 
@@ -77,54 +169,22 @@ int run_pass(const Plan& plan, int kind, const Bufs& bufs, const tde_opts* opts,
              const std::function<int(void*)>& enqueue) {
     const bool use_graph = !(opts && (opts->flags & TDE_FLAG_NO_GRAPH)) && !timing_enabled();
     if (use_graph) {
-        hipGraphExec_t ge = nullptr;
-        int rc;
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            rc = graph_for(plan, kind, bufs, enqueue, &ge);
-        }
+        GraphEntry* ge = nullptr;
+        const int rc = graph_for(plan, kind, bufs, enqueue, &ge);
         if (rc != TDE_OK) return rc;
-        return hipGraphLaunch(ge, (hipStream_t)stream) == hipSuccess ? TDE_OK : TDE_EDEVICE;
+        if (hipGraphLaunch(ge->exec, (hipStream_t)stream) != hipSuccess) return TDE_EDEVICE;
+        return hipEventRecord(ge->done, (hipStream_t)stream) == hipSuccess ? TDE_OK : TDE_EDEVICE;
     }
     return enqueue(stream) == 0 ? TDE_OK : TDE_EDEVICE;
 }
 
-void free_plan(Plan* p) {
-    if (p->d_merges) (void)hipFree(p->d_merges);
-    if (p->d_leaves) (void)hipFree(p->d_leaves);
-    if (p->d_offs) (void)hipFree(p->d_offs);
-    if (p->d_blkm) (void)hipFree(p->d_blkm);
-    if (p->d_shdr) (void)hipFree(p->d_shdr);
-    if (p->d_smer) (void)hipFree(p->d_smer);
-    p->d_shdr = nullptr;
-    p->d_smer = nullptr;
-    p->d_blkm = nullptr;
-    p->d_merges = nullptr;
-    p->d_leaves = nullptr;
-    p->d_offs = nullptr;
-}
-
-// In-wave merge trees of every leaf size 1..kLeafMax (leaf-local offsets).
-void sub_trees(std::vector<SubHdr>* hdr, std::vector<SubMerge>* mer) {
-    hdr->assign(kLeafMax + 1, SubHdr{});
-    mer->clear();
-    for (int l = 1; l <= kLeafMax; ++l) {
-        const LevelTables t = build_tree(1, {0, (long long)l});
-        SubHdr& h = (*hdr)[l];
-        h.mbase = (int)mer->size();
-        h.H = (int)t.mstart.size();
-        for (int k = 0; k < h.H; ++k) h.lv[k] = (unsigned char)t.mstart[k];
-        h.lv[h.H] = (unsigned char)t.merges.size();
-        for (const MergeRec& R : t.merges)
-            mer->push_back(SubMerge{(unsigned char)R.off, (unsigned char)R.nL, (unsigned char)R.nR, (unsigned char)R.pk});
-    }
-}
-
+// Caller holds g_mu.
 int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vector<long long>& offs, Plan** out) {
     PlanKey key{device, leaf, cols, wmin, dc, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
-        *out = it->second.get();
+        g_plan_lru.splice(g_plan_lru.begin(), g_plan_lru, it->second);
+        *out = it->second->plan.get();
         return TDE_OK;
     }
     auto p = std::make_unique<Plan>();
@@ -134,78 +194,49 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vect
     p->wide_min = wmin;
     p->leaf_dc = dc;
     p->offs = offs;
-    p->B = (int)offs.size() - 1;
-    p->ntot = offs.back();
-    const LevelTables t = build_tree(leaf, offs);
-    const std::vector<MergeRec>& flat = t.merges;
-    int maxM = 1;
-    long long maxN = 1;
-    std::vector<int> blkm;
-    for (size_t h = 0; h < t.mstart.size(); ++h) {
-        LevelInfo info{};
-        info.mstart = t.mstart[h];
-        info.M = t.mcount[h];
-        info.N = t.ncols[h];
-        info.smax = t.smax[h];
-        // blkm[b] = merge holding packed column min(b*kWG, N-1), b = 0..nb
-        info.bstart = (int)blkm.size();
-        const long long nb = (info.N + kWG - 1) / kWG;
-        int m = 0;
-        for (long long b = 0; b <= nb; ++b) {
-            const long long c = std::min(b * (long long)kWG, info.N - 1);
-            while (m + 1 < info.M && flat[info.mstart + m + 1].pk <= c) ++m;
-            blkm.push_back(m);
-        }
-        maxM = std::max(maxM, info.M);
-        maxN = std::max(maxN, info.N);
-        p->levels.push_back(info);
-    }
-    p->maxM = maxM;
-    p->maxN = maxN;
-    p->nmerges = (int)flat.size();
-    if ((int)p->levels.size() > kMaxLevels) return TDE_EINVAL;
-    p->nleaves = (int)t.leaves.size();
-    int lmax = 1;
-    for (auto& L : t.leaves) lmax = std::max(lmax, L.size);
-    p->leafmax = lmax;
+    if (plan_host(p.get()) != 0) return TDE_EINVAL;
     auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
         if (bytes == 0) bytes = 8;
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
         if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
         return true;
     };
-    bool ok = upload((void**)&p->d_merges, flat.empty() ? nullptr : flat.data(), flat.size() * sizeof(MergeRec)) &&
-              upload((void**)&p->d_leaves, t.leaves.empty() ? nullptr : t.leaves.data(),
-                     t.leaves.size() * sizeof(LeafRec)) &&
+    auto vec = [](const auto& v) -> const void* { return v.empty() ? nullptr : (const void*)v.data(); };
+    bool ok = upload((void**)&p->d_merges, vec(p->h_merges), p->h_merges.size() * sizeof(MergeRec)) &&
+              upload((void**)&p->d_leaves, vec(p->h_leaves), p->h_leaves.size() * sizeof(LeafRec)) &&
               upload((void**)&p->d_offs, offs.data(), offs.size() * sizeof(long long)) &&
-              upload((void**)&p->d_blkm, blkm.empty() ? nullptr : blkm.data(), blkm.size() * sizeof(int));
-    if (ok && dc) {
-        std::vector<SubHdr> sh;
-        std::vector<SubMerge> sm;
-        sub_trees(&sh, &sm);
-        ok = upload((void**)&p->d_shdr, sh.data(), sh.size() * sizeof(SubHdr)) &&
-             upload((void**)&p->d_smer, sm.data(), sm.size() * sizeof(SubMerge));
-    }
+              upload((void**)&p->d_blkm, vec(p->h_blkm), p->h_blkm.size() * sizeof(int));
+    if (ok && dc)
+        ok = upload((void**)&p->d_shdr, vec(p->h_shdr), p->h_shdr.size() * sizeof(SubHdr)) &&
+             upload((void**)&p->d_smer, vec(p->h_smer), p->h_smer.size() * sizeof(SubMerge));
     if (!ok) {
         free_plan(p.get());
         return TDE_ENOMEM;
     }
+    while (g_plan_lru.size() >= kMaxPlans) evict_plan(std::prev(g_plan_lru.end()));
     *out = p.get();
-    g_plans.emplace(std::move(key), std::move(p));
+    g_plan_lru.push_front(PlanEntry{key, std::move(p)});
+    g_plans.emplace(std::move(key), g_plan_lru.begin());
     return TDE_OK;
 }
 
-int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin;
+int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr,
+                 int* cap = nullptr) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter;
     if (opts) {
         if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
         if (opts->sweep_cols != 0) C = opts->sweep_cols;
         if (opts->wide_min != 0) W = opts->wide_min;
+        if (opts->max_sweeps != 0) S = opts->max_sweeps;
+        for (int r : opts->reserved)
+            if (r != 0) return TDE_EINVAL;
     }
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
     if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
     if (W < 2) return TDE_EINVAL;
+    if (S < 1 || S > kSecMaxIter) return TDE_EINVAL;
+    if (cap) *cap = S;
     *leaf = L;
     *cols = C;
     if (wmin) *wmin = W;
@@ -245,7 +276,6 @@ int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** pl
     if (resolve_opts(opts, &leaf, &cols, &wmin, &dc) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
-    std::lock_guard<std::mutex> lk(g_mu);
     return make_plan(device, leaf, cols, wmin, dc, offs, plan);
 }
 
@@ -258,8 +288,10 @@ bool needs_e(const std::vector<long long>& offs) {
 int solve(const double* d, const double* e, const std::vector<long long>& offs, double* lambda, void* ws,
           size_t ws_bytes, void* stream, const tde_opts* opts, void* ckpt = nullptr, size_t ckpt_bytes = 0,
           double* qfirst = nullptr, double* qlast = nullptr) {
-    int leaf, cols;
-    if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    int leaf, cols, wmin, cap;
+    bool dc;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap) != TDE_OK) return TDE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     const long long ntot = offs.back();
     const long long B = (long long)offs.size() - 1;
     if (ntot == 0) return TDE_OK;
@@ -273,6 +305,7 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
     if (rc != TDE_OK) return rc;
     Work w{};
     workspace_layout(ntot, B, ntot, (char*)ws, &w);
+    w.sec_cap = cap;
     if (qfirst || qlast) {
         w.qfirst = qfirst;
         w.qlast = qlast;
@@ -296,8 +329,10 @@ int solve(const double* d, const double* e, const std::vector<long long>& offs, 
 int backward(const double* d, const double* e, const std::vector<long long>& offs, const double* gin,
              const void* ckpt, size_t ckpt_bytes, double* gd, double* ge, void* ws, size_t ws_bytes, void* stream,
              const tde_opts* opts) {
-    int leaf, cols;
-    if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    int leaf, cols, wmin, cap;
+    bool dc;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap) != TDE_OK) return TDE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     const long long ntot = offs.back();
     const long long B = (long long)offs.size() - 1;
     if (ntot == 0) return TDE_OK;
@@ -312,6 +347,7 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
     if (ws_bytes < fw + grad_layout(ntot, ntot, nullptr, nullptr)) return TDE_EINVAL;
     Work w{};
     workspace_layout(ntot, B, ntot, (char*)ws, &w);
+    w.sec_cap = cap;
     Grad gr{};
     grad_layout(ntot, plan->nmerges, (char*)ws + fw, &gr);
     Ckpt ck{};
@@ -323,13 +359,29 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
 
 // Driver pre-pass: pairwise merge schedule of the blocks of every problem
 // (balanced over the blocks, levelled by height), cached per split.
+// Bounded, least recently used first out; an evicted schedule's table is
+// freed after the device has finished with it.
 struct RunMerges {
     std::vector<std::pair<int, int>> levels;  // (first record, count) per pass
     MergeRec* d_recs = nullptr;
+    int device = 0;
 };
 using RunKey = std::tuple<int, std::vector<long long>, std::vector<long long>>;
-std::map<RunKey, RunMerges> g_runs;
-constexpr size_t kMaxRunSchedules = 64;
+constexpr size_t kMaxRunSchedules = 32;
+struct RunEntry {
+    RunKey key;
+    RunMerges rm;
+};
+std::list<RunEntry> g_run_lru;  // front = most recently used
+std::map<RunKey, std::list<RunEntry>::iterator> g_runs;
+
+void free_runs(RunMerges* rm) {
+    if (!rm->d_recs) return;
+    DeviceScope ds(rm->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(rm->d_recs);
+    rm->d_recs = nullptr;
+}
 
 int run_merge_build(const std::vector<long long>& nb, int bs, int be, std::vector<std::vector<MergeRec>>* lv) {
     if (be - bs <= 1) return 0;
@@ -346,17 +398,19 @@ int run_merge_build(const std::vector<long long>& nb, int bs, int be, std::vecto
 
 int get_run_merges(int device, const std::vector<long long>& offs, const std::vector<long long>& nb,
                    const RunMerges** out) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     RunKey key{device, offs, nb};
     auto it = g_runs.find(key);
     if (it != g_runs.end()) {
-        *out = &it->second;
+        g_run_lru.splice(g_run_lru.begin(), g_run_lru, it->second);
+        *out = &it->second->rm;
         return TDE_OK;
     }
-    if (g_runs.size() >= kMaxRunSchedules) {
-        for (auto& kv : g_runs)
-            if (kv.second.d_recs) (void)hipFree(kv.second.d_recs);
-        g_runs.clear();
+    while (g_run_lru.size() >= kMaxRunSchedules) {
+        auto last = std::prev(g_run_lru.end());
+        free_runs(&last->rm);
+        g_runs.erase(last->key);
+        g_run_lru.erase(last);
     }
     std::vector<std::vector<MergeRec>> lv;
     size_t bi = 0;  // first block of problem b
@@ -367,6 +421,7 @@ int get_run_merges(int device, const std::vector<long long>& offs, const std::ve
         bi = be;
     }
     RunMerges rm;
+    rm.device = device;
     std::vector<MergeRec> flat;
     for (auto& L : lv) {
         std::sort(L.begin(), L.end(), [](const MergeRec& a, const MergeRec& b) { return a.off < b.off; });
@@ -380,7 +435,9 @@ int get_run_merges(int device, const std::vector<long long>& offs, const std::ve
             return TDE_EDEVICE;
         }
     }
-    *out = &g_runs.emplace(std::move(key), std::move(rm)).first->second;
+    g_run_lru.push_front(RunEntry{key, std::move(rm)});
+    g_runs.emplace(std::move(key), g_run_lru.begin());
+    *out = &g_run_lru.front().rm;
     return TDE_OK;
 }
 
@@ -388,6 +445,7 @@ int solve_split(const double* d, const double* e, const std::vector<long long>& 
                 size_t ws_bytes, void* stream, const tde_opts* opts, int64_t* nblocks) {
     int leaf, cols;
     if (resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     const long long ntot = offs.back();
     if (nblocks) *nblocks = 0;
     if (ntot == 0) return TDE_OK;
@@ -551,13 +609,21 @@ int tde_timing_read(double* ms, int64_t* launches, int nkinds) {
 }
 
 void tde_release_plans(void) {
-    std::lock_guard<std::mutex> lk(tde::g_mu);
-    tde::drop_graphs();
-    for (auto& kv : tde::g_plans) tde::free_plan(kv.second.get());
-    tde::g_plans.clear();
-    for (auto& kv : tde::g_runs)
-        if (kv.second.d_recs) (void)hipFree(kv.second.d_recs);
+    std::lock_guard<std::recursive_mutex> lk(tde::g_mu);
+    while (!tde::g_plan_lru.empty()) tde::evict_plan(std::prev(tde::g_plan_lru.end()));
+    tde::drop_graphs_if([](const tde::GraphEntry&) { return true; });
+    for (auto& r : tde::g_run_lru) tde::free_runs(&r.rm);
+    tde::g_run_lru.clear();
     tde::g_runs.clear();
+}
+
+int tde_cache_sizes(int64_t* out, int n) {
+    if (!out || n < 0) return TDE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(tde::g_mu);
+    const int64_t v[3] = {(int64_t)tde::g_plan_lru.size(), (int64_t)tde::g_graph_lru.size(),
+                          (int64_t)tde::g_run_lru.size()};
+    for (int k = 0; k < n && k < 3; ++k) out[k] = v[k];
+    return TDE_OK;
 }
 
 const char* tde_status_string(int status) {

@@ -112,63 +112,86 @@ TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) 
 }
 
 // ---------------------------------------------------------------------------
-// Leaf: implicit QL with a Wilkinson-type shift on one small tridiagonal,
+// Leaf: implicit QL with a Wilkinson shift on one small tridiagonal,
 // accumulating only selected rows of the eigenvector matrix (Algorithm 1,
 // leaf step; rows of Q G are the selected rows of Q times G, Lemma 2).
-// `rows` applies each plane rotation to columns i, i+1 of the tracked rows
+//
+// The step is the implicit symmetric QR step with a Wilkinson shift of Golub
+// and Van Loan (Matrix Computations, 4th ed., Section 8.3, Algorithm 8.3.2)
+// in its QL mirror image: shift from the top 2x2 block of the active block
+// [l, m], first plane rotation from the shifted last column, bulge chased
+// upward, top coupling converging.  A rotation in plane (k, k+1) with cosine c
+// and sine s maps rows k, k+1 to c r_k - s r_(k+1), s r_k + c r_(k+1); applied
+// from both sides it changes the 2x2 block (a, f; f, g) through
+// w = s (a - g) + 2 c f:  a' = a - s w,  g' = g + s w,  f' = c w - f
+// (the rotation's c^2 / s^2 form rewritten with c^2 + s^2 = 1, trace kept
+// exactly), scales the coupling above by c and leaves the bulge s e_(k-1) at
+// (k-1, k+1); the next rotation (c, s) = (e_(k+1), b)/hypot(b, e_(k+1))
+// removes a bulge b at (k, k+2).  The eigenvector rows follow Q <- Q R^T.
+//
+// `rows` applies each plane rotation to columns k, k+1 of the tracked rows
 // (rot) and mirrors the final ascending sort (swap).  The scalar recurrence is
 // the same for every choice of tracked rows, and contraction is off, so the
 // forward pass (rows 0 and l-1) and the adjoint's recomputation (one row per
 // lane) see bitwise the same eigenvalues and rotations.  Arrays are strided
-// (st = lanes sharing an LDS tile).  Returns 0 or ST_LEAF_NOCONV.
+// (st = lanes sharing an LDS tile).  Returns 0 or ST_LEAF_NOCONV (an
+// eigenvalue needed more than 60 steps).
 // ---------------------------------------------------------------------------
 template <class Rows>
 TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsigned* nrot) {
 #pragma clang fp contract(off)
 #define A_(p, i) p[(i) * st]
     int status = 0;
-    unsigned rot = 0;
+    unsigned nr = 0;
     A_(e, nl - 1) = 0.0;
     for (int l = 0; l < nl; ++l) {
-        int iter = 0;
+        int steps = 0;
         for (;;) {
+            // end of the unreduced block that starts at l
             int m = l;
-            for (; m + 1 < nl; ++m) {
-                double dd = fabs(A_(d, m)) + fabs(A_(d, m + 1));
-                if (fabs(A_(e, m)) <= DBL_EPSILON * dd) break;
+            while (m + 1 < nl && fabs(A_(e, m)) > DBL_EPSILON * (fabs(A_(d, m)) + fabs(A_(d, m + 1)))) ++m;
+            if (m + 1 < nl) A_(e, m) = 0.0;
+            if (m == l) break;  // d[l] converged
+            if (++steps > 60) {
+                status = ST_LEAF_NOCONV;
+                break;
             }
-            if (m == l) break;
-            if (++iter > 60) { status = ST_LEAF_NOCONV; break; }
-            double g = (A_(d, l + 1) - A_(d, l)) / (2.0 * A_(e, l));
-            double r = hypot(g, 1.0);
-            g = A_(d, m) - A_(d, l) + A_(e, l) / (g + (g >= 0.0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool split = false;
-            for (int i = m - 1; i >= l; --i) {
-                double f = s * A_(e, i);
-                double b = c * A_(e, i);
-                r = hypot(f, g);
-                A_(e, i + 1) = r;
-                if (r == 0.0) {
-                    A_(d, i + 1) -= p;
-                    A_(e, m) = 0.0;
-                    split = true;
-                    break;
+            // Wilkinson shift: eigenvalue of the top 2x2 block nearer to d[l]
+            double mu = A_(d, l);
+            {
+                const double f = A_(e, l);
+                const double h = (A_(d, l + 1) - mu) / (2.0 * f);
+                const double r = hypot(h, 1.0);
+                mu -= f / (h + (h >= 0.0 ? r : -r));
+            }
+            double c, s;
+            {
+                const double x = A_(d, m) - mu, y = A_(e, m - 1);
+                const double r = hypot(x, y);
+                c = (r == 0.0) ? 1.0 : x / r;
+                s = (r == 0.0) ? 0.0 : y / r;
+            }
+            double bulge = 0.0;
+            for (int k = m - 1; k >= l; --k) {
+                if (k < m - 1) {
+                    const double ek1 = A_(e, k + 1);
+                    const double r = hypot(bulge, ek1);
+                    c = (r == 0.0) ? 1.0 : ek1 / r;
+                    s = (r == 0.0) ? 0.0 : bulge / r;
+                    A_(e, k + 1) = r;
                 }
-                s = f / r;
-                c = g / r;
-                g = A_(d, i + 1) - p;
-                r = (A_(d, i) - g) * s + 2.0 * c * b;
-                p = s * r;
-                A_(d, i + 1) = g + p;
-                g = c * r - b;
-                ++rot;
-                rows.rot(i, c, s);
+                const double a = A_(d, k), g = A_(d, k + 1), f = A_(e, k);
+                const double w = s * (a - g) + 2.0 * c * f;
+                A_(d, k) = a - s * w;
+                A_(d, k + 1) = g + s * w;
+                A_(e, k) = c * w - f;
+                if (k > l) {
+                    bulge = s * A_(e, k - 1);
+                    A_(e, k - 1) = c * A_(e, k - 1);
+                }
+                ++nr;
+                rows.rot(k, c, s);
             }
-            if (split) continue;
-            A_(d, l) -= p;
-            A_(e, l) = g;
-            A_(e, m) = 0.0;
         }
     }
     // ascending order, rows permuted alongside
@@ -183,7 +206,7 @@ TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsig
             rows.swap(i, k);
         }
     }
-    *nrot = rot;
+    *nrot = nr;
     return status;
 #undef A_
 }
@@ -454,7 +477,8 @@ TDE_DEV void sec_split(const SecRoot& r, int kk, int* L1, int* R0) {
 // phi - psi (every left term is negative, every right term positive).
 template <class Red>
 TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const double* __restrict__ Z,
-                         const double* __restrict__ W, double rho, int sub, int G, int* org_out, double* tau_out) {
+                         const double* __restrict__ W, double rho, int sub, int G, int cap, int* org_out,
+                         double* tau_out) {
     if (K == 1) {
         *org_out = 0;
         *tau_out = rho * Z[0] * Z[0];
@@ -477,7 +501,7 @@ TDE_DEV int secular_root(int k, int K, const double* __restrict__ D, const doubl
         zz = Red::sum(zz);
         sec_start_last(K, D, Z, rho, zz, &r);
     }
-    for (int it = 1; it <= kSecMaxIter; ++it) {
+    for (int it = 1; it <= cap; ++it) {
         int L1, R0;
         sec_split(r, kk, &L1, &R0);
         sec_sweep<Red, false>(K, D, W, D[r.o], r.tau, L1, R0, sub, G, s);
@@ -790,7 +814,8 @@ TDE_DEV int body_secular(long long g, int m, const MergeRec* __restrict__ mr, co
     int o;
     double tau;
     const long long b = sp.ks - voff;
-    const int it = secular_root<Red>((int)(g - sp.ks), sp.K, Dv + b, w.Za + sp.ks, Wv + b, rho, sub, G, &o, &tau);
+    const int it =
+        secular_root<Red>((int)(g - sp.ks), sp.K, Dv + b, w.Za + sp.ks, Wv + b, rho, sub, G, w.sec_cap, &o, &tau);
     if (sub == 0) {
         w.org[g] = o;
         w.tau[g] = tau;

@@ -157,6 +157,7 @@ struct Work {
     double* qfirst;            // [n] or null: first eigenvector row of each output eigenvalue (rows mode)
     double* qlast;             // [n] or null: last eigenvector row of each output eigenvalue (rows mode)
     int rows_out;              // 1: the top merges also propagate rows (qfirst / qlast requested)
+    int sec_cap;               // secular iterations allowed per root before ST_SEC_NOCONV (kSecMaxIter)
 };
 
 // Forward checkpoint for the reverse pass: per level h (slot stride n), the

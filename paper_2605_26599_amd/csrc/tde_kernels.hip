@@ -349,7 +349,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
             Km = merge_span(smr[m], wl.scan).K;
             const int it = body_secular<RedSerial>(lane, m, smr, eL, pmax, wl, 0, 1, wl.Da, wl.Wa, 0);
             if (it < 0) bad = 1;
-            const unsigned long long sw = (Km > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+            const unsigned long long sw = (Km > 1) ? (unsigned long long)((it < 0 ? w.sec_cap : it) + 1) : 0ULL;
             terms += sw * (unsigned long long)Km;
             roots += 1;
         }
@@ -848,7 +848,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
             done = false;
         }
         int its = 0;
-        for (int it = 1; it <= kSecMaxIter; ++it) {
+        for (int it = 1; it <= w.sec_cap; ++it) {
             if (__all(done)) break;
             const int L1 = r.orgl ? kk : kk + 1;
             const int R0 = r.orgl ? kk + 1 : kk + 2;
@@ -877,7 +877,7 @@ __device__ void secular_wide(int bid, int nbw, const MergeRec* __restrict__ mr, 
             const double dor = D[r.o];
             w.dorg[ks + k] = dor;
             w.rootval[ks + k] = dor + r.tau;
-            const unsigned long long sw = (unsigned long long)((done ? its : kSecMaxIter) + 1);
+            const unsigned long long sw = (unsigned long long)((done ? its : w.sec_cap) + 1);
             sweeps += sw;
             terms += sw * (unsigned long long)K;
             roots += 1;
@@ -1090,7 +1090,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (sub == 0) {
                     const MergeSpan sp = merge_span(mr[mg], w.scan);
                     const unsigned long long sw =
-                        (sp.K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+                        (sp.K > 1) ? (unsigned long long)((it < 0 ? w.sec_cap : it) + 1) : 0ULL;
                     sweeps += sw;
                     terms += sw * (unsigned long long)sp.K;
                     roots += 1;
@@ -1185,9 +1185,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (sec_update(&r, rho, sm[0], sm[1], sm[2], sm[3], sm[2] - sm[0])) {
                     done = true;
                     used = it;
-                } else if (it >= kSecMaxIter) {
+                } else if (it >= w.sec_cap) {
                     done = true;
-                    used = kSecMaxIter;
+                    used = w.sec_cap;
                     bad = 1;
                 }
             }
@@ -1301,12 +1301,12 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     for (int k = grp; k < K; k += ng) {
         int o;
         double tau;
-        const int it = secular_root<RedGroup<G>>(k, K, sD, sZ, sW, rho, sub, G, &o, &tau);
+        const int it = secular_root<RedGroup<G>>(k, K, sD, sZ, sW, rho, sub, G, w.sec_cap, &o, &tau);
         if (it < 0) bad = 1;
         if (sub == 0) {
             sO[k] = o;
             sT[k] = tau;
-            const unsigned long long sw = (K > 1) ? (unsigned long long)((it < 0 ? kSecMaxIter : it) + 1) : 0ULL;
+            const unsigned long long sw = (K > 1) ? (unsigned long long)((it < 0 ? w.sec_cap : it) + 1) : 0ULL;
             sweeps += sw;
             terms += sw * (unsigned long long)K;
             roots += 1;
@@ -2297,132 +2297,6 @@ int enqueue_merge_runs(const MergeRec* recs, int M, const double* src, double* d
     if (n <= 0 || M <= 0) return 0;
     hipLaunchKernelGGL(k_merge_runs, dim3(nblk(n, kWG)), dim3(kWG), 0, (hipStream_t)stream, recs, M, src, dst, n);
     return (int)hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Workspace layout (all slices 256-byte aligned)
-// ---------------------------------------------------------------------------
-size_t workspace_layout(long long n, long long B, long long maxM, char* base, Work* w) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
-        char* p = base ? base + off : nullptr;
-        off += (bytes + 255) & ~(size_t)255;
-        return p;
-    };
-    const long long nn = n > 0 ? n : 1;
-    const long long nb = (nn + kWG - 1) / kWG + 2;
-    Work t{};
-    t.status = (int*)take(kCntOffset);
-    t.ticket = t.status ? (unsigned*)((char*)t.status + 16) : nullptr;
-    t.counters = (unsigned long long*)take(sizeof(unsigned long long) * CNT_N * kCntSlots);
-    t.pmax = (unsigned long long*)take(sizeof(unsigned long long) * (B > 0 ? B : 1));
-    t.lam = (double*)take(8 * nn);
-    t.blo = (double*)take(8 * nn);
-    t.bhi = (double*)take(8 * nn);
-    t.D = (double*)take(8 * nn);
-    t.Z = (double*)take(8 * nn);
-    t.RL = (double*)take(8 * nn);
-    t.RH = (double*)take(8 * nn);
-    t.src = (int*)take(4 * nn);
-    t.D2 = (double*)take(8 * nn);
-    t.Z2 = (double*)take(8 * nn);
-    t.RL2 = (double*)take(8 * nn);
-    t.RH2 = (double*)take(8 * nn);
-    t.st = (int*)take(4 * nn);
-    // prefix arrays: n + 1 entries for the level-wide scans, plus one per merge
-    // (at most n/2 + 1) for k_level_block's merge-local counts
-    t.scan = (int*)take(4 * (nn + nn / 2 + 2));
-    t.scanC = (int*)take(4 * (nn + nn / 2 + 2));
-    t.scanR = (int*)take(4 * (nn + nn / 2 + 2));
-    t.bsum = (int*)take(4 * nb);
-    t.bcnt = (int*)take(4 * (size_t)kMaxLevels * 2 * nb);
-    t.bsumA = t.bcnt;
-    t.bsumR = t.bcnt ? t.bcnt + nb : nullptr;
-    t.bsumAs = (int*)take(4 * nb);
-    t.bsumRs = (int*)take(4 * nb);
-    t.nnpos = (int*)take(4 * nn);
-    t.cf = (int*)take(4 * nn);
-    t.Da = (double*)take(8 * nn);
-    t.Za = (double*)take(8 * nn);
-    t.Wa = (double*)take(8 * nn);
-    t.RLa = (double*)take(8 * nn);
-    t.RHa = (double*)take(8 * nn);
-    t.amerge = (int*)take(4 * nn);
-    t.witems = (int*)take(4 * (nn + 2));
-    t.apos = (int*)take(4 * nn);
-    t.rpos = (int*)take(4 * nn);
-    t.dpos = (int*)take(4 * nn);
-    t.org = (int*)take(4 * nn);
-    t.tau = (double*)take(8 * nn);
-    t.rootval = (double*)take(8 * nn);
-    t.dorg = (double*)take(8 * nn);
-    t.zhat = (double*)take(8 * nn);
-    t.PBL = (double*)take(8 * nn);
-    t.PBH = (double*)take(8 * nn);
-    t.Dd = (double*)take(8 * nn);
-    t.RLd = (double*)take(8 * nn);
-    t.RHd = (double*)take(8 * nn);
-    t.Dr = (double*)take(8 * nn);
-    t.RLr = (double*)take(8 * nn);
-    t.RHr = (double*)take(8 * nn);
-    (void)maxM;
-    if (w) *w = t;
-    return off;
-}
-
-size_t grad_layout(long long n, long long nmerges, char* base, Grad* g) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
-        char* p = base ? base + off : nullptr;
-        off += (bytes + 255) & ~(size_t)255;
-        return p;
-    };
-    const long long nn = n > 0 ? n : 1;
-    Grad t{};
-    t.glam = (double*)take(8 * nn);
-    t.gblo = (double*)take(8 * nn);
-    t.gbhi = (double*)take(8 * nn);
-    t.gD = (double*)take(8 * nn);
-    t.gZ = (double*)take(8 * nn);
-    t.gRL = (double*)take(8 * nn);
-    t.gRH = (double*)take(8 * nn);
-    t.gD2 = (double*)take(8 * nn);
-    t.gZ2 = (double*)take(8 * nn);
-    t.gRL2 = (double*)take(8 * nn);
-    t.gRH2 = (double*)take(8 * nn);
-    t.glr = (double*)take(8 * nn);
-    t.gbr = (double*)take(8 * nn);
-    t.ghr = (double*)take(8 * nn);
-    t.coef = (double*)take(8 * 10 * nn);
-    t.chain = (RunState*)take(sizeof(RunState) * nn);
-    t.cdef = (RunState*)take(sizeof(RunState) * nn);
-    t.skey = (double*)take(8 * nn);
-    t.sidx = (int*)take(4 * nn);
-    t.grho = (double*)take(8 * (nmerges > 0 ? nmerges : 1));
-    t.gdp = (double*)take(8 * nn);
-    if (g) *g = t;
-    return off;
-}
-
-size_t ckpt_layout(long long n, int levels, char* base, Ckpt* c) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
-        char* p = base ? base + off : nullptr;
-        off += (bytes + 255) & ~(size_t)255;
-        return p;
-    };
-    const long long nn = n > 0 ? n : 1;
-    const long long H = levels > 0 ? levels : 0;
-    Ckpt t{};
-    t.n = nn;
-    (void)take(256);  // header slot: the size is never 0, even for a tree with no merges
-    t.lam = (double*)take(8 * nn * H);
-    t.blo = (double*)take(8 * nn * H);
-    t.bhi = (double*)take(8 * nn * H);
-    t.tau = (double*)take(8 * nn * H);
-    t.org = (int*)take(4 * nn * H);
-    if (c) *c = t;
-    return off;
 }
 
 }  // namespace tde

@@ -32,6 +32,12 @@ struct Plan {
     long long maxN = 1;  // most packed columns in one level
     std::vector<long long> offs;  // host copy of the problem offsets [B+1]
     std::vector<LevelInfo> levels;
+    // host tables (plan_host), uploaded to the device tables below
+    std::vector<MergeRec> h_merges;  // every merge, level after level
+    std::vector<int> h_blkm;         // per level, per block of kWG packed columns: first merge touched
+    std::vector<LeafRec> h_leaves;
+    std::vector<SubHdr> h_shdr;      // in-wave merge trees by leaf size (leaf_dc only)
+    std::vector<SubMerge> h_smer;
     // device tables owned by the plan
     int nmerges = 0;           // merges over all levels
     MergeRec* d_merges = nullptr;
@@ -41,6 +47,12 @@ struct Plan {
     SubHdr* d_shdr = nullptr;      // [kLeafMax+1] in-wave merge trees by leaf size (leaf_dc)
     SubMerge* d_smer = nullptr;
 };
+
+// Host tables of a plan from p->offs, p->leaf and p->leaf_dc (levels, merges,
+// leaves, block-to-merge map, in-wave trees).  0, or -1 when the tree has more
+// levels than the per-level counters hold.
+int plan_host(Plan* p);
+void sub_trees(std::vector<SubHdr>* hdr, std::vector<SubMerge>* mer);
 
 // Workspace layout for n packed columns, B problems and maxM merges per level.
 // With base == nullptr only the size is computed.

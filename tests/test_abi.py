@@ -70,6 +70,13 @@ def test_argument_errors_are_synchronous(L):
     bad.leaf = 0
     bad.flags = 4  # unknown flag bit
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(bad)) == tde.TDE_EINVAL
+    for field, value in [("max_sweeps", -1), ("max_sweeps", 97), ("wide_min", 1), ("sweep_cols", -3)]:
+        o = tde.tde_opts()
+        setattr(o, field, value)
+        assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(o)) == tde.TDE_EINVAL, field
+    o = tde.tde_opts()
+    o.reserved[1] = 7  # reserved fields must be zero
+    assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(o)) == tde.TDE_EINVAL
     offs = (ctypes.c_int64 * 3)(0, 5, 3)  # not monotone
     assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
     offs = (ctypes.c_int64 * 3)(1, 5, 9)  # does not start at 0
@@ -105,3 +112,13 @@ def test_checkpoint_and_backward_sizes(L):
                                   None) == tde.TDE_EINVAL
     assert L.tde_eigvals_backward(dummy, dummy, offs, 1, None, dummy, 1 << 30, dummy, dummy, dummy, 1 << 30,
                                   None, None) == tde.TDE_EINVAL
+
+
+def test_cache_sizes_query(L):
+    """The cache-size query answers without a device (empty caches here)."""
+    import paper_2605_26599_amd as tde
+
+    buf = (ctypes.c_int64 * 3)(-1, -1, -1)
+    assert L.tde_cache_sizes(buf, 3) == tde.TDE_OK
+    assert list(buf) == [0, 0, 0]
+    assert L.tde_cache_sizes(None, 3) == tde.TDE_EINVAL
