@@ -82,3 +82,38 @@ def test_leaf_ql_against_lapack(exe, fam):
         assert np.all(np.abs(np.abs(r0) - np.abs(Q[0])) <= tol), (fam, n)
         assert np.all(np.abs(np.abs(r1) - np.abs(Q[-1])) <= tol), (fam, n)
         assert np.all(np.abs(r0 * r1 - Q[0] * Q[-1]) <= tol), (fam, n)
+
+
+@pytest.fixture(scope="module")
+def br_exe(tmp_path_factory):
+    """The host CPU BR baseline (host_br.cpp) built under ASan/UBSan, serial
+    (OpenMP pragmas off), driven by tests/host/host_br_check.cpp."""
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("hostbr") / "host_br_check")
+    src = [os.path.join(ROOT, "tests", "host", "host_br_check.cpp"),
+           os.path.join(ROOT, "paper_2605_26599_amd", "csrc", "host_br.cpp")]
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-Wno-unknown-pragmas", "-o", out] + src
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return out
+
+
+@pytest.mark.parametrize("fam,n", [("uniform", 1), ("uniform", 2), ("uniform", 33), ("normal", 700),
+                                   ("toeplitz", 300), ("wilkinson", 129), ("clustered", 500),
+                                   ("paper_clustered", 257)])
+def test_host_br_sanitized(br_exe, fam, n):
+    import oracle
+
+    d, e = tdgen.tridiag(fam, n)
+    if fam == "normal":
+        e = e.copy()
+        e[::50] = 0.0  # blocks through the driver's split
+    inp = " ".join([str(n)] + [repr(float(x)) for x in d] + [repr(float(x)) for x in e])
+    r = subprocess.run([br_exe], input=inp, capture_output=True, text=True, env=_env(), timeout=120)
+    assert r.returncode == 0, r.stderr[-4000:]
+    rows = r.stdout.split()
+    assert int(rows[0]) == 0
+    lam = np.array([float(x) for x in rows[1:1 + n]])
+    assert np.abs(lam - oracle.eigvals(d, e)).max() <= 2e-11 * max(tdgen.tnorm1(d, e), 1e-300)
