@@ -2,6 +2,7 @@
 
   python -m paper_2605_26599_amd.profsum stats  <kernel_stats.csv> <bench.jsonl> <out.md> <title> <command>
   python -m paper_2605_26599_amd.profsum traffic <fetch_counter.csv> <write_counter.csv> <copy_bytes> <out.json> <out.md> <command>
+  python -m paper_2605_26599_amd.profsum fp64 <counter.csv> <kernel_trace.csv> <bench.jsonl> <out.json> <out.md> <title> <command>
 
 `stats` folds the per-instance kernel statistics of a `--kernel-trace --stats`
 run into per-kernel totals and sets them beside the live HIP-event timing of
@@ -10,6 +11,9 @@ WRITE_SIZE; KiB per dispatch) into HBM bytes per launch for each kernel
 family, scaled by the same counters' reading for a plain device copy of
 known size (bench.py --calibrate-copy), and records the hash of the kernel
 sources so bench.py reports the figure only while the kernels are unchanged.
+`fp64` sets hardware-counted FP64 FLOP/s (SQ_INSTS_VALU_*_F64 counters of a
+`--pmc` run, durations from a `--kernel-trace` run of the same command) beside
+the algorithmic FLOP/s of each kernel family.
 """
 import csv
 import json
@@ -112,10 +116,109 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
     print("\n".join(lines))
 
 
+# Kernel family -> bench.py launch kind (the kinds whose algorithmic work the
+# library's counters measure).
+KIND_OF = {"k_secular": "secular", "k_secular_wide": "secular", "k_lowner": "lowner", "k_lowner_wide": "lowner",
+           "k_rows": "rows", "k_rows_wide": "rows", "k_small_merge": "small", "k_level_block": "level",
+           "k_leaf": "leaf", "k_leaf_dc": "leaf"}
+FP64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64")
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _dispatch_counters(path):
+    """Per dispatch (in dispatch order): (family, {counter: value})."""
+    by = {}
+    for r in csv.DictReader(open(path)):
+        did = int(r["Dispatch_Id"])
+        ent = by.setdefault(did, [_family(r["Kernel_Name"]), {}])
+        ent[1][r["Counter_Name"]] = ent[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [by[k] for k in sorted(by)]
+
+
+def _dispatch_durations(path):
+    """Per dispatch (in dispatch order): (family, duration ns)."""
+    rows = []
+    for r in csv.DictReader(open(path)):
+        rows.append((int(r["Dispatch_Id"]), _family(r["Kernel_Name"]),
+                     int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    return [(f, t) for _, f, t in rows]
+
+
+def fp64(counter_csv, trace_csv, bench_jsonl, out_json, out_md, title, cmd):
+    """Hardware FP64 FLOP/s per kernel family: FLOPs from the SQ_INSTS_VALU_*_F64
+    counters (64 lanes per wave instruction, an FMA counted as two), time from
+    a kernel trace of the same command; the i-th dispatch of a family in one
+    run is matched with the i-th in the other.  Beside it, the algorithmic
+    rate from the library's work counters as bench.py accounts them."""
+    import os
+
+    cnt = _dispatch_counters(counter_csv)
+    dur = _dispatch_durations(trace_csv)
+    fl, tm = defaultdict(list), defaultdict(list)
+    for f, c in cnt:
+        fl[f].append(64.0 * (c.get(FP64_COUNTERS[0], 0.0) + c.get(FP64_COUNTERS[1], 0.0)
+                             + c.get(FP64_COUNTERS[3], 0.0) + 2.0 * c.get(FP64_COUNTERS[2], 0.0)))
+    for f, t in dur:
+        tm[f].append(float(t))
+    b = json.loads([ln for ln in open(bench_jsonl) if ln.startswith("{")][-1])
+    work = b.get("work_flops_per_step", {})
+    launches = b.get("launches_per_step_by_kind", {})
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.dirname(here))
+    import bench
+
+    lines = [f"# {title}", "", "Commands (repository root, one MI355X):", "", "```", cmd, "```", "",
+             "Hardware FP64 FLOPs = 64 x (ADD_F64 + MUL_F64 + TRANS_F64 + 2 FMA_F64) wave instructions "
+             "(`SQ_INSTS_VALU_*_F64`), over the kernel-trace durations of the same dispatches; peak "
+             f"{PEAK_FP64_TFLOPS} TFLOP/s.  Algorithmic FLOPs are the library's work counters times bench.py's "
+             "per-unit figures (6 per pole term, 3 per Loewner pair, 8 per row pair).", "",
+             "| kernel | dispatches | HW GFLOP/launch | avg us | HW TFLOP/s | HW % of peak | algorithmic TFLOP/s "
+             "| alg. % of peak |", "|---|---|---|---|---|---|---|---|"]
+    rec = {"source_hash": bench.source_hash(), "kernels": {}}
+    fams = [f for f in fl if f in tm and len(fl[f]) == len(tm[f])]
+    for f in sorted(fams, key=lambda f: -sum(tm[f])):
+        F, T = sum(fl[f]), sum(tm[f])
+        if F <= 0 or T <= 0:
+            continue
+        hw = F / T / 1e3  # flop per ns = GFLOP/s; / 1e3 -> TFLOP/s
+        kind = KIND_OF.get(f)
+        alg = ""
+        algp = ""
+        if kind and kind in work and launches.get(kind):
+            # every launch of the kind in the profiled run belongs to a solve
+            # of the same workload: solves = dispatches of the kind / launches per solve
+            kd = [g for g in fams if KIND_OF.get(g) == kind]
+            solves = sum(len(tm[g]) for g in kd) / launches[kind]
+            share = T / sum(sum(tm[g]) for g in kd)
+            a = work[kind] * solves * share / T / 1e3
+            alg, algp = f"{a:.3f}", f"{100 * a / PEAK_FP64_TFLOPS:.2f}%"
+        n = len(fl[f])
+        lines.append(f"| {f} | {n} | {F / n / 1e9:.4g} | {T / n / 1e3:.2f} | {hw:.3f} | "
+                     f"{100 * hw / PEAK_FP64_TFLOPS:.2f}% | {alg} | {algp} |")
+        rec["kernels"][f] = {"hw_flops_per_launch": F / n, "avg_us": T / n / 1e3, "hw_tflops": hw}
+    # the largest dispatches of the widest kernel: the big merges of the solve
+    for f in ("k_secular_wide", "k_secular"):
+        if f in fams and len(tm[f]) > 0:
+            order = sorted(range(len(tm[f])), key=lambda i: -tm[f][i])[:max(1, len(tm[f]) // 8)]
+            F = sum(fl[f][i] for i in order)
+            T = sum(tm[f][i] for i in order)
+            lines += ["", f"Longest eighth of the `{f}` dispatches (the largest merges): {len(order)} dispatches, "
+                          f"{T / len(order) / 1e3:.1f} us average, {F / T / 1e3:.3f} TFLOP/s hardware-counted "
+                          f"({100 * F / T / 1e3 / PEAK_FP64_TFLOPS:.2f}% of peak)."]
+            rec["kernels"][f]["hw_tflops_longest_eighth"] = F / T / 1e3
+            break
+    json.dump(rec, open(out_json, "w"), indent=1)
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:7])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:8])
+    elif sys.argv[1] == "fp64":
+        fp64(*sys.argv[2:9])
     else:
         raise SystemExit(__doc__)

@@ -83,3 +83,33 @@ def test_committed_traffic_record_names_known_kernels():
         if kind == "calibration":
             continue
         assert r["kernel"].startswith("k_") and r["bytes_per_launch"] > 0 and len(r["source_hash"]) == 16
+
+
+def test_profsum_fp64_counts_lanes_and_fma(tmp_path):
+    """Hardware FLOPs = 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave
+    instructions per dispatch, over the kernel-trace durations of the same
+    dispatches (matched in order); the algorithmic rate uses bench.py's work
+    per solve and launches per solve."""
+    from paper_2605_26599_amd import profsum
+
+    cnt, trace = tmp_path / "c.csv", tmp_path / "t.csv"
+    rows = []
+    for did in (1, 2):
+        for c, v in [("SQ_INSTS_VALU_ADD_F64", 100.0), ("SQ_INSTS_VALU_MUL_F64", 10.0),
+                     ("SQ_INSTS_VALU_FMA_F64", 50.0), ("SQ_INSTS_VALU_TRANS_F64", 5.0)]:
+            rows.append([did, "void tde::k_secular_wide<8>(x)", c, v])
+    _write(cnt, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    _write(trace, ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [[1, "void tde::k_secular_wide<8>(x)", 1000, 2000], [2, "void tde::k_secular_wide<8>(x)", 5000, 8000]])
+    bench_out = tmp_path / "b.txt"
+    bench_out.write_text(json.dumps({"work_flops_per_step": {"secular": 4.0e5},
+                                     "launches_per_step_by_kind": {"secular": 1}}) + "\n")
+    js, md = tmp_path / "f.json", tmp_path / "f.md"
+    profsum.fp64(str(cnt), str(trace), str(bench_out), str(js), str(md), "title", "cmd")
+    rec = json.loads(js.read_text())["kernels"]["k_secular_wide"]
+    per = 64 * (100 + 10 + 5 + 2 * 50)
+    assert rec["hw_flops_per_launch"] == pytest.approx(per)
+    # 2 launches, 4000 ns in all: flop/ns = GFLOP/s, / 1e3 = TFLOP/s
+    assert rec["hw_tflops"] == pytest.approx(2 * per / 4000 / 1e3)
+    # two solves of 4e5 algorithmic flops over 4000 ns
+    assert "| 0.200 |" in md.read_text()
