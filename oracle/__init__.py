@@ -254,3 +254,54 @@ def boundary_rows(d, e):
     q0, q1 = Q[0].copy(), Q[-1].copy()
     sg = np.where((q0 < 0) | ((q0 == 0) & (q1 < 0)), -1.0, 1.0)
     return lam, q0 * sg, q1 * sg
+
+
+def selected_rows(d, e, rows):
+    """Eigenvalues and the requested rows of the eigenvector matrix of T
+    (Algorithm 1's requested rows sigma; Lemma 2: the rows of Q S are the
+    requested rows of Q times S), from LAPACK eigenvectors
+    (scipy.linalg.eigh_tridiagonal): returns (lam, Qs) with Qs[i, k] = q_(rows[i]) k
+    for ascending lam, rows in the order given (repeats allowed), each column
+    signed so that q_0k >= 0 (q_(n-1)k >= 0 when q_0k = 0) -- the convention of
+    boundary_rows."""
+    from scipy.linalg import eigh_tridiagonal
+
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    n = len(d)
+    if n == 0:
+        return np.zeros(0), np.zeros((len(rows), 0))
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    if n == 1:
+        return d.copy(), np.ones((len(rows), 1))
+    lam, Q = eigh_tridiagonal(d, e, lapack_driver="stemr")
+    sg = np.where((Q[0] < 0) | ((Q[0] == 0) & (Q[-1] < 0)), -1.0, 1.0)
+    return lam, Q[rows] * sg[None, :]
+
+
+def row_weights_interlacing(d, e, r):
+    """Squares q_rk^2 of row r of the eigenvector matrix from eigenvalues alone:
+    q_rk^2 = prod_j (lambda_k - mu_j) prod_j (lambda_k - nu_j) / prod_(j != k) (lambda_k - lambda_j),
+    with mu the spectrum of T[0:r, 0:r] and nu that of T[r+1:, r+1:] (the
+    classical identity for the diagonal of the resolvent of a tridiagonal:
+    (T - x)^-1_rr = chi_(0..r-1)(x) chi_(r+1..n-1)(x) / chi(x)).  Every
+    spectrum comes from bisection (eigvals); products run as chains of ratios
+    so they neither overflow nor underflow.  For small n only (O(n^2))."""
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    n = len(d)
+    lam = eigvals(d, e)
+    mu = eigvals(d[:r], e[:max(r - 1, 0)]) if r > 0 else np.zeros(0)
+    nu = eigvals(d[r + 1:], e[r + 1:]) if r + 1 < n else np.zeros(0)
+    out = np.empty(n)
+    for k in range(n):
+        others = np.delete(lam, k)
+        num = np.concatenate([mu, nu])
+        # n - 1 numerator and n - 1 denominator factors, paired in sorted order
+        ratio = 1.0
+        for a, b in zip(np.sort(num), np.sort(others)):
+            ratio *= (lam[k] - a) / (lam[k] - b)
+        out[k] = ratio
+    return out

@@ -291,3 +291,53 @@ def test_boundary_rows_identities():
         for kk in range(n):
             den = np.prod([lam[kk] - lam[j] for j in range(n) if j != kk])
             assert abs(q0[kk] * q1[kk] - pe / den) <= 1e-12 * max(1.0, abs(pe / den))
+
+
+# --- requested rows (Algorithm 1 with an arbitrary row list) ------------------
+
+@pytest.mark.parametrize("fam,n", [("uniform", 9), ("normal", 12), ("toeplitz", 10), ("clustered", 8),
+                                   ("wilkinson", 7)])
+def test_selected_rows_interlacing_identity(fam, n):
+    """q_rk^2 of every row from eigenvalues alone (the resolvent-diagonal
+    identity, through the bisection oracle's spectra of T and of the two
+    blocks left when row and column r are removed)."""
+    d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_TEST)
+    lam, Q = oracle.selected_rows(d, e, np.arange(n))
+    assert np.abs(lam - oracle.eigvals(d, e)).max() <= 1e-14 * tdgen.tnorm1(d, e)
+    for r in range(n):
+        w = oracle.row_weights_interlacing(d, e, r)
+        assert np.abs(w - Q[r] ** 2).max() <= 1e-12, r
+
+
+@pytest.mark.parametrize("fam,n", [("uniform", 30), ("normal", 25), ("toeplitz", 16)])
+def test_selected_rows_eigen_equation(fam, n):
+    """All rows requested, shuffled and repeated: the distinct rows form an
+    orthogonal Q with T Q = Q diag(lambda) (which fixes the relative signs of
+    the rows), repeats equal their first occurrence, and every column is signed
+    so that q_0k >= 0."""
+    d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_TEST)
+    g = np.random.default_rng(5)
+    perm = g.permutation(n)
+    rows = np.concatenate([perm, perm[:7]])
+    lam, Qs = oracle.selected_rows(d, e, rows)
+    Q = np.empty((n, n))
+    Q[perm] = Qs[:n]
+    assert np.array_equal(Qs[n:], Qs[:7])
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() <= 1e-13
+    assert np.abs(T @ Q - Q * lam[None, :]).max() <= 1e-13 * tdgen.tnorm1(d, e)
+    assert np.all((Q[0] > 0) | ((Q[0] == 0) & (Q[-1] >= 0)))
+
+
+def test_selected_rows_boundary_and_gauss():
+    """Rows {0, n-1} agree with boundary_rows; row 0 of the Legendre Jacobi
+    matrix gives the Gauss-Legendre weights (Golub-Welsch)."""
+    d, e = tdgen.tridiag("uniform", 40, cfg=tdgen.CFG_TEST)
+    lam, q0, q1 = oracle.boundary_rows(d, e)
+    lam2, Qs = oracle.selected_rows(d, e, [39, 0])
+    assert np.array_equal(lam, lam2) and np.array_equal(Qs[1], q0) and np.array_equal(Qs[0], q1)
+    n = 24
+    k = np.arange(1, n, dtype=np.float64)
+    _, Qs = oracle.selected_rows(np.zeros(n), k / np.sqrt(4.0 * k * k - 1.0), [0])
+    _, wgt = np.polynomial.legendre.leggauss(n)
+    assert np.abs(2.0 * Qs[0] ** 2 - wgt).max() <= 1e-13
