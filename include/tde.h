@@ -146,6 +146,39 @@ int tde_eigvals_rows(const double* d, const double* e, const int64_t* offsets, i
                      double* qfirst, double* qlast, void* ws, size_t ws_bytes, void* hip_stream,
                      const tde_opts* opts);
 
+/* Requested eigenvector rows: Algorithm 1 with an arbitrary row list.
+ *
+ * The paper's recursion takes at every node a list sigma_v of requested local
+ * rows and returns the node's eigenvalues with those rows of its eigenvector
+ * matrix: the requested rows of Q_v = (Q_L (+) Q_R) S_v are the requested rows
+ * of the children's matrices times S_v (Lemma 2, selected-row
+ * multiplication), and repeated or unordered requests are resolved by
+ * metadata (the text after Algorithm 1).  For one tridiagonal this returns
+ * every eigenvalue and the rows `rows` of the eigenvector matrix:
+ *   rows   [m]    HOST row indices in [0, n), any order, repeats allowed (m >= 0)
+ *   lambda [n]    output eigenvalues, ascending (device)
+ *   Q      [m*n]  output (device, row-major): Q[i*n + k] = q_(rows[i]),k, the
+ *                 rows[i]-th component of the unit eigenvector of lambda_k, each
+ *                 column signed so that q_0k >= 0 (q_(n-1)k >= 0 when q_0k = 0),
+ *                 the convention of tde_eigvals_rows; may be NULL when m = 0
+ *   ws     ws_bytes >= tde_selrows_workspace_bytes(n, m, opts) (device): the
+ *                 forward workspace, a checkpoint of the nodes' spectra and
+ *                 boundary rows per tree level, and 5 n doubles + m ints
+ * Leaves are solved by QL (TDE_FLAG_LEAF_DC is ignored).  One forward solve
+ * records every level's node spectra and boundary rows; then each pair of
+ * distinct requested rows takes one more pass up the same tree, riding in
+ * the two row channels the boundary rows use (deflation decisions and roots
+ * are those of the first pass, bit for bit), so the cost is about
+ * 1 + ceil(distinct rows / 2) forward solves.  Kernels are enqueued one by
+ * one (no graph); the call waits for the stream once at the end.  Returns
+ * TDE_OK or a negative code (TDE_EINVAL for a row outside [0, n)); device
+ * status via tde_get_status(ws).  tde_selrows_workspace_bytes returns 0 on a
+ * bad argument. */
+size_t tde_selrows_workspace_bytes(int64_t n, int64_t m, const tde_opts* opts);
+int tde_eigvals_selrows(const double* d, const double* e, int64_t n, const int64_t* rows, int64_t m,
+                        double* lambda, double* Q, void* ws, size_t ws_bytes, void* hip_stream,
+                        const tde_opts* opts);
+
 /* Reverse mode (gradients of the eigenvalues).
  *
  * The paper computes eigenvalues only; these entry points add the adjoint of

@@ -19,6 +19,7 @@ __all__ = [
     "eigvals",
     "eigvals_batched",
     "eigvals_rows",
+    "eigvals_selrows",
     "eigvals_ckpt",
     "eigvals_backward",
     "differentiable_eigvals",
@@ -45,6 +46,8 @@ EXPORTS = (
     "tde_eigvals",
     "tde_eigvals_batched",
     "tde_eigvals_rows",
+    "tde_eigvals_selrows",
+    "tde_selrows_workspace_bytes",
     "tde_eigvals_split",
     "tde_checkpoint_bytes",
     "tde_backward_workspace_bytes",
@@ -134,6 +137,10 @@ def lib():
         L.tde_release_plans.restype = None
         L.tde_cache_sizes.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.tde_cache_sizes.restype = ctypes.c_int
+        L.tde_selrows_workspace_bytes.argtypes = [i64, i64, optp]
+        L.tde_selrows_workspace_bytes.restype = sz
+        L.tde_eigvals_selrows.argtypes = [vp, vp, i64, i64p, i64, vp, vp, vp, sz, vp, optp]
+        L.tde_eigvals_selrows.restype = ctypes.c_int
         L.tde_status_string.argtypes = [ctypes.c_int]
         L.tde_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -346,6 +353,40 @@ def eigvals_rows(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_rows device status")
     return lam, q0, q1
+
+
+def eigvals_selrows(d: torch.Tensor, e: torch.Tensor, rows, leaf=None, sweep_cols=None, wide_min=None,
+                    check: bool = True):
+    """Eigenvalues (ascending) of one tridiagonal and the requested rows of its
+    eigenvector matrix: Q[i, k] = q_(rows[i]) k, rows in any order with repeats
+    allowed, every column signed so that q_0k >= 0 (q_(n-1)k >= 0 when
+    q_0k = 0).  Leaves are solved by QL.  Waits for the stream.  Returns
+    (lam[n], Q[m, n])."""
+    _check_input(d, e)
+    n = d.numel()
+    if e.numel() < max(n - 1, 0):
+        raise ValueError("e must hold n-1 entries")
+    rl = [int(r) for r in rows]
+    m = len(rl)
+    lam = torch.empty(n, dtype=torch.float64, device=d.device)
+    Q = torch.empty((m, n), dtype=torch.float64, device=d.device)
+    arr = (ctypes.c_int64 * max(m, 1))(*rl)
+    opts = _opts(leaf, True, sweep_cols, wide_min)
+    nb = int(lib().tde_selrows_workspace_bytes(n, m, opts))
+    if nb == 0:
+        raise TDEError(TDE_EINVAL, "tde_selrows_workspace_bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=d.device)
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_selrows(d.data_ptr(), e.data_ptr() if e.numel() else None, n, arr, m,
+                                       lam.data_ptr(), Q.data_ptr(), ws.data_ptr(), ws.numel(), stream, opts)
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_eigvals_selrows")
+        if check:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_eigvals_selrows device status")
+    return lam, Q
 
 
 # --- reverse mode -------------------------------------------------------------

@@ -357,6 +357,111 @@ int backward(const double* d, const double* e, const std::vector<long long>& off
                     [&](void* s) { return enqueue_backward(*plan, w, gr, ck, d, e, gin, gd, ge, s); });
 }
 
+// Requested rows (Algorithm 1 with an arbitrary row list sigma): the
+// workspace beyond the forward's holds a forward checkpoint, the current
+// nodes' vectors of the two rows a pass carries, the unsigned top rows 0 and
+// n-1, a discarded eigenvalue output and the first-occurrence map.
+struct SelLayout {
+    size_t fw, total;
+    Ckpt ck;
+    double *xa, *xb, *q0, *q1, *xout;
+    int* first;
+};
+
+size_t selrows_layout(long long n, long long m, int levels, char* base, SelLayout* L) {
+    SelLayout t{};
+    t.fw = workspace_layout(n, 1, n, nullptr, nullptr);
+    size_t off = t.fw;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const long long nn = n > 0 ? n : 1;
+    char* ckb = take(ckpt_layout(n, levels, nullptr, nullptr));
+    ckpt_layout(n, levels, ckb, &t.ck);
+    t.xa = (double*)take(8 * nn);
+    t.xb = (double*)take(8 * nn);
+    t.q0 = (double*)take(8 * nn);
+    t.q1 = (double*)take(8 * nn);
+    t.xout = (double*)take(8 * nn);
+    t.first = (int*)take(4 * (m > 0 ? m : 1));
+    t.total = off;
+    if (L) *L = t;
+    return off;
+}
+
+int selrows(const double* d, const double* e, long long n, const int64_t* rows, long long m, double* lambda,
+            double* Q, void* ws, size_t ws_bytes, void* stream, const tde_opts* opts) {
+    int leaf, cols, wmin, cap;
+    bool dc;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap) != TDE_OK) return TDE_EINVAL;
+    if (n < 0 || n > (long long)0x3fffffff || m < 0 || m > (long long)0x3fffffff) return TDE_EINVAL;
+    if (n == 0) return m == 0 ? TDE_OK : TDE_EINVAL;
+    if (!d || !lambda || !ws || (n > 1 && !e) || (m > 0 && (!rows || !Q))) return TDE_EINVAL;
+    for (long long i = 0; i < m; ++i)
+        if (rows[i] < 0 || rows[i] >= n) return TDE_EINVAL;
+    // leaves by QL (the passes rely on the leaf recurrence tracking any row)
+    tde_opts o{};
+    if (opts) o = *opts;
+    o.flags &= ~TDE_FLAG_LEAF_DC;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    const std::vector<long long> offs{0, n};
+    Plan* plan = nullptr;
+    int rc = get_plan(&o, offs, &plan);
+    if (rc != TDE_OK) return rc;
+    SelLayout sl{};
+    const int H = tree_levels(leaf, offs);
+    if ((int)plan->levels.size() > H || ws_bytes < selrows_layout(n, m, H, nullptr, nullptr)) return TDE_EINVAL;
+    selrows_layout(n, m, H, (char*)ws, &sl);
+    // distinct rows, ascending, and the first request of each
+    std::vector<int> first((size_t)(m > 0 ? m : 1));
+    std::map<long long, int> slot;
+    for (long long i = 0; i < m; ++i) {
+        auto it = slot.find(rows[i]);
+        if (it == slot.end()) it = slot.emplace(rows[i], (int)i).first;
+        first[(size_t)i] = it->second;
+    }
+    std::vector<std::pair<long long, int>> uniq(slot.begin(), slot.end());
+    Work w{};
+    workspace_layout(n, 1, n, (char*)ws, &w);
+    w.sec_cap = cap;
+    // pass 0: eigenvalues, checkpoint, unsigned top rows 0 and n-1
+    w.rows_out = 1;
+    w.rows_raw = 1;
+    w.qfirst = sl.q0;
+    w.qlast = sl.q1;
+    if (enqueue_solve(*plan, w, d, e, lambda, stream, &sl.ck) != 0) return TDE_EDEVICE;
+    // one pass per two distinct rows
+    for (size_t u = 0; u < uniq.size(); u += 2) {
+        Work wx = w;
+        wx.qfirst = wx.qlast = nullptr;
+        wx.rows_raw = 0;
+        wx.xmode = 1;
+        wx.xa = sl.xa;
+        wx.xb = sl.xb;
+        wx.xa_row = uniq[u].first;
+        wx.xq_a = Q + (size_t)uniq[u].second * (size_t)n;
+        if (u + 1 < uniq.size()) {
+            wx.xb_row = uniq[u + 1].first;
+            wx.xq_b = Q + (size_t)uniq[u + 1].second * (size_t)n;
+        } else {
+            wx.xb_row = -1;
+            wx.xq_b = nullptr;
+        }
+        if (enqueue_solve(*plan, wx, d, e, sl.xout, stream, nullptr, &sl.ck) != 0) return TDE_EDEVICE;
+    }
+    if (m > 0) {
+        if (hipMemcpyAsync(sl.first, first.data(), sizeof(int) * (size_t)m, hipMemcpyHostToDevice,
+                           (hipStream_t)stream) != hipSuccess)
+            return TDE_EDEVICE;
+        if (enqueue_selrows_fix(Q, m, n, sl.first, sl.q0, sl.q1, stream) != 0) return TDE_EDEVICE;
+        // the host map must outlive the copy: wait for it (pageable memory)
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return TDE_EDEVICE;
+    }
+    return TDE_OK;
+}
+
 // Driver pre-pass: pairwise merge schedule of the blocks of every problem
 // (balanced over the blocks, levelled by height), cached per split.
 // Bounded, least recently used first out; an evicted schedule's table is
@@ -533,6 +638,19 @@ int tde_eigvals_rows(const double* d, const double* e, const int64_t* offsets, i
     if (!qfirst && !qlast) return TDE_EINVAL;
     if (B == 0 || offs.back() == 0) return TDE_OK;
     return tde::solve(d, e, offs, lambda, ws, ws_bytes, hip_stream, opts, nullptr, 0, qfirst, qlast);
+}
+
+size_t tde_selrows_workspace_bytes(int64_t n, int64_t m, const tde_opts* opts) {
+    int leaf, cols;
+    if (n < 0 || m < 0 || tde::resolve_opts(opts, &leaf, &cols) != TDE_OK) return 0;
+    const std::vector<long long> offs{0, (long long)n};
+    return tde::selrows_layout(n, m, tde::tree_levels(leaf, offs), nullptr, nullptr);
+}
+
+int tde_eigvals_selrows(const double* d, const double* e, int64_t n, const int64_t* rows, int64_t m,
+                        double* lambda, double* Q, void* ws, size_t ws_bytes, void* hip_stream,
+                        const tde_opts* opts) {
+    return tde::selrows(d, e, (long long)n, rows, (long long)m, lambda, Q, ws, ws_bytes, hip_stream, opts);
 }
 
 size_t tde_checkpoint_bytes(const int64_t* offsets, int64_t B, const tde_opts* opts) {

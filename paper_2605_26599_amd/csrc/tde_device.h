@@ -243,15 +243,17 @@ struct TwoRows {
     }
 };
 
-// Forward leaf: eigenvalues (ascending, in d) and rows 0 and l-1 (r0, r1).
-TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st, unsigned* nrot) {
+// Forward leaf: eigenvalues (ascending, in d) and rows ra and rb (r0, r1;
+// by default 0 and l-1, the boundary rows).
+TDE_DEV int leaf_ql(int nl, double* d, double* e, double* r0, double* r1, int st, unsigned* nrot, int ra,
+                    int rb) {
     TwoRows rows;
     rows.a.q = r0;
     rows.a.st = st;
     rows.b.q = r1;
     rows.b.st = st;
-    rows.a.init(nl, 0);
-    rows.b.init(nl, nl - 1);
+    rows.a.init(nl, ra);
+    rows.b.init(nl, rb);
     return leaf_ql_core(nl, d, e, st, rows, nrot);
 }
 
@@ -613,6 +615,13 @@ TDE_DEV int merge_emit(const MergeRec& R, int c, double x, double rho, double sg
         rl = 0.0;
         rh = w.bhi[R.off + c];
     }
+    if (w.xmode) {
+        // requested rows: a row reaches this merge from the child that holds it
+        const bool cl = c < R.nL;
+        const long long mid = R.off + R.nL, end = mid + R.nR;
+        rl = (w.xa_row >= R.off && w.xa_row < end && (w.xa_row < mid) == cl) ? w.xa[R.off + c] : 0.0;
+        rh = (w.xb_row >= R.off && w.xb_row < end && (w.xb_row < mid) == cl) ? w.xb[R.off + c] : 0.0;
+    }
     w.D[P] = x;
     w.Z[P] = z;
     w.RL[P] = rl;
@@ -895,7 +904,7 @@ TDE_DEV int roots_cmp_count(const double* __restrict__ Da, const int* __restrict
 // eigenvalue, signed so that the first entry is >= 0 (the last when the first
 // is 0).
 TDE_DEV void store_rows(const Work& w, long long P, double bl, double bh) {
-    const double sg = (bl < 0.0 || (bl == 0.0 && bh < 0.0)) ? -1.0 : 1.0;
+    const double sg = (!w.rows_raw && (bl < 0.0 || (bl == 0.0 && bh < 0.0))) ? -1.0 : 1.0;
     if (w.qfirst) w.qfirst[P] = sg * bl;
     if (w.qlast) w.qlast[P] = sg * bh;
 }
@@ -934,6 +943,18 @@ TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
         if (rows) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
     }
     const long long P = R.off + pos;
+    if (w.xmode) {
+        const bool ha = w.xa_row >= R.off && w.xa_row < R.off + s;
+        const bool hb = w.xb_row >= R.off && w.xb_row < R.off + s;
+        if (root) {
+            if (ha && w.xq_a) w.xq_a[P] = bl;
+            if (hb && w.xq_b) w.xq_b[P] = bh;
+        } else {
+            if (ha) w.xa[P] = bl;
+            if (hb) w.xb[P] = bh;
+        }
+        return;
+    }
     if (root) {
         out[P] = val * scale_of(pmax[R.prob]);
         if (w.rows_out) store_rows(w, P, bl, bh);
@@ -959,7 +980,21 @@ TDE_DEV int body_leaf(const LeafRec& L, const double* __restrict__ d, const doub
         sd[i * st] = di;
         se[i * st] = (i + 1 < nl) ? e[L.off + i] * inv : 0.0;
     }
-    int status = leaf_ql(nl, sd, se, s0, s1, st, nrot);
+    // tracked rows: 0 and l-1, or in a requested-rows pass the requested rows
+    // the leaf holds
+    const bool ha = w.xmode && w.xa_row >= L.off && w.xa_row < L.off + nl;
+    const bool hb = w.xmode && w.xb_row >= L.off && w.xb_row < L.off + nl;
+    int status = leaf_ql(nl, sd, se, s0, s1, st, nrot, ha ? (int)(w.xa_row - L.off) : 0,
+                         hb ? (int)(w.xb_row - L.off) : nl - 1);
+    if (w.xmode) {
+        double* da = (L.flags & LF_WHOLE) ? w.xq_a : w.xa;
+        double* db = (L.flags & LF_WHOLE) ? w.xq_b : w.xb;
+        for (int i = 0; i < nl; ++i) {
+            if (ha && da) da[L.off + i] = s0[i * st];
+            if (hb && db) db[L.off + i] = s1[i * st];
+        }
+        return status;
+    }
     if (L.flags & LF_WHOLE) {
         const double sc = 1.0 / inv;
         for (int i = 0; i < nl; ++i) {

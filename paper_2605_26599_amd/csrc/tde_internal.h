@@ -158,6 +158,19 @@ struct Work {
     double* qlast;             // [n] or null: last eigenvector row of each output eigenvalue (rows mode)
     int rows_out;              // 1: the top merges also propagate rows (qfirst / qlast requested)
     int sec_cap;               // secular iterations allowed per root before ST_SEC_NOCONV (kSecMaxIter)
+    int rows_raw;              // rows mode: store the top rows as computed (no sign normalisation)
+    // Requested-rows pass (xmode = 1): the two row channels carry rows xa_row and
+    // xb_row of every node that contains them (global indices, -1 = none) instead
+    // of the parent's first and last rows; z still comes from the node boundary
+    // rows (lam, blo, bhi then point at a forward checkpoint's level slot, read
+    // only).  xa / xb hold those rows of the current nodes (global positions, in
+    // place across levels); the top merge writes them to xq_a / xq_b (length n).
+    int xmode;
+    long long xa_row, xb_row;
+    double* xa;
+    double* xb;
+    double* xq_a;
+    double* xq_b;
 };
 
 // Forward checkpoint for the reverse pass: per level h (slot stride n), the

@@ -1898,6 +1898,23 @@ __global__ __launch_bounds__(kWG) void k_bwd_edges(const long long* __restrict__
     if (b < B && offs[b + 1] > offs[b]) ge[offs[b + 1] - 1] = 0.0;
 }
 
+// Requested rows: sign every eigenvector column like the boundary rows (the
+// first entry >= 0, the last when the first is 0; q0 / q1 are the unsigned top
+// rows of the same solve) and copy repeated requests from their first
+// occurrence.  One thread per column; Q is [m][n], row i at Q + i n.
+__global__ __launch_bounds__(kWG) void k_selrows_fix(double* __restrict__ Q, long long m, long long n,
+                                                     const int* __restrict__ first, const double* __restrict__ q0,
+                                                     const double* __restrict__ q1) {
+    const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double a = q0[k], b = q1[k];
+    const double sg = (a < 0.0 || (a == 0.0 && b < 0.0)) ? -1.0 : 1.0;
+    for (long long i = 0; i < m; ++i)
+        if (first[i] == i) Q[i * n + k] *= sg;
+    for (long long i = 0; i < m; ++i)
+        if (first[i] != i) Q[i * n + k] = Q[(long long)first[i] * n + k];
+}
+
 // ---------------------------------------------------------------------------
 // Optional per-kernel timing: HIP events recorded on the solve's stream
 // around every launch, summed per launch kind on read-back.
@@ -2103,7 +2120,7 @@ static void enqueue_setup(const Plan& p, const Work& w, void* stream) {
 }
 
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
-                  const Ckpt* ck) {
+                  const Ckpt* ck, const Ckpt* xsrc) {
     if (p.ntot == 0) return 0;
     enqueue_setup(p, w, stream);
     TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
@@ -2131,6 +2148,13 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         const long long N = L.N;
         const unsigned nb = nblk(N, kWG);
         Work wl = level_work(w, p.ntot, h);
+        if (xsrc) {
+            // requested-rows pass: the level's node spectra and boundary rows from the checkpoint
+            const long long so = (long long)h * xsrc->n;
+            wl.lam = xsrc->lam + so;
+            wl.blo = xsrc->blo + so;
+            wl.bhi = xsrc->bhi + so;
+        }
         if (ck) {
             const long long so = (long long)h * ck->n;
             TDE_LAUNCH_K(KIND_SETUP, k_ckpt_save, nb, kWG, stream, mr, blkm, N, w, ck->lam + so, ck->blo + so,
@@ -2285,6 +2309,13 @@ __global__ __launch_bounds__(kWG) void k_merge_runs(const MergeRec* __restrict__
     if (i < R.nL) pos = i + count_lt(src + R.off + R.nL, R.nR, x);
     else pos = (i - R.nL) + count_le(src + R.off, R.nL, x);
     dst[R.off + pos] = x;
+}
+
+int enqueue_selrows_fix(double* Q, long long m, long long n, const int* first, const double* q0,
+                        const double* q1, void* stream) {
+    if (m <= 0 || n <= 0) return 0;
+    TDE_LAUNCH_K(KIND_ASSEMBLE, k_selrows_fix, nblk(n, kWG), kWG, stream, Q, m, n, first, q0, q1);
+    return (int)hipGetLastError();
 }
 
 int enqueue_split_flags(const double* d, const double* e, long long n, int* flags, void* stream) {

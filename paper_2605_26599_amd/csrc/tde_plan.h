@@ -71,7 +71,16 @@ size_t ckpt_layout(long long n, int levels, char* base, Ckpt* c);
 // Enqueue one full solve (scale, leaves, every level) on stream; with ck, also
 // record the checkpoint the reverse pass reads.
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
-                  const Ckpt* ck = nullptr);
+                  const Ckpt* ck = nullptr, const Ckpt* xsrc = nullptr);
+// With xsrc (a requested-rows pass, w.xmode = 1): every level reads its node
+// spectra and boundary rows from the checkpoint xsrc of a forward solve of the
+// same inputs and plan instead of the workspace.
+
+// Requested rows: sign the columns of Q [m][n] by the unsigned top rows q0, q1
+// (first entry >= 0) and copy repeated rows from their first occurrence
+// first[i] (device).
+int enqueue_selrows_fix(double* Q, long long m, long long n, const int* first, const double* q0,
+                        const double* q1, void* stream);
 
 // Driver pre-pass: negligible-coupling flags (flags[i] = 1: a block starts at
 // column i), and one pass of pairwise merges of ascending runs (src -> dst).

@@ -199,7 +199,7 @@ def fp64(counter_csv, trace_csv, bench_jsonl, out_json, out_md, title, cmd):
         rec["kernels"][f] = {"hw_flops_per_launch": F / n, "avg_us": T / n / 1e3, "hw_tflops": hw}
     # the largest dispatches of the widest kernel: the big merges of the solve
     for f in ("k_secular_wide", "k_secular"):
-        if f in fams and len(tm[f]) > 0:
+        if f in rec["kernels"] and len(tm[f]) > 0:
             order = sorted(range(len(tm[f])), key=lambda i: -tm[f][i])[:max(1, len(tm[f]) // 8)]
             F = sum(fl[f][i] for i in order)
             T = sum(tm[f][i] for i in order)

@@ -122,3 +122,24 @@ def test_cache_sizes_query(L):
     assert L.tde_cache_sizes(buf, 3) == tde.TDE_OK
     assert list(buf) == [0, 0, 0]
     assert L.tde_cache_sizes(None, 3) == tde.TDE_EINVAL
+
+
+def test_selrows_sizes_and_argument_errors(L):
+    """The requested-rows workspace is linear in n (plus the checkpoint's
+    n x levels) and in m; rows outside [0, n) are rejected before any device
+    work (the pointers passed are never dereferenced)."""
+    import paper_2605_26599_amd as tde
+
+    a = L.tde_selrows_workspace_bytes(1 << 14, 4, None)
+    b = L.tde_selrows_workspace_bytes(1 << 14, 4 + (1 << 16), None)
+    assert a > tde.workspace_bytes(1 << 14)
+    assert b - a >= 4 * (1 << 16)
+    fake = ctypes.c_void_p(4096)
+    for rows in ([5, 100], [-1], [0, 99, 100]):
+        arr = (ctypes.c_int64 * len(rows))(*rows)
+        rc = L.tde_eigvals_selrows(fake, fake, 100, arr, len(rows), fake, fake, fake, 1 << 30, None, None)
+        assert rc == tde.TDE_EINVAL
+    # m > 0 with no row list, and an empty problem with requested rows
+    assert L.tde_eigvals_selrows(fake, fake, 100, None, 2, fake, fake, fake, 1 << 30, None, None) == tde.TDE_EINVAL
+    arr = (ctypes.c_int64 * 1)(0)
+    assert L.tde_eigvals_selrows(fake, fake, 0, arr, 1, fake, fake, fake, 1 << 30, None, None) == tde.TDE_EINVAL
