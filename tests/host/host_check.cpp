@@ -178,7 +178,7 @@ static int mode_leaf() {
     for (int i = 0; i + 1 < n; ++i)
         if (std::scanf("%lf", &e[(size_t)i]) != 1) return 2;
     unsigned nrot = 0;
-    const int st = leaf_ql(n, d.data(), e.data(), r0.data(), r1.data(), 1, &nrot);
+    const int st = leaf_ql(n, d.data(), e.data(), r0.data(), r1.data(), 1, &nrot, 0, n - 1);
     std::printf("%d %u\n", st, nrot);
     for (int i = 0; i < n; ++i) std::printf("%.17g %.17g %.17g\n", d[(size_t)i], r0[(size_t)i], r1[(size_t)i]);
     return 0;
