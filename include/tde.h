@@ -224,6 +224,27 @@ int tde_eigvals_backward(const double* d, const double* e, const int64_t* offset
                          const double* glambda, const void* ckpt, size_t ckpt_bytes, double* gd, double* ge,
                          void* ws, size_t ws_bytes, void* hip_stream, const tde_opts* opts);
 
+/* Allocation-free solve, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  As tde_eigvals for one tridiagonal of n <= 65536 columns, but
+ * without a workspace argument: the workspace and the merge-tree tables live
+ * in a fixed 24 MiB device array inside the library, one per GPU, held until
+ * the process ends.  The call copies the tree tables into it with
+ * asynchronous host-to-device copies on the stream and enqueues the kernels
+ * one by one (no graph); it calls no hipMalloc or hipFree and allocates no
+ * other device memory (host-side plans are cached, bounded).
+ *   d, e, n, lambda, hip_stream, opts: as tde_eigvals (TDE_FLAG_NO_GRAPH is
+ *            implied; timing mode does not apply)
+ *   status   (device int, may be NULL) receives the solve's status bits in
+ *            stream order: 0 ok, 1 non-finite input, 2 or 4 a leaf or secular
+ *            iteration hit its cap
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls on one stream are ordered, calls that overlap on one GPU
+ * (two streams or threads at once) race.  Returns TDE_EINVAL for n > 65536 or
+ * a bad argument, TDE_EDEVICE if the array's address cannot be looked up. */
+int tde_eigvals_noalloc(const double* d, const double* e, int64_t n, double* lambda, int* status,
+                        void* hip_stream, const tde_opts* opts);
+
 /* Waits for the stream, then reads the device status word of the last solve
  * that used ws: TDE_OK, TDE_ENONFINITE or TDE_ENOCONV.  Returns a negative code
  * if the read itself fails. */

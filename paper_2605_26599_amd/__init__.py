@@ -20,6 +20,7 @@ __all__ = [
     "eigvals_batched",
     "eigvals_rows",
     "eigvals_selrows",
+    "eigvals_noalloc",
     "eigvals_ckpt",
     "eigvals_backward",
     "differentiable_eigvals",
@@ -49,6 +50,7 @@ EXPORTS = (
     "tde_eigvals_selrows",
     "tde_selrows_workspace_bytes",
     "tde_eigvals_split",
+    "tde_eigvals_noalloc",
     "tde_checkpoint_bytes",
     "tde_backward_workspace_bytes",
     "tde_eigvals_ckpt",
@@ -141,6 +143,8 @@ def lib():
         L.tde_selrows_workspace_bytes.restype = sz
         L.tde_eigvals_selrows.argtypes = [vp, vp, i64, i64p, i64, vp, vp, vp, sz, vp, optp]
         L.tde_eigvals_selrows.restype = ctypes.c_int
+        L.tde_eigvals_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, optp]
+        L.tde_eigvals_noalloc.restype = ctypes.c_int
         L.tde_status_string.argtypes = [ctypes.c_int]
         L.tde_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -286,6 +290,36 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
             st = lib().tde_get_status(ws.data_ptr(), stream)
             if st != TDE_OK:
                 raise TDEError(st, "tde_eigvals_batched device status")
+    return out
+
+
+def eigvals_noalloc(d: torch.Tensor, e: torch.Tensor, out: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None, leaf=None, sweep_cols=None, wide_min=None,
+                    leaf_dc=None) -> torch.Tensor:
+    """Eigenvalues (ascending) of one tridiagonal of at most 65536 columns,
+    through the entry point that allocates no device memory (its workspace is
+    a fixed array inside the library, shared by every call on the device:
+    calls that overlap on one GPU race).  status, if given, is a device int32
+    tensor that receives the solve's device status bits in stream order (0 =
+    ok, 1 = non-finite input, 2 or 4 = a leaf or secular iteration hit its
+    cap).  Nothing is synchronised."""
+    _check_input(d, e)
+    n = d.numel()
+    if e.numel() < max(n - 1, 0):
+        raise ValueError("e must hold n-1 entries")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=d.device)
+    if out.dtype != torch.float64 or out.device != d.device or not out.is_contiguous() or out.numel() < n:
+        raise ValueError("out must be a contiguous float64 tensor of at least n entries on d's device")
+    if status is not None and (status.dtype != torch.int32 or status.device != d.device or status.numel() < 1):
+        raise ValueError("status must be an int32 tensor on d's device")
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    with torch.cuda.device(d.device):
+        rc = lib().tde_eigvals_noalloc(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
+                                       status.data_ptr() if status is not None else None, stream,
+                                       _opts(leaf, False, sweep_cols, wide_min, leaf_dc))
+    if rc != TDE_OK:
+        raise TDEError(rc, "tde_eigvals_noalloc")
     return out
 
 

@@ -1926,6 +1926,7 @@ struct TimedLaunch {
 };
 std::mutex g_tmu;
 bool g_timing = false;
+thread_local bool t_untimed = false;  // this thread's launches are never timed
 std::vector<TimedLaunch> g_timed;
 
 struct TimingScope {
@@ -1933,7 +1934,7 @@ struct TimingScope {
     void* stream;
     hipEvent_t a = nullptr, b = nullptr;
     bool on;
-    TimingScope(int k, void* s) : kind(k), stream(s), on(g_timing) {
+    TimingScope(int k, void* s) : kind(k), stream(s), on(g_timing && !t_untimed) {
         if (on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, (hipStream_t)stream);
         else on = false;
     }
@@ -1951,6 +1952,8 @@ void timing_enable(bool on) {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_timing = on;
 }
+
+void timing_suppress(bool on) { t_untimed = on; }
 
 bool timing_enabled() {
     std::lock_guard<std::mutex> lk(g_tmu);

@@ -61,6 +61,10 @@ size_t workspace_layout(long long n, long long B, long long maxM, char* base, Wo
 // Optional per-kernel timing (HIP events around every launch, per kind).
 void timing_enable(bool on);
 bool timing_enabled();
+// Launches enqueued by the calling thread are (not) timed, whatever
+// timing_enable says (timing creates events, which the allocation-free entry
+// point must not do).
+void timing_suppress(bool on);
 int timing_read(double* ms, long long* count, int nkinds);
 
 // Reverse-pass scratch (n columns, nmerges merges) and forward checkpoint
