@@ -75,7 +75,12 @@ typedef struct {
     int max_sweeps; /* secular iterations allowed per root, 1..96; 0 = default (96).
                        A root still unconverged at the cap sets TDE_ENOCONV (a
                        small cap forces that path from the host, for tests) */
-    int reserved[3]; /* must be 0 */
+    int group_max;  /* most lanes per root (4, 8 or 16) in the merges with at most
+                       512 active roots, which run one workgroup per merge; 0 = by
+                       level (16 on levels of fewer than 512 merges, else 4).  The
+                       sums are formed in one fixed order whatever the lane count,
+                       so this changes speed, not results */
+    int reserved[2]; /* must be 0 */
 } tde_opts;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */

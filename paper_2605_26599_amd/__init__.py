@@ -74,7 +74,8 @@ class TDEError(RuntimeError):
 
 class tde_opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
-                ("wide_min", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("wide_min", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("group_max", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 _lib = None
@@ -168,21 +169,24 @@ TDE_FLAG_LEAF_DC = 2
 # one wave (the reverse mode's checkpointing forward keeps QL leaves).
 # max_sweeps: secular iterations allowed per root (a small value forces the
 # non-convergence status, for tests).
-_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None}
+# group_max: most lanes per root in the fused small merges (4, 8, 16; None = by level).
+_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None, "group_max": None}
 
 
-def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None):
+def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None, group_max=None):
     _shape_defaults["wide_min"] = wide_min
     _shape_defaults["leaf_dc"] = leaf_dc
     _shape_defaults["max_sweeps"] = max_sweeps
+    _shape_defaults["group_max"] = group_max
 
 
-def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None):
+def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None):
     wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
     leaf_dc = _shape_defaults["leaf_dc"] if leaf_dc is None else leaf_dc
+    group_max = _shape_defaults["group_max"] if group_max is None else group_max
     max_sweeps = _shape_defaults["max_sweeps"]
     if (leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc
-            and max_sweeps is None):
+            and max_sweeps is None and not group_max):
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
@@ -190,6 +194,7 @@ def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None):
     o.sweep_cols = int(sweep_cols or 0)
     o.wide_min = int(wide_min or 0)
     o.max_sweeps = int(max_sweeps or 0)
+    o.group_max = int(group_max or 0)
     return ctypes.byref(o)
 
 
@@ -228,7 +233,7 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-            sweep_cols=None, wide_min=None, leaf_dc=None) -> torch.Tensor:
+            sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
     off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
     replays a captured HIP graph of the whole solve (captured on first use for
@@ -250,7 +255,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
                                ws.data_ptr(), ws.numel(), stream,
-                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc))
+                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -262,7 +267,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-                    sweep_cols=None, wide_min=None, leaf_dc=None) -> torch.Tensor:
+                    sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -283,7 +288,8 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     stream = torch.cuda.current_stream(d.device).cuda_stream
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
-                                       ws.numel(), stream, _opts(leaf, graph, sweep_cols, wide_min, leaf_dc))
+                                       ws.numel(), stream,
+                                       _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:

@@ -169,8 +169,8 @@ TDE_DEV void bwd_defl_sums(int K, const double* __restrict__ D, const int* __res
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int b = sub; b < K; b += G) {
         const double Do = D[org[b]];
-        double k = 1.0 / ((Dp - Do) - tau[b]);
-        if (i >= 0) k *= 1.0 / ((Di - Do) - tau[b]);
+        double k = rcp_nr((Dp - Do) - tau[b]);
+        if (i >= 0) k *= rcp_nr((Di - Do) - tau[b]);
         s0 += bl[b] * k;
         s1 += bh[b] * k;
         s2 += gl[b] * k;
@@ -286,9 +286,13 @@ TDE_DEV void run_step_adjoint(const RunState& cur, const RunState& nx, const Run
 // segment's final survivor i (a secular column; one sweep over the roots).
 // Two deflated columns at exactly equal poles contribute nothing (the node's
 // eigenvectors there are free to rotate and the loss cannot depend on it).
+//
+// A group of G lanes handles one run: every lane walks the chain (writing the
+// same values to the same addresses) and the group splits each O(K) coupling
+// sum (lane `sub` of G).
 template <class Red>
 TDE_DEV void body_bwd_runs(long long g, int m, const MergeRec* __restrict__ mr, const Work& w, const Grad& gr,
-                           long long cstride) {
+                           long long cstride, int sub, int G) {
     const int* __restrict__ nnpos = w.nnpos;
     const long long t = nnpos[g];
     const MergeRec R = mr[m];
@@ -377,7 +381,7 @@ TDE_DEV void body_bwd_runs(long long g, int m, const MergeRec* __restrict__ mr, 
             const long long ps = nnpos[q - 1];
             const int i = (int)(w.scan[ps] - ks);
             double S[4];
-            bwd_defl_sums<RedSerial>(K, w.Da + ks, w.org + ks, w.tau + ks, gr.coef + ks, cstride, dj.D, i, 0, 1, S);
+            bwd_defl_sums<Red>(K, w.Da + ks, w.org + ks, w.tau + ks, gr.coef + ks, cstride, dj.D, i, sub, G, S);
             const double a2 = w.zhat[ks + i] * (gbl * S[0] + gbh * S[1] - dj.L * S[2] - dj.H * S[3]);
             gE += coefv * a2;
         }

@@ -34,7 +34,7 @@ namespace {
 // ---------------------------------------------------------------------------
 std::recursive_mutex g_mu;
 
-using PlanKey = std::tuple<int, int, int, int, bool, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, int, bool, int, std::vector<long long>>;
 constexpr size_t kMaxPlans = 32;
 struct PlanEntry {
     PlanKey key;
@@ -179,8 +179,9 @@ int run_pass(const Plan& plan, int kind, const Bufs& bufs, const tde_opts* opts,
 }
 
 // Caller holds g_mu.
-int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vector<long long>& offs, Plan** out) {
-    PlanKey key{device, leaf, cols, wmin, dc, offs};
+int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, const std::vector<long long>& offs,
+              Plan** out) {
+    PlanKey key{device, leaf, cols, wmin, dc, gmax, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         g_plan_lru.splice(g_plan_lru.begin(), g_plan_lru, it->second);
@@ -193,6 +194,7 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vect
     p->sweep_cols = cols;
     p->wide_min = wmin;
     p->leaf_dc = dc;
+    p->group_max = gmax;
     p->offs = offs;
     if (plan_host(p.get()) != 0) return TDE_EINVAL;
     auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
@@ -221,17 +223,20 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, const std::vect
 }
 
 int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr,
-                 int* cap = nullptr) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter;
+                 int* cap = nullptr, int* gmax = nullptr) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0;
     if (opts) {
         if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
         if (opts->sweep_cols != 0) C = opts->sweep_cols;
         if (opts->wide_min != 0) W = opts->wide_min;
         if (opts->max_sweeps != 0) S = opts->max_sweeps;
+        Gm = opts->group_max;
         for (int r : opts->reserved)
             if (r != 0) return TDE_EINVAL;
     }
+    if (Gm != 0 && Gm != 4 && Gm != 8 && Gm != 16) return TDE_EINVAL;
+    if (gmax) *gmax = Gm;
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
     if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
     if (W < 2) return TDE_EINVAL;
@@ -271,12 +276,12 @@ int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* off
 }
 
 int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** plan) {
-    int leaf, cols, wmin;
+    int leaf, cols, wmin, cap, gmax;
     bool dc;
-    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc) != TDE_OK) return TDE_EINVAL;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap, &gmax) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
-    return make_plan(device, leaf, cols, wmin, dc, offs, plan);
+    return make_plan(device, leaf, cols, wmin, dc, gmax, offs, plan);
 }
 
 bool needs_e(const std::vector<long long>& offs) {

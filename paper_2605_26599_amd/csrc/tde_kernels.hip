@@ -1289,6 +1289,202 @@ constexpr int kFuseMax = 512;
 constexpr int kFuseThreads = 512;
 constexpr int kFuseWideS = 2048;
 
+
+// ---------------------------------------------------------------------------
+// Canonical group sums for the fused small merges.  Term j of a sweep (a
+// pole, or a root for the Loewner products) belongs to partial s = j mod 16,
+// which accumulates its terms in increasing j; the 16 partials meet in one
+// fixed tree: s with 15 - s, then s with 7 - s within each half, then s with
+// s ^ 2, then s with s ^ 1.  A group of G lanes (G = 4, 8 or 16) gives lane l
+// the 16 / G partials that the first log2(16 / G) tree steps fold onto l
+// (G = 16: l; 8: l, 15 - l; 4: l, 15 - l, 7 - l, 8 + l), folds them locally in
+// tree order and takes the remaining steps as DPP lane moves.  Every G gives
+// the same bits, so the lanes per root can follow the level's parallelism
+// (many lanes per root when a level has few merges, few when it has many)
+// without changing any result: a batched solve still equals the single ones.
+// ---------------------------------------------------------------------------
+template <int G>
+struct Canon {
+    static_assert(G == 4 || G == 8 || G == 16, "canonical groups of 4, 8 or 16 lanes");
+    static constexpr int M = 16 / G;  // partials per lane
+    __device__ __forceinline__ static int slot(int l, int q) {
+        return q == 0 ? l : (q == 1 ? 15 - l : (q == 2 ? 7 - l : 8 + l));
+    }
+    __device__ __forceinline__ static double fold_sum(const double* p) {
+        if (M == 1) return p[0];
+        if (M == 2) return p[0] + p[1];
+        return (p[0] + p[1]) + (p[2] + p[3]);
+    }
+    __device__ __forceinline__ static double fold_prod(const double* p) {
+        if (M == 1) return p[0];
+        if (M == 2) return p[0] * p[1];
+        return (p[0] * p[1]) * (p[2] * p[3]);
+    }
+    __device__ __forceinline__ static double sum(const double* p) {
+        double x = fold_sum(p);
+        if (G >= 16) x += dpp_move<kDppMirror>(x);
+        if (G >= 8) x += dpp_move<kDppHalfMirror>(x);
+        x += dpp_move<kDppSwap2>(x);
+        x += dpp_move<kDppSwap1>(x);
+        return x;
+    }
+    __device__ __forceinline__ static double prod(const double* p) {
+        double x = fold_prod(p);
+        if (G >= 16) x *= dpp_move<kDppMirror>(x);
+        if (G >= 8) x *= dpp_move<kDppHalfMirror>(x);
+        x *= dpp_move<kDppSwap2>(x);
+        x *= dpp_move<kDppSwap1>(x);
+        return x;
+    }
+};
+
+// Runs body(q, j) for every term j < K of this lane's partials q, in
+// increasing j per partial (whole chunks of 16 first, then the tail).
+template <int G, class Body>
+__device__ __forceinline__ void canon_for(int K, int sub, Body body) {
+    constexpr int M = Canon<G>::M;
+    int off[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) off[q] = Canon<G>::slot(sub, q);
+    int c = 0;
+    _Pragma("unroll 2") for (; c + 16 <= K; c += 16) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) body(q, c + off[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+        if (c + off[q] < K) body(q, c + off[q]);
+}
+
+// sec_sweep with canonical partial sums (same per-term arithmetic).
+template <int G, bool ZZ>
+__device__ __forceinline__ void sec_sweep_c(int K, const double* __restrict__ D, const double* __restrict__ W,
+                                            double Do, double tau, int L1, int R0, int sub, double* s) {
+    constexpr int M = Canon<G>::M;
+    double ps[M], dps[M], ph[M], dph[M], zz[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) ps[q] = dps[q] = ph[q] = dph[q] = zz[q] = 0.0;
+    const unsigned exw = (unsigned)(R0 - L1);
+    canon_for<G>(K, sub, [&](int q, int j) {
+        const double wr = W[j];
+        const double rr = rcp_nr((D[j] - Do) - tau);
+        const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : wr;
+        const double t = wj * rr;
+        const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
+        ps[q] += tl;
+        dps[q] = fma(tl, rr, dps[q]);
+        ph[q] += th;
+        dph[q] = fma(th, rr, dph[q]);
+        if (ZZ) zz[q] += wr;
+    });
+    s[0] = Canon<G>::sum(ps);
+    s[1] = Canon<G>::sum(dps);
+    s[2] = Canon<G>::sum(ph);
+    s[3] = Canon<G>::sum(dph);
+    if (ZZ) s[4] = Canon<G>::sum(zz);
+}
+
+// secular_root with canonical sweeps (same iteration and stopping rules).
+template <int G>
+__device__ __forceinline__ int secular_root_c(int k, int K, const double* __restrict__ D,
+                                              const double* __restrict__ Z, const double* __restrict__ W, double rho,
+                                              int sub, int cap, int* org_out, double* tau_out) {
+    if (K == 1) {
+        *org_out = 0;
+        *tau_out = rho * Z[0] * Z[0];
+        return 0;
+    }
+    const int kk = (k < K - 1) ? k : K - 2;
+    SecRoot r;
+    double s[5];
+    if (k < K - 1) {
+        sec_sweep_c<G, false>(K, D, W, D[kk], 0.5 * (D[kk + 1] - D[kk]), kk, kk + 2, sub, s);
+        if (sec_start_interior(k, D, Z, rho, s[0], s[1], s[2], s[3], &r)) {
+            *org_out = r.o;
+            *tau_out = r.tau;
+            return 0;
+        }
+    } else {
+        constexpr int M = Canon<G>::M;
+        double zz[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) zz[q] = 0.0;
+        canon_for<G>(K, sub, [&](int q, int j) { zz[q] += W[j]; });
+        sec_start_last(K, D, Z, rho, Canon<G>::sum(zz), &r);
+    }
+    for (int it = 1; it <= cap; ++it) {
+        int L1, R0;
+        sec_split(r, kk, &L1, &R0);
+        sec_sweep_c<G, false>(K, D, W, D[r.o], r.tau, L1, R0, sub, s);
+        if (sec_update(&r, rho, s[0], s[1], s[2], s[3], s[2] - s[0])) {
+            *org_out = r.o;
+            *tau_out = r.tau;
+            return it;
+        }
+    }
+    *org_out = r.o;
+    *tau_out = r.tau;
+    return -1;
+}
+
+// lowner_z with canonical partial products: each partial multiplies its
+// factors 8 at a time (one division per 8 of its factors), as lowner_z does.
+template <int G>
+__device__ __forceinline__ double lowner_z_c(int i, int K, const double* __restrict__ D,
+                                             const double* __restrict__ Z, const int* __restrict__ org,
+                                             const double* __restrict__ tau, double rho, int sub) {
+    constexpr int M = Canon<G>::M;
+    const double di = D[i];
+    double prod[M], pn[M], pd[M];
+    int cnt[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        prod[q] = pn[q] = pd[q] = 1.0;
+        cnt[q] = 0;
+    }
+    canon_for<G>(K, sub, [&](int q, int k) {
+        const double num = (D[org[k]] - di) + tau[k];
+        double den;
+        if (k < i) den = D[k] - di;
+        else if (k < K - 1) den = D[k + 1] - di;
+        else den = 1.0;
+        pn[q] *= num;
+        pd[q] *= den;
+        if (++cnt[q] == 8) {
+            prod[q] *= pn[q] / pd[q];
+            pn[q] = 1.0;
+            pd[q] = 1.0;
+            cnt[q] = 0;
+        }
+    });
+#pragma unroll
+    for (int q = 0; q < M; ++q) prod[q] *= pn[q] / pd[q];
+    const double z2 = Canon<G>::prod(prod) / rho;
+    const double zi = sqrt(fmax(z2, 0.0));
+    return (Z[i] < 0.0) ? -zi : zi;
+}
+
+// root_rows with canonical partial sums.
+template <int G>
+__device__ __forceinline__ void root_rows_c(int K, const double* __restrict__ D, const double* __restrict__ zh,
+                                            const double* __restrict__ RL, const double* __restrict__ RH, int org,
+                                            double tau, int sub, double* bl_out, double* bh_out) {
+    constexpr int M = Canon<G>::M;
+    const double Do = D[org];
+    double ss[M], bl[M], bh[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) ss[q] = bl[q] = bh[q] = 0.0;
+    canon_for<G>(K, sub, [&](int q, int i) {
+        const double y = zh[i] * rcp_nr((D[i] - Do) - tau);
+        ss[q] = fma(y, y, ss[q]);
+        bl[q] = fma(RL[i], y, bl[q]);
+        bh[q] = fma(RH[i], y, bh[q]);
+    });
+    const double inv = 1.0 / sqrt(Canon<G>::sum(ss));
+    *bl_out = Canon<G>::sum(bl) * inv;
+    *bh_out = Canon<G>::sum(bh) * inv;
+}
+
 // cbase: the first of the four counters (terms, Loewner pairs, row pairs,
 // roots) that single out this kernel's share of the work.
 template <int NT, int G>
@@ -1301,7 +1497,7 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     for (int k = grp; k < K; k += ng) {
         int o;
         double tau;
-        const int it = secular_root<RedGroup<G>>(k, K, sD, sZ, sW, rho, sub, G, w.sec_cap, &o, &tau);
+        const int it = secular_root_c<G>(k, K, sD, sZ, sW, rho, sub, w.sec_cap, &o, &tau);
         if (it < 0) bad = 1;
         if (sub == 0) {
             sO[k] = o;
@@ -1320,7 +1516,7 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     }
     if (!(R.flags & MF_ROOT) || w.rows_out) {
         for (int i = grp; i < K; i += ng) {
-            const double zh = lowner_z<RedGroup<G>>(i, K, sD, sZ, sO, sT, rho, sub, G);
+            const double zh = lowner_z_c<G>(i, K, sD, sZ, sO, sT, rho, sub);
             if (sub == 0) {
                 sH[i] = zh;
                 w.zhat[ks + i] = zh;
@@ -1330,7 +1526,7 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
         __syncthreads();
         for (int k = grp; k < K; k += ng) {
             double bl, bh;
-            root_rows<RedGroup<G>>(K, sD, sH, sL, sR, sO[k], sT[k], sub, G, &bl, &bh);
+            root_rows_c<G>(K, sD, sH, sL, sR, sO[k], sT[k], sub, &bl, &bh);
             if (sub == 0) {
                 w.PBL[ks + k] = bl;
                 w.PBH[ks + k] = bh;
@@ -1349,18 +1545,22 @@ __device__ __forceinline__ void small_merge_body(const MergeRec& R, int K, long 
     count_add(w.counters, cbase + 3, roots);
 }
 
-// LDS staging of one merge's active arrays for the fused root steps.
-struct SmallStage {
-    double D[kFuseMax], W[kFuseMax], Z[kFuseMax], T[kFuseMax], H[kFuseMax], L[kFuseMax], R[kFuseMax];
-    int O[kFuseMax];
+// LDS staging of one merge's active arrays for the fused root steps (room
+// for CAP active columns).
+template <int CAP>
+struct SmallStageT {
+    double D[CAP], W[CAP], Z[CAP], T[CAP], H[CAP], L[CAP], R[CAP];
+    int O[CAP];
 };
+using SmallStage = SmallStageT<kFuseMax>;
 
-// Roots, Loewner z and rows of one merge with 1 <= K <= kFuseMax active
-// columns at active index ks (the whole workgroup; block-uniform arguments).
-template <int NT>
+// Roots, Loewner z and rows of one merge with 1 <= K <= CAP active columns at
+// active index ks (the whole workgroup; block-uniform arguments).  gmax caps
+// the lanes per root (4, 8 or 16); the results do not depend on it.
+template <int NT, class Stage>
 __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long long ks, const double* e,
                                                   const unsigned long long* __restrict__ pmax, const Work& w,
-                                                  SmallStage& sg, int cbase) {
+                                                  Stage& sg, int cbase, int gmax) {
     for (int i = threadIdx.x; i < K; i += NT) {
         sg.D[i] = w.Da[ks + i];
         sg.W[i] = w.Wa[ks + i];
@@ -1371,28 +1571,31 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     double sgn;
     const double rho = merge_rho(R, e, pmax, &sgn);
     __syncthreads();
-    // lanes per root from the merge alone: G = min(16, 1024 / K) (a root's
-    // sweeps are latency-bound chains, so more lanes per root pay even when a
-    // 512-thread workgroup then takes two passes over the roots: measured on
-    // single solves and large batches against 512 / K and 2048 / K)
-    const int ref = 2 * kFuseThreads;
-    if (K * 16 <= ref) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
-    else if (K * 8 <= ref) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
-    else if (K * 4 <= ref) small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
-    else if (K * 2 <= ref) small_merge_body<NT, 2>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
-    else small_merge_body<NT, 1>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    // lanes per root: min(16, 1024 / K) rounded down to a power of two, at
+    // least 4 (a root's sweeps are latency-bound chains, so on levels of few
+    // merges more lanes per root pay even when the workgroup then takes
+    // several passes over the roots), capped by gmax (levels of many merges
+    // are throughput-bound: fewer lanes per root repeat less of each root's
+    // update); the canonical sums make the choice invisible in the results
+    const int gk = (K * 16 <= 1024) ? 16 : ((K * 8 <= 1024) ? 8 : 4);
+    const int G = gk < gmax ? gk : gmax;
+    if (G >= 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else if (G >= 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    else small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
 }
 
-template <int NT>
+// One workgroup of NT threads per merge of the level; CAP >= the level's
+// largest merge (so >= every K), staged in LDS.
+template <int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__ mr, const double* __restrict__ e,
-                                                    const unsigned long long* __restrict__ pmax, Work w) {
+                                                    const unsigned long long* __restrict__ pmax, Work w, int gmax) {
     if (input_nonfinite(w)) return;
     const MergeRec R = mr[blockIdx.x];
     const MergeSpan sp = merge_span(R, w.scan);
     const int K = sp.K;
-    if (K < 1 || K > kFuseMax) return;  // block-uniform
-    __shared__ SmallStage sg;
-    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS);
+    if (K < 1 || K > kFuseMax || K > CAP) return;  // block-uniform
+    __shared__ SmallStageT<CAP> sg;
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -1420,9 +1623,10 @@ constexpr int kLevelBlockMaxMerges = 1024;
 static bool level_blocked(const LevelInfo& L) { return L.smax <= kFuseMax && L.M <= kLevelBlockMaxMerges; }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__ mr, const double* __restrict__ e,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_level_block(
+    const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                     const unsigned long long* __restrict__ pmax, Work w,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int gmax) {
     if (input_nonfinite(w)) return;
     __shared__ MergeRec sm[1];
     __shared__ int wsum[16];
@@ -1520,7 +1724,7 @@ __global__ __launch_bounds__(NT) void k_level_block(const MergeRec* __restrict__
     __syncthreads();
     // roots, Loewner z, rows
     const int K = v.scan[pk + s];
-    if (K >= 1) small_merge_solve<NT>(R, K, 0, e, pmax, v, sg, CNT_LB_TERMS);
+    if (K >= 1) small_merge_solve<NT>(R, K, 0, e, pmax, v, sg, CNT_LB_TERMS, gmax);
     __syncthreads();
     // the parent's spectrum and rows, or the problem's eigenvalues
     for (int i = threadIdx.x; i < s; i += NT) body_assemble(pk + i, 0, sm, pmax, v, out);
@@ -1798,17 +2002,22 @@ __global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ 
     }
 }
 
-// dL/dz of the negligible-z columns of non-top merges.
+// dL/dz of the negligible-z columns of non-top merges: G lanes per column
+// (the group splits the sum over the merge's roots).
+template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
     if (input_nonfinite(w)) return;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t >= N || w.st[t] != 0) return;
+    const long long t = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+    const int sub = (int)(threadIdx.x % G);
+    if (t >= N || w.st[t] != 0) return;  // group-uniform
     const MergeRec R = mr[merge_of(mr, blkm, t)];
     if (R.flags & MF_ROOT) return;
     const MergeSpan sp = merge_span(R, w.scan);
-    gr.gZ[t] = bwd_negligible_z<RedSerial>(sp.K, w.Da + sp.ks, w.org + sp.ks, w.tau + sp.ks, gr.coef + sp.ks, cstride,
-                                           w.D[t], w.RL[t], w.RH[t], gr.gRL[t], gr.gRH[t], 0, 1);
+    const double gz = bwd_negligible_z<RedGroup<G>>(sp.K, w.Da + sp.ks, w.org + sp.ks, w.tau + sp.ks,
+                                                    gr.coef + sp.ks, cstride, w.D[t], w.RL[t], w.RH[t], gr.gRL[t],
+                                                    gr.gRH[t], sub, G);
+    if (sub == 0) gr.gZ[t] = gz;
 }
 
 // dL/drho~ of each merge: sum_k gtot_k / (rho^2 N_k^2), one workgroup per merge.
@@ -1834,13 +2043,16 @@ __global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ m
     }
 }
 
+// One run per group of G lanes (grid-stride over the candidates).
+template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
     if (input_nonfinite(w)) return;
     const long long total = w.scanC[N];
-    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x)
-        body_bwd_runs<RedSerial>(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr, cstride);
+    const int sub = (int)(threadIdx.x % G);
+    const long long stride = (long long)gridDim.x * (blockDim.x / G);
+    for (long long g = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G; g < total; g += stride)
+        body_bwd_runs<RedGroup<G>>(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr, cstride, sub, G);
 }
 
 __global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
@@ -2018,17 +2230,43 @@ static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw) {
     *nbw = (int)wb;
 }
 
+// Lanes per root of the fused small merges on a level of M merges: a
+// caller's cap, else 16 when the level has few merges (latency-bound: every
+// lane of a root's group shortens its sweeps) and 4 when it has many
+// (throughput-bound: fewer lanes repeat less of each root's update).
+constexpr int kFewMerges = 512;
+static int fused_gmax(int M, int group_max) {
+    if (group_max > 0) return group_max;
+    return M < kFewMerges ? 16 : 4;
+}
+
+// Fused small merges of one level: a workgroup per merge, its shape from the
+// level's largest merge (LDS room and threads for that many active columns).
+static void launch_small(int smax, const MergeRec* mr, int M, const double* e, const Work& w, int gmax,
+                         void* stream) {
+    const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    const unsigned g = (unsigned)M;
+    if (smax >= kFuseWideS)
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<2 * kFuseThreads, kFuseMax>), g, 2 * kFuseThreads, stream, mr, e, pm,
+                     w, gmax);
+    else if (smax > 256)
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w,
+                     gmax);
+    else if (smax > 128)
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<256, 256>), g, 256, stream, mr, e, pm, w, gmax);
+    else if (smax > 64)
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 128>), g, 128, stream, mr, e, pm, w, gmax);
+    else
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax);
+}
+
 template <int G>
 static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                           const Work& w, void* stream) {
+                           const Work& w, int gmax, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = kFuseMax;
     // merges with at most kFuseMax active roots: one workgroup each
-    if (smax >= kFuseWideS)
-        TDE_LAUNCH_K(KIND_SMALL, k_small_merge<2 * kFuseThreads>, (unsigned)M, 2 * kFuseThreads, stream, mr, e, pm,
-                     w);
-    else
-        TDE_LAUNCH_K(KIND_SMALL, k_small_merge<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e, pm, w);
+    launch_small(smax, mr, M, e, w, gmax, stream);
     if (smax <= kFuseMax) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
@@ -2059,13 +2297,13 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
 }
 
 static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                         const Work& w, void* stream) {
+                         const Work& w, int gmax, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, stream); break;
-        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, stream); break;
-        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, stream); break;
-        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, stream); break;
-        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, stream); break;
+        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
+        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
+        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
+        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
+        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
     }
 }
 
@@ -2169,12 +2407,12 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             // every merge of the level fits one workgroup: the whole merge in one launch
             // (with a checkpoint, its roots land at the merge's packed positions)
             TDE_LAUNCH_K(KIND_LEVEL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
-                         (const unsigned long long*)w.pmax, wl, out);
+                         (const unsigned long long*)w.pmax, wl, out, fused_gmax(M, p.group_max));
             continue;
         }
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
-        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, stream);
+        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max), stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
     }
@@ -2196,6 +2434,17 @@ static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* 
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
 }
 
+// The couplings deflation drops (negligible columns, rotated runs), G lanes
+// per column or run.
+template <int G>
+static void launch_bwd_defl(long long N, const MergeRec* mr, const int* blkm, const Work& w,
+                            const Grad& gr, long long cs, void* stream) {
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl<G>, nblk(N * G, kWG), kWG, stream, mr, blkm, N, w, gr, cs);
+    const unsigned gr_runs = nblk(N * G, kWG);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs<G>, gr_runs < 4096u * G ? gr_runs : 4096u * G, kWG, stream, mr, blkm, N,
+                 w, gr, cs);
+}
+
 int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
                      const double* e, const double* gin, double* gd, double* ge, void* stream) {
     if (p.ntot == 0) return 0;
@@ -2211,7 +2460,6 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
         const int M = L.M;
         const long long N = L.N;
         const unsigned nb = nblk(N, kWG);
-        const unsigned gstride = nb < 4096u ? nb : 4096u;
         const long long so = (long long)hh * ck.n;
         Work wl = level_work(w, p.ntot, hh);
         wl.lam = ck.lam + so;
@@ -2235,10 +2483,15 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
             case 8: launch_bwd_roots_g<8>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
             default: launch_bwd_roots_g<16>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
         }
-        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl, nb, kWG, stream, mr, blkm, N, wl, gr, cs);
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_grho, (unsigned)M, kWG, stream, mr, e, (const unsigned long long*)w.pmax, wl,
                      gr, cs, L.mstart);
-        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs, gstride, kWG, stream, mr, blkm, N, wl, gr, cs);
+        switch (lanes_per_root(L.smax, p.sweep_cols)) {
+            case 1: launch_bwd_defl<1>(N, mr, blkm, wl, gr, cs, stream); break;
+            case 2: launch_bwd_defl<2>(N, mr, blkm, wl, gr, cs, stream); break;
+            case 4: launch_bwd_defl<4>(N, mr, blkm, wl, gr, cs, stream); break;
+            case 8: launch_bwd_defl<8>(N, mr, blkm, wl, gr, cs, stream); break;
+            default: launch_bwd_defl<16>(N, mr, blkm, wl, gr, cs, stream); break;
+        }
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax,
                      wl, gr);
     }

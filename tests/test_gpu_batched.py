@@ -90,3 +90,31 @@ def test_c4_batched_4096(tde):
         _check_problem(batch, lam, b, full=b in full)
         if b in full:
             _check_problem(batch, lam, b, full=False)
+
+
+@pytest.mark.parametrize("fam", ["uniform", "toeplitz", "clustered"])
+def test_group_max_does_not_change_results(tde, fam):
+    """The fused small merges sum in one fixed tree whatever the lanes per
+    root: every group_max gives the same bits, single and batched."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    d, e = tdgen.tridiag(fam, 9000)
+    dv, ev = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+    tol = GATE * tdgen.tnorm1(d, e)
+    exact = oracle.eigvals(d, e)
+    for kw in ({}, {"leaf": 64, "leaf_dc": True}, {"leaf": 16}):
+        ref = None
+        for gm in (None, 4, 8, 16):
+            _step(f"group_max={gm} {fam} {kw}")
+            lam = tde.eigvals(dv, ev, group_max=gm, **kw).cpu().numpy()
+            if ref is None:
+                ref = lam
+                assert np.abs(lam - exact).max() <= tol
+            else:
+                assert np.array_equal(lam, ref), (gm, kw)
+    batch = tdgen.batched(fam if fam != "toeplitz" else "uniform", count=300, lo=32, hi=1500, inst=5)
+    bd, be = torch.from_numpy(batch.d).to(dev), torch.from_numpy(batch.e).to(dev)
+    outs = [tde.eigvals_batched(bd, be, batch.offsets, group_max=gm).cpu().numpy() for gm in (None, 4, 8, 16)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
