@@ -12,6 +12,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``exact_charpoly_roots`` -- brute force for tiny n: exact rational
   characteristic polynomial of the dense matrix (Faddeev-LeVerrier), roots by
   ``mpmath.polyroots`` at 60+ digits.  Pins the bisection oracle.
+* ``householder_tridiagonal`` / ``dense_eigvals`` -- textbook Householder
+  reduction of a dense symmetric matrix to tridiagonal form (the reduction
+  phase of dense EVD, Section 2.1), then bisection.
 * ``grad_reference`` -- dense Hellmann-Feynman gradient of L = sum_k w_k lambda_k:
   dL/dd_i = sum_k w_k q_ik^2, dL/de_i = sum_k 2 w_k q_ik q_(i+1)k, with Q from
   LAPACK (``scipy.linalg.eigh_tridiagonal``).
@@ -305,3 +308,49 @@ def row_weights_interlacing(d, e, r):
             ratio *= (lam[k] - a) / (lam[k] - b)
         out[k] = ratio
     return out
+
+
+# ----------------------------------------------------------------------------
+# Dense front end: reduction of a symmetric matrix to tridiagonal form.
+# ----------------------------------------------------------------------------
+
+def householder_tridiagonal(A):
+    """Orthogonal reduction of a real symmetric A to tridiagonal T = H^T A H
+    (the reduction phase of dense symmetric EVD, Section 2.1: the eigenvalues
+    of T are those of A).  Textbook Householder reduction in FP64, one
+    reflector per column: for column k, H_k = I - beta v v^T maps A[k+1:, k]
+    onto a multiple of e_1 and is applied from both sides to the trailing
+    block (p = beta B v, w = p - (beta/2)(p^T v) v, B <- B - v w^T - w v^T).
+    Returns (d, e): the diagonal and subdiagonal of T."""
+    A = np.array(A, dtype=np.float64, copy=True)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    for k in range(n - 2):
+        x = A[k + 1:, k].copy()
+        nx = np.linalg.norm(x)
+        if nx == 0.0:
+            continue
+        alpha = -nx if x[0] >= 0.0 else nx
+        v = x
+        v[0] -= alpha
+        vv = float(v @ v)
+        if vv == 0.0:
+            continue
+        beta = 2.0 / vv
+        B = A[k + 1:, k + 1:]
+        p = beta * (B @ v)
+        w = p - (0.5 * beta * float(p @ v)) * v
+        B -= np.outer(v, w) + np.outer(w, v)
+        A[k + 1:, k] = 0.0
+        A[k, k + 1:] = 0.0
+        A[k + 1, k] = alpha
+        A[k, k + 1] = alpha
+    return np.diag(A).copy(), np.diag(A, -1).copy()
+
+
+def dense_eigvals(A):
+    """Eigenvalues (ascending) of a dense real symmetric A: Householder
+    reduction to tridiagonal form, then Sturm bisection (eigvals)."""
+    d, e = householder_tridiagonal(A)
+    return eigvals(d, e)

@@ -341,3 +341,45 @@ def test_selected_rows_boundary_and_gauss():
     _, Qs = oracle.selected_rows(np.zeros(n), k / np.sqrt(4.0 * k * k - 1.0), [0])
     _, wgt = np.polynomial.legendre.leggauss(n)
     assert np.abs(2.0 * Qs[0] ** 2 - wgt).max() <= 1e-13
+
+
+# --- dense front end (reduction to tridiagonal form) --------------------------
+
+def _prescribed(n, seed, spread=1.0):
+    g = np.random.default_rng(seed)
+    Q, R = np.linalg.qr(g.standard_normal((n, n)))
+    Q = Q * np.sign(np.diag(R))[None, :]
+    lam = np.sort(g.uniform(-spread, spread, n))
+    return Q @ np.diag(lam) @ Q.T, lam
+
+
+@pytest.mark.parametrize("n", [3, 5, 40, 200])
+def test_dense_reduction_prescribed_spectrum(n):
+    """A = Q diag(lambda) Q^T with a random orthogonal Q: the reduced
+    tridiagonal has exactly the prescribed eigenvalues (to the reduction's
+    rounding), and trace and Frobenius norm are kept."""
+    A, lam = _prescribed(n, 7 + n)
+    A = 0.5 * (A + A.T)
+    d, e = oracle.householder_tridiagonal(A)
+    assert d.shape == (n,) and e.shape == (n - 1,)
+    got = oracle.eigvals(d, e)
+    assert np.abs(got - lam).max() <= 64 * n * np.finfo(float).eps * np.abs(lam).max()
+    assert abs(d.sum() - np.trace(A)) <= 1e-12 * n
+    assert abs((d @ d + 2 * e @ e) - np.sum(A * A)) <= 1e-12 * np.sum(A * A)
+
+
+def test_dense_reduction_special_cases():
+    """A tridiagonal input stays tridiagonal up to the signs of e; n = 1, 2
+    need no reflector; 2 J - I (J the 3 x 3 all-ones matrix) has eigenvalues
+    5, -1, -1."""
+    d0, e0 = tdgen.tridiag("uniform", 30, cfg=tdgen.CFG_TEST)
+    T = np.diag(d0) + np.diag(e0, 1) + np.diag(e0, -1)
+    d, e = oracle.householder_tridiagonal(T)
+    assert np.abs(d - d0).max() <= 1e-15 and np.abs(np.abs(e) - np.abs(e0)).max() <= 1e-15
+    d, e = oracle.householder_tridiagonal(np.array([[3.0]]))
+    assert d.tolist() == [3.0] and e.size == 0
+    d, e = oracle.householder_tridiagonal(np.array([[1.0, 2.0], [2.0, -1.0]]))
+    assert d.tolist() == [1.0, -1.0] and e.tolist() == [2.0]
+    A = 2.0 * np.ones((3, 3)) - np.eye(3)
+    lam = oracle.dense_eigvals(A)
+    assert np.abs(lam - np.array([-1.0, -1.0, 5.0])).max() <= 1e-14
