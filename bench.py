@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--leaf-dc", action="store_true", help="with --leaf: solve leaves by divide and conquer "
                     "inside one wave")
+    ap.add_argument("--group-max", type=int, default=0, help="most lanes per root in the fused small merges "
+                    "(4, 8, 16; 0 = by level)")
+    ap.add_argument("--wide-blocks", type=int, default=0, help="most workgroups of a wide-sweep launch "
+                    "(0 = library default)")
     ap.add_argument("--wide-min", type=int, default=0, help="active roots from which a merge uses the wide "
                     "secular sweep (0 = library default)")
     ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
@@ -65,6 +69,8 @@ def parse():
                     help="time (and let a profiler see) only the reverse-mode step of one gradient workload: "
                          "checkpointing forward + backward, n = 8192 or 256 x 1024, with --leaf, --sweep-cols "
                          "and --wide-min (defaults 8, 16, 1024)")
+    ap.add_argument("--dense", type=int, default=0, metavar="N",
+                    help="time only the dense front end (reduction + solve) on an N x N matrix")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, run one plain device-to-device copy of MIB MiB (a kernel of known traffic "
                          "that hardware-counter runs use to scale FETCH_SIZE / WRITE_SIZE)")
@@ -372,7 +378,8 @@ def grad_ratio(tde, dev, reps=20):
         out = torch.empty(n, dtype=torch.float64, device=dev)
         # the forward alone: its fastest configuration (any leaf solver)
         r = autotune.tune(d, e, offs, reps=3)
-        fcfg = dict(leaf=r["leaf"], sweep_cols=r["sweep_cols"], wide_min=r["wide_min"], leaf_dc=r["leaf_dc"])
+        fcfg = dict(leaf=r["leaf"], sweep_cols=r["sweep_cols"], wide_min=r["wide_min"], leaf_dc=r["leaf_dc"],
+                    group_max=r["group_max"] or None, wide_blocks=r["wide_blocks"] or None)
 
         def fwd():
             if offs is None:
@@ -429,9 +436,10 @@ def _runs(step, warm=2, reps=5):
 
 # Launch configurations each secondary workload is timed with (the best is
 # reported with its configuration): in-wave leaves of 64 with three sweep
-# shapes, and QL leaves of 32.
+# shapes (one with a small wide-sweep grid), and QL leaves of 32.
 SECONDARY_CFGS = ({"leaf": 64, "leaf_dc": True, "sweep_cols": 32, "wide_min": 32},
                   {"leaf": 64, "leaf_dc": True, "sweep_cols": 16, "wide_min": 64},
+                  {"leaf": 64, "leaf_dc": True, "sweep_cols": 16, "wide_min": 64, "wide_blocks": 256},
                   {"leaf": 64, "leaf_dc": True, "sweep_cols": 64, "wide_min": 32},
                   {"leaf": 32, "leaf_dc": False, "sweep_cols": 32, "wide_min": 32})
 
@@ -570,6 +578,56 @@ def toeplitz_roofline(tde, dev, cfg, steps=5):
     return r
 
 
+def dense_record(tde, dev, n=4096, reps=3):
+    """Dense front end on a matrix with a prescribed spectrum: A = Q diag(lambda)
+    Q^T, Q a seeded random orthogonal matrix, lambda ~ U(-1, 1); Householder
+    reduction on the device plus the boundary-row solve.  Each timed step
+    starts from a fresh device copy of A (the reduction destroys it); the copy
+    is timed alone and subtracted.  The trailing-matrix products of the
+    reduction read sum_c 8 (n - c - 1)^2 bytes, the figure its HBM rate uses."""
+    import numpy as np
+    import torch
+
+    g = np.random.default_rng(np.random.SeedSequence([2605, 26599, 6, n]))
+    Q, R = np.linalg.qr(g.standard_normal((n, n)))
+    Q = Q * np.sign(np.diag(R))[None, :]
+    lam = np.sort(g.uniform(-1.0, 1.0, n))
+    A = Q @ (lam[:, None] * Q.T)
+    A = 0.5 * (A + A.T)
+    src = torch.from_numpy(A).to(dev)
+    work = torch.empty_like(src)
+
+    def copy():
+        work.copy_(src)
+
+    def solve():
+        work.copy_(src)
+        tde.dense_eigvals(work, overwrite=True, check=False)
+
+    solve()
+    torch.cuda.synchronize()
+    out = tde.dense_eigvals(src.clone(), overwrite=True).cpu().numpy()
+    tc = timed(copy, reps) / reps
+    ts = timed(solve, reps) / reps - tc
+    # the tridiagonal solve alone on the reduced (d, e)
+    _, d, e = tde.dense_eigvals(src.clone(), overwrite=True, return_tridiagonal=True)
+    o = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def tri():
+        tde.eigvals(d, e, out=o, check=False)
+
+    tri()
+    tt = timed(tri, reps) / reps
+    m = np.arange(n - 2, 0, -1, dtype=np.float64)
+    sym_bytes = float(8.0 * np.sum(m * m))
+    err = float(np.abs(out - lam).max())
+    norm1 = float(np.abs(A).sum(axis=0).max())
+    return {"workload": f"dense symmetric n={n}, prescribed spectrum U(-1,1), seeded random orthogonal Q",
+            "ms": ts, "eigvals_per_s": n / (ts / 1e3), "tridiagonal_solve_ms": tt, "reduction_ms": ts - tt,
+            "trailing_product_bytes": sym_bytes, "reduction_hbm_gbs_lower_bound": sym_bytes / ((ts - tt) * 1e-3) / 1e9,
+            "max_abs_err_vs_prescribed": err, "err_over_norm1": err / norm1, "gate_over_norm1": 2e-11}
+
+
 def split_prepass(tde, dev, reps=10):
     """Driver pre-pass on a reducible input: n = 65536 uniform with every 97th
     coupling zeroed (676 unreduced blocks), split solve against the plain one
@@ -614,6 +672,14 @@ def main():
     if args.grad:
         grad_only(args)
         return
+    if args.dense:
+        import torch
+
+        import paper_2605_26599_amd as tde
+
+        print(json.dumps(dense_record(tde, torch.device("cuda:0"), n=args.dense, reps=max(args.steps, 1))),
+              flush=True)
+        return
     import numpy as np
     import torch
 
@@ -628,14 +694,22 @@ def main():
         tde.set_defaults(wide_min=args.wide_min)
 
     def choose(d, e, offs, label):
-        """(leaf, sweep_cols, wide_min, leaf_dc): explicit flags, else the autotuner (untimed)."""
+        """Launch options: explicit flags, else the autotuner (untimed)."""
         if args.leaf or args.sweep_cols or args.no_tune:
-            return args.leaf or None, args.sweep_cols or None, args.wide_min or None, bool(args.leaf_dc)
+            return {"leaf": args.leaf or None, "sweep_cols": args.sweep_cols or None,
+                    "wide_min": args.wide_min or None, "leaf_dc": bool(args.leaf_dc),
+                    "group_max": args.group_max or None, "wide_blocks": args.wide_blocks or None}
         r = autotune.tune(d, e, offs, reps=3)
         tuning[label] = {"leaf": r["leaf"], "leaf_dc": r["leaf_dc"], "sweep_cols": r["sweep_cols"],
-                         "wide_min": r["wide_min"], "best_ms": r["ms"], "configs_tried": len(r["table"]),
-                         "tune_s": r["tune_s"]}
-        return r["leaf"], r["sweep_cols"], r["wide_min"], r["leaf_dc"]
+                         "wide_min": r["wide_min"], "group_max": r["group_max"], "wide_blocks": r["wide_blocks"],
+                         "best_ms": r["ms"], "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
+        return {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "wide_min": r["wide_min"], "leaf_dc": r["leaf_dc"],
+                "group_max": r["group_max"] or None, "wide_blocks": r["wide_blocks"] or None}
+
+    def describe(cfg):
+        return {"leaf": cfg["leaf"] or "default", "leaf_solver": "dc" if cfg["leaf_dc"] else "ql",
+                "sweep_cols": cfg["sweep_cols"] or "default", "wide_min": cfg["wide_min"] or "default",
+                "group_max": cfg["group_max"] or "by level", "wide_blocks": cfg["wide_blocks"] or "default"}
 
     def make_batched():
         batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)
@@ -643,21 +717,19 @@ def main():
         e = torch.from_numpy(batch.e).to(dev)
         out = torch.empty(int(batch.offsets[-1]), dtype=torch.float64, device=dev)
         offs = batch.offsets
-        bleaf, bcols, bwide, bdc = choose(d, e, offs, "batched")
+        bcfg = choose(d, e, offs, "batched")
 
         def step():
-            tde.eigvals_batched(d, e, offs, leaf=bleaf, sweep_cols=bcols, wide_min=bwide, leaf_dc=bdc, out=out,
-                                check=False)
+            tde.eigvals_batched(d, e, offs, out=out, check=False, **bcfg)
 
-        return batch, step, (bleaf, bcols, bwide, bdc)
+        return batch, step, bcfg
 
     if args.batched:
-        batch, step, (leaf, cols, wide, dc) = make_batched()
+        batch, step, cfg = make_batched()
         n_cols = int(batch.offsets[-1])
         workload = {"workload": f"batched: 4096 tridiagonals, sizes log-uniform in [32,4096] "
                                 f"({n_cols} columns), d,e ~ U(-1,1)", "problems": 4096, "columns": n_cols,
-                    "leaf": leaf or "default", "leaf_solver": "dc" if dc else "ql",
-                    "sweep_cols": cols or "default", "wide_min": wide or "default"}
+                    **describe(cfg)}
         metric, unit, per_step = "batched solves/s", "solves/s", 4096
         dn = en = None
     else:
@@ -667,14 +739,13 @@ def main():
         e = torch.from_numpy(en).to(dev)
         out = torch.empty(n, dtype=torch.float64, device=dev)
         n_cols = n
-        leaf, cols, wide, dc = choose(d, e, None, "single")
+        cfg = choose(d, e, None, "single")
 
         def step():
-            tde.eigvals(d, e, leaf=leaf, sweep_cols=cols, wide_min=wide, leaf_dc=dc, out=out, check=False)
+            tde.eigvals(d, e, out=out, check=False, **cfg)
 
         workload = {"workload": f"single tridiagonal n={n}, family {args.family} (seeded synthetic)", "n": n,
-                    "leaf": leaf or "default", "leaf_solver": "dc" if dc else "ql",
-                    "sweep_cols": cols or "default", "wide_min": wide or "default"}
+                    **describe(cfg)}
         metric, unit, per_step = f"FP64 tridiag eigvals/s @n={n}", "eigvals/s", n
 
     for _ in range(args.warmup):
@@ -749,6 +820,7 @@ def main():
         sec["batched_ms_per_step"] = bms
         sec["grad_fwd_bwd_over_fwd"] = grad_ratio(tde, dev)
         sec["split_prepass"] = split_prepass(tde, dev)
+        sec["dense_front_end"] = dense_record(tde, dev)
         sec["configs"] = configs_record(tde, dev)
         sec["toeplitz_roofline"] = toeplitz_roofline(tde, dev, sec["configs"]["c2_toeplitz_n65536"]["config"])
     if not args.no_cpu and dn is not None:

@@ -77,10 +77,14 @@ typedef struct {
                        small cap forces that path from the host, for tests) */
     int group_max;  /* most lanes per root (4, 8 or 16) in the merges with at most
                        512 active roots, which run one workgroup per merge; 0 = by
-                       level (16 on levels of fewer than 512 merges, else 4).  The
+                       level (16 on levels of fewer than 1024 merges, else 4).  The
                        sums are formed in one fixed order whatever the lane count,
                        so this changes speed, not results */
-    int reserved[2]; /* must be 0 */
+    int wide_blocks; /* most workgroups of each wide-sweep launch, 0..2^20; 0 = default
+                       (4096).  Those launches loop over their 64-root items;
+                       fewer blocks cost less where they find no work, more keep
+                       more waves per compute unit where they carry the solve */
+    int reserved[1]; /* must be 0 */
 } tde_opts;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -183,6 +187,31 @@ size_t tde_selrows_workspace_bytes(int64_t n, int64_t m, const tde_opts* opts);
 int tde_eigvals_selrows(const double* d, const double* e, int64_t n, const int64_t* rows, int64_t m,
                         double* lambda, double* Q, void* ws, size_t ws_bytes, void* hip_stream,
                         const tde_opts* opts);
+
+/* Dense front end: eigenvalues of a dense real symmetric matrix.
+ *
+ * Dense symmetric EVD first reduces A to a tridiagonal T = Q^T A Q by
+ * orthogonal transformations, whose eigenvalues are those of A, and then
+ * solves T (Section 2.1); for eigenvalues only Q is not kept.  This entry
+ * point reduces A on the device (blocked Householder reflectors in panels of
+ * 32 columns: per column a reflector and the product of the trailing matrix
+ * with it, per panel one rank-64 update of the trailing matrix on the FP64
+ * matrix cores) and solves T by boundary-row divide and conquer.
+ *   A      [lda*n]  device, column-major, the whole symmetric matrix (both
+ *                   triangles, which must agree); destroyed: the reduction
+ *                   updates its trailing blocks in place
+ *   lda    >= n
+ *   lambda [n]      output eigenvalues of A, ascending (device)
+ *   d_out  [n], e_out [n-1]  device, may be NULL: the diagonal and subdiagonal of T
+ *   ws     ws_bytes >= tde_dense_workspace_bytes(n, opts) (device): the
+ *                   solver's workspace (first, so tde_get_status(ws) reads its
+ *                   status), then 64 n + 3 n + 32 doubles of reduction scratch
+ * Asynchronous on the stream; the reduction's kernels are enqueued one by
+ * one (three per column, one per panel).  Returns TDE_OK or a negative code.
+ * tde_dense_workspace_bytes returns 0 on a bad argument. */
+size_t tde_dense_workspace_bytes(int64_t n, const tde_opts* opts);
+int tde_dense_eigvals(double* A, int64_t n, int64_t lda, double* lambda, double* d_out, double* e_out, void* ws,
+                      size_t ws_bytes, void* hip_stream, const tde_opts* opts);
 
 /* Reverse mode (gradients of the eigenvalues).
  *

@@ -21,6 +21,7 @@ __all__ = [
     "eigvals_rows",
     "eigvals_selrows",
     "eigvals_noalloc",
+    "dense_eigvals",
     "eigvals_ckpt",
     "eigvals_backward",
     "differentiable_eigvals",
@@ -51,6 +52,8 @@ EXPORTS = (
     "tde_selrows_workspace_bytes",
     "tde_eigvals_split",
     "tde_eigvals_noalloc",
+    "tde_dense_workspace_bytes",
+    "tde_dense_eigvals",
     "tde_checkpoint_bytes",
     "tde_backward_workspace_bytes",
     "tde_eigvals_ckpt",
@@ -75,7 +78,7 @@ class TDEError(RuntimeError):
 class tde_opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
                 ("wide_min", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("group_max", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("wide_blocks", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 _lib = None
@@ -144,6 +147,10 @@ def lib():
         L.tde_selrows_workspace_bytes.restype = sz
         L.tde_eigvals_selrows.argtypes = [vp, vp, i64, i64p, i64, vp, vp, vp, sz, vp, optp]
         L.tde_eigvals_selrows.restype = ctypes.c_int
+        L.tde_dense_workspace_bytes.argtypes = [i64, optp]
+        L.tde_dense_workspace_bytes.restype = sz
+        L.tde_dense_eigvals.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp, optp]
+        L.tde_dense_eigvals.restype = ctypes.c_int
         L.tde_eigvals_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, optp]
         L.tde_eigvals_noalloc.restype = ctypes.c_int
         L.tde_status_string.argtypes = [ctypes.c_int]
@@ -170,23 +177,26 @@ TDE_FLAG_LEAF_DC = 2
 # max_sweeps: secular iterations allowed per root (a small value forces the
 # non-convergence status, for tests).
 # group_max: most lanes per root in the fused small merges (4, 8, 16; None = by level).
-_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None, "group_max": None}
+# wide_blocks: most workgroups of a wide-sweep launch (None = library default).
+_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None, "group_max": None, "wide_blocks": None}
 
 
-def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None, group_max=None):
+def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None, group_max=None, wide_blocks=None):
     _shape_defaults["wide_min"] = wide_min
     _shape_defaults["leaf_dc"] = leaf_dc
     _shape_defaults["max_sweeps"] = max_sweeps
     _shape_defaults["group_max"] = group_max
+    _shape_defaults["wide_blocks"] = wide_blocks
 
 
-def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None):
+def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None):
     wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
     leaf_dc = _shape_defaults["leaf_dc"] if leaf_dc is None else leaf_dc
     group_max = _shape_defaults["group_max"] if group_max is None else group_max
+    wide_blocks = _shape_defaults["wide_blocks"] if wide_blocks is None else wide_blocks
     max_sweeps = _shape_defaults["max_sweeps"]
     if (leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc
-            and max_sweeps is None and not group_max):
+            and max_sweeps is None and not group_max and not wide_blocks):
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
@@ -195,6 +205,7 @@ def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_
     o.wide_min = int(wide_min or 0)
     o.max_sweeps = int(max_sweeps or 0)
     o.group_max = int(group_max or 0)
+    o.wide_blocks = int(wide_blocks or 0)
     return ctypes.byref(o)
 
 
@@ -233,7 +244,7 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-            sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None) -> torch.Tensor:
+            sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
     off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
     replays a captured HIP graph of the whole solve (captured on first use for
@@ -255,7 +266,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
                                ws.data_ptr(), ws.numel(), stream,
-                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max))
+                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -267,7 +278,8 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-                    sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None) -> torch.Tensor:
+                    sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None,
+                    wide_blocks=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -289,7 +301,7 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
                                        ws.numel(), stream,
-                                       _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max))
+                                       _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:
@@ -327,6 +339,50 @@ def eigvals_noalloc(d: torch.Tensor, e: torch.Tensor, out: torch.Tensor | None =
     if rc != TDE_OK:
         raise TDEError(rc, "tde_eigvals_noalloc")
     return out
+
+
+def dense_eigvals(A: torch.Tensor, overwrite: bool = False, leaf=None, sweep_cols=None, wide_min=None,
+                  leaf_dc=None, return_tridiagonal: bool = False, check: bool = True):
+    """Eigenvalues (ascending) of a dense real symmetric matrix A (n x n float64
+    device tensor, both triangles): Householder reduction to tridiagonal form
+    on the device, then the boundary-row solve.  A symmetric matrix is its own
+    transpose, so torch's row-major storage serves as the column-major input.
+    overwrite=False reduces a copy; True lets the reduction destroy A.
+    return_tridiagonal=True also returns (d, e) of the reduced matrix."""
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.float64 or not A.is_cuda or A.dim() != 2:
+        raise TypeError("A must be a 2-D float64 CUDA (HIP) tensor")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    work = A if overwrite else A.clone()
+    if not work.is_contiguous():
+        raise ValueError("A must be contiguous")
+    lam = torch.empty(n, dtype=torch.float64, device=A.device)
+    d = torch.empty(n, dtype=torch.float64, device=A.device) if return_tridiagonal else None
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=A.device) if return_tridiagonal else None
+    opts = _opts(leaf, True, sweep_cols, wide_min, leaf_dc)
+    nb = int(lib().tde_dense_workspace_bytes(n, opts))
+    if nb == 0 and n > 0:
+        raise TDEError(TDE_EINVAL, "tde_dense_workspace_bytes")
+    key = ("dense", A.device.index, torch.cuda.current_stream(A.device).cuda_stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=A.device)
+        _ws_cache[key] = ws
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    with torch.cuda.device(A.device):
+        rc = lib().tde_dense_eigvals(work.data_ptr(), n, n, lam.data_ptr(), d.data_ptr() if d is not None else None,
+                                     e.data_ptr() if e is not None else None, ws.data_ptr(), ws.numel(), stream,
+                                     opts)
+        if rc != TDE_OK:
+            raise TDEError(rc, "tde_dense_eigvals")
+        if check and n > 0:
+            st = lib().tde_get_status(ws.data_ptr(), stream)
+            if st != TDE_OK:
+                raise TDEError(st, "tde_dense_eigvals device status")
+    if return_tridiagonal:
+        return lam, d, e[:max(n - 1, 0)]
+    return lam
 
 
 # --- driver pre-pass: split at negligible couplings ----------------------------

@@ -1,14 +1,18 @@
 """Autotuner for the solver's launch shape.
 
-Four knobs change speed but not the method: the leaf size (largest block of
+Knobs that change speed but not the method: the leaf size (largest block of
 the merge tree), how leaves are solved (QL, or their own divide and conquer
 inside one wave), the target number of poles each lane sweeps in the
-root-parallel kernels (which sets the lanes per root, G <= 16, per level) and
+root-parallel kernels (which sets the lanes per root, G <= 16, per level),
 the number of active roots from which a merge uses the wide sweeps (64 roots
-per workgroup, poles split over its waves).  `tune` times every combination
-on the device (graph replay, inputs resident) and keeps the fastest.  Results are cached in a JSON file keyed by the GPU
-architecture and a size bucket (log2 of the column count, batch or single),
-so later runs reuse them without re-timing.
+per workgroup, poles split over its waves), and two workgroup-shape knobs:
+the most lanes per root in the fused small merges (4, 8, 16, or chosen per
+level) and the most workgroups of a wide-sweep launch.  `tune` times every
+combination of the first four on the device (graph replay, inputs resident),
+then the shape knobs around the fastest, and keeps the fastest.  Results are
+cached in a JSON file keyed by the GPU architecture and a size bucket (log2
+of the column count, batch or single), so later runs reuse them without
+re-timing.
 """
 from __future__ import annotations
 
@@ -23,6 +27,8 @@ LEAVES = (2, 4, 8, 16, 32)     # QL leaves
 DC_LEAVES = (32, 64)           # leaves solved by divide and conquer inside one wave
 SWEEP_COLS = (8, 16, 32, 64)
 WIDE_MIN = (1024, 64, 32)
+# (group_max, wide_blocks) tried around the best of the grid above (0 = library default)
+SHAPES = ((0, 0), (4, 0), (16, 0), (0, 256), (0, 1024), (4, 256), (16, 256))
 
 
 def cache_path() -> str:
@@ -60,11 +66,13 @@ def _store(db: dict) -> None:
 
 
 def lookup(n_total: int, batch: int = 1, device=None):
-    """Cached (leaf, sweep_cols, wide_min, leaf_dc) for this size bucket, or None."""
+    """Cached (leaf, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks)
+    for this size bucket, or None."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     rec = _load().get(_arch(dev), {}).get(bucket(n_total, batch))
-    if rec and "leaf_dc" in rec:
-        return int(rec["leaf"]), int(rec["sweep_cols"]), int(rec["wide_min"]), bool(rec["leaf_dc"])
+    if rec and "wide_blocks" in rec:
+        return (int(rec["leaf"]), int(rec["sweep_cols"]), int(rec["wide_min"]), bool(rec["leaf_dc"]),
+                int(rec["group_max"]), int(rec["wide_blocks"]))
     return None
 
 
@@ -81,44 +89,53 @@ def _time(step, reps: int) -> float:
 
 
 def tune(d: torch.Tensor, e: torch.Tensor, offsets=None, reps: int = 5, leaves=LEAVES, sweep_cols=SWEEP_COLS,
-         wide_mins=WIDE_MIN, dc_leaves=DC_LEAVES, store: bool = True) -> dict:
-    """Time every (leaf, leaf solver, sweep_cols, wide_min) on this input;
+         wide_mins=WIDE_MIN, dc_leaves=DC_LEAVES, shapes=SHAPES, store: bool = True) -> dict:
+    """Time every (leaf, leaf solver, sweep_cols, wide_min) on this input, then
+    the workgroup-shape knobs (group_max, wide_blocks) around the fastest;
     return and cache the best.
 
     d, e are device tensors (single problem: e has n-1 entries; batch: offsets
     is the host offsets sequence).  Returns {"leaf", "leaf_dc", "sweep_cols",
-    "wide_min", "ms", "table": [(leaf, leaf_dc, cols, wide_min, ms), ...],
-    "tune_s"}.
+    "wide_min", "group_max", "wide_blocks", "ms", "table": [(leaf, leaf_dc,
+    cols, wide_min, group_max, wide_blocks, ms), ...], "tune_s"}.
     """
     import paper_2605_26599_amd as tde
 
     t0 = time.perf_counter()
     out = torch.empty(d.numel(), dtype=torch.float64, device=d.device)
     table = []
+
+    def run(leaf, dc, cols, wm, gm, wb):
+        if offsets is None:
+            def step():
+                tde.eigvals(d, e, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm, group_max=gm or None,
+                            wide_blocks=wb or None, out=out, check=False)
+        else:
+            def step():
+                tde.eigvals_batched(d, e, offsets, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm,
+                                    group_max=gm or None, wide_blocks=wb or None, out=out, check=False)
+        step()
+        step()
+        table.append((leaf, dc, cols, wm, gm, wb, _time(step, reps)))
+
     cands = [(leaf, False) for leaf in leaves] + [(leaf, True) for leaf in dc_leaves]
     for leaf, dc in cands:
         for cols in sweep_cols:
             for wm in wide_mins:
-                if offsets is None:
-                    def step(leaf=leaf, dc=dc, cols=cols, wm=wm):
-                        tde.eigvals(d, e, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm, out=out,
-                                    check=False)
-                else:
-                    def step(leaf=leaf, dc=dc, cols=cols, wm=wm):
-                        tde.eigvals_batched(d, e, offsets, leaf=leaf, leaf_dc=dc, sweep_cols=cols, wide_min=wm,
-                                            out=out, check=False)
-                step()
-                step()
-                table.append((leaf, dc, cols, wm, _time(step, reps)))
-    best = min(table, key=lambda r: r[4])
+                run(leaf, dc, cols, wm, 0, 0)
+    b = min(table, key=lambda r: r[6])
+    for gm, wb in shapes:
+        if (gm, wb) != (0, 0):
+            run(b[0], b[1], b[2], b[3], gm, wb)
+    best = min(table, key=lambda r: r[6])
     n_total = int(d.numel()) if offsets is None else int(offsets[-1])
     batch = 1 if offsets is None else len(offsets) - 1
-    res = {"leaf": best[0], "leaf_dc": best[1], "sweep_cols": best[2], "wide_min": best[3], "ms": best[4],
+    res = {"leaf": best[0], "leaf_dc": best[1], "sweep_cols": best[2], "wide_min": best[3],
+           "group_max": best[4], "wide_blocks": best[5], "ms": best[6],
            "table": table, "tune_s": time.perf_counter() - t0, "bucket": bucket(n_total, batch)}
     if store:
         db = _load()
-        db.setdefault(_arch(d.device), {})[res["bucket"]] = {"leaf": best[0], "leaf_dc": best[1],
-                                                            "sweep_cols": best[2], "wide_min": best[3],
-                                                            "ms": best[4]}
+        db.setdefault(_arch(d.device), {})[res["bucket"]] = {k: res[k] for k in (
+            "leaf", "leaf_dc", "sweep_cols", "wide_min", "group_max", "wide_blocks", "ms")}
         _store(db)
     return res

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtde.so")
 ARCH = os.environ.get("TDE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tde_kernels.hip", "tde_api.cpp", "tde_planner.cpp", "tde_noalloc.hip"]
+SOURCES = ["tde_kernels.hip", "tde_api.cpp", "tde_planner.cpp", "tde_noalloc.hip", "tde_dense.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

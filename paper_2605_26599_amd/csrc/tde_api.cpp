@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/tde.h"
+#include "tde_dense.h"
 #include "tde_plan.h"
 #include "tde_tree.h"
 
@@ -34,7 +35,7 @@ namespace {
 // ---------------------------------------------------------------------------
 std::recursive_mutex g_mu;
 
-using PlanKey = std::tuple<int, int, int, int, bool, int, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, int, bool, int, int, std::vector<long long>>;
 constexpr size_t kMaxPlans = 32;
 struct PlanEntry {
     PlanKey key;
@@ -46,7 +47,7 @@ std::map<PlanKey, std::list<PlanEntry>::iterator> g_plans;
 // Captured passes: one executable graph per (plan, pass kind, buffers).
 // Capture runs on an internal stream per device; replays run on the
 // caller's stream.
-enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2, PASS_ROWS = 3 };
+enum { PASS_SOLVE = 0, PASS_CKPT = 1, PASS_BACKWARD = 2, PASS_ROWS = 3, PASS_DENSE = 4 };
 using Bufs = std::array<const void*, 8>;
 using GraphKey = std::tuple<const Plan*, int, Bufs>;
 constexpr size_t kMaxGraphs = 64;
@@ -179,9 +180,9 @@ int run_pass(const Plan& plan, int kind, const Bufs& bufs, const tde_opts* opts,
 }
 
 // Caller holds g_mu.
-int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, const std::vector<long long>& offs,
-              Plan** out) {
-    PlanKey key{device, leaf, cols, wmin, dc, gmax, offs};
+int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, int wblocks,
+              const std::vector<long long>& offs, Plan** out) {
+    PlanKey key{device, leaf, cols, wmin, dc, gmax, wblocks, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         g_plan_lru.splice(g_plan_lru.begin(), g_plan_lru, it->second);
@@ -195,6 +196,7 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, const
     p->wide_min = wmin;
     p->leaf_dc = dc;
     p->group_max = gmax;
+    p->wide_blocks = wblocks;
     p->offs = offs;
     if (plan_host(p.get()) != 0) return TDE_EINVAL;
     auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
@@ -223,8 +225,8 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, const
 }
 
 int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr,
-                 int* cap = nullptr, int* gmax = nullptr) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0;
+                 int* cap = nullptr, int* gmax = nullptr, int* wblocks = nullptr) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0, Wb = 0;
     if (opts) {
         if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
@@ -232,11 +234,14 @@ int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr
         if (opts->wide_min != 0) W = opts->wide_min;
         if (opts->max_sweeps != 0) S = opts->max_sweeps;
         Gm = opts->group_max;
+        Wb = opts->wide_blocks;
         for (int r : opts->reserved)
             if (r != 0) return TDE_EINVAL;
     }
     if (Gm != 0 && Gm != 4 && Gm != 8 && Gm != 16) return TDE_EINVAL;
+    if (Wb < 0 || Wb > (1 << 20)) return TDE_EINVAL;
     if (gmax) *gmax = Gm;
+    if (wblocks) *wblocks = Wb;
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
     if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
     if (W < 2) return TDE_EINVAL;
@@ -276,12 +281,12 @@ int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* off
 }
 
 int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** plan) {
-    int leaf, cols, wmin, cap, gmax;
+    int leaf, cols, wmin, cap, gmax, wblocks;
     bool dc;
-    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap, &gmax) != TDE_OK) return TDE_EINVAL;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap, &gmax, &wblocks) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
-    return make_plan(device, leaf, cols, wmin, dc, gmax, offs, plan);
+    return make_plan(device, leaf, cols, wmin, dc, gmax, wblocks, offs, plan);
 }
 
 bool needs_e(const std::vector<long long>& offs) {
@@ -656,6 +661,46 @@ int tde_eigvals_selrows(const double* d, const double* e, int64_t n, const int64
                         double* lambda, double* Q, void* ws, size_t ws_bytes, void* hip_stream,
                         const tde_opts* opts) {
     return tde::selrows(d, e, (long long)n, rows, (long long)m, lambda, Q, ws, ws_bytes, hip_stream, opts);
+}
+
+size_t tde_dense_workspace_bytes(int64_t n, const tde_opts* opts) {
+    int leaf, cols;
+    if (n < 0 || n > (int64_t)0x3fffffff || tde::resolve_opts(opts, &leaf, &cols) != TDE_OK) return 0;
+    return tde::dense_layout(n, nullptr, nullptr) + tde::workspace_layout(n, 1, n, nullptr, nullptr);
+}
+
+int tde_dense_eigvals(double* A, int64_t n, int64_t lda, double* lambda, double* d_out, double* e_out, void* ws,
+                      size_t ws_bytes, void* hip_stream, const tde_opts* opts) {
+    int leaf, cols;
+    if (n < 0 || n > (int64_t)0x3fffffff || tde::resolve_opts(opts, &leaf, &cols) != TDE_OK) return TDE_EINVAL;
+    if (n == 0) return TDE_OK;
+    if (!A || !lambda || !ws || lda < n) return TDE_EINVAL;
+    // the solver's workspace first (its status word is where tde_get_status
+    // looks), the reduction's scratch after it
+    const size_t sb = tde::workspace_layout(n, 1, n, nullptr, nullptr);
+    if (ws_bytes < sb + tde::dense_layout(n, nullptr, nullptr)) return TDE_EINVAL;
+    tde::DenseWork dw{};
+    tde::dense_layout(n, (char*)ws + sb, &dw);
+    const std::vector<long long> offs{0, (long long)n};
+    {
+        // the reduction's launches (two per column) are captured once per
+        // (size, buffers) into a graph, like the solve's
+        std::lock_guard<std::recursive_mutex> lk(tde::g_mu);
+        tde::Plan* plan = nullptr;
+        const int rc = tde::get_plan(opts, offs, &plan);
+        if (rc != TDE_OK) return rc;
+        const tde::Bufs bufs{A, ws, (const void*)(intptr_t)lda, nullptr, nullptr, nullptr, nullptr, nullptr};
+        const int rr = tde::run_pass(*plan, tde::PASS_DENSE, bufs, opts, hip_stream, [&](void* s) {
+            return tde::enqueue_dense_reduce(A, lda, (int)n, dw, s);
+        });
+        if (rr != TDE_OK) return rr;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (d_out && hipMemcpyAsync(d_out, dw.d, 8 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return TDE_EDEVICE;
+    if (e_out && n > 1 && hipMemcpyAsync(e_out, dw.e, 8 * (size_t)(n - 1), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return TDE_EDEVICE;
+    return tde::solve(dw.d, dw.e, offs, lambda, ws, sb, hip_stream, opts);
 }
 
 size_t tde_checkpoint_bytes(const int64_t* offsets, int64_t B, const tde_opts* opts) {

@@ -1,0 +1,29 @@
+// Dense front end: blocked Householder reduction of a symmetric matrix to
+// tridiagonal form (Section 2.1), feeding the boundary-row solver.
+#pragma once
+#include <stddef.h>
+
+namespace tde {
+
+constexpr int kNb = 32;  // panel width (reflectors per trailing update)
+
+// Scratch of one reduction of an n x n matrix: the panel's reflectors V and
+// the matching W (n x kNb each, column-major, global row index), the product
+// y = A22 v, the panel's tau, and the tridiagonal's d[n], e[n].
+struct DenseWork {
+    double* V;
+    double* W;
+    double* y;
+    double* tau;
+    double* d;
+    double* e;
+};
+
+// Layout of DenseWork at base (size only when base == nullptr).
+size_t dense_layout(long long n, char* base, DenseWork* dw);
+
+// Enqueue the reduction of A (n x n, column-major, leading dimension lda,
+// both triangles, overwritten) to d, e of dw.
+int enqueue_dense_reduce(double* A, long long lda, int n, const DenseWork& dw, void* stream);
+
+}  // namespace tde

@@ -1,0 +1,286 @@
+// Dense front end: reduction of a real symmetric matrix to tridiagonal form
+// on the MI355X, then the boundary-row solve of the tridiagonal.
+//
+// Dense symmetric EVD first reduces A to T = Q^T A Q by orthogonal
+// transformations (the eigenvalues of T are those of A) and then solves the
+// tridiagonal problem (Section 2.1); for eigenvalues only the transformations
+// are not kept.  The reduction here is the blocked Householder scheme of
+// LAPACK's symmetric tridiagonal reduction (lower triangle, panel width kNb):
+// inside a panel, column c is brought up to date with the panel's earlier
+// reflectors, its reflector v (v_0 = 1) and tau are formed, and
+// w = tau (A22 v - V (W^T v) - W (V^T v)) + alpha v with
+// alpha = -tau/2 (w^T v) is taken against the trailing matrix as it stood at
+// the start of the panel; after the panel the trailing matrix receives the
+// rank-2b update A22 <- A22 - V W^T - W V^T as one matrix product on the FP64
+// matrix cores.  A is kept in full (both triangles), so the per-column
+// product A22 v reads whole columns (contiguous in memory, column-major):
+// y_r = A[:, r] . v, one wave per column r.
+//
+// Per column: k_trd_symv (one wave per trailing column), then k_trd_wcol
+// (one workgroup: the column's w and the next column's reflector); per panel:
+// k_trd_col for its first column and k_trd_syr2k.  The memory
+// traffic is dominated by the trailing-matrix reads of k_trd_symv (about
+// 8 n^3 / 3 bytes in all); the panel products are about 4 n^3 / 3 FLOP on
+// the matrix cores (both triangles).
+#include <hip/hip_runtime.h>
+
+#include "tde_dense.h"
+
+namespace tde {
+
+namespace {
+
+constexpr int kColThreads = 1024;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup (every thread gets it); red: one double per wave.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NT / 64; ++k) t += red[k];  // fixed order: every thread the same bits
+    return t;
+}
+
+// Column c = p + i: bring rows c..n-1 up to date with the panel's first i
+// reflectors, record the diagonal entry, and form the reflector of rows
+// c+1..n-1 (stored as column i of V with v_(c+1) = 1; tau[i]; e[c] = beta).
+// The whole workgroup (kColThreads threads) takes part.
+__device__ __forceinline__ void col_body(const double* __restrict__ A, long long lda, int n, int c, int i,
+                                         double* __restrict__ V, const double* __restrict__ W,
+                                         double* __restrict__ tau, double* __restrict__ d, double* __restrict__ e,
+                                         double* red, double* s_scale) {
+    const long long ln = n;
+    const double* __restrict__ col = A + (long long)c * lda;
+    double ssq = 0.0;
+    for (int r = c + (int)threadIdx.x; r < n; r += kColThreads) {
+        double a = col[r];
+        for (int j = 0; j < i; ++j)
+            a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
+        if (r == c) d[c] = a;
+        else V[i * ln + r] = a;
+        if (r >= c + 2) ssq = fma(a, a, ssq);
+    }
+    const double xn2 = block_sum<kColThreads>(ssq, red);  // barriers: V's column is complete
+    if (threadIdx.x == 0) {
+        const double alpha = V[i * ln + c + 1];
+        double t = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            const double nrm = sqrt(fma(alpha, alpha, xn2));
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        tau[i] = t;
+        e[c] = beta;
+        *s_scale = scale;
+    }
+    __syncthreads();
+    const double scale = *s_scale;
+    for (int r = c + 2 + (int)threadIdx.x; r < n; r += kColThreads) V[i * ln + r] *= scale;
+    if (threadIdx.x == 0) V[i * ln + c + 1] = 1.0;
+}
+
+__global__ __launch_bounds__(kColThreads) void k_trd_col(const double* __restrict__ A, long long lda, int n, int c,
+                                                        int i, double* __restrict__ V, const double* __restrict__ W,
+                                                        double* __restrict__ tau, double* __restrict__ d,
+                                                        double* __restrict__ e) {
+    __shared__ double red[kColThreads / 64];
+    __shared__ double s_scale;
+    col_body(A, lda, n, c, i, V, W, tau, d, e, red, &s_scale);
+}
+
+// y_r = A[c+1:, r] . v for every trailing column r (symmetric A: column r
+// holds row r), one wave per column; v is column i of V.
+__global__ __launch_bounds__(256) void k_trd_symv(const double* __restrict__ A, long long lda, int n, int c, int i,
+                                                 const double* __restrict__ V, double* __restrict__ y) {
+    const int r = c + 1 + (int)((blockIdx.x * 256 + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;  // wave-uniform
+    const double* __restrict__ col = A + (long long)r * lda;
+    const double* __restrict__ v = V + (long long)i * n;
+    double acc0 = 0.0, acc1 = 0.0;
+    int j = c + 1 + lane;
+    for (; j + 64 < n; j += 128) {
+        acc0 = fma(col[j], v[j], acc0);
+        acc1 = fma(col[j + 64], v[j + 64], acc1);
+    }
+    if (j < n) acc0 = fma(col[j], v[j], acc0);
+    const double s = wave_sum(acc0 + acc1);
+    if (lane == 0) y[r] = s;
+}
+
+// w = tau (y - V (W^T v) - W (V^T v)) over rows c+1..n-1, then
+// w += -tau/2 (w^T v) v; stored as column i of W.  The 2i dot products are
+// one per wave (wave-level reductions), the rest is row-parallel.
+__device__ __forceinline__ void w_body(int n, int c, int i, const double* __restrict__ V, double* __restrict__ W,
+                                       const double* __restrict__ y, const double* __restrict__ tau, double* sWv,
+                                       double* sVv, double* red) {
+    const long long ln = n;
+    const double* __restrict__ v = V + (long long)i * n;
+    const double t = tau[i];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = wid; q < 2 * i; q += kColThreads / 64) {
+        const double* __restrict__ u = (q < i) ? W + (long long)q * n : V + (long long)(q - i) * n;
+        double acc = 0.0;
+        for (int r = c + 1 + lane; r < n; r += 64) acc = fma(u[r], v[r], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (q < i) sWv[q] = acc;
+            else sVv[q - i] = acc;
+        }
+    }
+    __syncthreads();
+    double* __restrict__ wcol = W + (long long)i * n;
+    double wv = 0.0;
+    for (int r = c + 1 + (int)threadIdx.x; r < n; r += kColThreads) {
+        double a = y[r];
+        for (int j = 0; j < i; ++j) a -= V[j * ln + r] * sWv[j] + W[j * ln + r] * sVv[j];
+        a *= t;
+        wcol[r] = a;
+        wv = fma(a, v[r], wv);
+    }
+    const double alpha = -0.5 * t * block_sum<kColThreads>(wv, red);
+    for (int r = c + 1 + (int)threadIdx.x; r < n; r += kColThreads) wcol[r] = fma(alpha, v[r], wcol[r]);
+}
+
+// w of column c, then (next != 0) column c + 1 of the same panel: one
+// workgroup does both, so a column costs two launches (this and the
+// trailing product).
+__global__ __launch_bounds__(kColThreads) void k_trd_wcol(const double* __restrict__ A, long long lda, int n, int c,
+                                                         int i, double* __restrict__ V, double* __restrict__ W,
+                                                         const double* __restrict__ y, double* __restrict__ tau,
+                                                         double* __restrict__ d, double* __restrict__ e, int next) {
+    __shared__ double sWv[kNb], sVv[kNb];
+    __shared__ double red[kColThreads / 64];
+    __shared__ double s_scale;
+    w_body(n, c, i, V, W, y, tau, sWv, sVv, red);
+    if (!next) return;  // block-uniform
+    __syncthreads();    // column i of W is complete
+    col_body(A, lda, n, c + 1, i + 1, V, W, tau, d, e, red, &s_scale);
+}
+
+// Trailing update A[q:, q:] -= V W^T + W V^T (rows and columns q..n-1, both
+// triangles) on the FP64 matrix cores.  With U = [V | W] and Z = [W | V]
+// (n x 2b) the update is U Z^T.  One wave per 32 x 32 tile of A, as 2 x 2
+// blocks of V_MFMA_F64_16X16X4F64 (D = A_op B_op + C, A_op 16 x 4, B_op
+// 4 x 16): A_op[i][k] = Z[s0 + i][k], B_op[k][j] = U[r0 + j][k], so
+// D[i][j] is the update of A[r0 + j][s0 + i]; lane l supplies A_op[l % 16][l / 16]
+// and B_op[l / 16][l % 16] and holds D[4 t + l / 16][l % 16] in its register
+// t = 0..3, i.e. row r0 + l % 16 of column s0 + 4 t + l / 16: sixteen lanes
+// touch sixteen consecutive rows of one column.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_trd_syr2k(double* __restrict__ A, long long lda, int n, int q, int b,
+                                                  const double* __restrict__ V, const double* __restrict__ W,
+                                                  int tiles) {
+    const int wave = (int)((blockIdx.x * 256 + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    const int tr = wave % tiles, tc = wave / tiles;
+    if (tc >= tiles) return;  // wave-uniform
+    const int r0 = q + 32 * tr, s0 = q + 32 * tc;
+    const long long ln = n;
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb) acc[a][bb] = v4d{0.0, 0.0, 0.0, 0.0};
+    // rows of this lane's operands (out-of-range rows contribute zero)
+    const int sr0 = s0 + li, sr1 = s0 + 16 + li;  // Z rows (A operand), blocks ib = 0, 1
+    const int ur0 = r0 + li, ur1 = r0 + 16 + li;  // U rows (B operand), blocks jb = 0, 1
+    for (int k0 = 0; k0 < 2 * b; k0 += 4) {
+        const int k = k0 + lk;
+        double za0 = 0.0, za1 = 0.0, ub0 = 0.0, ub1 = 0.0;
+        if (k < 2 * b) {
+            // Z = [W | V], U = [V | W]
+            const double* __restrict__ zc = (k < b) ? W + (long long)k * ln : V + (long long)(k - b) * ln;
+            const double* __restrict__ uc = (k < b) ? V + (long long)k * ln : W + (long long)(k - b) * ln;
+            if (sr0 < n) za0 = zc[sr0];
+            if (sr1 < n) za1 = zc[sr1];
+            if (ur0 < n) ub0 = uc[ur0];
+            if (ur1 < n) ub1 = uc[ur1];
+        }
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(za0, ub0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(za0, ub1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(za1, ub0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(za1, ub1, acc[1][1], 0, 0, 0);
+    }
+    for (int ib = 0; ib < 2; ++ib)
+        for (int jb = 0; jb < 2; ++jb) {
+            const int r = r0 + 16 * jb + li;
+            if (r >= n) continue;
+            for (int t = 0; t < 4; ++t) {
+                const int s = s0 + 16 * ib + 4 * t + lk;
+                if (s < n) A[(long long)s * lda + r] -= acc[ib][jb][t];
+            }
+        }
+}
+
+// The last 2 x 2 (or 1 x 1) block after every update.
+__global__ void k_trd_tail(const double* __restrict__ A, long long lda, int n, double* __restrict__ d,
+                           double* __restrict__ e) {
+    if (threadIdx.x != 0 || n < 1) return;
+    if (n == 1) {
+        d[0] = A[0];
+        return;
+    }
+    d[n - 2] = A[(long long)(n - 2) * lda + (n - 2)];
+    d[n - 1] = A[(long long)(n - 1) * lda + (n - 1)];
+    e[n - 2] = A[(long long)(n - 2) * lda + (n - 1)];
+}
+
+}  // namespace
+
+size_t dense_layout(long long n, char* base, DenseWork* dw) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const long long nn = n > 0 ? n : 1;
+    DenseWork t{};
+    t.V = (double*)take(8 * nn * kNb);
+    t.W = (double*)take(8 * nn * kNb);
+    t.y = (double*)take(8 * nn);
+    t.tau = (double*)take(8 * kNb);
+    t.d = (double*)take(8 * nn);
+    t.e = (double*)take(8 * nn);
+    if (dw) *dw = t;
+    return off;
+}
+
+int enqueue_dense_reduce(double* A, long long lda, int n, const DenseWork& dw, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 0) return 0;
+    for (int p = 0; p < n - 2; p += kNb) {
+        const int b = (n - 2 - p < kNb) ? n - 2 - p : kNb;
+        hipLaunchKernelGGL(k_trd_col, dim3(1), dim3(kColThreads), 0, s, A, lda, n, p, 0, dw.V, dw.W, dw.tau, dw.d,
+                           dw.e);
+        for (int i = 0; i < b; ++i) {
+            const int c = p + i;
+            const int m = n - c - 1;  // trailing columns
+            hipLaunchKernelGGL(k_trd_symv, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, lda, n, c, i, dw.V,
+                               dw.y);
+            hipLaunchKernelGGL(k_trd_wcol, dim3(1), dim3(kColThreads), 0, s, A, lda, n, c, i, dw.V, dw.W, dw.y,
+                               dw.tau, dw.d, dw.e, (i + 1 < b) ? 1 : 0);
+        }
+        const int q = p + b;
+        const int M = n - q;
+        const int tiles = (M + 31) / 32;
+        const long long waves = (long long)tiles * tiles;
+        hipLaunchKernelGGL(k_trd_syr2k, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A, lda, n, q, b, dw.V,
+                           dw.W, tiles);
+    }
+    hipLaunchKernelGGL(k_trd_tail, dim3(1), dim3(64), 0, s, A, lda, n, dw.d, dw.e);
+    return (int)hipGetLastError();
+}
+
+}  // namespace tde

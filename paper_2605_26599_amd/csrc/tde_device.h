@@ -28,6 +28,10 @@
 #ifndef TDE_RCP_ESTIMATE
 #define TDE_RCP_ESTIMATE(x) __builtin_amdgcn_rcp(x)
 #endif
+// Hardware reciprocal square root estimate (refined by rot_gen below).
+#ifndef TDE_RSQ_ESTIMATE
+#define TDE_RSQ_ESTIMATE(x) __builtin_amdgcn_rsq(x)
+#endif
 
 namespace tde {
 
@@ -137,6 +141,29 @@ TDE_DEV bool close_pair(double Da, double za, double Db, double zb, double tol) 
 // (st = lanes sharing an LDS tile).  Returns 0 or ST_LEAF_NOCONV (an
 // eigenvalue needed more than 60 steps).
 // ---------------------------------------------------------------------------
+// Plane rotation (c, s) with c = x/r, s = y/r, r = sqrt(x^2 + y^2) (c = 1,
+// s = 0 when r = 0).  In the usual range r comes from one reciprocal square
+// root (hardware estimate and two Newton steps) instead of a scaled hypot
+// and two divisions; outside it (squares that could underflow or overflow)
+// the scaled hypot and the divisions are used.
+TDE_DEV double rot_gen(double x, double y, double* c, double* s) {
+#pragma clang fp contract(off)
+    const double mx = fmax(fabs(x), fabs(y));
+    if (mx > 1e-140 && mx < 1e140) {
+        const double r2 = x * x + y * y;
+        double q = TDE_RSQ_ESTIMATE(r2);
+        q = q * (1.5 - (0.5 * r2) * (q * q));
+        q = q * (1.5 - (0.5 * r2) * (q * q));
+        *c = x * q;
+        *s = y * q;
+        return r2 * q;
+    }
+    const double r = hypot(x, y);
+    *c = (r == 0.0) ? 1.0 : x / r;
+    *s = (r == 0.0) ? 0.0 : y / r;
+    return r;
+}
+
 template <class Rows>
 TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsigned* nrot) {
 #pragma clang fp contract(off)
@@ -147,9 +174,24 @@ TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsig
     for (int l = 0; l < nl; ++l) {
         int steps = 0;
         for (;;) {
-            // end of the unreduced block that starts at l
+            // end of the unreduced block that starts at l (the entries are
+            // read four at a time, so the loads do not wait on each other)
             int m = l;
-            while (m + 1 < nl && fabs(A_(e, m)) > DBL_EPSILON * (fabs(A_(d, m)) + fabs(A_(d, m + 1)))) ++m;
+            for (;;) {
+                if (m + 4 < nl) {
+                    const double e0 = A_(e, m), e1 = A_(e, m + 1), e2 = A_(e, m + 2), e3 = A_(e, m + 3);
+                    const double d0 = A_(d, m), d1 = A_(d, m + 1), d2 = A_(d, m + 2), d3 = A_(d, m + 3),
+                                 d4 = A_(d, m + 4);
+                    if (!(fabs(e0) > DBL_EPSILON * (fabs(d0) + fabs(d1)))) break;
+                    if (!(fabs(e1) > DBL_EPSILON * (fabs(d1) + fabs(d2)))) { m += 1; break; }
+                    if (!(fabs(e2) > DBL_EPSILON * (fabs(d2) + fabs(d3)))) { m += 2; break; }
+                    if (!(fabs(e3) > DBL_EPSILON * (fabs(d3) + fabs(d4)))) { m += 3; break; }
+                    m += 4;
+                } else {
+                    while (m + 1 < nl && fabs(A_(e, m)) > DBL_EPSILON * (fabs(A_(d, m)) + fabs(A_(d, m + 1)))) ++m;
+                    break;
+                }
+            }
             if (m + 1 < nl) A_(e, m) = 0.0;
             if (m == l) break;  // d[l] converged
             if (++steps > 60) {
@@ -165,33 +207,44 @@ TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsig
                 mu -= f / (h + (h >= 0.0 ? r : -r));
             }
             double c, s;
-            {
-                const double x = A_(d, m) - mu, y = A_(e, m - 1);
-                const double r = hypot(x, y);
-                c = (r == 0.0) ? 1.0 : x / r;
-                s = (r == 0.0) ? 0.0 : y / r;
-            }
+            (void)rot_gen(A_(d, m) - mu, A_(e, m - 1), &c, &s);
+            // the chase carries the entries it has just updated in registers
+            // and loads the next two untouched ones ahead (d(k-1), e(k-2):
+            // nothing writes them before their use), so no step waits on a
+            // store-then-load through LDS
             double bulge = 0.0;
+            double ek1 = 0.0;            // e(k+1) as updated by the previous step
+            double dk1 = A_(d, m);       // d(k+1)
+            double ek = A_(e, m - 1);    // e(k)
+            double dk = A_(d, m - 1);    // d(k)
+            double ekm1 = (m - 2 >= l) ? A_(e, m - 2) : 0.0;  // e(k-1)
+            rows.chase_begin(m);
             for (int k = m - 1; k >= l; --k) {
-                if (k < m - 1) {
-                    const double ek1 = A_(e, k + 1);
-                    const double r = hypot(bulge, ek1);
-                    c = (r == 0.0) ? 1.0 : ek1 / r;
-                    s = (r == 0.0) ? 0.0 : bulge / r;
-                    A_(e, k + 1) = r;
-                }
-                const double a = A_(d, k), g = A_(d, k + 1), f = A_(e, k);
+                const double dn = (k - 1 >= l) ? A_(d, k - 1) : 0.0;
+                const double en = (k - 2 >= l) ? A_(e, k - 2) : 0.0;
+                if (k < m - 1) A_(e, k + 1) = rot_gen(ek1, bulge, &c, &s);
+                const double a = dk, g = dk1, f = ek;
                 const double w = s * (a - g) + 2.0 * c * f;
-                A_(d, k) = a - s * w;
+                const double dkn = a - s * w;
+                A_(d, k) = dkn;
                 A_(d, k + 1) = g + s * w;
-                A_(e, k) = c * w - f;
+                const double ekn = c * w - f;
+                A_(e, k) = ekn;
+                double ekm1n = ekm1;
                 if (k > l) {
-                    bulge = s * A_(e, k - 1);
-                    A_(e, k - 1) = c * A_(e, k - 1);
+                    bulge = s * ekm1;
+                    ekm1n = c * ekm1;
+                    A_(e, k - 1) = ekm1n;
                 }
                 ++nr;
                 rows.rot(k, c, s);
+                ek1 = ekn;
+                dk1 = dkn;
+                ek = ekm1n;
+                dk = dn;
+                ekm1 = en;
             }
+            rows.chase_end(l);
         }
     }
     // ascending order, rows permuted alongside
@@ -212,17 +265,25 @@ TDE_DEV int leaf_ql_core(int nl, double* d, double* e, int st, Rows& rows, unsig
 }
 
 // One tracked row q (row `row` of Q; q starts as that row of the identity).
+// A chase applies rot(k) for k = m-1 down to l; the entry it is about to
+// combine with (q[k+1]) is carried in a register from one rotation to the
+// next (chase_begin loads q[m], chase_end stores the last one at q[l]), so
+// no rotation waits on the previous one's store.
 struct RowTrack {
     double* q;
     int st;
+    double cur;
     TDE_DEV void init(int nl, int row) {
         for (int i = 0; i < nl; ++i) q[i * st] = (i == row) ? 1.0 : 0.0;
     }
+    TDE_DEV void chase_begin(int m) { cur = q[m * st]; }
+    TDE_DEV void chase_end(int l) { q[l * st] = cur; }
     TDE_DEV void rot(int i, double c, double s) {
 #pragma clang fp contract(off)
-        const double t = q[(i + 1) * st];
-        q[(i + 1) * st] = s * q[i * st] + c * t;
-        q[i * st] = c * q[i * st] - s * t;
+        const double t = cur;
+        const double qi = q[i * st];
+        q[(i + 1) * st] = s * qi + c * t;
+        cur = c * qi - s * t;
     }
     TDE_DEV void swap(int i, int k) {
         const double t = q[i * st];
@@ -233,6 +294,14 @@ struct RowTrack {
 
 struct TwoRows {
     RowTrack a, b;
+    TDE_DEV void chase_begin(int m) {
+        a.chase_begin(m);
+        b.chase_begin(m);
+    }
+    TDE_DEV void chase_end(int l) {
+        a.chase_end(l);
+        b.chase_end(l);
+    }
     TDE_DEV void rot(int i, double c, double s) {
         a.rot(i, c, s);
         b.rot(i, c, s);

@@ -168,13 +168,17 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
     __shared__ double sd[LMAX * 64], se[LMAX * 64], s0[LMAX * 64], s1[LMAX * 64];
     const int lane = threadIdx.x;
     const int li = blockIdx.x * 64 + lane;
-    if (li >= nleaves) return;
-    const LeafRec L = leaves[li];
     unsigned nrot = 0;
-    const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64, &nrot);
-    if (st) atomicOr(w.status, st);
-    count_add1(w.counters, CNT_LEAF_COLS, (unsigned long long)L.size);
-    count_add1(w.counters, CNT_LEAF_ROT, (unsigned long long)nrot);
+    unsigned long long cols = 0;
+    if (li < nleaves) {
+        const LeafRec L = leaves[li];
+        const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64, &nrot);
+        if (st) atomicOr(w.status, st);
+        cols = (unsigned long long)L.size;
+    }
+    // one atomic per wave for each counter (every lane reaches this point)
+    count_add(w.counters, CNT_LEAF_COLS, cols);
+    count_add(w.counters, CNT_LEAF_ROT, (unsigned long long)nrot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1616,13 +1620,22 @@ __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__
 // columns with all lanes busy, while a workgroup per merge would queue
 // thousands of mostly idle 512-thread groups (a merge's result is the same
 // either way).
+// Levels of merges of at most kLevelBlockSmallCols columns always take them:
+// their workgroups are sized to the merge (64 or 128 threads, a few KB of
+// LDS), so even tens of thousands of them do not crowd the compute units.
 constexpr int kLevelBlockMaxMerges = 1024;
+#ifndef TDE_LEVEL_BLOCK_SMALL_COLS
+#define TDE_LEVEL_BLOCK_SMALL_COLS 128
+#endif
+constexpr int kLevelBlockSmallCols = TDE_LEVEL_BLOCK_SMALL_COLS;
 
 // Levels run by k_level_block (forward; the reverse pass reads their
 // checkpointed roots from the merges' packed positions).
-static bool level_blocked(const LevelInfo& L) { return L.smax <= kFuseMax && L.M <= kLevelBlockMaxMerges; }
+static bool level_blocked(const LevelInfo& L) {
+    return L.smax <= kFuseMax && (L.M <= kLevelBlockMaxMerges || L.smax <= kLevelBlockSmallCols);
+}
 
-template <int NT>
+template <int NT, int CAP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_level_block(
     const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                     const unsigned long long* __restrict__ pmax, Work w,
@@ -1630,7 +1643,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (input_nonfinite(w)) return;
     __shared__ MergeRec sm[1];
     __shared__ int wsum[16];
-    __shared__ SmallStage sg;
+    __shared__ SmallStageT<CAP> sg;
     const MergeRec R = mr[blockIdx.x];
     if (threadIdx.x == 0) sm[0] = R;
     const int s = R.nL + R.nR;
@@ -2219,13 +2232,20 @@ static int lanes_per_root(int smax, int cols) {
 }
 
 // Grid of a root kernel: the regular tiles plus, when the level has a merge
-// large enough, up to 4096 wide blocks.
-static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw) {
+// large enough, up to wblocks wide blocks (default kWideGridMax; they loop
+// over the level's 64-root items, so a level with more items than blocks
+// still gets them all).  The wide launches must be in the graph whenever a
+// level has a merge large enough, because the active counts are known only
+// on the device; where they find nothing (random spectra), a smaller grid
+// costs less, where they carry the solve (Toeplitz-like spectra) a larger
+// one keeps more waves per compute unit: the autotuner picks.
+constexpr long long kWideGridMax = 4096;
+static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw, long long wblocks = kWideGridMax) {
     long long nb = (N * G + kWG - 1) / kWG;
     if (nb > 8192) nb = 8192;
     if (nb < 1) nb = 1;
     long long wb = wide ? (N + 63) / 64 : 0;
-    if (wb > 4096) wb = 4096;
+    if (wb > wblocks) wb = wblocks;
     *nbn = (int)nb;
     *nbw = (int)wb;
 }
@@ -2234,14 +2254,15 @@ static void root_grid(long long N, int G, bool wide, int* nbn, int* nbw) {
 // caller's cap, else 16 when the level has few merges (latency-bound: every
 // lane of a root's group shortens its sweeps) and 4 when it has many
 // (throughput-bound: fewer lanes repeat less of each root's update).
-constexpr int kFewMerges = 512;
+constexpr int kFewMerges = 1024;
 static int fused_gmax(int M, int group_max) {
     if (group_max > 0) return group_max;
     return M < kFewMerges ? 16 : 4;
 }
 
-// Fused small merges of one level: a workgroup per merge, its shape from the
-// level's largest merge (LDS room and threads for that many active columns).
+// Fused small merges of one level: a workgroup per merge; on levels of many
+// merges its shape follows the level's largest merge (LDS room and threads
+// for that many active columns), on levels of few it is the full size.
 static void launch_small(int smax, const MergeRec* mr, int M, const double* e, const Work& w, int gmax,
                          void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
@@ -2249,7 +2270,7 @@ static void launch_small(int smax, const MergeRec* mr, int M, const double* e, c
     if (smax >= kFuseWideS)
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<2 * kFuseThreads, kFuseMax>), g, 2 * kFuseThreads, stream, mr, e, pm,
                      w, gmax);
-    else if (smax > 256)
+    else if (smax > 256 || M < kFewMerges)
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w,
                      gmax);
     else if (smax > 128)
@@ -2260,9 +2281,28 @@ static void launch_small(int smax, const MergeRec* mr, int M, const double* e, c
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax);
 }
 
+// Whole merges in one workgroup each: 512 threads on levels of few merges
+// (each merge's chain of steps is latency-bound, so more threads per merge
+// shorten it), else a workgroup sized to the level's largest merge (levels of
+// many merges are throughput-bound).
+static void launch_level_block(int smax, const MergeRec* mr, int M, const double* e, const Work& w, double* out,
+                               int gmax, void* stream) {
+    const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    const unsigned g = (unsigned)M;
+    if (smax > 256 || M <= kLevelBlockMaxMerges)
+        TDE_LAUNCH_K(KIND_LEVEL, (k_level_block<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w, out,
+                     gmax);
+    else if (smax > 128)
+        TDE_LAUNCH_K(KIND_LEVEL, (k_level_block<256, 256>), g, 256, stream, mr, e, pm, w, out, gmax);
+    else if (smax > 64)
+        TDE_LAUNCH_K(KIND_LEVEL, (k_level_block<128, 128>), g, 128, stream, mr, e, pm, w, out, gmax);
+    else
+        TDE_LAUNCH_K(KIND_LEVEL, (k_level_block<64, 64>), g, 64, stream, mr, e, pm, w, out, gmax);
+}
+
 template <int G>
 static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                           const Work& w, int gmax, void* stream) {
+                           const Work& w, int gmax, int wblocks, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = kFuseMax;
     // merges with at most kFuseMax active roots: one workgroup each
@@ -2271,7 +2311,7 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
     int nbn, nbw;
-    root_grid(N, G, wide, &nbn, &nbw);
+    root_grid(N, G, wide, &nbn, &nbw, wblocks);
     // every merge too large for k_small_merge is wide: no regular tiles
     if (wide_min <= fuse_max + 1) nbn = 0;
     const unsigned grid = (unsigned)(nbn + nbw);
@@ -2297,13 +2337,13 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
 }
 
 static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                         const Work& w, int gmax, void* stream) {
+                         const Work& w, int gmax, int wblocks, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
-        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
-        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
-        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
-        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, stream); break;
+        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
+        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
+        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
+        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
+        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
     }
 }
 
@@ -2406,13 +2446,13 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         if (level_blocked(L)) {
             // every merge of the level fits one workgroup: the whole merge in one launch
             // (with a checkpoint, its roots land at the merge's packed positions)
-            TDE_LAUNCH_K(KIND_LEVEL, k_level_block<kFuseThreads>, (unsigned)M, kFuseThreads, stream, mr, e,
-                         (const unsigned long long*)w.pmax, wl, out, fused_gmax(M, p.group_max));
+            launch_level_block(L.smax, mr, M, e, wl, out, fused_gmax(M, p.group_max), stream);
             continue;
         }
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
-        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max), stream);
+        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max),
+                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
     }

@@ -27,6 +27,7 @@ struct Plan {
     int wide_min = kWideMin;  // merges with at least this many active roots use the wide secular sweep
     bool leaf_dc = false;     // forward passes solve the leaves by divide and conquer inside one wave
     int group_max = 0;        // lanes per root in the fused small merges (4, 8, 16); 0 = by level
+    int wide_blocks = 0;      // most workgroups of a wide root launch; 0 = default (4096)
     int nleaves = 0;
     int leafmax = 1;     // largest leaf size in the plan
     int maxM = 1;        // most merges in one level

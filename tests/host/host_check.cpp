@@ -18,6 +18,8 @@
 
 #define TDE_DEV inline
 #define TDE_RCP_ESTIMATE(x) (1.0 / (x))
+// a single-precision estimate, as coarse as the hardware one, so the Newton steps are exercised
+#define TDE_RSQ_ESTIMATE(x) ((1.0 / std::sqrt(x)) * (1.0 + 3e-8))
 #include "../../paper_2605_26599_amd/csrc/tde_device.h"
 #include "../../paper_2605_26599_amd/csrc/tde_plan.h"
 #include "../../paper_2605_26599_amd/csrc/tde_tree.h"

@@ -70,12 +70,13 @@ def test_argument_errors_are_synchronous(L):
     bad.leaf = 0
     bad.flags = 4  # unknown flag bit
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(bad)) == tde.TDE_EINVAL
-    for field, value in [("max_sweeps", -1), ("max_sweeps", 97), ("wide_min", 1), ("sweep_cols", -3)]:
+    for field, value in [("max_sweeps", -1), ("max_sweeps", 97), ("wide_min", 1), ("sweep_cols", -3),
+                         ("group_max", 2), ("group_max", 32), ("wide_blocks", -1)]:
         o = tde.tde_opts()
         setattr(o, field, value)
         assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(o)) == tde.TDE_EINVAL, field
     o = tde.tde_opts()
-    o.reserved[1] = 7  # reserved fields must be zero
+    o.reserved[0] = 7  # reserved fields must be zero
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(o)) == tde.TDE_EINVAL
     offs = (ctypes.c_int64 * 3)(0, 5, 3)  # not monotone
     assert L.tde_eigvals_batched(dummy, dummy, offs, 2, dummy, dummy, 1 << 30, None, None) == tde.TDE_EINVAL
