@@ -2016,14 +2016,18 @@ __global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ 
 }
 
 // dL/dz of the negligible-z columns of non-top merges: G lanes per column
-// (the group splits the sum over the merge's roots).
+// (the group splits the sum over the merge's roots).  Groups take the
+// level's negligible columns in their compacted order (dpos), so whole
+// waves either work or leave.
 template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
     if (input_nonfinite(w)) return;
-    const long long t = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+    const long long q = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
     const int sub = (int)(threadIdx.x % G);
-    if (t >= N || w.st[t] != 0) return;  // group-uniform
+    const long long nneg = N - w.scan[N] - w.scanR[N];
+    if (q >= nneg) return;  // group-uniform
+    const long long t = w.dpos[q];
     const MergeRec R = mr[merge_of(mr, blkm, t)];
     if (R.flags & MF_ROOT) return;
     const MergeSpan sp = merge_span(R, w.scan);
