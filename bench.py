@@ -329,7 +329,7 @@ def grad_case(tde, dev, name):
     return d, e, w, offs, n
 
 
-def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide):
+def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None):
     """Checkpointing forward + backward step (all buffers resident)."""
     import torch
 
@@ -339,9 +339,10 @@ def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide):
     ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
 
     def fb():
-        tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, out=out, ckpt=ck, check=False)
-        tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, gd=gd, ge=ge,
-                             check=False)
+        tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks, out=out,
+                         ckpt=ck, check=False)
+        tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks,
+                             gd=gd, ge=ge, check=False)
     return fb
 
 
@@ -354,7 +355,7 @@ def grad_only(args):
     dev = torch.device("cuda:0")
     d, e, w, offs, n = grad_case(tde, dev, args.grad)
     leaf, cols, wide = args.leaf or 8, args.sweep_cols or 16, args.wide_min or 1024
-    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide)
+    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, args.wide_blocks or None)
     for _ in range(max(args.warmup, 1)):
         fb()
     torch.cuda.synchronize()
@@ -362,7 +363,7 @@ def grad_only(args):
     print(json.dumps({"metric": "fwd+bwd ms", "value": ms, "unit": "ms", "steps": args.steps,
                       "higher_is_better": False,
                       "config": {"workload": f"gradient {args.grad}", "leaf": leaf, "sweep_cols": cols,
-                                 "wide_min": wide}}), flush=True)
+                                 "wide_min": wide, "wide_blocks": args.wide_blocks or None}}), flush=True)
 
 
 def grad_ratio(tde, dev, reps=20):
@@ -392,15 +393,16 @@ def grad_ratio(tde, dev, reps=20):
         for leaf in (4, 8, 16, 32):
             for cols in (16, 64):
                 for wide in (1024, 64):
-                    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide)
-                    fb()
-                    fb()
-                    t = timed(fb, 3) / 3
-                    if best is None or t < best[0]:
-                        best = (t, leaf, cols, wide)
-        _, bleaf, bcols, bwide = best
-        fwdbwd = make_fwdbwd(tde, dev, d, e, w, offs, n, bleaf, bcols, bwide)
-        qcfg = dict(leaf=bleaf, sweep_cols=bcols, wide_min=bwide)
+                    for wb in (None, 256):
+                        fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wb)
+                        fb()
+                        fb()
+                        t = timed(fb, 3) / 3
+                        if best is None or t < best[0]:
+                            best = (t, leaf, cols, wide, wb)
+        _, bleaf, bcols, bwide, bwb = best
+        fwdbwd = make_fwdbwd(tde, dev, d, e, w, offs, n, bleaf, bcols, bwide, bwb)
+        qcfg = dict(leaf=bleaf, sweep_cols=bcols, wide_min=bwide, wide_blocks=bwb)
 
         def fwd_same():
             if offs is None:

@@ -502,9 +502,12 @@ def checkpoint_bytes(n: int, offsets=None, leaf=None, sweep_cols=None) -> int:
 
 
 def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, out=None,
-                 ckpt=None, workspace=None, check: bool = True, graph: bool = True, wide_min=None):
+                 ckpt=None, workspace=None, check: bool = True, graph: bool = True, wide_min=None,
+                 group_max=None, wide_blocks=None):
     """Eigenvalues as eigvals / eigvals_batched (offsets None = one problem with
-    e[n-1]), plus the checkpoint the reverse pass reads.  Returns (lambda, ckpt)."""
+    e[n-1]), plus the checkpoint the reverse pass reads.  Returns (lambda, ckpt).
+    group_max and wide_blocks are launch-shape options (results do not
+    depend on them)."""
     _check_input(d, e)
     offs, B, arr = _offsets(d.numel(), offsets)
     n = offs[-1]
@@ -525,7 +528,8 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_ckpt(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, out.data_ptr(),
                                     ckpt.data_ptr(), ckpt.numel(), ws.data_ptr(), ws.numel(), stream,
-                                    _opts(leaf, graph, sweep_cols, wide_min))
+                                    _opts(leaf, graph, sweep_cols, wide_min, group_max=group_max,
+                                          wide_blocks=wide_blocks))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_ckpt")
         if check:
@@ -537,7 +541,8 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
 
 def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt: torch.Tensor, offsets=None,
                      leaf=None, sweep_cols=None, workspace=None, check: bool = True, graph: bool = True,
-                     gd: torch.Tensor | None = None, ge: torch.Tensor | None = None, wide_min=None):
+                     gd: torch.Tensor | None = None, ge: torch.Tensor | None = None, wide_min=None,
+                     group_max=None, wide_blocks=None):
     """dL/dd and dL/de for L = sum_k glam_k lambda_k, from the checkpoint of
     eigvals_ckpt on the same inputs and options.  Returns (gd[n], ge[n]) with
     ge in the batched layout (the last slot of every problem is 0); gd and ge
@@ -566,7 +571,8 @@ def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt:
         rc = lib().tde_eigvals_backward(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B,
                                         glam.data_ptr(), ckpt.data_ptr(), ckpt.numel(), gd.data_ptr(),
                                         ge.data_ptr(), ws.data_ptr(), ws.numel(), stream,
-                                        _opts(leaf, graph, sweep_cols, wide_min))
+                                        _opts(leaf, graph, sweep_cols, wide_min, group_max=group_max,
+                                              wide_blocks=wide_blocks))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_backward")
         if check:

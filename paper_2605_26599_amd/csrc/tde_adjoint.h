@@ -290,6 +290,28 @@ TDE_DEV void run_step_adjoint(const RunState& cur, const RunState& nx, const Run
 // A group of G lanes handles one run: every lane walks the chain (writing the
 // same values to the same addresses) and the group splits each O(K) coupling
 // sum (lane `sub` of G).
+//
+// bwd_run_head is the per-candidate first step, one lane per candidate: a
+// candidate in no run passes its adjoints straight through (the forward
+// copied it), and the candidate that starts a run reports itself so that a
+// group can take the run.
+TDE_DEV bool bwd_run_head(long long g, int m, const MergeRec* __restrict__ mr, const Work& w, const Grad& gr) {
+    const long long t = w.nnpos[g];
+    const MergeRec R = mr[m];
+    const int s = R.nL + R.nR;
+    const long long gs = w.scanC[R.pk], ge = w.scanC[R.pk + s];
+    const double tol = merge_tol(w.D, R.pk, s);
+    const bool cl_next = (g + 1 < ge) && cand_close(w, g, g + 1, tol);
+    const bool cl_prev = (g > gs) && cand_close(w, g - 1, g, tol);
+    if (cl_prev) return false;
+    if (cl_next) return true;
+    gr.gD[t] = gr.gD2[t];
+    gr.gZ[t] = gr.gZ2[t];
+    gr.gRL[t] = gr.gRL2[t];
+    gr.gRH[t] = gr.gRH2[t];
+    return false;
+}
+
 template <class Red>
 TDE_DEV void body_bwd_runs(long long g, int m, const MergeRec* __restrict__ mr, const Work& w, const Grad& gr,
                            long long cstride, int sub, int G) {
@@ -437,14 +459,17 @@ TDE_DEV void body_bwd_merge(long long t, int m, const MergeRec* __restrict__ mr,
     }
 }
 
-// Leaf adjoint for row r (one lane per row).  sd, se: this lane's own copy of
-// the leaf's torn diagonal and off-diagonal (stride st); Q, X: the leaf's
-// nl x nl eigenvector matrix and Q (diag(gl) + B), column-major (element
-// (r, k) at [k nl + r]), shared by the leaf's lanes.  body_bwd_leaf_q
-// recomputes the QL and stores row r of Q (and the eigenvalues from lane 0);
-// after a barrier body_bwd_leaf_x forms row r of X; after another barrier
-// body_bwd_leaf_out writes dL/dd'_r and the adjoint of the in-leaf coupling r:
-// gT = X Q^T, gd'_r = gT_rr, ge_r = gT_{r,r+1} + gT_{r+1,r}.
+// Leaf adjoint, R rows per lane (rows sub, sub + lanes, ... of the leaf,
+// `lanes` lanes per leaf).  sd, se: this lane's own copy of the leaf's torn
+// diagonal and off-diagonal (stride st); Q, X: the leaf's eigenvector matrix
+// and Q (diag(gl) + B), column-major with leading dimension ld >= nl (element
+// (r, k) at [k ld + r]), shared by the leaf's lanes.  bwd_leaf_q recomputes
+// the QL, tracking the lane's rows of Q (a row index at or past nl only
+// writes rows of the ld x ld block that no lane reads), and stores the
+// eigenvalues from the lane that holds row 0; after a barrier body_bwd_leaf_x
+// forms row r of X; after another barrier body_bwd_leaf_out writes dL/dd'_r
+// and the adjoint of the in-leaf coupling r: gT = X Q^T, gd'_r = gT_rr,
+// ge_r = gT_{r,r+1} + gT_{r+1,r}.
 TDE_DEV void leaf_load(const LeafRec& L, const double* __restrict__ d, const double* __restrict__ e,
                        const unsigned long long* __restrict__ pmax, double* sd, double* se, int st) {
     const double inv = 1.0 / scale_of(pmax[L.prob]);
@@ -458,47 +483,74 @@ TDE_DEV void leaf_load(const LeafRec& L, const double* __restrict__ d, const dou
     }
 }
 
-TDE_DEV int body_bwd_leaf_q(const LeafRec& L, int r, const double* __restrict__ d, const double* __restrict__ e,
-                            const unsigned long long* __restrict__ pmax, double* sd, double* se, int st,
-                            double* Q, double* lam) {
+// R tracked rows, every rotation applied to each.
+template <int R>
+struct RowsR {
+    RowTrack t[R];
+    TDE_DEV void chase_begin(int m) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k].chase_begin(m);
+    }
+    TDE_DEV void chase_end(int l) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k].chase_end(l);
+    }
+    TDE_DEV void rot(int i, double c, double s) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k].rot(i, c, s);
+    }
+    TDE_DEV void swap(int i, int k2) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k].swap(i, k2);
+    }
+};
+
+template <int R>
+TDE_DEV int bwd_leaf_q(const LeafRec& L, int sub, int lanes, const double* __restrict__ d,
+                       const double* __restrict__ e, const unsigned long long* __restrict__ pmax, double* sd,
+                       double* se, int st, double* Q, int ld, double* lam) {
     const int nl = L.size;
     leaf_load(L, d, e, pmax, sd, se, st);
-    RowTrack row;
-    row.q = Q + r;
-    row.st = nl;
-    row.init(nl, r);
+    RowsR<R> rows;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        rows.t[k].q = Q + sub + k * lanes;
+        rows.t[k].st = ld;
+        rows.t[k].init(nl, sub + k * lanes);
+    }
     unsigned nrot = 0;
-    const int status = leaf_ql_core(nl, sd, se, st, row, &nrot);
-    if (r == 0)
+    const int status = leaf_ql_core(nl, sd, se, st, rows, &nrot);
+    if (sub == 0)
         for (int k = 0; k < nl; ++k) lam[k] = sd[k * st];
     return status;
 }
 
-TDE_DEV void body_bwd_leaf_x(const LeafRec& L, int r, const Grad& gr, const double* Q, const double* lam, double* X) {
+TDE_DEV void body_bwd_leaf_x(const LeafRec& L, int r, const Grad& gr, const double* Q, int ld, const double* lam,
+                             double* X) {
     const int nl = L.size;
     for (int k = 0; k < nl; ++k) {
         const double gb = gr.gblo[L.off + k], gh = gr.gbhi[L.off + k];
-        double acc = Q[k * nl + r] * gr.glam[L.off + k];
+        double acc = Q[k * ld + r] * gr.glam[L.off + k];
         for (int j = 0; j < nl; ++j) {
             if (j == k) continue;
             const double den = lam[k] - lam[j];
             if (den == 0.0) continue;
-            acc += Q[j * nl + r] * (Q[j * nl] * gb + Q[j * nl + nl - 1] * gh) / den;
+            acc += Q[j * ld + r] * (Q[j * ld] * gb + Q[j * ld + nl - 1] * gh) / den;
         }
-        X[k * nl + r] = acc;
+        X[k * ld + r] = acc;
     }
 }
 
-TDE_DEV void body_bwd_leaf_out(const LeafRec& L, int r, const Grad& gr, const double* Q, const double* X,
+TDE_DEV void body_bwd_leaf_out(const LeafRec& L, int r, const Grad& gr, const double* Q, const double* X, int ld,
                                double* gd, double* ge) {
     const int nl = L.size;
     double dd = 0.0;
-    for (int k = 0; k < nl; ++k) dd += X[k * nl + r] * Q[k * nl + r];
+    for (int k = 0; k < nl; ++k) dd += X[k * ld + r] * Q[k * ld + r];
     gr.gdp[L.off + r] = dd;
     gd[L.off + r] = dd;
     if (r + 1 < nl) {
         double off = 0.0;
-        for (int k = 0; k < nl; ++k) off += X[k * nl + r] * Q[k * nl + r + 1] + X[k * nl + r + 1] * Q[k * nl + r];
+        for (int k = 0; k < nl; ++k) off += X[k * ld + r] * Q[k * ld + r + 1] + X[k * ld + r + 1] * Q[k * ld + r];
         ge[L.off + r] = off;
     }
 }

@@ -182,20 +182,186 @@ __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves,
 }
 
 // ---------------------------------------------------------------------------
-// Leaves solved by divide and conquer inside one wave (one workgroup of 64
-// lanes per leaf of at most 64 columns).  The leaf's own merge tree (balanced
-// halving down to single columns, Section 3.1; levelled by height) runs level
-// by level with every level array in LDS, one lane per column or per root.
-// Each merge runs the same per-column and per-root steps as the global levels
-// (merged order and z~, negligible-z and close-pole deflation, secular roots,
-// Loewner z, boundary rows, three-list assembly); only the level-wide
-// compactions differ: a wave ballot replaces the block scans.  The leaf's top
-// merge writes its node's spectrum and rows to the global arrays (or the
-// scaled eigenvalues when the leaf is a whole problem).
+// Merges inside one wave: the in-wave leaves and the levels of many small
+// merges keep every level array in LDS, one lane per column or per root.
 // ---------------------------------------------------------------------------
 constexpr int kDcCols = kLeafMax;  // columns of one in-wave leaf
 static_assert(kDcCols == 64, "one lane per column of an in-wave leaf");
 
+// LDS of one in-wave level: 18 double arrays of kDcCols entries (21 with the
+// node state), 7 int arrays of kDcCols (+1) entries and the level's merge
+// records (at most kDcCols / 2: every merge has two or more columns).
+template <bool Nodes>
+struct WaveLds {
+    double b[(Nodes ? 21 : 18) * kDcCols];
+    int i[3 * kDcCols + 4 * (kDcCols + 1)];
+    MergeRec smr[kDcCols / 2];
+};
+
+// Level arrays of an in-wave level in LDS.  A level runs merge | flags | runs |
+// three-way split | roots | Loewner | rows | assembly; the merged and rotated
+// columns (D, Z, RL, RH, D2, Z2) are last read by the split, so the later
+// steps' arrays live in them: active z (split to Loewner) in Z, tau in D, the
+// root values in D2, z-hat in Z2, the parent rows in RL and RH; the roots'
+// origins reuse the candidate positions, last read by the runs.  Fewer arrays
+// let more waves share a compute unit.  With Nodes, the node state lam, blo,
+// bhi gets LDS storage too.
+template <bool Nodes>
+__device__ __forceinline__ void wave_arrays(WaveLds<Nodes>& sh, Work& wl) {
+    constexpr int C = kDcCols;
+    double* p = sh.b;
+    if (Nodes) {
+        wl.lam = p; p += C;  wl.blo = p; p += C;  wl.bhi = p; p += C;
+    }
+    wl.D = p; p += C;    wl.Z = p; p += C;    wl.RL = p; p += C;   wl.RH = p; p += C;
+    wl.D2 = p; p += C;   wl.Z2 = p; p += C;   wl.RL2 = p; p += C;  wl.RH2 = p; p += C;
+    wl.Da = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;  wl.RHa = p; p += C;
+    wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
+    wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;
+    wl.Za = wl.Z;        wl.tau = wl.D;       wl.rootval = wl.D2;  wl.zhat = wl.Z2;
+    wl.PBL = wl.RL;      wl.PBH = wl.RH;
+    int* q = sh.i;
+    wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = wl.nnpos;
+    wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
+}
+
+// Work done by the in-wave levels of one wave (for the counters).
+struct WaveCount {
+    unsigned long long terms = 0, sweeps = 0, roots = 0, lpairs = 0, rpairs = 0, mcols = 0;
+    int bad = 0;
+};
+
+// Roots, Loewner z and rows of an in-wave level with the canonical group sums
+// of the whole-merge workgroups (defined with them below).
+__device__ void wave_roots_canon(const MergeRec* smr, int K, const double* __restrict__ e,
+                                 const unsigned long long* __restrict__ pmax, const Work& wl,
+                                 int* __restrict__ corg, double* __restrict__ ctau, long long pk0, WaveCount& c);
+
+// One level of merges inside one wave: M merges (records in smr, pk local to
+// the level arrays of wl), N columns in all, one lane per column or per active
+// root.  Each merge runs the same per-column and per-root steps as the
+// level-wide kernels (merged order and z~, negligible-z and close-pole
+// deflation, secular roots, Loewner z, boundary rows, three-list assembly);
+// only the compactions differ: a wave ballot replaces the block scans.  The
+// children's spectra and rows are read through wl, the parents' are written
+// through wl, or through wt when `top` (or the scaled eigenvalues to out for a
+// problem's top merge).
+// With corg, every root's origin and offset are also stored at the merge's
+// packed position pk0 + smr[m].pk + (root index within the merge).  Canonical:
+// the root steps take four lanes per root and the canonical group sums, so a
+// level gives the same bits as in a whole-merge workgroup; otherwise one lane
+// per root sums serially.
+template <bool Canonical>
+__device__ __forceinline__ void wave_level(const MergeRec* smr, int M, int N, const double* __restrict__ e,
+                                           const unsigned long long* __restrict__ pmax, const Work& wl,
+                                           const Work& wt, bool top, double* __restrict__ out,
+                                           int* __restrict__ corg, double* __restrict__ ctau, long long pk0,
+                                           WaveCount& c) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    c.mcols += (lane == 0) ? (unsigned long long)N : 0ULL;
+    // merged order, z~, negligible-z flags (lane = child column; its flag
+    // lands with it at the merged position)
+    if (lane < N) {
+        int fl;
+        body_merge(lane, find_merge(smr, M, lane), smr, e, pmax, wl, &fl);
+    }
+    __syncthreads();
+    const int f = (lane < N) ? wl.st[lane] : 0;
+    const unsigned long long cm = __ballot(f != 0);
+    if (lane < N) {
+        const int gc = (int)__popcll(cm & below);
+        wl.scanC[lane] = gc;
+        if (f) wl.nnpos[gc] = lane;
+    }
+    if (lane == 0) wl.scanC[N] = (int)__popcll(cm);
+    __syncthreads();
+    // close-pole runs
+    if (lane < (int)__popcll(cm)) body_runs(lane, find_merge(smr, M, wl.nnpos[lane]), smr, wl, [](long long) {});
+    __syncthreads();
+    // three-way split
+    const int s = (lane < N) ? wl.st[lane] : 0;
+    const unsigned long long am = __ballot(lane < N && s == 1);
+    const unsigned long long rm = __ballot(lane < N && s == 2);
+    const int g = (int)__popcll(am & below), gr = (int)__popcll(rm & below);
+    if (lane < N) {
+        wl.scan[lane] = g;
+        wl.scanR[lane] = gr;
+        if (s == 1) {
+            const double z = wl.Z2[lane];
+            wl.Da[g] = wl.D2[lane];
+            wl.Za[g] = z;
+            wl.Wa[g] = z * z;
+            wl.RLa[g] = wl.RL2[lane];
+            wl.RHa[g] = wl.RH2[lane];
+            wl.amerge[g] = find_merge(smr, M, lane);
+        } else if (s == 2) {
+            wl.Dr[gr] = wl.D2[lane];
+            wl.RLr[gr] = wl.RL2[lane];
+            wl.RHr[gr] = wl.RH2[lane];
+        } else {
+            const int q = lane - g - gr;
+            wl.Dd[q] = wl.D[lane];
+            wl.RLd[q] = wl.RL[lane];
+            wl.RHd[q] = wl.RH[lane];
+        }
+    }
+    if (lane == 0) {
+        wl.scan[N] = (int)__popcll(am);
+        wl.scanR[N] = (int)__popcll(rm);
+    }
+    __syncthreads();
+    // secular roots, Loewner z, boundary rows
+    const int K = (int)__popcll(am);
+    if (Canonical) {
+        wave_roots_canon(smr, K, e, pmax, wl, corg, ctau, pk0, c);
+        if (lane < N) body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wl, out);
+        __syncthreads();
+        return;
+    }
+    // (one lane per active root)
+    const int m = (lane < K) ? wl.amerge[lane] : 0;
+    const bool rowsm = (lane < K) && (!(smr[m].flags & MF_ROOT) || wl.rows_out);
+    int Km = 0;
+    if (lane < K) {
+        const MergeSpan sp = merge_span(smr[m], wl.scan);
+        Km = sp.K;
+        const int it = body_secular<RedSerial>(lane, m, smr, e, pmax, wl, 0, 1, wl.Da, wl.Wa, 0);
+        if (it < 0) c.bad = 1;
+        const unsigned long long sw = (Km > 1) ? (unsigned long long)((it < 0 ? wl.sec_cap : it) + 1) : 0ULL;
+        c.terms += sw * (unsigned long long)Km;
+        c.roots += 1;
+        if (corg) {
+            const long long gp = pk0 + smr[m].pk + (lane - sp.ks);
+            corg[gp] = wl.org[lane];
+            ctau[gp] = wl.tau[lane];
+        }
+    }
+    __syncthreads();
+    if (lane < K) body_lowner<RedSerial>(lane, m, smr, e, pmax, wl, 0, 1, wl.Da, wl.org, wl.tau, 0);
+    __syncthreads();
+    if (lane < K) body_rows<RedSerial>(lane, m, smr, wl, 0, 1, wl.Da, wl.zhat, wl.RLa, wl.RHa, 0);
+    if (rowsm) {
+        c.lpairs += (unsigned long long)Km;
+        c.rpairs += (unsigned long long)Km;
+    }
+    __syncthreads();
+    // parent spectra and rows (in place), or the problem's outputs
+    if (lane < N) {
+        if (top) body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wt, out);
+        else body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wl, out);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Leaves solved by divide and conquer inside one wave (one workgroup of 64
+// lanes per leaf of at most 64 columns).  The leaf's own merge tree (balanced
+// halving down to single columns, Section 3.1; levelled by height) runs level
+// by level with every level array in LDS (wave_level).  The leaf's top merge
+// writes its node's spectrum and rows to the global arrays (or the scaled
+// eigenvalues when the leaf is a whole problem).
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leaves,
                                                const SubHdr* __restrict__ shdr,
                                                const SubMerge* __restrict__ smer,
@@ -203,40 +369,17 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
                                                const unsigned long long* __restrict__ pmax, Work w,
                                                double* __restrict__ out) {
     if (input_nonfinite(w)) return;
-    constexpr int C = kDcCols;
-    __shared__ double sb[21 * C];
-    __shared__ int sbi[3 * C + 4 * (C + 1)];
-    __shared__ MergeRec smr[C / 2];
+    __shared__ WaveLds<true> sh;
     const LeafRec L = leaves[blockIdx.x];
     const int l = L.size;
     const int lane = threadIdx.x;
     const double inv = 1.0 / scale_of(pmax[L.prob]);
     const double* eL = e + L.off;  // merge records below carry leaf-local offsets
 
-    // level arrays in LDS.  A level runs merge | flags | runs | three-way
-    // split | roots | Loewner | rows | assembly; the merged and rotated
-    // columns (D, Z, RL, RH, D2, Z2) are last read by the split, so the later
-    // steps' arrays live in them: active z (split to Loewner) in Z, tau in D,
-    // the root values in D2, z-hat in Z2, the parent rows in RL and RH; the
-    // roots' origins reuse the candidate positions, last read by the runs.  (The
-    // node state lam, blo, bhi keeps its own storage: nodes that no merge of
-    // this level touches carry their values to a higher level.)  Fewer arrays
-    // let more leaves share a compute unit.
+    // level arrays and the node state (nodes that no merge of a level touches
+    // carry their values to a higher level) in LDS
     Work wl = w;
-    {
-        double* p = sb;
-        wl.lam = p; p += C;  wl.blo = p; p += C;  wl.bhi = p; p += C;
-        wl.D = p; p += C;    wl.Z = p; p += C;    wl.RL = p; p += C;   wl.RH = p; p += C;
-        wl.D2 = p; p += C;   wl.Z2 = p; p += C;   wl.RL2 = p; p += C;  wl.RH2 = p; p += C;
-        wl.Da = p; p += C;   wl.Wa = p; p += C;   wl.RLa = p; p += C;  wl.RHa = p; p += C;
-        wl.Dd = p; p += C;   wl.RLd = p; p += C;  wl.RHd = p; p += C;
-        wl.Dr = p; p += C;   wl.RLr = p; p += C;  wl.RHr = p; p += C;
-        wl.Za = wl.Z;        wl.tau = wl.D;       wl.rootval = wl.D2;  wl.zhat = wl.Z2;
-        wl.PBL = wl.RL;      wl.PBH = wl.RH;
-        int* q = sbi;
-        wl.src = q; q += C;  wl.nnpos = q; q += C;  wl.amerge = q; q += C;  wl.org = wl.nnpos;
-        wl.st = q; q += C + 1;  wl.scan = q; q += C + 1;  wl.scanC = q; q += C + 1;  wl.scanR = q; q += C + 1;
-    }
+    wave_arrays(sh, wl);
     // destinations of the leaf's top merge
     Work wt = wl;
     wt.lam = w.lam + L.off;
@@ -272,113 +415,78 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
     if (l <= 1) return;
     const SubHdr* hd = shdr + l;  // read in place: a local copy of lv[] would live in scratch
     const int H = hd->H, mbase = hd->mbase;
-    const unsigned long long below = (1ULL << lane) - 1ULL;
-    unsigned long long terms = 0, roots = 0, lpairs = 0, rpairs = 0, mcols = 0;
-    int bad = 0;
+    WaveCount c;
     for (int h = 0; h < H; ++h) {
         const int m0 = hd->lv[h];
         const int M = hd->lv[h + 1] - m0;
         const bool top = (h == H - 1);
         if (lane < M) {
-            const SubMerge s = smer[mbase + m0 + lane];
+            const SubMerge sm = smer[mbase + m0 + lane];
             MergeRec R;
-            R.off = s.off;
-            R.pk = s.pk;
-            R.nL = s.nL;
-            R.nR = s.nR;
+            R.off = sm.off;
+            R.pk = sm.pk;
+            R.nL = sm.nL;
+            R.nR = sm.nR;
             R.prob = L.prob;
             R.flags = (top && (L.flags & LF_WHOLE)) ? MF_ROOT : 0;
-            smr[lane] = R;
+            sh.smr[lane] = R;
         }
         __syncthreads();
-        const int N = (int)smr[M - 1].pk + smr[M - 1].nL + smr[M - 1].nR;
-        mcols += (lane == 0) ? (unsigned long long)N : 0ULL;
-        // merged order, z~, negligible-z flags (lane = child column; its flag
-        // lands with it at the merged position)
-        if (lane < N) {
-            int fl;
-            body_merge(lane, find_merge(smr, M, lane), smr, eL, pmax, wl, &fl);
-        }
-        __syncthreads();
-        const int f = (lane < N) ? wl.st[lane] : 0;
-        const unsigned long long cm = __ballot(f != 0);
-        if (lane < N) {
-            const int gc = (int)__popcll(cm & below);
-            wl.scanC[lane] = gc;
-            if (f) wl.nnpos[gc] = lane;
-        }
-        if (lane == 0) wl.scanC[N] = (int)__popcll(cm);
-        __syncthreads();
-        // close-pole runs
-        if (lane < (int)__popcll(cm)) body_runs(lane, find_merge(smr, M, wl.nnpos[lane]), smr, wl, [](long long) {});
-        __syncthreads();
-        // three-way split
-        const int s = (lane < N) ? wl.st[lane] : 0;
-        const unsigned long long am = __ballot(lane < N && s == 1);
-        const unsigned long long rm = __ballot(lane < N && s == 2);
-        const int g = (int)__popcll(am & below), gr = (int)__popcll(rm & below);
-        if (lane < N) {
-            wl.scan[lane] = g;
-            wl.scanR[lane] = gr;
-            if (s == 1) {
-                const double z = wl.Z2[lane];
-                wl.Da[g] = wl.D2[lane];
-                wl.Za[g] = z;
-                wl.Wa[g] = z * z;
-                wl.RLa[g] = wl.RL2[lane];
-                wl.RHa[g] = wl.RH2[lane];
-                wl.amerge[g] = find_merge(smr, M, lane);
-            } else if (s == 2) {
-                wl.Dr[gr] = wl.D2[lane];
-                wl.RLr[gr] = wl.RL2[lane];
-                wl.RHr[gr] = wl.RH2[lane];
-            } else {
-                const int q = lane - g - gr;
-                wl.Dd[q] = wl.D[lane];
-                wl.RLd[q] = wl.RL[lane];
-                wl.RHd[q] = wl.RH[lane];
-            }
-        }
-        if (lane == 0) {
-            wl.scan[N] = (int)__popcll(am);
-            wl.scanR[N] = (int)__popcll(rm);
-        }
-        __syncthreads();
-        // secular roots, Loewner z, boundary rows: one lane per active root
-        const int K = (int)__popcll(am);
-        const int m = (lane < K) ? wl.amerge[lane] : 0;
-        const bool rowsm = (lane < K) && (!(smr[m].flags & MF_ROOT) || w.rows_out);
-        int Km = 0;
-        if (lane < K) {
-            Km = merge_span(smr[m], wl.scan).K;
-            const int it = body_secular<RedSerial>(lane, m, smr, eL, pmax, wl, 0, 1, wl.Da, wl.Wa, 0);
-            if (it < 0) bad = 1;
-            const unsigned long long sw = (Km > 1) ? (unsigned long long)((it < 0 ? w.sec_cap : it) + 1) : 0ULL;
-            terms += sw * (unsigned long long)Km;
-            roots += 1;
-        }
-        __syncthreads();
-        if (lane < K) body_lowner<RedSerial>(lane, m, smr, eL, pmax, wl, 0, 1, wl.Da, wl.org, wl.tau, 0);
-        __syncthreads();
-        if (lane < K) body_rows<RedSerial>(lane, m, smr, wl, 0, 1, wl.Da, wl.zhat, wl.RLa, wl.RHa, 0);
-        if (rowsm) {
-            lpairs += (unsigned long long)Km;
-            rpairs += (unsigned long long)Km;
-        }
-        __syncthreads();
-        // parent spectra and rows (in place), or the leaf's outputs
-        if (lane < N) {
-            if (top) body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wt, outL);
-            else body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wl, outL);
-        }
-        __syncthreads();
+        const int N = (int)sh.smr[M - 1].pk + sh.smr[M - 1].nL + sh.smr[M - 1].nR;
+        wave_level<false>(sh.smr, M, N, eL, pmax, wl, wt, top, outL, nullptr, nullptr, 0, c);
     }
-    if (bad) atomicOr(w.status, ST_SEC_NOCONV);
-    count_add(w.counters, CNT_DC_TERMS, terms);
-    count_add(w.counters, CNT_DC_ROOTS, roots);
-    count_add(w.counters, CNT_DC_LOW_PAIRS, lpairs);
-    count_add(w.counters, CNT_DC_ROW_PAIRS, rpairs);
-    count_add(w.counters, CNT_MERGE_COLS, mcols);
+    if (c.bad) atomicOr(w.status, ST_SEC_NOCONV);
+    count_add(w.counters, CNT_DC_TERMS, c.terms);
+    count_add(w.counters, CNT_DC_ROOTS, c.roots);
+    count_add(w.counters, CNT_DC_LOW_PAIRS, c.lpairs);
+    count_add(w.counters, CNT_DC_ROW_PAIRS, c.rpairs);
+    count_add(w.counters, CNT_MERGE_COLS, c.mcols);
+}
+
+// ---------------------------------------------------------------------------
+// Levels of many merges of at most kDcCols columns: one wave per pack of
+// consecutive merges holding at most kDcCols columns in all (the plan's pack
+// table: first merge of every pack, then the level's merge count), the level
+// arrays in LDS as in the in-wave leaves, the children's spectra and rows read
+// from the node arrays and the parents' written back in place.  A dependent
+// chain of LDS steps per wave instead of global-memory round trips per step,
+// and up to four small merges per wave instead of a mostly idle workgroup
+// each.  With corg (a checkpointing forward), the roots land at the merges'
+// packed positions as k_level_block stores them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_level_wave(const MergeRec* __restrict__ mr, const int* __restrict__ packs,
+                                                  const double* __restrict__ e,
+                                                  const unsigned long long* __restrict__ pmax, Work w,
+                                                  double* __restrict__ out, int save_roots) {
+    if (input_nonfinite(w)) return;
+    __shared__ WaveLds<false> sh;
+    const int lane = threadIdx.x;
+    const int m0 = packs[blockIdx.x], M = packs[blockIdx.x + 1] - m0;
+    const long long pk0 = mr[m0].pk;
+    if (lane < M) {
+        MergeRec R = mr[m0 + lane];
+        R.pk -= pk0;
+        sh.smr[lane] = R;
+    }
+    Work wl = w;
+    wave_arrays(sh, wl);
+    __syncthreads();
+    const int N = (int)sh.smr[M - 1].pk + sh.smr[M - 1].nL + sh.smr[M - 1].nR;
+    WaveCount c;
+    wave_level<true>(sh.smr, M, N, e, pmax, wl, wl, false, out, save_roots ? w.org : nullptr,
+                     save_roots ? w.tau : nullptr, pk0, c);
+    if (c.bad) atomicOr(w.status, ST_SEC_NOCONV);
+    // the whole-merge workgroups' counters (the same work, counted alike)
+    count_add(w.counters, CNT_SEC_TERMS, c.terms);
+    count_add(w.counters, CNT_SWEEPS, c.sweeps);
+    count_add(w.counters, CNT_ROOTS, c.roots);
+    count_add(w.counters, CNT_LOW_PAIRS, c.lpairs);
+    count_add(w.counters, CNT_ROW_PAIRS, c.rpairs);
+    count_add(w.counters, CNT_LB_TERMS, c.terms);
+    count_add(w.counters, CNT_LB_LOW_PAIRS, c.lpairs);
+    count_add(w.counters, CNT_LB_ROW_PAIRS, c.rpairs);
+    count_add(w.counters, CNT_LB_ROOTS, c.roots);
+    count_add(w.counters, CNT_MERGE_COLS, c.mcols);
 }
 
 // ---------------------------------------------------------------------------
@@ -1360,33 +1468,116 @@ __device__ __forceinline__ void canon_for(int K, int sub, Body body) {
         if (c + off[q] < K) body(q, c + off[q]);
 }
 
-// sec_sweep with canonical partial sums (same per-term arithmetic).
+// The same canonical value from one lane: partial(s) accumulates terms
+// j = s, s + 16, ... in increasing j; the partials meet in the tree above:
+// B_q = (P_q + P_15-q) + (P_7-q + P_8+q) for q < 4, then (B_0 + B_2) +
+// (B_1 + B_3).  The B_q are formed one per loop trip (in the order 0, 2, 1,
+// 3) so that only four partials are live at a time.  Addition and
+// multiplication commute exactly, so the order inside each pair is free.
+template <class Part, class Op>
+__device__ __forceinline__ auto canon1(Part part, Op op) {
+    decltype(part(0)) c0{}, c1{};
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+        const int q = (t == 0) ? 0 : ((t == 1) ? 2 : ((t == 2) ? 1 : 3));
+        const auto b = op(op(part(q), part(15 - q)), op(part(7 - q), part(8 + q)));
+        if (t == 0) c0 = b;
+        else if (t == 1) c0 = op(c0, b);
+        else if (t == 2) c1 = b;
+        else c1 = op(c1, b);
+    }
+    return op(c0, c1);
+}
+
+struct Sums4 {
+    double a, b, c, d;
+};
+__device__ __forceinline__ Sums4 add4(const Sums4& x, const Sums4& y) {
+    return Sums4{x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d};
+}
+struct Sums3 {
+    double a, b, c;
+};
+__device__ __forceinline__ Sums3 add3(const Sums3& x, const Sums3& y) { return Sums3{x.a + y.a, x.b + y.b, x.c + y.c}; }
+__device__ __forceinline__ double add1(double x, double y) { return x + y; }
+__device__ __forceinline__ double mul1(double x, double y) { return x * y; }
+
+// sec_sweep with canonical partial sums (same per-term arithmetic): a group of
+// G = 4, 8 or 16 lanes, or one lane (G = 1).
 template <int G, bool ZZ>
 __device__ __forceinline__ void sec_sweep_c(int K, const double* __restrict__ D, const double* __restrict__ W,
                                             double Do, double tau, int L1, int R0, int sub, double* s) {
-    constexpr int M = Canon<G>::M;
-    double ps[M], dps[M], ph[M], dph[M], zz[M];
+    if constexpr (G == 1) {
+        static_assert(!ZZ, "one-lane sweeps sum z^2 separately");
+        const unsigned exw = (unsigned)(R0 - L1);
+        const Sums4 r = canon1(
+            [&](int q) {
+                Sums4 a{0.0, 0.0, 0.0, 0.0};
+                for (int j = q; j < K; j += 16) {
+                    const double wr = W[j];
+                    const double rr = rcp_nr((D[j] - Do) - tau);
+                    const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : wr;
+                    const double t = wj * rr;
+                    const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
+                    a.a += tl;
+                    a.b = fma(tl, rr, a.b);
+                    a.c += th;
+                    a.d = fma(th, rr, a.d);
+                }
+                return a;
+            },
+            add4);
+        s[0] = r.a;
+        s[1] = r.b;
+        s[2] = r.c;
+        s[3] = r.d;
+    } else {
+        constexpr int M = Canon<G>::M;
+        double ps[M], dps[M], ph[M], dph[M], zz[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) ps[q] = dps[q] = ph[q] = dph[q] = zz[q] = 0.0;
-    const unsigned exw = (unsigned)(R0 - L1);
-    canon_for<G>(K, sub, [&](int q, int j) {
-        const double wr = W[j];
-        const double rr = rcp_nr((D[j] - Do) - tau);
-        const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : wr;
-        const double t = wj * rr;
-        const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
-        ps[q] += tl;
-        dps[q] = fma(tl, rr, dps[q]);
-        ph[q] += th;
-        dph[q] = fma(th, rr, dph[q]);
-        if (ZZ) zz[q] += wr;
-    });
-    s[0] = Canon<G>::sum(ps);
-    s[1] = Canon<G>::sum(dps);
-    s[2] = Canon<G>::sum(ph);
-    s[3] = Canon<G>::sum(dph);
-    if (ZZ) s[4] = Canon<G>::sum(zz);
+        for (int q = 0; q < M; ++q) ps[q] = dps[q] = ph[q] = dph[q] = zz[q] = 0.0;
+        const unsigned exw = (unsigned)(R0 - L1);
+        canon_for<G>(K, sub, [&](int q, int j) {
+            const double wr = W[j];
+            const double rr = rcp_nr((D[j] - Do) - tau);
+            const double wj = ((unsigned)(j - L1) < exw) ? 0.0 : wr;
+            const double t = wj * rr;
+            const double tl = fmin(t, 0.0), th = fmax(t, 0.0);
+            ps[q] += tl;
+            dps[q] = fma(tl, rr, dps[q]);
+            ph[q] += th;
+            dph[q] = fma(th, rr, dph[q]);
+            if (ZZ) zz[q] += wr;
+        });
+        s[0] = Canon<G>::sum(ps);
+        s[1] = Canon<G>::sum(dps);
+        s[2] = Canon<G>::sum(ph);
+        s[3] = Canon<G>::sum(dph);
+        if (ZZ) s[4] = Canon<G>::sum(zz);
+    }
 }
+
+// Canonical sum of W[0..K).
+template <int G>
+__device__ __forceinline__ double canon_wsum(int K, const double* __restrict__ W, int sub) {
+    if constexpr (G == 1) {
+        return canon1(
+            [&](int q) {
+                double a = 0.0;
+                for (int j = q; j < K; j += 16) a += W[j];
+                return a;
+            },
+            add1);
+    } else {
+        constexpr int M = Canon<G>::M;
+        double zz[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) zz[q] = 0.0;
+        canon_for<G>(K, sub, [&](int q, int j) { zz[q] += W[j]; });
+        return Canon<G>::sum(zz);
+    }
+}
+
 
 // secular_root with canonical sweeps (same iteration and stopping rules).
 template <int G>
@@ -1409,12 +1600,7 @@ __device__ __forceinline__ int secular_root_c(int k, int K, const double* __rest
             return 0;
         }
     } else {
-        constexpr int M = Canon<G>::M;
-        double zz[M];
-#pragma unroll
-        for (int q = 0; q < M; ++q) zz[q] = 0.0;
-        canon_for<G>(K, sub, [&](int q, int j) { zz[q] += W[j]; });
-        sec_start_last(K, D, Z, rho, Canon<G>::sum(zz), &r);
+        sec_start_last(K, D, Z, rho, canon_wsum<G>(K, W, sub), &r);
     }
     for (int it = 1; it <= cap; ++it) {
         int L1, R0;
@@ -1437,35 +1623,63 @@ template <int G>
 __device__ __forceinline__ double lowner_z_c(int i, int K, const double* __restrict__ D,
                                              const double* __restrict__ Z, const int* __restrict__ org,
                                              const double* __restrict__ tau, double rho, int sub) {
-    constexpr int M = Canon<G>::M;
     const double di = D[i];
-    double prod[M], pn[M], pd[M];
-    int cnt[M];
+    if constexpr (G == 1) {
+        const double z2 = canon1(
+                              [&](int q) {
+                                  double prod = 1.0, pn = 1.0, pd = 1.0;
+                                  int cnt = 0;
+                                  for (int k = q; k < K; k += 16) {
+                                      const double num = (D[org[k]] - di) + tau[k];
+                                      double den;
+                                      if (k < i) den = D[k] - di;
+                                      else if (k < K - 1) den = D[k + 1] - di;
+                                      else den = 1.0;
+                                      pn *= num;
+                                      pd *= den;
+                                      if (++cnt == 8) {
+                                          prod *= pn / pd;
+                                          pn = 1.0;
+                                          pd = 1.0;
+                                          cnt = 0;
+                                      }
+                                  }
+                                  return prod * (pn / pd);
+                              },
+                              mul1) /
+                          rho;
+        const double zi = sqrt(fmax(z2, 0.0));
+        return (Z[i] < 0.0) ? -zi : zi;
+    } else {
+        constexpr int M = Canon<G>::M;
+        double prod[M], pn[M], pd[M];
+        int cnt[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        prod[q] = pn[q] = pd[q] = 1.0;
-        cnt[q] = 0;
-    }
-    canon_for<G>(K, sub, [&](int q, int k) {
-        const double num = (D[org[k]] - di) + tau[k];
-        double den;
-        if (k < i) den = D[k] - di;
-        else if (k < K - 1) den = D[k + 1] - di;
-        else den = 1.0;
-        pn[q] *= num;
-        pd[q] *= den;
-        if (++cnt[q] == 8) {
-            prod[q] *= pn[q] / pd[q];
-            pn[q] = 1.0;
-            pd[q] = 1.0;
+        for (int q = 0; q < M; ++q) {
+            prod[q] = pn[q] = pd[q] = 1.0;
             cnt[q] = 0;
         }
-    });
+        canon_for<G>(K, sub, [&](int q, int k) {
+            const double num = (D[org[k]] - di) + tau[k];
+            double den;
+            if (k < i) den = D[k] - di;
+            else if (k < K - 1) den = D[k + 1] - di;
+            else den = 1.0;
+            pn[q] *= num;
+            pd[q] *= den;
+            if (++cnt[q] == 8) {
+                prod[q] *= pn[q] / pd[q];
+                pn[q] = 1.0;
+                pd[q] = 1.0;
+                cnt[q] = 0;
+            }
+        });
 #pragma unroll
-    for (int q = 0; q < M; ++q) prod[q] *= pn[q] / pd[q];
-    const double z2 = Canon<G>::prod(prod) / rho;
-    const double zi = sqrt(fmax(z2, 0.0));
-    return (Z[i] < 0.0) ? -zi : zi;
+        for (int q = 0; q < M; ++q) prod[q] *= pn[q] / pd[q];
+        const double z2 = Canon<G>::prod(prod) / rho;
+        const double zi = sqrt(fmax(z2, 0.0));
+        return (Z[i] < 0.0) ? -zi : zi;
+    }
 }
 
 // root_rows with canonical partial sums.
@@ -1473,20 +1687,106 @@ template <int G>
 __device__ __forceinline__ void root_rows_c(int K, const double* __restrict__ D, const double* __restrict__ zh,
                                             const double* __restrict__ RL, const double* __restrict__ RH, int org,
                                             double tau, int sub, double* bl_out, double* bh_out) {
-    constexpr int M = Canon<G>::M;
     const double Do = D[org];
-    double ss[M], bl[M], bh[M];
+    if constexpr (G == 1) {
+        const Sums3 r = canon1(
+            [&](int q) {
+                Sums3 a{0.0, 0.0, 0.0};
+                for (int i = q; i < K; i += 16) {
+                    const double y = zh[i] * rcp_nr((D[i] - Do) - tau);
+                    a.a = fma(y, y, a.a);
+                    a.b = fma(RL[i], y, a.b);
+                    a.c = fma(RH[i], y, a.c);
+                }
+                return a;
+            },
+            add3);
+        const double inv = 1.0 / sqrt(r.a);
+        *bl_out = r.b * inv;
+        *bh_out = r.c * inv;
+    } else {
+        constexpr int M = Canon<G>::M;
+        double ss[M], bl[M], bh[M];
 #pragma unroll
-    for (int q = 0; q < M; ++q) ss[q] = bl[q] = bh[q] = 0.0;
-    canon_for<G>(K, sub, [&](int q, int i) {
-        const double y = zh[i] * rcp_nr((D[i] - Do) - tau);
-        ss[q] = fma(y, y, ss[q]);
-        bl[q] = fma(RL[i], y, bl[q]);
-        bh[q] = fma(RH[i], y, bh[q]);
-    });
-    const double inv = 1.0 / sqrt(Canon<G>::sum(ss));
-    *bl_out = Canon<G>::sum(bl) * inv;
-    *bh_out = Canon<G>::sum(bh) * inv;
+        for (int q = 0; q < M; ++q) ss[q] = bl[q] = bh[q] = 0.0;
+        canon_for<G>(K, sub, [&](int q, int i) {
+            const double y = zh[i] * rcp_nr((D[i] - Do) - tau);
+            ss[q] = fma(y, y, ss[q]);
+            bl[q] = fma(RL[i], y, bl[q]);
+            bh[q] = fma(RH[i], y, bh[q]);
+        });
+        const double inv = 1.0 / sqrt(Canon<G>::sum(ss));
+        *bl_out = Canon<G>::sum(bl) * inv;
+        *bh_out = Canon<G>::sum(bh) * inv;
+    }
+}
+
+// The root steps of an in-wave level (k_level_wave): one lane per active
+// root, each merge's arrays read in place from the level arrays in LDS; the
+// same arithmetic and canonical sums as small_merge_body (one lane per root
+// repeats no root's update across lanes, which on merges this small costs
+// more than the sums themselves).
+__device__ void wave_roots_canon(const MergeRec* smr, int K, const double* __restrict__ e,
+                                 const unsigned long long* __restrict__ pmax, const Work& wl,
+                                 int* __restrict__ corg, double* __restrict__ ctau, long long pk0, WaveCount& c) {
+    constexpr int G = 1;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane % G;
+    for (int g = lane / G; g < K; g += 64 / G) {  // group-uniform
+        const MergeRec R = smr[wl.amerge[g]];
+        const MergeSpan sp = merge_span(R, wl.scan);
+        double sgn;
+        const double rho = merge_rho(R, e, pmax, &sgn);
+        const double* D = wl.Da + sp.ks;
+        int o;
+        double tau;
+        const int it = secular_root_c<G>((int)(g - sp.ks), sp.K, D, wl.Za + sp.ks, wl.Wa + sp.ks, rho, sub,
+                                         wl.sec_cap, &o, &tau);
+        if (sub == 0) {
+            if (it < 0) c.bad = 1;
+            wl.org[g] = o;
+            wl.tau[g] = tau;
+            wl.rootval[g] = D[o] + tau;
+            const unsigned long long sw = (sp.K > 1) ? (unsigned long long)((it < 0 ? wl.sec_cap : it) + 1) : 0ULL;
+            c.sweeps += sw;
+            c.terms += sw * (unsigned long long)sp.K;
+            c.roots += 1;
+            if (corg) {
+                const long long gp = pk0 + R.pk + (g - sp.ks);
+                corg[gp] = o;
+                ctau[gp] = tau;
+            }
+        }
+    }
+    __syncthreads();
+    for (int g = lane / G; g < K; g += 64 / G) {
+        const MergeRec R = smr[wl.amerge[g]];
+        if ((R.flags & MF_ROOT) && !wl.rows_out) continue;  // group-uniform
+        const MergeSpan sp = merge_span(R, wl.scan);
+        double sgn;
+        const double rho = merge_rho(R, e, pmax, &sgn);
+        const double zh = lowner_z_c<G>((int)(g - sp.ks), sp.K, wl.Da + sp.ks, wl.Za + sp.ks, wl.org + sp.ks,
+                                        wl.tau + sp.ks, rho, sub);
+        if (sub == 0) {
+            wl.zhat[g] = zh;
+            c.lpairs += (unsigned long long)sp.K;
+        }
+    }
+    __syncthreads();
+    for (int g = lane / G; g < K; g += 64 / G) {
+        const MergeRec R = smr[wl.amerge[g]];
+        if ((R.flags & MF_ROOT) && !wl.rows_out) continue;
+        const MergeSpan sp = merge_span(R, wl.scan);
+        double bl, bh;
+        root_rows_c<G>(sp.K, wl.Da + sp.ks, wl.zhat + sp.ks, wl.RLa + sp.ks, wl.RHa + sp.ks, wl.org[g], wl.tau[g],
+                       sub, &bl, &bh);
+        if (sub == 0) {
+            wl.PBL[g] = bl;
+            wl.PBH[g] = bh;
+            c.rpairs += (unsigned long long)sp.K;
+        }
+    }
+    __syncthreads();
 }
 
 // cbase: the first of the four counters (terms, Loewner pairs, row pairs,
@@ -1629,10 +1929,20 @@ constexpr int kLevelBlockMaxMerges = 1024;
 #endif
 constexpr int kLevelBlockSmallCols = TDE_LEVEL_BLOCK_SMALL_COLS;
 
-// Levels run by k_level_block (forward; the reverse pass reads their
-// checkpointed roots from the merges' packed positions).
+// Levels of more merges than this, all of at most kDcCols columns, run in
+// waves (k_level_wave) in the forward passes that keep no rows; fewer merges
+// keep k_level_block, whose wider workgroups shorten each merge's chain.
+#ifndef TDE_LEVEL_WAVE_MIN_MERGES
+#define TDE_LEVEL_WAVE_MIN_MERGES 1024
+#endif
+constexpr int kLevelWaveMinMerges = TDE_LEVEL_WAVE_MIN_MERGES;
+
+static bool level_waved(const LevelInfo& L) { return L.nwp > 0 && L.M > kLevelWaveMinMerges; }
+
+// Levels run by k_level_block or k_level_wave (forward; the reverse pass reads
+// their checkpointed roots from the merges' packed positions).
 static bool level_blocked(const LevelInfo& L) {
-    return L.smax <= kFuseMax && (L.M <= kLevelBlockMaxMerges || L.smax <= kLevelBlockSmallCols);
+    return level_waved(L) || (L.smax <= kFuseMax && (L.M <= kLevelBlockMaxMerges || L.smax <= kLevelBlockSmallCols));
 }
 
 template <int NT, int CAP>
@@ -2060,16 +2370,28 @@ __global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ m
     }
 }
 
-// One run per group of G lanes (grid-stride over the candidates).
+// Candidates one per lane (grid-stride): those in no run pass straight
+// through, and each group of G lanes then takes, one after another, the runs
+// that start among its G candidates.
 template <int G>
 __global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, Work w, Grad gr, long long cstride) {
     if (input_nonfinite(w)) return;
     const long long total = w.scanC[N];
-    const int sub = (int)(threadIdx.x % G);
-    const long long stride = (long long)gridDim.x * (blockDim.x / G);
-    for (long long g = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G; g < total; g += stride)
-        body_bwd_runs<RedGroup<G>>(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr, cstride, sub, G);
+    const int lane = (int)(threadIdx.x & 63);
+    const int sub = lane % G;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x - sub); g0 < total; g0 += stride) {
+        const long long g = g0 + sub;
+        const bool head = g < total && bwd_run_head(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr);
+        // this group's G bits of the wave's ballot (group-uniform)
+        unsigned long long heads = (__ballot(head) >> (lane - sub)) & ((G == 64) ? ~0ull : ((1ull << G) - 1));
+        while (heads) {
+            const long long h = g0 + __builtin_ctzll(heads);
+            heads &= heads - 1;
+            body_bwd_runs<RedGroup<G>>(h, merge_of(mr, blkm, w.nnpos[h]), mr, w, gr, cstride, sub, G);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
@@ -2080,36 +2402,43 @@ __global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ 
     if (t < N) body_bwd_merge(t, merge_of(mr, blkm, t), mr, e, pmax, w, gr);
 }
 
-// Leaves: 64 / LMAX leaves per 64-lane workgroup, one lane per leaf row.
-// Each lane recomputes the QL on its own copy of the leaf (LDS, lane-strided)
-// tracking its row of Q; the leaf's Q and X are shared in LDS.
-template <int LMAX>
+// Leaves: LMAX / R lanes per leaf, R rows per lane (64 R / LMAX leaves per
+// 64-lane workgroup).  Each lane recomputes the QL on its own copy of the leaf
+// (LDS, lane-strided) tracking its rows of Q; the leaf's Q (leading dimension
+// LMAX) is shared in LDS, and X takes the space of the QL copies once every
+// lane is done with them.  Fewer lanes per leaf repeat the QL fewer times.
+template <int LMAX, int R>
 __global__ __launch_bounds__(64) void k_bwd_leaf(const LeafRec* __restrict__ leaves, int nleaves,
                                                  const double* __restrict__ d, const double* __restrict__ e,
                                                  const unsigned long long* __restrict__ pmax, Work w, Grad gr,
                                                  double* __restrict__ gd, double* __restrict__ ge) {
     if (input_nonfinite(w)) return;
-    constexpr int P = 64 / LMAX;
-    __shared__ double sd[LMAX * 64], se[LMAX * 64];
-    __shared__ double sQ[P * LMAX * LMAX], sX[P * LMAX * LMAX], sL[64];
+    constexpr int LPL = LMAX / R;  // lanes per leaf
+    constexpr int P = 64 / LPL;    // leaves per workgroup
+    static_assert(LPL * R == LMAX && P * LPL == 64, "lanes per leaf divide the wave");
+    static_assert(P * LMAX * LMAX <= 2 * LMAX * 64, "X fits in the QL copies");
+    __shared__ double sde[2 * LMAX * 64];
+    __shared__ double sQ[P * LMAX * LMAX], sL[P * LMAX];
     const int lane = threadIdx.x;
-    const int slot = lane / LMAX, r = lane % LMAX;
+    const int slot = lane / LPL, sub = lane % LPL;
     const long long li = (long long)blockIdx.x * P + slot;
     LeafRec L{};
     bool act = false;
     if (li < nleaves) {
         L = leaves[li];
-        act = r < L.size;
+        act = sub < L.size;
     }
     double* Q = sQ + slot * LMAX * LMAX;
-    double* X = sX + slot * LMAX * LMAX;
     double* lam = sL + slot * LMAX;
     int st = 0;
-    if (act) st = body_bwd_leaf_q(L, r, d, e, pmax, sd + lane, se + lane, 64, Q, lam);
+    if (act) st = bwd_leaf_q<R>(L, sub, LPL, d, e, pmax, sde + lane, sde + LMAX * 64 + lane, 64, Q, LMAX, lam);
     __syncthreads();
-    if (act) body_bwd_leaf_x(L, r, gr, Q, lam, X);
+    double* X = sde + slot * LMAX * LMAX;
+    if (act)
+        for (int r = sub; r < L.size; r += LPL) body_bwd_leaf_x(L, r, gr, Q, LMAX, lam, X);
     __syncthreads();
-    if (act) body_bwd_leaf_out(L, r, gr, Q, X, gd, ge);
+    if (act)
+        for (int r = sub; r < L.size; r += LPL) body_bwd_leaf_out(L, r, gr, Q, X, LMAX, gd, ge);
     if (st) atomicOr(w.status, st);
 }
 
@@ -2448,9 +2777,14 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             wl.tau = ck->tau + so;
         }
         if (level_blocked(L)) {
-            // every merge of the level fits one workgroup: the whole merge in one launch
-            // (with a checkpoint, its roots land at the merge's packed positions)
-            launch_level_block(L.smax, mr, M, e, wl, out, fused_gmax(M, p.group_max), stream);
+            // every merge of the level fits one workgroup (or a pack of them one
+            // wave): the whole merge in one launch (with a checkpoint, its roots
+            // land at the merge's packed positions)
+            if (level_waved(L) && !w.rows_out && !xsrc)
+                TDE_LAUNCH_K(KIND_LEVEL, k_level_wave, (unsigned)L.nwp, 64, stream, mr, p.d_blkm + L.wpstart, e,
+                             (const unsigned long long*)w.pmax, wl, out, ck ? 1 : 0);
+            else
+                launch_level_block(L.smax, mr, M, e, wl, out, fused_gmax(M, p.group_max), stream);
             continue;
         }
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
@@ -2484,9 +2818,9 @@ template <int G>
 static void launch_bwd_defl(long long N, const MergeRec* mr, const int* blkm, const Work& w,
                             const Grad& gr, long long cs, void* stream) {
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl<G>, nblk(N * G, kWG), kWG, stream, mr, blkm, N, w, gr, cs);
-    const unsigned gr_runs = nblk(N * G, kWG);
-    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs<G>, gr_runs < 4096u * G ? gr_runs : 4096u * G, kWG, stream, mr, blkm, N,
-                 w, gr, cs);
+    const unsigned gr_runs = nblk(N, kWG);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs<G>, gr_runs < 4096u ? gr_runs : 4096u, kWG, stream, mr, blkm, N, w, gr,
+                 cs);
 }
 
 int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
@@ -2541,17 +2875,17 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
     }
     if (p.nleaves > 0) {
         if (p.leafmax <= 8)
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<8>, nblk(p.nleaves, 8), 64, stream, p.d_leaves, p.nleaves, d, e,
-                         w.pmax, w, gr, gd, ge);
+            TDE_LAUNCH_K(KIND_BACKWARD, (k_bwd_leaf<8, 2>), nblk(p.nleaves, 16), 64, stream, p.d_leaves, p.nleaves, d,
+                         e, w.pmax, w, gr, gd, ge);
         else if (p.leafmax <= 16)
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<16>, nblk(p.nleaves, 4), 64, stream, p.d_leaves, p.nleaves, d, e,
-                         w.pmax, w, gr, gd, ge);
+            TDE_LAUNCH_K(KIND_BACKWARD, (k_bwd_leaf<16, 1>), nblk(p.nleaves, 4), 64, stream, p.d_leaves, p.nleaves, d,
+                         e, w.pmax, w, gr, gd, ge);
         else if (p.leafmax <= 32)
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<32>, nblk(p.nleaves, 2), 64, stream, p.d_leaves, p.nleaves, d, e,
-                         w.pmax, w, gr, gd, ge);
+            TDE_LAUNCH_K(KIND_BACKWARD, (k_bwd_leaf<32, 1>), nblk(p.nleaves, 2), 64, stream, p.d_leaves, p.nleaves, d,
+                         e, w.pmax, w, gr, gd, ge);
         else
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_leaf<64>, (unsigned)p.nleaves, 64, stream, p.d_leaves, p.nleaves, d, e,
-                         w.pmax, w, gr, gd, ge);
+            TDE_LAUNCH_K(KIND_BACKWARD, (k_bwd_leaf<64, 1>), (unsigned)p.nleaves, 64, stream, p.d_leaves, p.nleaves,
+                         d, e, w.pmax, w, gr, gd, ge);
     }
     if (p.nmerges > 0)
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_tear, nblk(p.nmerges, kWG), kWG, stream, p.d_merges, p.nmerges, e,

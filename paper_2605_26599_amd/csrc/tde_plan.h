@@ -16,6 +16,9 @@ struct LevelInfo {
     long long N;  // packed columns in this level (sum of merge sizes)
     int smax;     // largest merge (columns) in this level
     int bstart;   // first entry of this level's per-block merge table
+    int wpstart;  // levels of merges of at most kLeafMax columns: first entry of the
+                  // in-wave pack table (first merge of every pack, then M) in h_blkm
+    int nwp;      // packs of such a level (0: none)
 };
 
 struct Plan {
@@ -36,7 +39,8 @@ struct Plan {
     std::vector<LevelInfo> levels;
     // host tables (plan_host), uploaded to the device tables below
     std::vector<MergeRec> h_merges;  // every merge, level after level
-    std::vector<int> h_blkm;         // per level, per block of kWG packed columns: first merge touched
+    std::vector<int> h_blkm;         // per level, per block of kWG packed columns: first merge touched;
+                                     // then the level's in-wave pack table, if any
     std::vector<LeafRec> h_leaves;
     std::vector<SubHdr> h_shdr;      // in-wave merge trees by leaf size (leaf_dc only)
     std::vector<SubMerge> h_smer;

@@ -50,6 +50,23 @@ int plan_host(Plan* p) {
             while (m + 1 < info.M && t.merges[info.mstart + m + 1].pk <= c) ++m;
             p->h_blkm.push_back(m);
         }
+        // in-wave packs: consecutive merges, at most kLeafMax columns per pack
+        info.wpstart = (int)p->h_blkm.size();
+        info.nwp = 0;
+        if (info.smax <= kLeafMax) {
+            int cols = 0;
+            for (int j = 0; j < info.M; ++j) {
+                const MergeRec& R = t.merges[info.mstart + j];
+                const int s = R.nL + R.nR;
+                if (j == 0 || cols + s > kLeafMax) {
+                    p->h_blkm.push_back(j);
+                    ++info.nwp;
+                    cols = 0;
+                }
+                cols += s;
+            }
+            p->h_blkm.push_back(info.M);
+        }
         maxM = std::max(maxM, info.M);
         maxN = std::max(maxN, info.N);
         p->levels.push_back(info);

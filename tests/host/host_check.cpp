@@ -87,6 +87,29 @@ static void check_plan(const std::vector<long long>& offs, int leaf, bool dc) {
             const MergeRec& R = p.h_merges[(size_t)(I.mstart + m)];
             CHECK(R.pk <= c && c < R.pk + R.nL + R.nR);
         }
+        // in-wave packs (levels of merges of at most kLeafMax columns): ascending
+        // first merges from 0, then M; each pack at most kLeafMax columns, and no
+        // pack could have taken its successor's first merge
+        CHECK(I.wpstart == (int)bi);
+        if (I.smax <= kLeafMax) {
+            CHECK(I.nwp >= 1 && bi + (size_t)I.nwp + 1 <= p.h_blkm.size());
+            CHECK(p.h_blkm[bi] == 0 && p.h_blkm[bi + (size_t)I.nwp] == I.M);
+            for (int k = 0; k < I.nwp; ++k) {
+                const int a = p.h_blkm[bi + (size_t)k], z = p.h_blkm[bi + (size_t)k + 1];
+                CHECK(a < z);
+                const MergeRec& A = p.h_merges[(size_t)(I.mstart + a)];
+                const MergeRec& Z = p.h_merges[(size_t)(I.mstart + z - 1)];
+                const long long cols = Z.pk + Z.nL + Z.nR - A.pk;
+                CHECK(cols <= kLeafMax);
+                if (z < I.M) {
+                    const MergeRec& F = p.h_merges[(size_t)(I.mstart + z)];
+                    CHECK(cols + F.nL + F.nR > kLeafMax);
+                }
+            }
+            bi += (size_t)I.nwp + 1;
+        } else {
+            CHECK(I.nwp == 0);
+        }
     }
     CHECK(bi == p.h_blkm.size());
     // every problem of more than `leaf` columns ends with its root merge

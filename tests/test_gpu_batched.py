@@ -78,6 +78,27 @@ def test_batched_equals_single(tde):
         assert np.array_equal(one, lam[lo:hi]), b
 
 
+@pytest.mark.parametrize("fam", ["uniform", "clustered", "wilkinson"])
+def test_wave_levels_equal_block_levels(tde, fam):
+    """Levels of more than 1024 merges of at most 64 columns run one wave per
+    pack of merges, levels of fewer merges one workgroup per merge; the roots
+    take the same canonical sums either way, so a problem's eigenvalues do not
+    depend on how many problems share its levels (1500 problems of 40..64
+    columns at leaf 8: every level waved, root merges included; their first 64
+    alone: every level in workgroups)."""
+    _step(f"in-wave levels == whole-merge workgroups, {fam}")
+    probs = [tdgen.tridiag(fam, 40 + (i % 25), inst=i) for i in range(1500)]
+    big, small = tdgen.pack(probs), tdgen.pack(probs[:64])
+    a = _solve_batch(tde, big, leaf=8)
+    b = _solve_batch(tde, small, leaf=8)
+    n = int(small.offsets[-1])
+    assert np.array_equal(a[:n], b)
+    for p in range(0, 64, 9):
+        _check_problem(small, b, p)
+    for p in range(64, 1500, 97):
+        _check_problem(big, a, p)
+
+
 def test_c4_batched_4096(tde):
     """Every problem of the batch: 48 bisected in full, all 4096 certified
     eigenvalue by eigenvalue with two Sturm counts each."""
