@@ -232,7 +232,8 @@ struct WaveCount {
 };
 
 // Roots, Loewner z and rows of an in-wave level with the canonical group sums
-// of the whole-merge workgroups (defined with them below).
+// of the whole-merge workgroups (defined with them below), G lanes per root.
+template <int G>
 __device__ void wave_roots_canon(const MergeRec* smr, int K, const double* __restrict__ e,
                                  const unsigned long long* __restrict__ pmax, const Work& wl,
                                  int* __restrict__ corg, double* __restrict__ ctau, long long pk0, WaveCount& c);
@@ -247,11 +248,11 @@ __device__ void wave_roots_canon(const MergeRec* smr, int K, const double* __res
 // through wl, or through wt when `top` (or the scaled eigenvalues to out for a
 // problem's top merge).
 // With corg, every root's origin and offset are also stored at the merge's
-// packed position pk0 + smr[m].pk + (root index within the merge).  Canonical:
-// the root steps take four lanes per root and the canonical group sums, so a
-// level gives the same bits as in a whole-merge workgroup; otherwise one lane
+// packed position pk0 + smr[m].pk + (root index within the merge).  CG > 0:
+// the root steps take CG lanes per root and the canonical group sums, so a
+// level gives the same bits as in a whole-merge workgroup; CG = 0: one lane
 // per root sums serially.
-template <bool Canonical>
+template <int CG>
 __device__ __forceinline__ void wave_level(const MergeRec* smr, int M, int N, const double* __restrict__ e,
                                            const unsigned long long* __restrict__ pmax, const Work& wl,
                                            const Work& wt, bool top, double* __restrict__ out,
@@ -313,8 +314,8 @@ __device__ __forceinline__ void wave_level(const MergeRec* smr, int M, int N, co
     __syncthreads();
     // secular roots, Loewner z, boundary rows
     const int K = (int)__popcll(am);
-    if (Canonical) {
-        wave_roots_canon(smr, K, e, pmax, wl, corg, ctau, pk0, c);
+    if constexpr (CG > 0) {
+        wave_roots_canon<CG>(smr, K, e, pmax, wl, corg, ctau, pk0, c);
         if (lane < N) body_assemble(lane, find_merge(smr, M, lane), smr, pmax, wl, out);
         __syncthreads();
         return;
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
         }
         __syncthreads();
         const int N = (int)sh.smr[M - 1].pk + sh.smr[M - 1].nL + sh.smr[M - 1].nR;
-        wave_level<false>(sh.smr, M, N, eL, pmax, wl, wt, top, outL, nullptr, nullptr, 0, c);
+        wave_level<0>(sh.smr, M, N, eL, pmax, wl, wt, top, outL, nullptr, nullptr, 0, c);
     }
     if (c.bad) atomicOr(w.status, ST_SEC_NOCONV);
     count_add(w.counters, CNT_DC_TERMS, c.terms);
@@ -452,8 +453,11 @@ __global__ __launch_bounds__(64) void k_leaf_dc(const LeafRec* __restrict__ leav
 // chain of LDS steps per wave instead of global-memory round trips per step,
 // and up to four small merges per wave instead of a mostly idle workgroup
 // each.  With corg (a checkpointing forward), the roots land at the merges'
-// packed positions as k_level_block stores them.
+// packed positions as k_level_block stores them.  G lanes per root: one on
+// levels of merges of at most 32 columns (a root's update costs more than its
+// few terms there), four on merges of up to 64.
 // ---------------------------------------------------------------------------
+template <int G>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_level_wave(const MergeRec* __restrict__ mr, const int* __restrict__ packs,
                                                   const double* __restrict__ e,
                                                   const unsigned long long* __restrict__ pmax, Work w,
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __syncthreads();
     const int N = (int)sh.smr[M - 1].pk + sh.smr[M - 1].nL + sh.smr[M - 1].nR;
     WaveCount c;
-    wave_level<true>(sh.smr, M, N, e, pmax, wl, wl, false, out, save_roots ? w.org : nullptr,
+    wave_level<G>(sh.smr, M, N, e, pmax, wl, wl, false, out, save_roots ? w.org : nullptr,
                      save_roots ? w.tau : nullptr, pk0, c);
     if (c.bad) atomicOr(w.status, ST_SEC_NOCONV);
     // the whole-merge workgroups' counters (the same work, counted alike)
@@ -1721,15 +1725,13 @@ __device__ __forceinline__ void root_rows_c(int K, const double* __restrict__ D,
     }
 }
 
-// The root steps of an in-wave level (k_level_wave): one lane per active
-// root, each merge's arrays read in place from the level arrays in LDS; the
-// same arithmetic and canonical sums as small_merge_body (one lane per root
-// repeats no root's update across lanes, which on merges this small costs
-// more than the sums themselves).
+// The root steps of an in-wave level (k_level_wave): G lanes per active root
+// (64 / G roots at a time), each merge's arrays read in place from the level
+// arrays in LDS; the same arithmetic and canonical sums as small_merge_body.
+template <int G>
 __device__ void wave_roots_canon(const MergeRec* smr, int K, const double* __restrict__ e,
                                  const unsigned long long* __restrict__ pmax, const Work& wl,
                                  int* __restrict__ corg, double* __restrict__ ctau, long long pk0, WaveCount& c) {
-    constexpr int G = 1;
     const int lane = threadIdx.x & 63;
     const int sub = lane % G;
     for (int g = lane / G; g < K; g += 64 / G) {  // group-uniform
@@ -2780,8 +2782,11 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
             // every merge of the level fits one workgroup (or a pack of them one
             // wave): the whole merge in one launch (with a checkpoint, its roots
             // land at the merge's packed positions)
-            if (level_waved(L) && !w.rows_out && !xsrc)
-                TDE_LAUNCH_K(KIND_LEVEL, k_level_wave, (unsigned)L.nwp, 64, stream, mr, p.d_blkm + L.wpstart, e,
+            if (level_waved(L) && !w.rows_out && !xsrc && L.smax <= 32)
+                TDE_LAUNCH_K(KIND_LEVEL, k_level_wave<1>, (unsigned)L.nwp, 64, stream, mr, p.d_blkm + L.wpstart, e,
+                             (const unsigned long long*)w.pmax, wl, out, ck ? 1 : 0);
+            else if (level_waved(L) && !w.rows_out && !xsrc)
+                TDE_LAUNCH_K(KIND_LEVEL, k_level_wave<4>, (unsigned)L.nwp, 64, stream, mr, p.d_blkm + L.wpstart, e,
                              (const unsigned long long*)w.pmax, wl, out, ck ? 1 : 0);
             else
                 launch_level_block(L.smax, mr, M, e, wl, out, fused_gmax(M, p.group_max), stream);
