@@ -329,7 +329,7 @@ def grad_case(tde, dev, name):
     return d, e, w, offs, n
 
 
-def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None):
+def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None, gmax=None):
     """Checkpointing forward + backward step (all buffers resident)."""
     import torch
 
@@ -339,10 +339,10 @@ def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None):
     ck = torch.empty(tde.checkpoint_bytes(n, offs, leaf, cols), dtype=torch.uint8, device=dev)
 
     def fb():
-        tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks, out=out,
-                         ckpt=ck, check=False)
+        tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks,
+                         group_max=gmax, out=out, ckpt=ck, check=False)
         tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks,
-                             gd=gd, ge=ge, check=False)
+                             group_max=gmax, gd=gd, ge=ge, check=False)
     return fb
 
 
@@ -355,7 +355,7 @@ def grad_only(args):
     dev = torch.device("cuda:0")
     d, e, w, offs, n = grad_case(tde, dev, args.grad)
     leaf, cols, wide = args.leaf or 8, args.sweep_cols or 16, args.wide_min or 1024
-    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, args.wide_blocks or None)
+    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, args.wide_blocks or None, args.group_max or None)
     for _ in range(max(args.warmup, 1)):
         fb()
     torch.cuda.synchronize()
@@ -363,7 +363,8 @@ def grad_only(args):
     print(json.dumps({"metric": "fwd+bwd ms", "value": ms, "unit": "ms", "steps": args.steps,
                       "higher_is_better": False,
                       "config": {"workload": f"gradient {args.grad}", "leaf": leaf, "sweep_cols": cols,
-                                 "wide_min": wide, "wide_blocks": args.wide_blocks or None}}), flush=True)
+                                 "wide_min": wide, "wide_blocks": args.wide_blocks or None,
+                                 "group_max": args.group_max or None}}), flush=True)
 
 
 def grad_ratio(tde, dev, reps=20):
