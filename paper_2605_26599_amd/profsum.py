@@ -22,9 +22,14 @@ import sys
 from collections import defaultdict
 
 
+def _short(name: str) -> str:
+    """Kernel name without namespaces, return type and parameter list."""
+    name = name.replace("(anonymous namespace)::", "")
+    return re.sub(r"\(.*", "", name).replace("void ", "").replace("tde::", "").strip()
+
+
 def _family(name: str) -> str:
-    short = re.sub(r"\(.*", "", name).replace("void ", "").replace("tde::", "").strip()
-    return re.sub(r"<.*>", "", short)
+    return re.sub(r"<.*>", "", _short(name))
 
 
 def stats(stats_csv, bench_jsonl, out_md, title, cmd):
@@ -43,14 +48,16 @@ def stats(stats_csv, bench_jsonl, out_md, title, cmd):
     lines += ["", "Instances as reported by rocprofv3 (`--stats`):", "",
               "| name | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
-        short = re.sub(r"\(.*", "", r["Name"]).replace("void ", "").replace("tde::", "")
+        short = _short(r["Name"])
         lines.append(f"| {short} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
     b = json.loads([ln for ln in open(bench_jsonl) if ln.startswith("{")][-1])
     rf = b.get("roofline")
     if rf:
-        # the eight-wave launches of wide-only levels belong to the same step
-        parts = [agg[k] for k in (rf["kernel"], rf["kernel"] + "_wide") if k in agg]
+        # the eight-wave launches of wide-only levels belong to the same step, and
+        # the in-wave whole-merge launches to the same kind as k_level_block
+        fams = (rf["kernel"], rf["kernel"] + "_wide") + (("k_level_wave",) if rf["kernel"] == "k_level_block" else ())
+        parts = [agg[k] for k in fams if k in agg]
         fam = [sum(p[0] for p in parts), sum(p[1] for p in parts)] if parts else None
         lines += ["", "The same workload as measured live by bench.py (HIP events, instrumented timed region):", "",
                   f"- ms per solve (un-instrumented timed region): {b['ms_per_step']:.3f}",
