@@ -59,6 +59,8 @@ def parse():
                     "(4, 8, 16; 0 = by level)")
     ap.add_argument("--wide-blocks", type=int, default=0, help="most workgroups of a wide-sweep launch "
                     "(0 = library default)")
+    ap.add_argument("--fuse-few", type=int, default=0, help="on levels of few merges, the most active roots "
+                    "one workgroup solves (0 = library default, 512)")
     ap.add_argument("--wide-min", type=int, default=0, help="active roots from which a merge uses the wide "
                     "secular sweep (0 = library default)")
     ap.add_argument("--batched", action="store_true", help="headline = 4096 problems, log-uniform sizes [32,4096]")
@@ -381,7 +383,8 @@ def grad_ratio(tde, dev, reps=20):
         # the forward alone: its fastest configuration (any leaf solver)
         r = autotune.tune(d, e, offs, reps=3)
         fcfg = dict(leaf=r["leaf"], sweep_cols=r["sweep_cols"], wide_min=r["wide_min"], leaf_dc=r["leaf_dc"],
-                    group_max=r["group_max"] or None, wide_blocks=r["wide_blocks"] or None)
+                    group_max=r["group_max"] or None, wide_blocks=r["wide_blocks"] or None,
+                    fuse_few=r["fuse_few"] or None)
 
         def fwd():
             if offs is None:
@@ -443,6 +446,7 @@ def _runs(step, warm=2, reps=5):
 SECONDARY_CFGS = ({"leaf": 64, "leaf_dc": True, "sweep_cols": 32, "wide_min": 32},
                   {"leaf": 64, "leaf_dc": True, "sweep_cols": 16, "wide_min": 64},
                   {"leaf": 64, "leaf_dc": True, "sweep_cols": 16, "wide_min": 64, "wide_blocks": 256},
+                  {"leaf": 64, "leaf_dc": True, "sweep_cols": 16, "wide_min": 1024, "fuse_few": 32},
                   {"leaf": 64, "leaf_dc": True, "sweep_cols": 64, "wide_min": 32},
                   {"leaf": 32, "leaf_dc": False, "sweep_cols": 32, "wide_min": 32})
 
@@ -701,18 +705,22 @@ def main():
         if args.leaf or args.sweep_cols or args.no_tune:
             return {"leaf": args.leaf or None, "sweep_cols": args.sweep_cols or None,
                     "wide_min": args.wide_min or None, "leaf_dc": bool(args.leaf_dc),
-                    "group_max": args.group_max or None, "wide_blocks": args.wide_blocks or None}
+                    "group_max": args.group_max or None, "wide_blocks": args.wide_blocks or None,
+                    "fuse_few": args.fuse_few or None}
         r = autotune.tune(d, e, offs, reps=3)
         tuning[label] = {"leaf": r["leaf"], "leaf_dc": r["leaf_dc"], "sweep_cols": r["sweep_cols"],
                          "wide_min": r["wide_min"], "group_max": r["group_max"], "wide_blocks": r["wide_blocks"],
-                         "best_ms": r["ms"], "configs_tried": len(r["table"]), "tune_s": r["tune_s"]}
+                         "fuse_few": r["fuse_few"], "best_ms": r["ms"], "configs_tried": len(r["table"]),
+                         "tune_s": r["tune_s"]}
         return {"leaf": r["leaf"], "sweep_cols": r["sweep_cols"], "wide_min": r["wide_min"], "leaf_dc": r["leaf_dc"],
-                "group_max": r["group_max"] or None, "wide_blocks": r["wide_blocks"] or None}
+                "group_max": r["group_max"] or None, "wide_blocks": r["wide_blocks"] or None,
+                "fuse_few": r["fuse_few"] or None}
 
     def describe(cfg):
         return {"leaf": cfg["leaf"] or "default", "leaf_solver": "dc" if cfg["leaf_dc"] else "ql",
                 "sweep_cols": cfg["sweep_cols"] or "default", "wide_min": cfg["wide_min"] or "default",
-                "group_max": cfg["group_max"] or "by level", "wide_blocks": cfg["wide_blocks"] or "default"}
+                "group_max": cfg["group_max"] or "by level", "wide_blocks": cfg["wide_blocks"] or "default",
+                "fuse_few": cfg["fuse_few"] or "default"}
 
     def make_batched():
         batch = tdgen.batched("uniform", count=4096, lo=32, hi=4096, inst=0)

@@ -84,6 +84,11 @@ typedef struct {
                        (4096).  Those launches loop over their 64-root items;
                        fewer blocks cost less where they find no work, more keep
                        more waves per compute unit where they carry the solve */
+    int fuse_few;   /* on levels of fewer than 1024 merges, the most active roots a
+                       merge may have for one workgroup to solve it, 2..512; 0 =
+                       default (512).  The larger merges of those levels go to the
+                       root-parallel kernels (the wide sweeps from wide_min on),
+                       which spread a merge's roots over many workgroups */
     int reserved[1]; /* must be 0 */
 } tde_opts;
 

@@ -78,7 +78,7 @@ class TDEError(RuntimeError):
 class tde_opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int), ("flags", ctypes.c_int), ("sweep_cols", ctypes.c_int),
                 ("wide_min", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("group_max", ctypes.c_int),
-                ("wide_blocks", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("wide_blocks", ctypes.c_int), ("fuse_few", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 _lib = None
@@ -178,25 +178,31 @@ TDE_FLAG_LEAF_DC = 2
 # non-convergence status, for tests).
 # group_max: most lanes per root in the fused small merges (4, 8, 16; None = by level).
 # wide_blocks: most workgroups of a wide-sweep launch (None = library default).
-_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None, "group_max": None, "wide_blocks": None}
+# fuse_few: on levels of fewer than 1024 merges, the most active roots of a
+# merge solved by one workgroup (None = 512); larger ones go root-parallel.
+_shape_defaults = {"wide_min": None, "leaf_dc": None, "max_sweeps": None, "group_max": None, "wide_blocks": None,
+                   "fuse_few": None}
 
 
-def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None, group_max=None, wide_blocks=None):
+def set_defaults(wide_min=None, leaf_dc=None, max_sweeps=None, group_max=None, wide_blocks=None, fuse_few=None):
     _shape_defaults["wide_min"] = wide_min
     _shape_defaults["leaf_dc"] = leaf_dc
     _shape_defaults["max_sweeps"] = max_sweeps
     _shape_defaults["group_max"] = group_max
     _shape_defaults["wide_blocks"] = wide_blocks
+    _shape_defaults["fuse_few"] = fuse_few
 
 
-def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None):
+def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None,
+          fuse_few=None):
     wide_min = _shape_defaults["wide_min"] if wide_min is None else wide_min
     leaf_dc = _shape_defaults["leaf_dc"] if leaf_dc is None else leaf_dc
     group_max = _shape_defaults["group_max"] if group_max is None else group_max
     wide_blocks = _shape_defaults["wide_blocks"] if wide_blocks is None else wide_blocks
+    fuse_few = _shape_defaults["fuse_few"] if fuse_few is None else fuse_few
     max_sweeps = _shape_defaults["max_sweeps"]
     if (leaf is None and graph and sweep_cols is None and wide_min is None and not leaf_dc
-            and max_sweeps is None and not group_max and not wide_blocks):
+            and max_sweeps is None and not group_max and not wide_blocks and not fuse_few):
         return None
     o = tde_opts()
     o.leaf = int(leaf or 0)
@@ -206,6 +212,7 @@ def _opts(leaf, graph=True, sweep_cols=None, wide_min=None, leaf_dc=None, group_
     o.max_sweeps = int(max_sweeps or 0)
     o.group_max = int(group_max or 0)
     o.wide_blocks = int(wide_blocks or 0)
+    o.fuse_few = int(fuse_few or 0)
     return ctypes.byref(o)
 
 
@@ -244,7 +251,8 @@ def _check_input(d: torch.Tensor, e: torch.Tensor | None):
 
 def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
-            sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None) -> torch.Tensor:
+            sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None, wide_blocks=None,
+            fuse_few=None) -> torch.Tensor:
     """Eigenvalues (ascending) of the tridiagonal T with diagonal d[n] and
     off-diagonal e[n-1], on d's device and torch's current stream.  graph=True
     replays a captured HIP graph of the whole solve (captured on first use for
@@ -266,7 +274,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals(d.data_ptr(), e.data_ptr() if e.numel() else None, n, out.data_ptr(),
                                ws.data_ptr(), ws.numel(), stream,
-                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks))
+                               _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks, fuse_few))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals")
         if check:
@@ -279,7 +287,7 @@ def eigvals(d: torch.Tensor, e: torch.Tensor, leaf=None, out: torch.Tensor | Non
 def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, check: bool = True, graph: bool = True,
                     sweep_cols=None, wide_min=None, leaf_dc=None, group_max=None,
-                    wide_blocks=None) -> torch.Tensor:
+                    wide_blocks=None, fuse_few=None) -> torch.Tensor:
     """Eigenvalues of B packed tridiagonals: problem b owns d[offsets[b]:offsets[b+1]]
     and e over the same range (last slot unused).  offsets is a host sequence."""
     _check_input(d, e)
@@ -301,7 +309,8 @@ def eigvals_batched(d: torch.Tensor, e: torch.Tensor, offsets, leaf=None, out: t
     with torch.cuda.device(d.device):
         rc = lib().tde_eigvals_batched(d.data_ptr(), e.data_ptr(), arr, B, out.data_ptr(), ws.data_ptr(),
                                        ws.numel(), stream,
-                                       _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks))
+                                       _opts(leaf, graph, sweep_cols, wide_min, leaf_dc, group_max, wide_blocks,
+                                             fuse_few))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_batched")
         if check:
@@ -503,11 +512,10 @@ def checkpoint_bytes(n: int, offsets=None, leaf=None, sweep_cols=None) -> int:
 
 def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, sweep_cols=None, out=None,
                  ckpt=None, workspace=None, check: bool = True, graph: bool = True, wide_min=None,
-                 group_max=None, wide_blocks=None):
+                 group_max=None, wide_blocks=None, fuse_few=None):
     """Eigenvalues as eigvals / eigvals_batched (offsets None = one problem with
     e[n-1]), plus the checkpoint the reverse pass reads.  Returns (lambda, ckpt).
-    group_max and wide_blocks are launch-shape options (results do not
-    depend on them)."""
+    group_max, wide_blocks and fuse_few are launch-shape options."""
     _check_input(d, e)
     offs, B, arr = _offsets(d.numel(), offsets)
     n = offs[-1]
@@ -529,7 +537,7 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
         rc = lib().tde_eigvals_ckpt(d.data_ptr(), e.data_ptr() if e.numel() else None, arr, B, out.data_ptr(),
                                     ckpt.data_ptr(), ckpt.numel(), ws.data_ptr(), ws.numel(), stream,
                                     _opts(leaf, graph, sweep_cols, wide_min, group_max=group_max,
-                                          wide_blocks=wide_blocks))
+                                          wide_blocks=wide_blocks, fuse_few=fuse_few))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_ckpt")
         if check:
@@ -542,7 +550,7 @@ def eigvals_ckpt(d: torch.Tensor, e: torch.Tensor, offsets=None, leaf=None, swee
 def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt: torch.Tensor, offsets=None,
                      leaf=None, sweep_cols=None, workspace=None, check: bool = True, graph: bool = True,
                      gd: torch.Tensor | None = None, ge: torch.Tensor | None = None, wide_min=None,
-                     group_max=None, wide_blocks=None):
+                     group_max=None, wide_blocks=None, fuse_few=None):
     """dL/dd and dL/de for L = sum_k glam_k lambda_k, from the checkpoint of
     eigvals_ckpt on the same inputs and options.  Returns (gd[n], ge[n]) with
     ge in the batched layout (the last slot of every problem is 0); gd and ge
@@ -572,7 +580,7 @@ def eigvals_backward(d: torch.Tensor, e: torch.Tensor, glam: torch.Tensor, ckpt:
                                         glam.data_ptr(), ckpt.data_ptr(), ckpt.numel(), gd.data_ptr(),
                                         ge.data_ptr(), ws.data_ptr(), ws.numel(), stream,
                                         _opts(leaf, graph, sweep_cols, wide_min, group_max=group_max,
-                                              wide_blocks=wide_blocks))
+                                              wide_blocks=wide_blocks, fuse_few=fuse_few))
         if rc != TDE_OK:
             raise TDEError(rc, "tde_eigvals_backward")
         if check:

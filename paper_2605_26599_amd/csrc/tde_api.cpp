@@ -35,7 +35,7 @@ namespace {
 // ---------------------------------------------------------------------------
 std::recursive_mutex g_mu;
 
-using PlanKey = std::tuple<int, int, int, int, bool, int, int, std::vector<long long>>;
+using PlanKey = std::tuple<int, int, int, int, bool, int, int, int, std::vector<long long>>;
 constexpr size_t kMaxPlans = 32;
 struct PlanEntry {
     PlanKey key;
@@ -180,9 +180,9 @@ int run_pass(const Plan& plan, int kind, const Bufs& bufs, const tde_opts* opts,
 }
 
 // Caller holds g_mu.
-int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, int wblocks,
+int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, int wblocks, int ffew,
               const std::vector<long long>& offs, Plan** out) {
-    PlanKey key{device, leaf, cols, wmin, dc, gmax, wblocks, offs};
+    PlanKey key{device, leaf, cols, wmin, dc, gmax, wblocks, ffew, offs};
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         g_plan_lru.splice(g_plan_lru.begin(), g_plan_lru, it->second);
@@ -197,6 +197,7 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, int w
     p->leaf_dc = dc;
     p->group_max = gmax;
     p->wide_blocks = wblocks;
+    p->fuse_few = ffew;
     p->offs = offs;
     if (plan_host(p.get()) != 0) return TDE_EINVAL;
     auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
@@ -225,8 +226,8 @@ int make_plan(int device, int leaf, int cols, int wmin, bool dc, int gmax, int w
 }
 
 int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr, bool* dc = nullptr,
-                 int* cap = nullptr, int* gmax = nullptr, int* wblocks = nullptr) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0, Wb = 0;
+                 int* cap = nullptr, int* gmax = nullptr, int* wblocks = nullptr, int* ffew = nullptr) {
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0, Wb = 0, Ff = 0;
     if (opts) {
         if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
         if (opts->leaf != 0) L = opts->leaf;
@@ -235,13 +236,16 @@ int resolve_opts(const tde_opts* opts, int* leaf, int* cols, int* wmin = nullptr
         if (opts->max_sweeps != 0) S = opts->max_sweeps;
         Gm = opts->group_max;
         Wb = opts->wide_blocks;
+        Ff = opts->fuse_few;
         for (int r : opts->reserved)
             if (r != 0) return TDE_EINVAL;
     }
     if (Gm != 0 && Gm != 4 && Gm != 8 && Gm != 16) return TDE_EINVAL;
     if (Wb < 0 || Wb > (1 << 20)) return TDE_EINVAL;
+    if (Ff != 0 && (Ff < 2 || Ff > kFuseMaxRoots)) return TDE_EINVAL;
     if (gmax) *gmax = Gm;
     if (wblocks) *wblocks = Wb;
+    if (ffew) *ffew = Ff;
     if (L < 1 || L > kLeafMax) return TDE_EINVAL;
     if (C < 1 || C > (1 << 20)) return TDE_EINVAL;
     if (W < 2) return TDE_EINVAL;
@@ -281,12 +285,12 @@ int check_offsets(const int64_t* offsets, int64_t B, std::vector<long long>* off
 }
 
 int get_plan(const tde_opts* opts, const std::vector<long long>& offs, Plan** plan) {
-    int leaf, cols, wmin, cap, gmax, wblocks;
+    int leaf, cols, wmin, cap, gmax, wblocks, ffew;
     bool dc;
-    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap, &gmax, &wblocks) != TDE_OK) return TDE_EINVAL;
+    if (resolve_opts(opts, &leaf, &cols, &wmin, &dc, &cap, &gmax, &wblocks, &ffew) != TDE_OK) return TDE_EINVAL;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return TDE_EDEVICE;
-    return make_plan(device, leaf, cols, wmin, dc, gmax, wblocks, offs, plan);
+    return make_plan(device, leaf, cols, wmin, dc, gmax, wblocks, ffew, offs, plan);
 }
 
 bool needs_e(const std::vector<long long>& offs) {
@@ -610,7 +614,7 @@ int solve_split(const double* d, const double* e, const std::vector<long long>& 
 
 extern "C" {
 
-int tde_version(void) { return 200; }
+int tde_version(void) { return 201; }
 
 size_t tde_workspace_bytes(int64_t n_total, int64_t batch, const tde_opts* opts) {
     int leaf, cols;

@@ -93,6 +93,7 @@ enum {
 
 constexpr int kWG = 256;         // threads per workgroup for element-parallel kernels
 constexpr int kLeafMax = 64;     // largest leaf the QL leaf kernel accepts
+constexpr int kFuseMaxRoots = 512;  // most active roots of a merge one fused workgroup solves
 constexpr int kDefaultLeaf = 8;  // leaf size when the caller does not choose one
 constexpr int kDefaultSweepCols = 8;  // poles per lane per sweep when the caller does not choose
 constexpr int kSecMaxIter = 96;  // secular iteration cap

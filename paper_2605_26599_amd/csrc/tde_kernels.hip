@@ -1401,7 +1401,7 @@ __global__ __launch_bounds__(NW * 64) void k_rows_wide(const MergeRec* __restric
 // bit for bit).  On random spectra nearly every merge is of this kind (a
 // hundred or so roots survive deflation).
 // ---------------------------------------------------------------------------
-constexpr int kFuseMax = 512;
+constexpr int kFuseMax = kFuseMaxRoots;
 constexpr int kFuseThreads = 512;
 constexpr int kFuseWideS = 2048;
 
@@ -1894,12 +1894,13 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
 // largest merge (so >= every K), staged in LDS.
 template <int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__ mr, const double* __restrict__ e,
-                                                    const unsigned long long* __restrict__ pmax, Work w, int gmax) {
+                                                    const unsigned long long* __restrict__ pmax, Work w, int gmax,
+                                                    int fuse_max) {
     if (input_nonfinite(w)) return;
     const MergeRec R = mr[blockIdx.x];
     const MergeSpan sp = merge_span(R, w.scan);
     const int K = sp.K;
-    if (K < 1 || K > kFuseMax || K > CAP) return;  // block-uniform
+    if (K < 1 || K > fuse_max || K > CAP) return;  // block-uniform
     __shared__ SmallStageT<CAP> sg;
     small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax);
 }
@@ -2595,25 +2596,33 @@ static int fused_gmax(int M, int group_max) {
     return M < kFewMerges ? 16 : 4;
 }
 
+// Most active roots of a merge that one workgroup solves (k_small_merge) on
+// a level of M merges: kFuseMax on levels of many merges (the workgroups fill
+// the chip); on levels of few merges the caller's fuse_few when given, so
+// that the larger merges go to the root-parallel kernels, which spread a
+// merge's roots over many workgroups where a lone workgroup per merge leaves
+// most compute units idle.
+static int level_fuse_max(int M, int fuse_few) { return (M < kFewMerges && fuse_few > 0) ? fuse_few : kFuseMax; }
+
 // Fused small merges of one level: a workgroup per merge; on levels of many
 // merges its shape follows the level's largest merge (LDS room and threads
 // for that many active columns), on levels of few it is the full size.
-static void launch_small(int smax, const MergeRec* mr, int M, const double* e, const Work& w, int gmax,
+static void launch_small(int smax, const MergeRec* mr, int M, const double* e, const Work& w, int gmax, int fuse_max,
                          void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const unsigned g = (unsigned)M;
     if (smax >= kFuseWideS)
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<2 * kFuseThreads, kFuseMax>), g, 2 * kFuseThreads, stream, mr, e, pm,
-                     w, gmax);
+                     w, gmax, fuse_max);
     else if (smax > 256 || M < kFewMerges)
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w,
-                     gmax);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w, gmax,
+                     fuse_max);
     else if (smax > 128)
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<256, 256>), g, 256, stream, mr, e, pm, w, gmax);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<256, 256>), g, 256, stream, mr, e, pm, w, gmax, fuse_max);
     else if (smax > 64)
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 128>), g, 128, stream, mr, e, pm, w, gmax);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 128>), g, 128, stream, mr, e, pm, w, gmax, fuse_max);
     else
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax, fuse_max);
 }
 
 // Whole merges in one workgroup each: 512 threads on levels of few merges
@@ -2637,12 +2646,12 @@ static void launch_level_block(int smax, const MergeRec* mr, int M, const double
 
 template <int G>
 static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                           const Work& w, int gmax, int wblocks, void* stream) {
+                           const Work& w, int gmax, int wblocks, int fuse_few, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
-    const int fuse_max = kFuseMax;
-    // merges with at most kFuseMax active roots: one workgroup each
-    launch_small(smax, mr, M, e, w, gmax, stream);
-    if (smax <= kFuseMax) return;  // no merge of the level can have more
+    const int fuse_max = level_fuse_max(M, fuse_few);
+    // merges with at most fuse_max active roots: one workgroup each
+    launch_small(smax, mr, M, e, w, gmax, fuse_max, stream);
+    if (smax <= fuse_max) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
     int nbn, nbw;
@@ -2672,13 +2681,13 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
 }
 
 static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                         const Work& w, int gmax, int wblocks, void* stream) {
+                         const Work& w, int gmax, int wblocks, int fuse_few, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
-        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
-        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
-        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
-        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, stream); break;
+        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
+        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
+        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
+        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
+        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
     }
 }
 
@@ -2795,7 +2804,7 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max),
-                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, stream);
+                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few, stream);
         TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
                      out);
     }

@@ -36,7 +36,7 @@ std::mutex g_na_mu;
 std::map<int, char*> g_scratch_ptr;  // device -> address of that device's scratch
 
 // Host-only plans (no device tables of their own), least recently used out.
-using NaKey = std::tuple<long long, int, int, int, bool, int, int>;
+using NaKey = std::tuple<long long, int, int, int, bool, int, int, int>;
 constexpr size_t kMaxNaPlans = 16;
 struct NaEntry {
     NaKey key;
@@ -59,8 +59,8 @@ int scratch_for(int device, char** out) {
     return TDE_OK;
 }
 
-const Plan* host_plan(long long n, int leaf, int cols, int wmin, bool dc, int gmax, int wblocks) {
-    NaKey key{n, leaf, cols, wmin, dc, gmax, wblocks};
+const Plan* host_plan(long long n, int leaf, int cols, int wmin, bool dc, int gmax, int wblocks, int ffew) {
+    NaKey key{n, leaf, cols, wmin, dc, gmax, wblocks, ffew};
     auto it = g_na_plans.find(key);
     if (it != g_na_plans.end()) {
         g_na_lru.splice(g_na_lru.begin(), g_na_lru, it->second);
@@ -73,6 +73,7 @@ const Plan* host_plan(long long n, int leaf, int cols, int wmin, bool dc, int gm
     p->leaf_dc = dc;
     p->group_max = gmax;
     p->wide_blocks = wblocks;
+    p->fuse_few = ffew;
     p->offs = {0, n};
     if (plan_host(p.get()) != 0) return nullptr;
     while (g_na_lru.size() >= kMaxNaPlans) {
@@ -88,7 +89,7 @@ const Plan* host_plan(long long n, int leaf, int cols, int wmin, bool dc, int gm
 
 int eigvals_noalloc(const double* d, const double* e, long long n, double* lambda, int* status, void* stream,
                     const tde_opts* opts) {
-    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0, Wb = 0;
+    int L = kDefaultLeaf, C = kDefaultSweepCols, W = kWideMin, S = kSecMaxIter, Gm = 0, Wb = 0, Ff = 0;
     bool dc = false;
     if (opts) {
         if (opts->flags & ~(TDE_FLAG_NO_GRAPH | TDE_FLAG_LEAF_DC)) return TDE_EINVAL;
@@ -98,6 +99,7 @@ int eigvals_noalloc(const double* d, const double* e, long long n, double* lambd
         if (opts->max_sweeps != 0) S = opts->max_sweeps;
         Gm = opts->group_max;
         Wb = opts->wide_blocks;
+        Ff = opts->fuse_few;
         for (int r : opts->reserved)
             if (r != 0) return TDE_EINVAL;
         dc = (opts->flags & TDE_FLAG_LEAF_DC) != 0;
@@ -105,6 +107,7 @@ int eigvals_noalloc(const double* d, const double* e, long long n, double* lambd
     if (L < 1 || L > kLeafMax || C < 1 || C > (1 << 20) || W < 2 || S < 1 || S > kSecMaxIter) return TDE_EINVAL;
     if (Gm != 0 && Gm != 4 && Gm != 8 && Gm != 16) return TDE_EINVAL;
     if (Wb < 0 || Wb > (1 << 20)) return TDE_EINVAL;
+    if (Ff != 0 && (Ff < 2 || Ff > kFuseMaxRoots)) return TDE_EINVAL;
     if (n < 0 || n > kNoAllocMaxN) return TDE_EINVAL;
     if (n == 0) return TDE_OK;
     if (!d || !lambda || (n > 1 && !e)) return TDE_EINVAL;
@@ -115,7 +118,7 @@ int eigvals_noalloc(const double* d, const double* e, long long n, double* lambd
     char* base = nullptr;
     int rc = scratch_for(device, &base);
     if (rc != TDE_OK) return rc;
-    const Plan* hp = host_plan(n, L, C, W, dc, Gm, Wb);
+    const Plan* hp = host_plan(n, L, C, W, dc, Gm, Wb, Ff);
     if (!hp) return TDE_EINVAL;
 
     // carve the scratch: tree tables first, then the workspace

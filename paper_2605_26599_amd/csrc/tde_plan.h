@@ -31,6 +31,7 @@ struct Plan {
     bool leaf_dc = false;     // forward passes solve the leaves by divide and conquer inside one wave
     int group_max = 0;        // lanes per root in the fused small merges (4, 8, 16); 0 = by level
     int wide_blocks = 0;      // most workgroups of a wide root launch; 0 = default (4096)
+    int fuse_few = 0;         // fused limit on levels of few merges (active roots); 0 = kFuseMax
     int nleaves = 0;
     int leafmax = 1;     // largest leaf size in the plan
     int maxM = 1;        // most merges in one level

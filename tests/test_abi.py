@@ -71,7 +71,8 @@ def test_argument_errors_are_synchronous(L):
     bad.flags = 4  # unknown flag bit
     assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(bad)) == tde.TDE_EINVAL
     for field, value in [("max_sweeps", -1), ("max_sweeps", 97), ("wide_min", 1), ("sweep_cols", -3),
-                         ("group_max", 2), ("group_max", 32), ("wide_blocks", -1)]:
+                         ("group_max", 2), ("group_max", 32), ("wide_blocks", -1), ("fuse_few", 1),
+                         ("fuse_few", 513), ("fuse_few", -4)]:
         o = tde.tde_opts()
         setattr(o, field, value)
         assert L.tde_eigvals(dummy, dummy, 10, dummy, dummy, 1 << 30, None, ctypes.byref(o)) == tde.TDE_EINVAL, field

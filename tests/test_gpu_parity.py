@@ -263,6 +263,35 @@ def test_lanes_per_root_variants(tde, cols):
         assert np.abs(lam - ref).max() <= GATE * tdgen.tnorm1(d, e)
 
 
+@pytest.mark.parametrize("fuse_few", [2, 32, 64])
+def test_fuse_few_variants(tde, fuse_few):
+    """On levels of few merges, the merges with more than fuse_few active
+    roots leave the fused workgroups for the root-parallel kernels: the
+    regular tiles (wide sweeps off) or, from wide_min on, the wide sweeps.
+    Every split meets the gate, single and batched."""
+    import torch
+
+    for wide_min in (None, 1 << 30):
+        for fam, n in [("uniform", 9000), ("toeplitz", 3000), ("clustered", 5000), ("wilkinson", 2001),
+                       ("normal", 4097)]:
+            _step(f"fuse_few={fuse_few} wide_min={wide_min} fam={fam} n={n}")
+            d, e = tdgen.tridiag(fam, n)
+            lam = tde.eigvals(torch.from_numpy(d).to(_dev()), torch.from_numpy(e).to(_dev()), fuse_few=fuse_few,
+                              wide_min=wide_min, leaf=64, leaf_dc=True)
+            lam = lam.cpu().numpy()
+            assert np.all(np.diff(lam) >= 0)
+            assert np.abs(lam - oracle.eigvals(d, e)).max() <= GATE * tdgen.tnorm1(d, e)
+        _step(f"fuse_few={fuse_few} wide_min={wide_min} batched")
+        probs = [tdgen.tridiag("uniform", s, inst=i) for i, s in enumerate([3000, 17, 1025, 64, 2500, 700])]
+        bt = tdgen.pack(probs)
+        lam = tde.eigvals_batched(torch.from_numpy(bt.d).to(_dev()), torch.from_numpy(bt.e).to(_dev()), bt.offsets,
+                                  fuse_few=fuse_few, wide_min=wide_min).cpu().numpy()
+        for b in range(bt.count):
+            db, eb = bt.problem(b)
+            lo, hi = int(bt.offsets[b]), int(bt.offsets[b + 1])
+            assert np.abs(lam[lo:hi] - oracle.eigvals(db, eb)).max() <= GATE * tdgen.tnorm1(db, eb), b
+
+
 # --- wide secular sweep (64 roots per workgroup, poles split over waves) ----
 
 @pytest.mark.parametrize("wide_min", [2, 64])
