@@ -331,7 +331,7 @@ def grad_case(tde, dev, name):
     return d, e, w, offs, n
 
 
-def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None, gmax=None):
+def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None, gmax=None, ffew=None):
     """Checkpointing forward + backward step (all buffers resident)."""
     import torch
 
@@ -342,9 +342,9 @@ def make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wblocks=None, gmax
 
     def fb():
         tde.eigvals_ckpt(d, e, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks,
-                         group_max=gmax, out=out, ckpt=ck, check=False)
+                         group_max=gmax, fuse_few=ffew, out=out, ckpt=ck, check=False)
         tde.eigvals_backward(d, e, w, ck, offs, leaf=leaf, sweep_cols=cols, wide_min=wide, wide_blocks=wblocks,
-                             group_max=gmax, gd=gd, ge=ge, check=False)
+                             group_max=gmax, fuse_few=ffew, gd=gd, ge=ge, check=False)
     return fb
 
 
@@ -357,7 +357,8 @@ def grad_only(args):
     dev = torch.device("cuda:0")
     d, e, w, offs, n = grad_case(tde, dev, args.grad)
     leaf, cols, wide = args.leaf or 8, args.sweep_cols or 16, args.wide_min or 1024
-    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, args.wide_blocks or None, args.group_max or None)
+    fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, args.wide_blocks or None, args.group_max or None,
+                     args.fuse_few or None)
     for _ in range(max(args.warmup, 1)):
         fb()
     torch.cuda.synchronize()
@@ -366,7 +367,8 @@ def grad_only(args):
                       "higher_is_better": False,
                       "config": {"workload": f"gradient {args.grad}", "leaf": leaf, "sweep_cols": cols,
                                  "wide_min": wide, "wide_blocks": args.wide_blocks or None,
-                                 "group_max": args.group_max or None}}), flush=True)
+                                 "group_max": args.group_max or None, "fuse_few": args.fuse_few or None}}),
+          flush=True)
 
 
 def grad_ratio(tde, dev, reps=20):
@@ -398,15 +400,16 @@ def grad_ratio(tde, dev, reps=20):
             for cols in (16, 64):
                 for wide in (1024, 64):
                     for wb in (None, 256):
-                        fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wb)
-                        fb()
-                        fb()
-                        t = timed(fb, 3) / 3
-                        if best is None or t < best[0]:
-                            best = (t, leaf, cols, wide, wb)
-        _, bleaf, bcols, bwide, bwb = best
-        fwdbwd = make_fwdbwd(tde, dev, d, e, w, offs, n, bleaf, bcols, bwide, bwb)
-        qcfg = dict(leaf=bleaf, sweep_cols=bcols, wide_min=bwide, wide_blocks=bwb)
+                        for ff in (None, 32):
+                            fb = make_fwdbwd(tde, dev, d, e, w, offs, n, leaf, cols, wide, wb, None, ff)
+                            fb()
+                            fb()
+                            t = timed(fb, 3) / 3
+                            if best is None or t < best[0]:
+                                best = (t, leaf, cols, wide, wb, ff)
+        _, bleaf, bcols, bwide, bwb, bff = best
+        fwdbwd = make_fwdbwd(tde, dev, d, e, w, offs, n, bleaf, bcols, bwide, bwb, None, bff)
+        qcfg = dict(leaf=bleaf, sweep_cols=bcols, wide_min=bwide, wide_blocks=bwb, fuse_few=bff)
 
         def fwd_same():
             if offs is None:
