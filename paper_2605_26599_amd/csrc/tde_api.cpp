@@ -687,7 +687,7 @@ int tde_dense_eigvals(double* A, int64_t n, int64_t lda, double* lambda, double*
     tde::dense_layout(n, (char*)ws + sb, &dw);
     const std::vector<long long> offs{0, (long long)n};
     {
-        // the reduction's launches (two per column) are captured once per
+        // the reduction's launches (three per column) are captured once per
         // (size, buffers) into a graph, like the solve's
         std::lock_guard<std::recursive_mutex> lk(tde::g_mu);
         tde::Plan* plan = nullptr;

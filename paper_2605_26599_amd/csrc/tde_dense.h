@@ -9,12 +9,17 @@ constexpr int kNb = 32;  // panel width (reflectors per trailing update)
 
 // Scratch of one reduction of an n x n matrix: the panel's reflectors V and
 // the matching W (n x kNb each, column-major, global row index), the product
-// y = A22 v, the panel's tau, and the tridiagonal's d[n], e[n].
+// y = A22 v, the panel's tau, the column's dot products W^T v and V^T v, the
+// row-parallel kernels' per-workgroup partial sums and their two arrival
+// tickets, and the tridiagonal's d[n], e[n].
 struct DenseWork {
     double* V;
     double* W;
     double* y;
     double* tau;
+    double* sdot;
+    double* part;
+    unsigned* ticket;
     double* d;
     double* e;
 };

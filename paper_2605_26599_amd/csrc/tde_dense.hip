@@ -16,12 +16,18 @@
 // product A22 v reads whole columns (contiguous in memory, column-major):
 // y_r = A[:, r] . v, one wave per column r.
 //
-// Per column: k_trd_symv (one wave per trailing column), then k_trd_wcol
-// (one workgroup: the column's w and the next column's reflector); per panel:
-// k_trd_col for its first column and k_trd_syr2k.  The memory
-// traffic is dominated by the trailing-matrix reads of k_trd_symv (about
-// 8 n^3 / 3 bytes in all); the panel products are about 4 n^3 / 3 FLOP on
-// the matrix cores (both triangles).
+// Per column three launches, each spread over the whole chip: k_trd_symv
+// (one wave per trailing column, plus one per dot product W^T v, V^T v),
+// k_trd_wrow (w row by row) and k_trd_colx (the next column brought up to
+// date and its reflector formed, row by row); per panel k_trd_colx for its
+// first column and k_trd_syr2k.  The two row-parallel kernels end in a
+// reduction (w^T v, the column's norm): every workgroup stores its partial
+// sum, and the last one to finish (an atomic ticket, no waiting) adds the
+// partials in workgroup order, forms the scalars and applies them to the
+// column, so the result does not depend on which workgroup finishes last.
+// The memory traffic is dominated by the trailing-matrix reads of k_trd_symv
+// (about 8 n^3 / 3 bytes in all); the panel products are about 4 n^3 / 3
+// FLOP on the matrix cores (both triangles).
 #include <hip/hip_runtime.h>
 
 #include "tde_dense.h"
@@ -30,7 +36,7 @@ namespace tde {
 
 namespace {
 
-constexpr int kColThreads = 1024;
+constexpr int kRowThreads = 128;  // rows per workgroup of the row-parallel kernels
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -50,122 +56,129 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-// Column c = p + i: bring rows c..n-1 up to date with the panel's first i
-// reflectors, record the diagonal entry, and form the reflector of rows
-// c+1..n-1 (stored as column i of V with v_(c+1) = 1; tau[i]; e[c] = beta).
-// The whole workgroup (kColThreads threads) takes part.
-__device__ __forceinline__ void col_body(const double* __restrict__ A, long long lda, int n, int c, int i,
-                                         double* __restrict__ V, const double* __restrict__ W,
-                                         double* __restrict__ tau, double* __restrict__ d, double* __restrict__ e,
-                                         double* red, double* s_scale) {
-    const long long ln = n;
-    const double* __restrict__ col = A + (long long)c * lda;
-    double ssq = 0.0;
-    for (int r = c + (int)threadIdx.x; r < n; r += kColThreads) {
-        double a = col[r];
-        for (int j = 0; j < i; ++j)
-            a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
-        if (r == c) d[c] = a;
-        else V[i * ln + r] = a;
-        if (r >= c + 2) ssq = fma(a, a, ssq);
-    }
-    const double xn2 = block_sum<kColThreads>(ssq, red);  // barriers: V's column is complete
+// The workgroup's partial sum goes to part[blockIdx.x]; returns true in the
+// last workgroup to arrive (every thread of it), which then sees every
+// partial.  The ticket is left at zero for the next use.
+__device__ __forceinline__ bool arrive_last(double partial, double* __restrict__ part,
+                                            unsigned* __restrict__ ticket, bool* s_last) {
     if (threadIdx.x == 0) {
-        const double alpha = V[i * ln + c + 1];
-        double t = 0.0, scale = 0.0, beta = alpha;
-        if (xn2 > 0.0) {
-            const double nrm = sqrt(fma(alpha, alpha, xn2));
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            t = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        tau[i] = t;
-        e[c] = beta;
-        *s_scale = scale;
+        part[blockIdx.x] = partial;
+        __threadfence();
+        const unsigned k = atomicAdd(ticket, 1u);
+        *s_last = (k == gridDim.x - 1);
+        if (*s_last) *ticket = 0u;
     }
     __syncthreads();
-    const double scale = *s_scale;
-    for (int r = c + 2 + (int)threadIdx.x; r < n; r += kColThreads) V[i * ln + r] *= scale;
-    if (threadIdx.x == 0) V[i * ln + c + 1] = 1.0;
+    const bool last = *s_last;
+    if (last) __threadfence();
+    return last;
 }
 
-__global__ __launch_bounds__(kColThreads) void k_trd_col(const double* __restrict__ A, long long lda, int n, int c,
-                                                        int i, double* __restrict__ V, const double* __restrict__ W,
-                                                        double* __restrict__ tau, double* __restrict__ d,
-                                                        double* __restrict__ e) {
-    __shared__ double red[kColThreads / 64];
-    __shared__ double s_scale;
-    col_body(A, lda, n, c, i, V, W, tau, d, e, red, &s_scale);
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int nb) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[b];  // workgroup order: the same bits whoever is last
+    return t;
+}
+
+// Column c, with the panel's first i reflectors: rows c..n-1 brought up to
+// date (a = A[:, c] - V W[c, :]^T - W V[c, :]^T), the diagonal entry
+// recorded, and the reflector of rows c+1..n-1 formed (column i of V with
+// v_(c+1) = 1; tau[i]; e[c] = beta).  One thread per row; the last
+// workgroup forms the reflector from the norm and scales the column.
+__global__ __launch_bounds__(kRowThreads) void k_trd_colx(const double* __restrict__ A, long long lda, int n, int c,
+                                                         int i, double* __restrict__ V, const double* __restrict__ W,
+                                                         double* __restrict__ tau, double* __restrict__ d,
+                                                         double* __restrict__ e, double* __restrict__ part,
+                                                         unsigned* __restrict__ ticket) {
+    __shared__ double red[kRowThreads / 64];
+    __shared__ bool s_last;
+    const long long ln = n;
+    const int r = c + (int)(blockIdx.x * kRowThreads + threadIdx.x);
+    double ssq = 0.0;
+    if (r < n) {
+        double a = A[(long long)c * lda + r];
+        for (int j = 0; j < i; ++j) a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
+        if (r == c) d[c] = a;
+        else V[i * ln + r] = a;
+        if (r >= c + 2) ssq = a * a;
+    }
+    const double bs = block_sum<kRowThreads>(ssq, red);
+    if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
+    const double xn2 = sum_parts(part, (int)gridDim.x);
+    const double alpha = V[i * ln + c + 1];
+    double t = 0.0, scale = 0.0, beta = alpha;
+    if (xn2 > 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, xn2));
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    for (int rr = c + 2 + (int)threadIdx.x; rr < n; rr += kRowThreads) V[i * ln + rr] *= scale;
+    if (threadIdx.x == 0) {
+        tau[i] = t;
+        e[c] = beta;
+        V[i * ln + c + 1] = 1.0;
+    }
 }
 
 // y_r = A[c+1:, r] . v for every trailing column r (symmetric A: column r
-// holds row r), one wave per column; v is column i of V.
+// holds row r), one wave per column; then one wave per dot product
+// sdot[q] = W_q . v (q < i) and sdot[i + q] = V_q . v over the same rows.
+// v is column i of V.
 __global__ __launch_bounds__(256) void k_trd_symv(const double* __restrict__ A, long long lda, int n, int c, int i,
-                                                 const double* __restrict__ V, double* __restrict__ y) {
-    const int r = c + 1 + (int)((blockIdx.x * 256 + threadIdx.x) >> 6);
+                                                 const double* __restrict__ V, const double* __restrict__ W,
+                                                 double* __restrict__ y, double* __restrict__ sdot) {
+    const int j = (int)((blockIdx.x * 256 + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    if (r >= n) return;  // wave-uniform
-    const double* __restrict__ col = A + (long long)r * lda;
+    const int m = n - c - 1;
+    if (j >= m + 2 * i) return;  // wave-uniform
+    const double* __restrict__ u;
+    if (j < m) u = A + (long long)(c + 1 + j) * lda;
+    else u = (j - m < i) ? W + (long long)(j - m) * n : V + (long long)(j - m - i) * n;
     const double* __restrict__ v = V + (long long)i * n;
     double acc0 = 0.0, acc1 = 0.0;
-    int j = c + 1 + lane;
-    for (; j + 64 < n; j += 128) {
-        acc0 = fma(col[j], v[j], acc0);
-        acc1 = fma(col[j + 64], v[j + 64], acc1);
+    int k = c + 1 + lane;
+    for (; k + 64 < n; k += 128) {
+        acc0 = fma(u[k], v[k], acc0);
+        acc1 = fma(u[k + 64], v[k + 64], acc1);
     }
-    if (j < n) acc0 = fma(col[j], v[j], acc0);
+    if (k < n) acc0 = fma(u[k], v[k], acc0);
     const double s = wave_sum(acc0 + acc1);
-    if (lane == 0) y[r] = s;
+    if (lane == 0) {
+        if (j < m) y[c + 1 + j] = s;
+        else sdot[j - m] = s;
+    }
 }
 
-// w = tau (y - V (W^T v) - W (V^T v)) over rows c+1..n-1, then
-// w += -tau/2 (w^T v) v; stored as column i of W.  The 2i dot products are
-// one per wave (wave-level reductions), the rest is row-parallel.
-__device__ __forceinline__ void w_body(int n, int c, int i, const double* __restrict__ V, double* __restrict__ W,
-                                       const double* __restrict__ y, const double* __restrict__ tau, double* sWv,
-                                       double* sVv, double* red) {
+// w = tau (y - V (W^T v) - W (V^T v)) over rows c+1..n-1, one thread per row,
+// then (last workgroup) w += -tau/2 (w^T v) v; stored as column i of W.
+__global__ __launch_bounds__(kRowThreads) void k_trd_wrow(int n, int c, int i, const double* __restrict__ V,
+                                                         double* __restrict__ W, const double* __restrict__ y,
+                                                         const double* __restrict__ tau,
+                                                         const double* __restrict__ sdot, double* __restrict__ part,
+                                                         unsigned* __restrict__ ticket) {
+    __shared__ double red[kRowThreads / 64];
+    __shared__ bool s_last;
     const long long ln = n;
-    const double* __restrict__ v = V + (long long)i * n;
     const double t = tau[i];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = wid; q < 2 * i; q += kColThreads / 64) {
-        const double* __restrict__ u = (q < i) ? W + (long long)q * n : V + (long long)(q - i) * n;
-        double acc = 0.0;
-        for (int r = c + 1 + lane; r < n; r += 64) acc = fma(u[r], v[r], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) {
-            if (q < i) sWv[q] = acc;
-            else sVv[q - i] = acc;
-        }
-    }
-    __syncthreads();
-    double* __restrict__ wcol = W + (long long)i * n;
+    const int r = c + 1 + (int)(blockIdx.x * kRowThreads + threadIdx.x);
     double wv = 0.0;
-    for (int r = c + 1 + (int)threadIdx.x; r < n; r += kColThreads) {
+    if (r < n) {
         double a = y[r];
-        for (int j = 0; j < i; ++j) a -= V[j * ln + r] * sWv[j] + W[j * ln + r] * sVv[j];
+        for (int j = 0; j < i; ++j) a -= V[j * ln + r] * sdot[j] + W[j * ln + r] * sdot[i + j];
         a *= t;
-        wcol[r] = a;
-        wv = fma(a, v[r], wv);
+        W[i * ln + r] = a;
+        wv = a * V[i * ln + r];
     }
-    const double alpha = -0.5 * t * block_sum<kColThreads>(wv, red);
-    for (int r = c + 1 + (int)threadIdx.x; r < n; r += kColThreads) wcol[r] = fma(alpha, v[r], wcol[r]);
+    const double bs = block_sum<kRowThreads>(wv, red);
+    if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
+    const double alpha = -0.5 * t * sum_parts(part, (int)gridDim.x);
+    for (int rr = c + 1 + (int)threadIdx.x; rr < n; rr += kRowThreads)
+        W[i * ln + rr] = fma(alpha, V[i * ln + rr], W[i * ln + rr]);
 }
 
-// w of column c, then (next != 0) column c + 1 of the same panel: one
-// workgroup does both, so a column costs two launches (this and the
-// trailing product).
-__global__ __launch_bounds__(kColThreads) void k_trd_wcol(const double* __restrict__ A, long long lda, int n, int c,
-                                                         int i, double* __restrict__ V, double* __restrict__ W,
-                                                         const double* __restrict__ y, double* __restrict__ tau,
-                                                         double* __restrict__ d, double* __restrict__ e, int next) {
-    __shared__ double sWv[kNb], sVv[kNb];
-    __shared__ double red[kColThreads / 64];
-    __shared__ double s_scale;
-    w_body(n, c, i, V, W, y, tau, sWv, sVv, red);
-    if (!next) return;  // block-uniform
-    __syncthreads();    // column i of W is complete
-    col_body(A, lda, n, c + 1, i + 1, V, W, tau, d, e, red, &s_scale);
+__global__ void k_trd_zero(unsigned* __restrict__ ticket) {
+    if (threadIdx.x < 2) ticket[threadIdx.x] = 0u;
 }
 
 // Trailing update A[q:, q:] -= V W^T + W V^T (rows and columns q..n-1, both
@@ -251,6 +264,9 @@ size_t dense_layout(long long n, char* base, DenseWork* dw) {
     t.W = (double*)take(8 * nn * kNb);
     t.y = (double*)take(8 * nn);
     t.tau = (double*)take(8 * kNb);
+    t.sdot = (double*)take(8 * 2 * kNb);
+    t.part = (double*)take(8 * (nn / kRowThreads + 2));
+    t.ticket = (unsigned*)take(8);
     t.d = (double*)take(8 * nn);
     t.e = (double*)take(8 * nn);
     if (dw) *dw = t;
@@ -260,17 +276,22 @@ size_t dense_layout(long long n, char* base, DenseWork* dw) {
 int enqueue_dense_reduce(double* A, long long lda, int n, const DenseWork& dw, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_trd_zero, dim3(1), dim3(64), 0, s, dw.ticket);
+    auto rows = [](int count) { return dim3((unsigned)((count + kRowThreads - 1) / kRowThreads)); };
     for (int p = 0; p < n - 2; p += kNb) {
         const int b = (n - 2 - p < kNb) ? n - 2 - p : kNb;
-        hipLaunchKernelGGL(k_trd_col, dim3(1), dim3(kColThreads), 0, s, A, lda, n, p, 0, dw.V, dw.W, dw.tau, dw.d,
-                           dw.e);
+        hipLaunchKernelGGL(k_trd_colx, rows(n - p), dim3(kRowThreads), 0, s, A, lda, n, p, 0, dw.V, dw.W, dw.tau,
+                           dw.d, dw.e, dw.part, dw.ticket);
         for (int i = 0; i < b; ++i) {
             const int c = p + i;
             const int m = n - c - 1;  // trailing columns
-            hipLaunchKernelGGL(k_trd_symv, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, lda, n, c, i, dw.V,
-                               dw.y);
-            hipLaunchKernelGGL(k_trd_wcol, dim3(1), dim3(kColThreads), 0, s, A, lda, n, c, i, dw.V, dw.W, dw.y,
-                               dw.tau, dw.d, dw.e, (i + 1 < b) ? 1 : 0);
+            hipLaunchKernelGGL(k_trd_symv, dim3((unsigned)((m + 2 * i + 3) / 4)), dim3(256), 0, s, A, lda, n, c, i,
+                               dw.V, dw.W, dw.y, dw.sdot);
+            hipLaunchKernelGGL(k_trd_wrow, rows(m), dim3(kRowThreads), 0, s, n, c, i, dw.V, dw.W, dw.y, dw.tau,
+                               dw.sdot, dw.part, dw.ticket);
+            if (i + 1 < b)
+                hipLaunchKernelGGL(k_trd_colx, rows(n - c - 1), dim3(kRowThreads), 0, s, A, lda, n, c + 1, i + 1,
+                                   dw.V, dw.W, dw.tau, dw.d, dw.e, dw.part, dw.ticket + 1);
         }
         const int q = p + b;
         const int M = n - q;
