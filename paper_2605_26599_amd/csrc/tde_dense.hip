@@ -74,9 +74,18 @@ __device__ __forceinline__ bool arrive_last(double partial, double* __restrict__
     return last;
 }
 
-__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int nb) {
+// Sum of part[0..nb) in workgroup order (the same bits whoever is last),
+// every thread of the workgroup; the partials pass through LDS so that their
+// loads are in flight together.
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int nb, double* sp) {
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[b];  // workgroup order: the same bits whoever is last
+    for (int b0 = 0; b0 < nb; b0 += kRowThreads) {
+        if (b0 + (int)threadIdx.x < nb) sp[threadIdx.x] = part[b0 + threadIdx.x];
+        __syncthreads();
+        const int cnt = (nb - b0 < kRowThreads) ? nb - b0 : kRowThreads;
+        for (int k = 0; k < cnt; ++k) t += sp[k];
+        __syncthreads();
+    }
     return t;
 }
 
@@ -97,6 +106,8 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_colx(const double* __restri
     double ssq = 0.0;
     if (r < n) {
         double a = A[(long long)c * lda + r];
+        // unrolled so that eight reflectors' loads are in flight together
+#pragma unroll 8
         for (int j = 0; j < i; ++j) a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
         if (r == c) d[c] = a;
         else V[i * ln + r] = a;
@@ -104,7 +115,8 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_colx(const double* __restri
     }
     const double bs = block_sum<kRowThreads>(ssq, red);
     if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
-    const double xn2 = sum_parts(part, (int)gridDim.x);
+    __shared__ double sp[kRowThreads];
+    const double xn2 = sum_parts(part, (int)gridDim.x, sp);
     const double alpha = V[i * ln + c + 1];
     double t = 0.0, scale = 0.0, beta = alpha;
     if (xn2 > 0.0) {
@@ -113,6 +125,7 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_colx(const double* __restri
         t = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
     }
+#pragma unroll 4
     for (int rr = c + 2 + (int)threadIdx.x; rr < n; rr += kRowThreads) V[i * ln + rr] *= scale;
     if (threadIdx.x == 0) {
         tau[i] = t;
@@ -165,6 +178,7 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_wrow(int n, int c, int i, c
     double wv = 0.0;
     if (r < n) {
         double a = y[r];
+#pragma unroll 8
         for (int j = 0; j < i; ++j) a -= V[j * ln + r] * sdot[j] + W[j * ln + r] * sdot[i + j];
         a *= t;
         W[i * ln + r] = a;
@@ -172,7 +186,9 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_wrow(int n, int c, int i, c
     }
     const double bs = block_sum<kRowThreads>(wv, red);
     if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
-    const double alpha = -0.5 * t * sum_parts(part, (int)gridDim.x);
+    __shared__ double sp[kRowThreads];
+    const double alpha = -0.5 * t * sum_parts(part, (int)gridDim.x, sp);
+#pragma unroll 4
     for (int rr = c + 1 + (int)threadIdx.x; rr < n; rr += kRowThreads)
         W[i * ln + rr] = fma(alpha, V[i * ln + rr], W[i * ln + rr]);
 }
