@@ -94,6 +94,28 @@ def test_rows_match_oracle(tde, fam, leaf):
         assert abs(np.sum(q0 * q0) - 1.0) <= 1e-12 and abs(np.sum(q1 * q1) - 1.0) <= 1e-12
 
 
+@pytest.mark.parametrize("wide_min", [None, 1 << 30])
+def test_rows_with_fuse_few(tde, wide_min):
+    """Rows with the fused limit lowered on levels of few merges (the larger
+    merges' roots, z-hat and rows then come from the root-parallel kernels:
+    the wide sweeps, or with wide_min 2^30 the regular tiles) match the
+    oracle as in the default setting."""
+    tde.set_defaults(fuse_few=32, wide_min=wide_min)
+    try:
+        for fam, n in [("uniform", 4097), ("toeplitz", 1000), ("clustered", 4097), ("normal", 3000)]:
+            _step(f"rows fuse_few=32 wide_min={wide_min} fam={fam} n={n}")
+            d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_TEST)
+            lam, q0, q1 = _rows(tde, d, e, leaf=32)
+            lr, r0, r1 = oracle.boundary_rows(d, e)
+            assert np.abs(lam - lr).max() <= 2e-11 * tdgen.tnorm1(d, e)
+            tol = TOL + 64.0 * np.finfo(float).eps * tdgen.tnorm1(d, e) / _gaps(lr)
+            assert np.all(np.abs(q0 - np.abs(r0)) <= tol)
+            assert np.all(np.abs(np.abs(q1) - np.abs(r1)) <= tol)
+            assert np.all(np.abs(q0 * q1 - r0 * r1) <= tol)
+    finally:
+        tde.set_defaults()
+
+
 def test_rows_batched_matches_single(tde):
     sizes = [0, 1, 2, 3, 70, 500, 1025]
     probs = [tdgen.tridiag("uniform", s, cfg=tdgen.CFG_TEST, inst=i) for i, s in enumerate(sizes)]

@@ -64,6 +64,27 @@ def test_noalloc_matches_eigvals_two_calls(tde, kw):
             assert oracle.certify(d, e, a, tol) == 0
 
 
+def test_noalloc_fuse_few(tde):
+    """The fused limit on levels of few merges reaches the allocation-free
+    plan too: two calls in a row (the second smaller) equal tde_eigvals."""
+    import torch
+
+    tde.set_defaults(fuse_few=32, wide_min=1 << 30)
+    try:
+        for fam, n in (("uniform", 65536), ("uniform", 9000)):
+            d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_FAMILIES)
+            dv, ev = _t(d), _t(e)
+            _step(f"fuse_few=32 {fam} n={n}")
+            lam_na = tde.eigvals_noalloc(dv, ev, leaf=64, leaf_dc=True, sweep_cols=8)
+            torch.cuda.synchronize()
+            lam_ref = tde.eigvals(dv, ev, leaf=64, leaf_dc=True, sweep_cols=8)
+            assert np.array_equal(lam_na.cpu().numpy(), lam_ref.cpu().numpy())
+            if n <= 9000:
+                assert float(np.abs(lam_ref.cpu().numpy() - oracle.eigvals(d, e)).max()) <= GATE * tdgen.tnorm1(d, e)
+    finally:
+        tde.set_defaults()
+
+
 def test_noalloc_status_and_limits(tde):
     import torch
 
