@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
   python -m paper_2605_26599_amd.profsum stats  <kernel_stats.csv> <bench.jsonl> <out.md> <title> <command>
-  python -m paper_2605_26599_amd.profsum traffic <fetch_counter.csv> <write_counter.csv> <copy_bytes> <out.json> <out.md> <command>
+  python -m paper_2605_26599_amd.profsum traffic <fetch_counter.csv> <write_counter.csv> <copy_bytes> <out.json> <out.md> <command> [<kernel_trace.csv>]
   python -m paper_2605_26599_amd.profsum fp64 <counter.csv> <kernel_trace.csv> <bench.jsonl> <out.json> <out.md> <title> <command>
 
 `stats` folds the per-instance kernel statistics of a `--kernel-trace --stats`
@@ -10,7 +10,10 @@ the same bench.py line.  `traffic` turns two `--pmc` runs (FETCH_SIZE, then
 WRITE_SIZE; KiB per dispatch) into HBM bytes per launch for each kernel
 family, scaled by the same counters' reading for a plain device copy of
 known size (bench.py --calibrate-copy), and records the hash of the kernel
-sources so bench.py reports the figure only while the kernels are unchanged.
+sources so bench.py reports the figure only while the kernels are unchanged;
+with a kernel trace of the same configuration it also gives each family's
+average duration and the HBM rate (bytes per launch over that duration)
+against the 8 TB/s peak.
 `fp64` sets hardware-counted FP64 FLOP/s (SQ_INSTS_VALU_*_F64 counters of a
 `--pmc` run, durations from a `--kernel-trace` run of the same command) beside
 the algorithmic FLOP/s of each kernel family.
@@ -81,7 +84,10 @@ def _counter(path, counter):
     return vals
 
 
-def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
+PEAK_HBM_GBS = 8000.0
+
+
+def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd, trace_csv=None):
     import os
 
     f = _counter(fetch_csv, "FETCH_SIZE")
@@ -103,9 +109,18 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
     lines = ["# HBM traffic per launch (rocprofv3 hardware counters)", "", "Commands (repository root, one MI355X):",
              "", "```", cmd, "```", "",
              f"Calibration: one plain device copy of {copy_bytes / 2**20:.0f} MiB ({ck}); "
-             f"scale factors fetch {kf:.4f}, write {kw:.4f} (known bytes / counter bytes).", "",
-             "| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) |",
-             "|---|---|---|---|---|"]
+             f"scale factors fetch {kf:.4f}, write {kw:.4f} (known bytes / counter bytes).", ""]
+    dur = defaultdict(list)
+    if trace_csv:
+        for fam, t in _dispatch_durations(trace_csv):
+            dur[fam].append(t)
+        lines += ["Durations: the average of each family's dispatches in a `--kernel-trace` run of the same "
+                  "configuration; HBM rate = scaled bytes per launch / that average, against the 8 TB/s peak.", "",
+                  "| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) "
+                  "| avg us | HBM GB/s | % of peak |", "|---|---|---|---|---|---|---|---|"]
+    else:
+        lines += ["| kernel | dispatches | fetch KiB/launch (raw) | write KiB/launch (raw) | HBM bytes/launch (scaled) |",
+                  "|---|---|---|---|---|"]
     kinds = {"k_secular": "secular", "k_lowner": "lowner", "k_rows": "rows", "k_secular_wide": "secular",
              "k_lowner_wide": "lowner", "k_rows_wide": "rows", "k_leaf": "leaf", "k_leaf_dc": "leaf",
              "k_small_merge": "small", "k_level_block": "level", "k_merge": "merge", "k_assemble": "assemble"}
@@ -115,7 +130,15 @@ def traffic(fetch_csv, write_csv, copy_bytes, out_json, out_md, cmd):
         fm = sum(f[k]) / len(f[k])
         wm = (sum(w[k]) / len(w[k])) if k in w and w[k] else 0.0
         b = fm * 1024 * kf + wm * 1024 * kw
-        lines.append(f"| {k} | {len(f[k])} | {fm:.1f} | {wm:.1f} | {b:.4g} |")
+        row = f"| {k} | {len(f[k])} | {fm:.1f} | {wm:.1f} | {b:.4g} |"
+        if trace_csv:
+            if dur.get(k):
+                us = sum(dur[k]) / len(dur[k]) / 1e3
+                gbs = b / (us * 1e-6) / 1e9
+                row += f" {us:.2f} | {gbs:.0f} | {100 * gbs / PEAK_HBM_GBS:.1f}% |"
+            else:
+                row += " | | |"
+        lines.append(row)
         if k in kinds:
             rec[kinds[k]] = {"kernel": k, "bytes_per_launch": b, "source_hash": bench.source_hash()}
     json.dump(rec, open(out_json, "w"), indent=1)
@@ -224,7 +247,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:7])
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:8])
+        traffic(*sys.argv[2:9])
     elif sys.argv[1] == "fp64":
         fp64(*sys.argv[2:9])
     else:
