@@ -272,3 +272,29 @@ def test_backward_lanes_per_root_variants(tde):
             lam, ck = tde.eigvals_ckpt(dv, ev, sweep_cols=cols)
             gd, ge = tde.eigvals_backward(dv, ev, _t(w), ck, sweep_cols=cols)
             _check_hf(d, e, w, lam.cpu().numpy(), gd.cpu().numpy(), ge.cpu().numpy()[: n - 1])
+
+
+@pytest.mark.parametrize("wide_min", [None, 1 << 30])
+def test_grad_with_fuse_few(tde, wide_min):
+    """Roots of the few-merge levels' larger merges taken by the root-parallel
+    kernels (fuse_few 32; the regular tiles when wide_min is 2^30) feed the
+    same reverse pass, single and batched."""
+    for fam, n in [("uniform", 8192), ("toeplitz", 2000), ("clustered", 3000)]:
+        _step(f"fuse_few=32 wide_min={wide_min} fam={fam} n={n}")
+        d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_GRAD)
+        w = tdgen.loss_weights(n)
+        dv, ev = _t(d), _t(e)
+        lam, ck = tde.eigvals_ckpt(dv, ev, leaf=8, fuse_few=32, wide_min=wide_min)
+        gd, ge = tde.eigvals_backward(dv, ev, _t(w), ck, leaf=8, fuse_few=32, wide_min=wide_min)
+        _check_hf(d, e, w, lam.cpu().numpy(), gd.cpu().numpy(), ge.cpu().numpy()[: n - 1])
+    _step(f"fuse_few=32 wide_min={wide_min} batched")
+    probs = [tdgen.tridiag("uniform", s, cfg=tdgen.CFG_GRAD, inst=i) for i, s in enumerate([1500, 40, 900, 2049])]
+    bt = tdgen.pack(probs)
+    w = tdgen.loss_weights(int(bt.offsets[-1]))
+    dv, ev = _t(bt.d), _t(bt.e)
+    lam, ck = tde.eigvals_ckpt(dv, ev, bt.offsets, leaf=8, fuse_few=32, wide_min=wide_min)
+    gd, ge = tde.eigvals_backward(dv, ev, _t(w), ck, bt.offsets, leaf=8, fuse_few=32, wide_min=wide_min)
+    lam, gd, ge = lam.cpu().numpy(), gd.cpu().numpy(), ge.cpu().numpy()
+    for b, (db, eb) in enumerate(probs):
+        lo, hi = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        _check_hf(db, eb, w[lo:hi], lam[lo:hi], gd[lo:hi], ge[lo:hi - 1])
