@@ -10,7 +10,8 @@ constexpr int kNb = 32;  // panel width (reflectors per trailing update)
 // Scratch of one reduction of an n x n matrix: the panel's reflectors V and
 // the matching W (n x kNb each, column-major, global row index), the product
 // y = A22 v, the panel's tau, the column's dot products W^T v and V^T v, the
-// row-parallel kernels' per-workgroup partial sums and their two arrival
+// next reflector unscaled (ua) with its scale and the last w's alpha (sc),
+// the row-parallel kernels' per-workgroup partial sums and their two arrival
 // tickets, and the tridiagonal's d[n], e[n].
 struct DenseWork {
     double* V;
@@ -18,6 +19,8 @@ struct DenseWork {
     double* y;
     double* tau;
     double* sdot;
+    double* ua;
+    double* sc;
     double* part;
     unsigned* ticket;
     double* d;

@@ -20,11 +20,13 @@
 // (one wave per trailing column, plus one per dot product W^T v, V^T v),
 // k_trd_wrow (w row by row) and k_trd_colx (the next column brought up to
 // date and its reflector formed, row by row); per panel k_trd_colx for its
-// first column and k_trd_syr2k.  The two row-parallel kernels end in a
-// reduction (w^T v, the column's norm): every workgroup stores its partial
-// sum, and the last one to finish (an atomic ticket, no waiting) adds the
-// partials in workgroup order, forms the scalars and applies them to the
-// column, so the result does not depend on which workgroup finishes last.
+// first column, k_trd_wfix after its last column, and k_trd_syr2k.  The two
+// row-parallel kernels end in a reduction (w^T v, the column's norm): every
+// workgroup stores its partial sum, and the last one to finish (an atomic
+// ticket, no waiting) adds the partials in workgroup order and forms the
+// scalars, so the result does not depend on which workgroup finishes last;
+// the next launch applies them to the column (the reflector's scale in
+// k_trd_symv, w's alpha v in the next k_trd_colx).
 // The memory traffic is dominated by the trailing-matrix reads of k_trd_symv
 // (about 8 n^3 / 3 bytes in all); the panel products are about 4 n^3 / 3
 // FLOP on the matrix cores (both triangles).
@@ -91,85 +93,105 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
 
 // Column c, with the panel's first i reflectors: rows c..n-1 brought up to
 // date (a = A[:, c] - V W[c, :]^T - W V[c, :]^T), the diagonal entry
-// recorded, and the reflector of rows c+1..n-1 formed (column i of V with
-// v_(c+1) = 1; tau[i]; e[c] = beta).  One thread per row; the last
-// workgroup forms the reflector from the norm and scales the column.
+// recorded, and the reflector of rows c+1..n-1 formed: its entries unscaled
+// in ua (ua[c+1] = alpha), tau[i], e[c] = beta and the scale of the other
+// entries in sc[0] (v = ua sc[0], v_(c+1) = 1; k_trd_symv stores v as column
+// i of V).  With i > 0 the previous column's w is completed on the way: its
+// rows below c receive alpha v (alpha = sc[1], from k_trd_wrow), row c is
+// used completed and never read again.  One thread per row; the last
+// workgroup forms the reflector from the norm.
 __global__ __launch_bounds__(kRowThreads) void k_trd_colx(const double* __restrict__ A, long long lda, int n, int c,
-                                                         int i, double* __restrict__ V, const double* __restrict__ W,
+                                                         int i, const double* __restrict__ V,
+                                                         double* __restrict__ W, double* __restrict__ ua,
                                                          double* __restrict__ tau, double* __restrict__ d,
-                                                         double* __restrict__ e, double* __restrict__ part,
-                                                         unsigned* __restrict__ ticket) {
+                                                         double* __restrict__ e, double* __restrict__ sc,
+                                                         double* __restrict__ part, unsigned* __restrict__ ticket) {
     __shared__ double red[kRowThreads / 64];
     __shared__ bool s_last;
     const long long ln = n;
     const int r = c + (int)(blockIdx.x * kRowThreads + threadIdx.x);
+    const int jl = i - 1;  // the previous column (i > 0)
+    const double alpha = (i > 0) ? sc[1] : 0.0;
+    const double wlc = (i > 0) ? fma(alpha, V[jl * ln + c], W[jl * ln + c]) : 0.0;
     double ssq = 0.0;
     if (r < n) {
         double a = A[(long long)c * lda + r];
         // unrolled so that eight reflectors' loads are in flight together
 #pragma unroll 8
-        for (int j = 0; j < i; ++j) a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
+        for (int j = 0; j < jl; ++j) a -= V[j * ln + r] * W[j * ln + c] + W[j * ln + r] * V[j * ln + c];
+        if (i > 0) {
+            const double wr = (r == c) ? wlc : fma(alpha, V[jl * ln + r], W[jl * ln + r]);
+            if (r > c) W[jl * ln + r] = wr;
+            a -= V[jl * ln + r] * wlc + wr * V[jl * ln + c];
+        }
         if (r == c) d[c] = a;
-        else V[i * ln + r] = a;
+        else ua[r] = a;
         if (r >= c + 2) ssq = a * a;
     }
     const double bs = block_sum<kRowThreads>(ssq, red);
     if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
     __shared__ double sp[kRowThreads];
     const double xn2 = sum_parts(part, (int)gridDim.x, sp);
-    const double alpha = V[i * ln + c + 1];
-    double t = 0.0, scale = 0.0, beta = alpha;
-    if (xn2 > 0.0) {
-        const double nrm = sqrt(fma(alpha, alpha, xn2));
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        t = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-    }
-#pragma unroll 4
-    for (int rr = c + 2 + (int)threadIdx.x; rr < n; rr += kRowThreads) V[i * ln + rr] *= scale;
     if (threadIdx.x == 0) {
+        const double ah = ua[c + 1];
+        double t = 0.0, scale = 0.0, beta = ah;
+        if (xn2 > 0.0) {
+            const double nrm = sqrt(fma(ah, ah, xn2));
+            beta = (ah >= 0.0) ? -nrm : nrm;
+            t = (beta - ah) / beta;
+            scale = 1.0 / (ah - beta);
+        }
         tau[i] = t;
         e[c] = beta;
-        V[i * ln + c + 1] = 1.0;
+        sc[0] = scale;
     }
 }
 
 // y_r = A[c+1:, r] . v for every trailing column r (symmetric A: column r
 // holds row r), one wave per column; then one wave per dot product
 // sdot[q] = W_q . v (q < i) and sdot[i + q] = V_q . v over the same rows.
-// v is column i of V.
+// v = ua sc[0] with v_(c+1) = 1 (k_trd_colx's reflector); the wave of
+// column r also stores v_r into column i of V.
 __global__ __launch_bounds__(256) void k_trd_symv(const double* __restrict__ A, long long lda, int n, int c, int i,
-                                                 const double* __restrict__ V, const double* __restrict__ W,
+                                                 double* __restrict__ V, const double* __restrict__ W,
+                                                 const double* __restrict__ ua, const double* __restrict__ sc,
                                                  double* __restrict__ y, double* __restrict__ sdot) {
     const int j = (int)((blockIdx.x * 256 + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     const int m = n - c - 1;
     if (j >= m + 2 * i) return;  // wave-uniform
+    const double scale = sc[0];
     const double* __restrict__ u;
     if (j < m) u = A + (long long)(c + 1 + j) * lda;
     else u = (j - m < i) ? W + (long long)(j - m) * n : V + (long long)(j - m - i) * n;
-    const double* __restrict__ v = V + (long long)i * n;
+    auto vk = [&](int k) { return (k == c + 1) ? 1.0 : ua[k] * scale; };
     double acc0 = 0.0, acc1 = 0.0;
     int k = c + 1 + lane;
     for (; k + 64 < n; k += 128) {
-        acc0 = fma(u[k], v[k], acc0);
-        acc1 = fma(u[k + 64], v[k + 64], acc1);
+        acc0 = fma(u[k], vk(k), acc0);
+        acc1 = fma(u[k + 64], vk(k + 64), acc1);
     }
-    if (k < n) acc0 = fma(u[k], v[k], acc0);
+    if (k < n) acc0 = fma(u[k], vk(k), acc0);
     const double s = wave_sum(acc0 + acc1);
     if (lane == 0) {
-        if (j < m) y[c + 1 + j] = s;
-        else sdot[j - m] = s;
+        if (j < m) {
+            y[c + 1 + j] = s;
+            V[(long long)i * n + c + 1 + j] = vk(c + 1 + j);
+        } else {
+            sdot[j - m] = s;
+        }
     }
 }
 
-// w = tau (y - V (W^T v) - W (V^T v)) over rows c+1..n-1, one thread per row,
-// then (last workgroup) w += -tau/2 (w^T v) v; stored as column i of W.
+// w' = tau (y - V (W^T v) - W (V^T v)) over rows c+1..n-1, one thread per
+// row, stored as column i of W; the last workgroup forms alpha = -tau/2
+// (w'^T v) into sc[1].  w = w' + alpha v is completed by the next column's
+// k_trd_colx, or by k_trd_wfix after a panel's last column.
 __global__ __launch_bounds__(kRowThreads) void k_trd_wrow(int n, int c, int i, const double* __restrict__ V,
                                                          double* __restrict__ W, const double* __restrict__ y,
                                                          const double* __restrict__ tau,
-                                                         const double* __restrict__ sdot, double* __restrict__ part,
-                                                         unsigned* __restrict__ ticket) {
+                                                         const double* __restrict__ sdot, double* __restrict__ sc,
+                                                         double* __restrict__ part, unsigned* __restrict__ ticket) {
     __shared__ double red[kRowThreads / 64];
     __shared__ bool s_last;
     const long long ln = n;
@@ -188,9 +210,15 @@ __global__ __launch_bounds__(kRowThreads) void k_trd_wrow(int n, int c, int i, c
     if (!arrive_last(bs, part, ticket, &s_last)) return;  // workgroup-uniform
     __shared__ double sp[kRowThreads];
     const double alpha = -0.5 * t * sum_parts(part, (int)gridDim.x, sp);
-#pragma unroll 4
-    for (int rr = c + 1 + (int)threadIdx.x; rr < n; rr += kRowThreads)
-        W[i * ln + rr] = fma(alpha, V[i * ln + rr], W[i * ln + rr]);
+    if (threadIdx.x == 0) sc[1] = alpha;
+}
+
+// w = w' + alpha v for column i of W, rows c+1..n-1 (after a panel's last column).
+__global__ __launch_bounds__(kRowThreads) void k_trd_wfix(int n, int c, int i, const double* __restrict__ V,
+                                                         double* __restrict__ W, const double* __restrict__ sc) {
+    const long long ln = n;
+    const int r = c + 1 + (int)(blockIdx.x * kRowThreads + threadIdx.x);
+    if (r < n) W[i * ln + r] = fma(sc[1], V[i * ln + r], W[i * ln + r]);
 }
 
 __global__ void k_trd_zero(unsigned* __restrict__ ticket) {
@@ -281,6 +309,8 @@ size_t dense_layout(long long n, char* base, DenseWork* dw) {
     t.y = (double*)take(8 * nn);
     t.tau = (double*)take(8 * kNb);
     t.sdot = (double*)take(8 * 2 * kNb);
+    t.ua = (double*)take(8 * nn);
+    t.sc = (double*)take(8 * 2);
     t.part = (double*)take(8 * (nn / kRowThreads + 2));
     t.ticket = (unsigned*)take(8);
     t.d = (double*)take(8 * nn);
@@ -296,18 +326,20 @@ int enqueue_dense_reduce(double* A, long long lda, int n, const DenseWork& dw, v
     auto rows = [](int count) { return dim3((unsigned)((count + kRowThreads - 1) / kRowThreads)); };
     for (int p = 0; p < n - 2; p += kNb) {
         const int b = (n - 2 - p < kNb) ? n - 2 - p : kNb;
-        hipLaunchKernelGGL(k_trd_colx, rows(n - p), dim3(kRowThreads), 0, s, A, lda, n, p, 0, dw.V, dw.W, dw.tau,
-                           dw.d, dw.e, dw.part, dw.ticket);
+        hipLaunchKernelGGL(k_trd_colx, rows(n - p), dim3(kRowThreads), 0, s, A, lda, n, p, 0, dw.V, dw.W, dw.ua,
+                           dw.tau, dw.d, dw.e, dw.sc, dw.part, dw.ticket);
         for (int i = 0; i < b; ++i) {
             const int c = p + i;
             const int m = n - c - 1;  // trailing columns
             hipLaunchKernelGGL(k_trd_symv, dim3((unsigned)((m + 2 * i + 3) / 4)), dim3(256), 0, s, A, lda, n, c, i,
-                               dw.V, dw.W, dw.y, dw.sdot);
+                               dw.V, dw.W, dw.ua, dw.sc, dw.y, dw.sdot);
             hipLaunchKernelGGL(k_trd_wrow, rows(m), dim3(kRowThreads), 0, s, n, c, i, dw.V, dw.W, dw.y, dw.tau,
-                               dw.sdot, dw.part, dw.ticket);
+                               dw.sdot, dw.sc, dw.part, dw.ticket);
             if (i + 1 < b)
                 hipLaunchKernelGGL(k_trd_colx, rows(n - c - 1), dim3(kRowThreads), 0, s, A, lda, n, c + 1, i + 1,
-                                   dw.V, dw.W, dw.tau, dw.d, dw.e, dw.part, dw.ticket + 1);
+                                   dw.V, dw.W, dw.ua, dw.tau, dw.d, dw.e, dw.sc, dw.part, dw.ticket + 1);
+            else
+                hipLaunchKernelGGL(k_trd_wfix, rows(m), dim3(kRowThreads), 0, s, n, c, i, dw.V, dw.W, dw.sc);
         }
         const int q = p + b;
         const int M = n - q;
