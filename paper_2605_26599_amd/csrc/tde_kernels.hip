@@ -85,37 +85,34 @@ __device__ __forceinline__ int block_incl_scan(int v, int* wsum) {
 }
 
 // Exclusive scans of the per-block counts in[0..nb) into out[0..nb], totals
-// in out[nb]; a second array pair is scanned when in2 is given.
+// in out[nb]; a second array pair is scanned when in2 is given.  Each thread
+// takes a run of consecutive counts (loaded together), so one workgroup scan
+// covers them all.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const int* in, int* out, const int* in2, int* out2, int nb) {
     __shared__ int wsum[16];
-    __shared__ int carry, carry2;
-    if (threadIdx.x == 0) {
-        carry = 0;
-        carry2 = 0;
+    const int cs = (nb + 1023) / 1024;
+    const int b0 = min(nb, (int)threadIdx.x * cs), b1 = min(nb, b0 + cs);
+    int s1 = 0, s2 = 0;
+#pragma unroll 4
+    for (int i = b0; i < b1; ++i) {
+        s1 += in[i];
+        if (in2) s2 += in2[i];
     }
+    const int incl = block_incl_scan(s1, wsum);
     __syncthreads();
-    for (int base = 0; base < nb; base += 1024) {
-        const int i = base + threadIdx.x;
-        const int v = (i < nb) ? in[i] : 0;
-        const int v2 = (in2 && i < nb) ? in2[i] : 0;
-        const int incl = block_incl_scan(v, wsum);
-        __syncthreads();
-        const int incl2 = block_incl_scan(v2, wsum);
-        const int c = carry, c2 = carry2;
-        if (i < nb) {
-            out[i] = c + incl - v;
-            if (in2) out2[i] = c2 + incl2 - v2;
+    const int incl2 = block_incl_scan(s2, wsum);
+    int r1 = incl - s1, r2 = incl2 - s2;
+    for (int i = b0; i < b1; ++i) {
+        out[i] = r1;
+        r1 += in[i];
+        if (in2) {
+            out2[i] = r2;
+            r2 += in2[i];
         }
-        __syncthreads();
-        if (threadIdx.x == 1023) {
-            carry = c + incl;
-            carry2 = c2 + incl2;
-        }
-        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out[nb] = carry;
-        if (in2) out2[nb] = carry2;
+    if (threadIdx.x == 1023) {
+        out[nb] = incl;
+        if (in2) out2[nb] = incl2;
     }
 }
 
