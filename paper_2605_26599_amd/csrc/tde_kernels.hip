@@ -154,22 +154,25 @@ __global__ __launch_bounds__(kWG) void k_maxabs(const double* __restrict__ d, co
 }
 
 // ---------------------------------------------------------------------------
-// Leaves: one lane per leaf, the leaf's working arrays in LDS (lane-strided).
+// Leaves: one lane per leaf, `per` leaves per wave (lanes 0..per-1), the
+// leaf's working arrays in LDS (lane-strided).  A wave's leaves run their QL
+// iterations in lockstep and wait for one another's extra sweeps, so with few
+// leaves fewer share a wave and more waves run side by side.
 // ---------------------------------------------------------------------------
 template <int LMAX>
 __global__ __launch_bounds__(64) void k_leaf(const LeafRec* __restrict__ leaves, int nleaves,
                                              const double* __restrict__ d, const double* __restrict__ e,
                                              const unsigned long long* __restrict__ pmax, Work w,
-                                             double* __restrict__ out) {
+                                             double* __restrict__ out, int per) {
     if (input_nonfinite(w)) return;
     __shared__ double sd[LMAX * 64], se[LMAX * 64], s0[LMAX * 64], s1[LMAX * 64];
     const int lane = threadIdx.x;
-    const int li = blockIdx.x * 64 + lane;
+    const long long li = (long long)blockIdx.x * per + lane;
     unsigned nrot = 0;
     unsigned long long cols = 0;
-    if (li < nleaves) {
+    if (lane < per && li < nleaves) {
         const LeafRec L = leaves[li];
-        const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, 64, &nrot);
+        const int st = body_leaf(L, d, e, pmax, w, out, sd + lane, se + lane, s0 + lane, s1 + lane, per, &nrot);
         if (st) atomicOr(w.status, st);
         cols = (unsigned long long)L.size;
     }
@@ -2741,6 +2744,18 @@ static void enqueue_setup(const Plan& p, const Work& w, void* stream) {
                  w.bcnt, nbc);
 }
 
+// QL leaves per wave: 64, or for fewer than 64 * kLeafWaves leaves the
+// largest power of two that still gives kLeafWaves waves (at least one leaf).
+// Spreading a handful of leaves over more waves shortens the solve (n = 1024
+// in leaves of 32: 1.0 -> 0.68 ms for the leaves); spreading thousands over
+// one wave per SIMD lengthens it (4096 leaves of 16: 0.30 -> 0.43 ms).
+constexpr int kLeafWaves = 64;
+static int leaves_per_wave(int nleaves) {
+    int per = 64;
+    while (per > 1 && (long long)nleaves < (long long)per * kLeafWaves) per >>= 1;
+    return per;
+}
+
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck, const Ckpt* xsrc) {
     if (p.ntot == 0) return 0;
@@ -2752,15 +2767,16 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         TDE_LAUNCH_K(KIND_LEAF, k_leaf_dc, (unsigned)p.nleaves, 64, stream, p.d_leaves, p.d_shdr, p.d_smer, d, e,
                      (const unsigned long long*)w.pmax, w, out);
     } else if (p.nleaves > 0) {
-        const unsigned g = nblk(p.nleaves, 64);
+        const int per = leaves_per_wave(p.nleaves);
+        const unsigned g = nblk(p.nleaves, per);
         if (p.leafmax <= 8)
-            TDE_LAUNCH_K(KIND_LEAF, k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<8>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out, per);
         else if (p.leafmax <= 16)
-            TDE_LAUNCH_K(KIND_LEAF, k_leaf<16>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<16>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out, per);
         else if (p.leafmax <= 32)
-            TDE_LAUNCH_K(KIND_LEAF, k_leaf<32>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<32>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out, per);
         else
-            TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out);
+            TDE_LAUNCH_K(KIND_LEAF, k_leaf<64>, g, 64, stream, p.d_leaves, p.nleaves, d, e, w.pmax, w, out, per);
     }
     for (size_t h = 0; h < p.levels.size(); ++h) {
         const LevelInfo& L = p.levels[h];
