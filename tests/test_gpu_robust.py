@@ -2,8 +2,9 @@
 
 * Non-convergence: a secular iteration cap of one sweep per root (the
   max_sweeps option) makes roots stop unconverged, and every kernel path that
-  solves roots (level-wide, fused small merges, whole-merge workgroups, wide
-  sweeps, in-wave leaves) must report TDE_ENOCONV while still exiting normally.
+  solves roots (level-wide, fused small merges, whole-merge workgroups,
+  in-wave levels, wide sweeps, in-wave leaves) must report TDE_ENOCONV while
+  still exiting normally.
 * Graph cache: more distinct buffer sets than the cache holds, replayed
   without synchronising in between, must each give the eager result bit for
   bit (an executable still queued must never be destroyed).
@@ -63,6 +64,42 @@ def test_forced_nonconvergence(tde, kw):
     _step(f"default cap {kw}")
     lam = tde.eigvals(dv, ev, **kw).cpu().numpy()
     assert np.abs(lam - oracle.eigvals(d, e)).max() <= GATE * tdgen.tnorm1(d, e)
+
+
+def test_forced_nonconvergence_waved_levels_and_tiles(tde):
+    """The in-wave levels (1500 problems of 40..64 columns at leaf 8: every
+    level of many small merges runs in waves) and the regular tiles that take
+    the few-merge levels' larger merges under fuse_few report the cap and
+    non-finite input like every other path."""
+    probs = [tdgen.tridiag("uniform", 40 + (i % 25), inst=i) for i in range(1500)]
+    bt = tdgen.pack(probs)
+    bd, be = _t(bt.d), _t(bt.e)
+    d, e = tdgen.tridiag("uniform", 9000)
+    dv, ev = _t(d), _t(e)
+    try:
+        tde.set_defaults(max_sweeps=1)
+        _step("max_sweeps=1 waved batch")
+        with pytest.raises(tde.TDEError) as ex:
+            tde.eigvals_batched(bd, be, bt.offsets, leaf=8)
+        assert ex.value.code == tde.TDE_ENOCONV
+        _step("max_sweeps=1 fuse_few 32 regular tiles")
+        with pytest.raises(tde.TDEError) as ex:
+            tde.eigvals(dv, ev, leaf=64, leaf_dc=True, fuse_few=32, wide_min=1 << 30)
+        assert ex.value.code == tde.TDE_ENOCONV
+    finally:
+        tde.set_defaults()
+    _step("non-finite entry in a waved batch")
+    bad = bt.d.copy()
+    bad[int(bt.offsets[700]) + 3] = np.inf
+    with pytest.raises(tde.TDEError) as ex:
+        tde.eigvals_batched(_t(bad), be, bt.offsets, leaf=8)
+    assert ex.value.code == tde.TDE_ENONFINITE
+    _step("default cap waved batch")
+    lam = tde.eigvals_batched(bd, be, bt.offsets, leaf=8).cpu().numpy()
+    for b in range(0, bt.count, 149):
+        db, eb = bt.problem(b)
+        lo, hi = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        assert np.abs(lam[lo:hi] - oracle.eigvals(db, eb)).max() <= GATE * tdgen.tnorm1(db, eb)
 
 
 def test_forced_nonconvergence_reverse_mode(tde):
