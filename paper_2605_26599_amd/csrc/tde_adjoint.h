@@ -27,6 +27,7 @@ namespace tde {
 
 
 // Gather the parent's adjoints onto the three lists (mirror of body_assemble).
+template <bool Wide>
 TDE_DEV void body_bwd_unassemble(long long t, int m, const MergeRec* __restrict__ mr, const Work& w,
                                  const Grad& gr) {
     const MergeRec R = mr[m];
@@ -47,18 +48,18 @@ TDE_DEV void body_bwd_unassemble(long long t, int m, const MergeRec* __restrict_
     int pos, list, q;
     if (i < K) {
         const double val = Da[og[i]] + ta[i];
-        pos = i + count_lt(Dr, nr, val) + count_lt(Dd, nn, val);
+        pos = i + count_lt<Wide>(Dr, nr, val) + count_lt<Wide>(Dd, nn, val);
         list = 0;
         q = i;
     } else if (i < K + nr) {
         q = i - K;
         const double val = Dr[q];
-        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_lt(Dd, nn, val);
+        pos = q + roots_cmp_count<Wide>(Da, og, ta, K, val) + count_lt<Wide>(Dd, nn, val);
         list = 1;
     } else {
         q = i - K - nr;
         const double val = Dd[q];
-        pos = q + roots_cmp_count(Da, og, ta, K, val, true) + count_le(Dr, nr, val);
+        pos = q + roots_cmp_count<Wide>(Da, og, ta, K, val) + count_le<Wide>(Dr, nr, val);
         list = 2;
     }
     const long long P = R.off + pos;

@@ -701,6 +701,46 @@ TDE_DEV int merge_emit(const MergeRec& R, int c, double x, double rho, double sg
     return flag;
 }
 
+// Partition point of an ascending array (how many values are < x, or <= x):
+// a binary search, or with Wide an 8-way search first, 7 probes read at once
+// (independent loads) each round, so a list of n values costs about log8(n)
+// dependent reads instead of log2(n) -- the better choice where few threads
+// run and each waits on its chain of reads, the worse where many threads
+// share the memory system.  Both give the same index.
+template <bool LE, bool Wide, class Val>
+TDE_DEV int count_part(const Val& v, int n, double x) {
+    int lo = 0, hi = n;
+    while (Wide && hi - lo > 8) {
+        const long long r = hi - lo;
+        double pv[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) pv[k] = v(lo + (int)((r * (k + 1)) >> 3));
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) c += (LE ? (pv[k] <= x) : (pv[k] < x)) ? 1 : 0;
+        // the answer lies after the c-th probe and at or before the (c+1)-th
+        const int nlo = c ? lo + (int)((r * c) >> 3) + 1 : lo;
+        const int nhi = (c < 7) ? lo + (int)((r * (c + 1)) >> 3) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double vm = v(mid);
+        if (LE ? (vm <= x) : (vm < x)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+template <bool Wide = false>
+TDE_DEV int count_lt(const double* __restrict__ v, int n, double x) {
+    return count_part<false, Wide>([v](int i) { return v[i]; }, n, x);
+}
+template <bool Wide = false>
+TDE_DEV int count_le(const double* __restrict__ v, int n, double x) {
+    return count_part<true, Wide>([v](int i) { return v[i]; }, n, x);
+}
+
 TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr,
                              const double* __restrict__ e, const unsigned long long* __restrict__ pmax,
                              const Work& w, int* flag_out) {
@@ -715,23 +755,11 @@ TDE_DEV long long body_merge(long long t, int m, const MergeRec* __restrict__ mr
     double x;
     if (i < R.nL) {
         x = lamL[i];
-        int lo = 0, hi = R.nR;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (lamR[mid] < x) lo = mid + 1;
-            else hi = mid;
-        }
-        pos = i + lo;
+        pos = i + count_lt(lamR, R.nR, x);
     } else {
         const int j = i - R.nL;
         x = lamR[j];
-        int lo = 0, hi = R.nL;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (lamL[mid] <= x) lo = mid + 1;
-            else hi = mid;
-        }
-        pos = j + lo;
+        pos = j + count_le(lamL, R.nL, x);
     }
     const long long P = R.pk + pos;
     *flag_out = merge_emit(R, i, x, rho, sgn, tol, w, P);
@@ -939,34 +967,12 @@ TDE_DEV void body_rows(long long g, int m, const MergeRec* __restrict__ mr, cons
 // negligible-z columns and the rotated-away columns -- into the parent's
 // spectrum, in place (or the scaled-back eigenvalues for a top merge).  Ties
 // order roots before rotated before negligible columns.
-TDE_DEV int count_lt(const double* __restrict__ v, int n, double x) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (v[mid] < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-TDE_DEV int count_le(const double* __restrict__ v, int n, double x) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (v[mid] <= x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
+//
+// Roots given as (origin index, tau) pairs, ascending: how many are <= x.
+template <bool Wide>
 TDE_DEV int roots_cmp_count(const double* __restrict__ Da, const int* __restrict__ og,
-                            const double* __restrict__ ta, int K, double x, bool inclusive) {
-    int lo = 0, hi = K;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        const double v = Da[og[mid]] + ta[mid];
-        if (inclusive ? (v <= x) : (v < x)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+                            const double* __restrict__ ta, int K, double x) {
+    return count_part<true, Wide>([Da, og, ta](int i) { return Da[og[i]] + ta[i]; }, K, x);
 }
 
 // Rows mode: first and last entries of the unit eigenvector of an output
@@ -978,6 +984,7 @@ TDE_DEV void store_rows(const Work& w, long long P, double bl, double bh) {
     if (w.qlast) w.qlast[P] = sg * bh;
 }
 
+template <bool Wide = false>
 TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
                            const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
     const MergeRec R = mr[m];
@@ -998,17 +1005,17 @@ TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
     double val, bl = 0.0, bh = 0.0;
     if (i < K) {
         val = rv[i];
-        pos = i + count_lt(Dr, nr, val) + count_lt(Dd, nn, val);
+        pos = i + count_lt<Wide>(Dr, nr, val) + count_lt<Wide>(Dd, nn, val);
         if (rows) { bl = w.PBL[ks + i]; bh = w.PBH[ks + i]; }
     } else if (i < K + nr) {
         const int q = i - K;
         val = Dr[q];
-        pos = q + count_le(rv, K, val) + count_lt(Dd, nn, val);
+        pos = q + count_le<Wide>(rv, K, val) + count_lt<Wide>(Dd, nn, val);
         if (rows) { bl = w.RLr[rs + q]; bh = w.RHr[rs + q]; }
     } else {
         const int q = i - K - nr;
         val = Dd[q];
-        pos = q + count_le(rv, K, val) + count_le(Dr, nr, val);
+        pos = q + count_le<Wide>(rv, K, val) + count_le<Wide>(Dr, nr, val);
         if (rows) { bl = w.RLd[ns + q]; bh = w.RHd[ns + q]; }
     }
     const long long P = R.off + pos;

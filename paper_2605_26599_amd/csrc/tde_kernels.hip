@@ -118,38 +118,76 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const int* in, int* out, c
 
 // ---------------------------------------------------------------------------
 // Validation and scale: pmax[b] = bits of max(|d|, |e|) over problem b;
-// non-finite entries raise ST_NONFINITE.
+// non-finite entries raise ST_NONFINITE.  A workgroup covers kMaxAbsPer * kWG
+// consecutive entries (kMaxAbsPer per thread, kWG apart, so every load is
+// coalesced); a thread folds its entries per problem and flushes a problem's
+// running maximum when it moves to the next, and a workgroup whose threads all
+// end in one problem issues a single atomic for all of them (one problem of
+// 65536 entries: 64 atomics on its word instead of one per wave).
 // ---------------------------------------------------------------------------
+constexpr int kMaxAbsPer = 4;
 __global__ __launch_bounds__(kWG) void k_maxabs(const double* __restrict__ d, const double* __restrict__ e,
                                                 const long long* __restrict__ offs, int B, long long ntot,
                                                 unsigned long long* pmax, int* status) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    int b = -1;
-    unsigned long long v = 0;
-    if (i < ntot) {
-        int lo = 0, hi = B - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= i) lo = mid;
-            else hi = mid - 1;
+    __shared__ unsigned long long sv[kWG / 64];
+    __shared__ int sb[kWG / 64];
+    const long long base = (long long)blockIdx.x * (kWG * kMaxAbsPer) + threadIdx.x;
+    int bc = -1, blo = 0;
+    long long bend = -1;  // end of problem blo
+    unsigned long long vc = 0;
+    bool fin = true;
+    for (int k = 0; k < kMaxAbsPer; ++k) {
+        const long long i = base + (long long)k * kWG;
+        if (i >= ntot) break;
+        if (i >= bend) {  // entries ascend, so problems never go back
+            int lo = blo, hi = B - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (offs[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            blo = lo;
+            bend = offs[lo + 1];
         }
-        b = lo;
+        const int lo = blo;
         double x = fabs(d[i]);
-        bool fin = x <= DBL_MAX;
-        if (i + 1 < offs[b + 1]) {
-            double y = fabs(e[i]);
-            fin = fin && (y <= DBL_MAX);
+        bool f = x <= DBL_MAX;
+        if (i + 1 < bend) {
+            const double y = fabs(e[i]);
+            f = f && (y <= DBL_MAX);
             x = fmax(x, y);
         }
-        if (!fin) atomicOr(status, ST_NONFINITE);
-        v = dbits(x);
+        fin = fin && f;
+        if (lo != bc) {
+            if (bc >= 0) atomicMax(&pmax[bc], vc);
+            bc = lo;
+            vc = 0;
+        }
+        const unsigned long long u = dbits(x);
+        vc = (u > vc) ? u : vc;
     }
-    const int b0 = __shfl(b, 0, 64);
-    if (__all(b == b0) && b0 >= 0) {
-        v = wave_max_u64(v);
-        if ((threadIdx.x & 63) == 0) atomicMax(&pmax[b0], v);
-    } else if (b >= 0) {
-        atomicMax(&pmax[b], v);
+    if (!fin) atomicOr(status, ST_NONFINITE);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b0 = __shfl(bc, 0, 64);
+    const bool wave_one = __all(bc == b0);
+    if (wave_one) vc = wave_max_u64(vc);
+    if (lane == 0) {
+        sb[wv] = wave_one ? b0 : -2;
+        sv[wv] = vc;
+    }
+    __syncthreads();
+    bool block_one = true;
+    unsigned long long vb = 0;
+    for (int q = 0; q < kWG / 64; ++q) {
+        block_one = block_one && (sb[q] == sb[0]);
+        vb = (sv[q] > vb) ? sv[q] : vb;
+    }
+    if (block_one) {
+        if (threadIdx.x == 0 && sb[0] >= 0) atomicMax(&pmax[sb[0]], vb);
+    } else if (wave_one) {
+        if (lane == 0 && b0 >= 0) atomicMax(&pmax[b0], vc);
+    } else if (bc >= 0) {
+        atomicMax(&pmax[bc], vc);
     }
 }
 
@@ -2161,12 +2199,13 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
     count_add(w.counters, CNT_ROW_PAIRS, pairs);
 }
 
+template <bool Wide>
 __global__ __launch_bounds__(kWG) void k_assemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                   long long N, const unsigned long long* __restrict__ pmax, Work w,
                                                   double* __restrict__ out) {
     if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < N) body_assemble(t, merge_of(mr, blkm, t), mr, pmax, w, out);
+    if (t < N) body_assemble<Wide>(t, merge_of(mr, blkm, t), mr, pmax, w, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2216,11 +2255,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_roots_gather(const MergeRec* __rest
     }
 }
 
+template <bool Wide>
 __global__ __launch_bounds__(kWG) void k_bwd_unassemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
                                                         long long N, Work w, Grad gr) {
     if (input_nonfinite(w)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < N) body_bwd_unassemble(t, merge_of(mr, blkm, t), mr, w, gr);
+    if (t < N) body_bwd_unassemble<Wide>(t, merge_of(mr, blkm, t), mr, w, gr);
 }
 
 constexpr int kStageBwd = 1024;
@@ -2756,11 +2796,17 @@ static int leaves_per_wave(int nleaves) {
     return per;
 }
 
+// Assembly searches its three lists 8 ways at a time on levels of at most
+// kWideSearchCols columns (few threads, each latency-bound: uniform n = 65536,
+// 94 -> 77 us of assembly per solve), binary on larger levels (a batch of
+// 4096 problems: the 8-way search was 2% slower there).
+constexpr long long kWideSearchCols = 1LL << 18;
+
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck, const Ckpt* xsrc) {
     if (p.ntot == 0) return 0;
     enqueue_setup(p, w, stream);
-    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
+    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG * kMaxAbsPer), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
     if (p.nleaves > 0 && p.leaf_dc && !ck) {
         // the checkpointing forward keeps the QL leaves the reverse pass differentiates
@@ -2818,8 +2864,12 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max),
                      p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few, stream);
-        TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble, nb, kWG, stream, mr, blkm, N, (const unsigned long long*)w.pmax, wl,
-                     out);
+        if (N <= kWideSearchCols)
+            TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble<true>, nb, kWG, stream, mr, blkm, N,
+                         (const unsigned long long*)w.pmax, wl, out);
+        else
+            TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble<false>, nb, kWG, stream, mr, blkm, N,
+                         (const unsigned long long*)w.pmax, wl, out);
     }
     return (int)hipGetLastError();
 }
@@ -2855,7 +2905,7 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
     if (p.ntot == 0) return 0;
     const long long cs = p.ntot;  // coefficient plane stride
     enqueue_setup(p, w, stream);
-    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
+    TDE_LAUNCH_K(KIND_SETUP, k_maxabs, nblk(p.ntot, kWG * kMaxAbsPer), kWG, stream, d, e, (const long long*)p.d_offs, p.B,
                  p.ntot, w.pmax, w.status);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_init, nblk(p.ntot, kWG), kWG, stream, p.ntot, gin, gr);
     for (size_t hh = p.levels.size(); hh-- > 0;) {
@@ -2880,7 +2930,10 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
             TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots_gather, nb < 4096u ? nb : 4096u, kWG, stream, mr, N, wl,
                          (const int*)(ck.org + so), (const double*)(ck.tau + so));
         }
-        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble, nb, kWG, stream, mr, blkm, N, wl, gr);
+        if (N <= kWideSearchCols)
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble<true>, nb, kWG, stream, mr, blkm, N, wl, gr);
+        else
+            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble<false>, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
             case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
             case 2: launch_bwd_roots_g<2>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
