@@ -8,6 +8,10 @@
 //   leaf    reads "n d_0..d_(n-1) e_0..e_(n-2)" from stdin, runs the leaf
 //           QL (rows 0 and n-1 tracked) and prints status, eigenvalues and
 //           the two rows.
+//   search  the assembly's partition-point searches (binary and 8-way, over
+//           plain lists and over roots given as origin + tau) against a
+//           linear count, on ascending lists with repeated values.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -209,9 +213,52 @@ static int mode_leaf() {
     return 0;
 }
 
+static void check_search(const std::vector<double>& v, double x) {
+    const int n = (int)v.size();
+    int lt = 0, le = 0;
+    for (double y : v) {
+        lt += (y < x) ? 1 : 0;
+        le += (y <= x) ? 1 : 0;
+    }
+    CHECK(count_lt<false>(v.data(), n, x) == lt);
+    CHECK(count_lt<true>(v.data(), n, x) == lt);
+    CHECK(count_le<false>(v.data(), n, x) == le);
+    CHECK(count_le<true>(v.data(), n, x) == le);
+    // the same values as roots: origin og[i] into a shuffled pole list, tau 0
+    std::vector<double> poles(v.rbegin(), v.rend());
+    std::vector<int> og((size_t)n);
+    std::vector<double> tau((size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) og[(size_t)i] = n - 1 - i;
+    CHECK(roots_cmp_count<false>(poles.data(), og.data(), tau.data(), n, x) == le);
+    CHECK(roots_cmp_count<true>(poles.data(), og.data(), tau.data(), n, x) == le);
+}
+
+static int mode_search() {
+    std::mt19937_64 rng(7);
+    for (int t = 0; t < 3000 && !g_fail; ++t) {
+        const int n = t < 200 ? t % 40 : (int)(rng() % (t < 2900 ? 3000 : 70000));
+        const int span = 1 + (int)(rng() % (n / 2 + 2));  // repeated values when span < n
+        std::vector<double> v((size_t)n);
+        for (auto& y : v) y = (double)(rng() % (unsigned)span);
+        std::sort(v.begin(), v.end());
+        for (int q = 0; q < 24 && !g_fail; ++q) {
+            const double x = (double)((long long)(rng() % (unsigned)(span + 2)) - 1) + ((q & 1) ? 0.5 : 0.0);
+            check_search(v, x);
+        }
+        if (n > 0 && !g_fail) {
+            check_search(v, v.front());
+            check_search(v, v.back());
+        }
+    }
+    if (g_fail) return 1;
+    std::printf("search ok\n");
+    return 0;
+}
+
 int main(int argc, char** argv) {
     if (argc > 1 && !std::strcmp(argv[1], "plan")) return mode_plan();
     if (argc > 1 && !std::strcmp(argv[1], "leaf")) return mode_leaf();
-    std::fprintf(stderr, "usage: host_check plan|leaf\n");
+    if (argc > 1 && !std::strcmp(argv[1], "search")) return mode_search();
+    std::fprintf(stderr, "usage: host_check plan|leaf|search\n");
     return 2;
 }

@@ -5,7 +5,8 @@ tests/host/host_check.cpp compiles tde_planner.cpp (merge-tree tables,
 block-to-merge maps, workspace / checkpoint / reverse-pass carving) and the
 device header's leaf QL as plain host C++.  The plan mode checks the tables
 and carvings of 400 random batches; the leaf mode returns eigenvalues and the
-first and last eigenvector rows of one leaf, compared here with LAPACK.
+first and last eigenvector rows of one leaf, compared here with LAPACK; the
+search mode checks the assembly's partition-point searches.
 """
 import os
 import shutil
@@ -43,6 +44,13 @@ def _env():
 def test_plan_tables_and_carving(exe):
     r = subprocess.run([exe, "plan"], capture_output=True, text=True, env=_env(), timeout=600)
     assert r.returncode == 0 and "plan ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
+
+
+def test_assembly_searches(exe):
+    """The assembly's partition-point searches, binary and 8-way, equal a
+    linear count on ascending lists with repeats (lengths 0 to 70000)."""
+    r = subprocess.run([exe, "search"], capture_output=True, text=True, env=_env(), timeout=600)
+    assert r.returncode == 0 and "search ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
 
 
 def _leaf(exe, d, e):
