@@ -2099,15 +2099,27 @@ template <int G, bool WithRoot>
 __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr, int M, long long N,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
-                                                int fuse_max, int nbn) {
+                                                int fuse_max, int nbn, const int* __restrict__ blkm, Grad gr,
+                                                int nbu, int wsearch) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ int sO[kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
+    // reverse pass: the last nbu workgroups gather the parent's adjoints onto
+    // the level's three lists (independent of z-hat, so in the same launch)
+    const int nbl = (int)gridDim.x - nbu;
+    if (WithRoot && (int)blockIdx.x >= nbl) {
+        const long long t = ((long long)blockIdx.x - nbl) * kWG + threadIdx.x;
+        if (t < N) {
+            if (wsearch) body_bwd_unassemble<true>(t, merge_of(mr, blkm, t), mr, w, gr);
+            else body_bwd_unassemble<false>(t, merge_of(mr, blkm, t), mr, w, gr);
+        }
+        return;
+    }
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        lowner_wide<kWideWaves, false>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
+        lowner_wide<kWideWaves, false>((int)blockIdx.x - nbn, nbl - nbn, mr, M, e, pmax, w, WithRoot, items, smem);
         return;
     }
     double* sD = smem;
@@ -2255,13 +2267,6 @@ __global__ __launch_bounds__(kWG) void k_bwd_roots_gather(const MergeRec* __rest
     }
 }
 
-template <bool Wide>
-__global__ __launch_bounds__(kWG) void k_bwd_unassemble(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
-                                                        long long N, Work w, Grad gr) {
-    if (input_nonfinite(w)) return;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < N) body_bwd_unassemble<Wide>(t, merge_of(mr, blkm, t), mr, w, gr);
-}
 
 constexpr int kStageBwd = 1024;
 
@@ -2371,12 +2376,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_poles(const MergeRec* __restrict__ 
 // dL/dz of the negligible-z columns of non-top merges: G lanes per column
 // (the group splits the sum over the merge's roots).  Groups take the
 // level's negligible columns in their compacted order (dpos), so whole
-// waves either work or leave.
+// waves either work or leave.  b: this workgroup's index among those of the
+// step.
 template <int G>
-__global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
-                                                  long long N, Work w, Grad gr, long long cstride) {
-    if (input_nonfinite(w)) return;
-    const long long q = (blockIdx.x * (long long)blockDim.x + threadIdx.x) / G;
+__device__ __forceinline__ void bwd_negl_block(int b, const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                               long long N, const Work& w, const Grad& gr, long long cstride) {
+    const long long q = ((long long)b * blockDim.x + threadIdx.x) / G;
     const int sub = (int)(threadIdx.x % G);
     const long long nneg = N - w.scan[N] - w.scanR[N];
     if (q >= nneg) return;  // group-uniform
@@ -2390,13 +2395,11 @@ __global__ __launch_bounds__(kWG) void k_bwd_negl(const MergeRec* __restrict__ m
     if (sub == 0) gr.gZ[t] = gz;
 }
 
-// dL/drho~ of each merge: sum_k gtot_k / (rho^2 N_k^2), one workgroup per merge.
-__global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ mr, const double* __restrict__ e,
-                                                  const unsigned long long* __restrict__ pmax, Work w, Grad gr,
-                                                  long long cstride, int mstart) {
-    if (input_nonfinite(w)) return;
-    __shared__ double part[kWG / 64];
-    const MergeRec R = mr[blockIdx.x];
+// dL/drho~ of merge m: sum_k gtot_k / (rho^2 N_k^2), one workgroup.
+__device__ __forceinline__ void bwd_grho_block(int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                               const unsigned long long* __restrict__ pmax, const Work& w,
+                                               const Grad& gr, long long cstride, int mstart, double* part) {
+    const MergeRec R = mr[m];
     const MergeSpan sp = merge_span(R, w.scan);
     const double* mu = gr.coef + 3 * cstride + sp.ks;
     double acc = 0.0;
@@ -2409,22 +2412,22 @@ __global__ __launch_bounds__(kWG) void k_bwd_grho(const MergeRec* __restrict__ m
         for (int i = 0; i < kWG / 64; ++i) s += part[i];
         double sgn;
         const double rho = merge_rho(R, e, pmax, &sgn);
-        gr.grho[mstart + blockIdx.x] = sp.K ? s / (rho * rho) : 0.0;
+        gr.grho[mstart + m] = sp.K ? s / (rho * rho) : 0.0;
     }
 }
 
-// Candidates one per lane (grid-stride): those in no run pass straight
-// through, and each group of G lanes then takes, one after another, the runs
-// that start among its G candidates.
+// Candidates one per lane (stride nb workgroups): those in no run pass
+// straight through, and each group of G lanes then takes, one after another,
+// the runs that start among its G candidates.
 template <int G>
-__global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
-                                                  long long N, Work w, Grad gr, long long cstride) {
-    if (input_nonfinite(w)) return;
+__device__ __forceinline__ void bwd_runs_block(int b, int nb, const MergeRec* __restrict__ mr,
+                                               const int* __restrict__ blkm, long long N, const Work& w,
+                                               const Grad& gr, long long cstride) {
     const long long total = w.scanC[N];
     const int lane = (int)(threadIdx.x & 63);
     const int sub = lane % G;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x - sub); g0 < total; g0 += stride) {
+    const long long stride = (long long)nb * blockDim.x;
+    for (long long g0 = (long long)b * blockDim.x + (threadIdx.x - sub); g0 < total; g0 += stride) {
         const long long g = g0 + sub;
         const bool head = g < total && bwd_run_head(g, merge_of(mr, blkm, w.nnpos[g]), mr, w, gr);
         // this group's G bits of the wave's ballot (group-uniform)
@@ -2435,6 +2438,26 @@ __global__ __launch_bounds__(kWG) void k_bwd_runs(const MergeRec* __restrict__ m
             body_bwd_runs<RedGroup<G>>(h, merge_of(mr, blkm, w.nnpos[h]), mr, w, gr, cstride, sub, G);
         }
     }
+}
+
+// The steps of a level after the pole adjoints, in one launch: workgroups
+// [0, nbr) the close-pole runs, [nbr, nbr + nbn) the negligible columns,
+// [nbr + nbn, nbr + nbn + M) one merge's dL/drho~ each.  All three read the
+// root coefficients and the node's adjoints and write disjoint outputs
+// (candidate columns and the runs' scratch, negligible columns, per-merge
+// rho), so they need no order among themselves, and the short ones run in
+// the long ones' shadow instead of after them.
+template <int G>
+__global__ __launch_bounds__(kWG) void k_bwd_defl(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
+                                                  long long N, const double* __restrict__ e,
+                                                  const unsigned long long* __restrict__ pmax, Work w, Grad gr,
+                                                  long long cstride, int mstart, int nbr, int nbn) {
+    if (input_nonfinite(w)) return;
+    __shared__ double part[kWG / 64];
+    const int b = (int)blockIdx.x;
+    if (b < nbr) bwd_runs_block<G>(b, nbr, mr, blkm, N, w, gr, cstride);
+    else if (b < nbr + nbn) bwd_negl_block<G>(b - nbr, mr, blkm, N, w, gr, cstride);
+    else bwd_grho_block(b - nbr - nbn, mr, e, pmax, w, gr, cstride, mstart, part);  // block-uniform
 }
 
 __global__ __launch_bounds__(kWG) void k_bwd_merge(const MergeRec* __restrict__ mr, const int* __restrict__ blkm,
@@ -2716,7 +2739,8 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     }
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
                  fuse_max, nbs, (int)rf);
-    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn);
+    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn,
+                 (const int*)nullptr, Grad{}, 0, 0);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn);
 }
 
@@ -2874,30 +2898,34 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
     return (int)hipGetLastError();
 }
 
+// Reverse pass of a level's roots: z-hat recomputed from the checkpointed
+// roots together with the unassembly of the parent's adjoints (one launch),
+// then the per-root coefficients and the per-pole adjoints.
 template <int G>
-static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                               const Work& w, const Grad& gr, long long cs, void* stream) {
+static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* mr, const int* blkm, int M,
+                               const double* e, const Work& w, const Grad& gr, long long cs, void* stream) {
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
     int nbn, nbw;
     root_grid(N, G, wide, &nbn, &nbw);
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
+    const unsigned nbu = nblk(N, kWG);
     if (wide) TDE_LAUNCH_K(KIND_BACKWARD, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, 0);
-    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min, 0,
-                 nbn);
+    TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw) + nbu, kWG, stream, mr, M, N, e, pm, w,
+                 wide_min, 0, nbn, blkm, gr, (int)nbu, N <= kWideSearchCols ? 1 : 0);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
 }
 
-// The couplings deflation drops (negligible columns, rotated runs), G lanes
-// per column or run.
+// The couplings deflation drops (negligible columns, rotated runs, G lanes
+// per column or run) and the merges' dL/drho~, one launch.
 template <int G>
-static void launch_bwd_defl(long long N, const MergeRec* mr, const int* blkm, const Work& w,
-                            const Grad& gr, long long cs, void* stream) {
-    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_negl<G>, nblk(N * G, kWG), kWG, stream, mr, blkm, N, w, gr, cs);
-    const unsigned gr_runs = nblk(N, kWG);
-    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_runs<G>, gr_runs < 4096u ? gr_runs : 4096u, kWG, stream, mr, blkm, N, w, gr,
-                 cs);
+static void launch_bwd_defl(long long N, int M, const MergeRec* mr, const int* blkm, const double* e,
+                            const Work& w, const Grad& gr, long long cs, int mstart, void* stream) {
+    const unsigned nbr = nblk(N, kWG) < 4096u ? nblk(N, kWG) : 4096u;
+    const unsigned nbn = nblk(N * G, kWG);
+    TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_defl<G>, nbr + nbn + (unsigned)M, kWG, stream, mr, blkm, N, e,
+                 (const unsigned long long*)w.pmax, w, gr, cs, mstart, (int)nbr, (int)nbn);
 }
 
 int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& ck, const double* d,
@@ -2930,25 +2958,19 @@ int enqueue_backward(const Plan& p, const Work& w, const Grad& gr, const Ckpt& c
             TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots_gather, nb < 4096u ? nb : 4096u, kWG, stream, mr, N, wl,
                          (const int*)(ck.org + so), (const double*)(ck.tau + so));
         }
-        if (N <= kWideSearchCols)
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble<true>, nb, kWG, stream, mr, blkm, N, wl, gr);
-        else
-            TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_unassemble<false>, nb, kWG, stream, mr, blkm, N, wl, gr);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
-            case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
-            case 2: launch_bwd_roots_g<2>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
-            case 4: launch_bwd_roots_g<4>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
-            case 8: launch_bwd_roots_g<8>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
-            default: launch_bwd_roots_g<16>(L.smax, p.wide_min, N, mr, M, e, wl, gr, cs, stream); break;
+            case 1: launch_bwd_roots_g<1>(L.smax, p.wide_min, N, mr, blkm, M, e, wl, gr, cs, stream); break;
+            case 2: launch_bwd_roots_g<2>(L.smax, p.wide_min, N, mr, blkm, M, e, wl, gr, cs, stream); break;
+            case 4: launch_bwd_roots_g<4>(L.smax, p.wide_min, N, mr, blkm, M, e, wl, gr, cs, stream); break;
+            case 8: launch_bwd_roots_g<8>(L.smax, p.wide_min, N, mr, blkm, M, e, wl, gr, cs, stream); break;
+            default: launch_bwd_roots_g<16>(L.smax, p.wide_min, N, mr, blkm, M, e, wl, gr, cs, stream); break;
         }
-        TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_grho, (unsigned)M, kWG, stream, mr, e, (const unsigned long long*)w.pmax, wl,
-                     gr, cs, L.mstart);
         switch (lanes_per_root(L.smax, p.sweep_cols)) {
-            case 1: launch_bwd_defl<1>(N, mr, blkm, wl, gr, cs, stream); break;
-            case 2: launch_bwd_defl<2>(N, mr, blkm, wl, gr, cs, stream); break;
-            case 4: launch_bwd_defl<4>(N, mr, blkm, wl, gr, cs, stream); break;
-            case 8: launch_bwd_defl<8>(N, mr, blkm, wl, gr, cs, stream); break;
-            default: launch_bwd_defl<16>(N, mr, blkm, wl, gr, cs, stream); break;
+            case 1: launch_bwd_defl<1>(N, M, mr, blkm, e, wl, gr, cs, L.mstart, stream); break;
+            case 2: launch_bwd_defl<2>(N, M, mr, blkm, e, wl, gr, cs, L.mstart, stream); break;
+            case 4: launch_bwd_defl<4>(N, M, mr, blkm, e, wl, gr, cs, L.mstart, stream); break;
+            case 8: launch_bwd_defl<8>(N, M, mr, blkm, e, wl, gr, cs, L.mstart, stream); break;
+            default: launch_bwd_defl<16>(N, M, mr, blkm, e, wl, gr, cs, L.mstart, stream); break;
         }
         TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_merge, nb, kWG, stream, mr, blkm, N, e, (const unsigned long long*)w.pmax,
                      wl, gr);
