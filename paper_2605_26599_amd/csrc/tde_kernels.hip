@@ -1194,18 +1194,34 @@ __device__ void rows_wide(int bid, int nbw, const MergeRec* __restrict__ mr, int
 constexpr int kRefillMax = 4;
 constexpr long long kRefillLanes = 1048576;
 
+// One merge of at most fuse_max (<= kFoldCap) active roots solved whole by a
+// workgroup of NT threads (roots, Loewner z, rows), staged in `stage`.
+constexpr int kFoldCap = 64;
+template <int NT>
+__device__ void small_merge_fold(int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                 const unsigned long long* __restrict__ pmax, const Work& w, int gmax, int fuse_max,
+                                 double* stage);
+
 template <int G>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(
     const MergeRec* __restrict__ mr, int M, long long N, const double* __restrict__ e,
-    const unsigned long long* __restrict__ pmax, Work w, int wide_min, int fuse_max, int nbn, int refill) {
+    const unsigned long long* __restrict__ pmax, Work w, int wide_min, int fuse_max, int nbn, int refill, int nsm,
+    int gmax) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
     __shared__ int s_next;
+    // the last nsm workgroups solve the level's small merges whole (one each;
+    // the tiles skip them), beside the tiles instead of in a launch of their own
+    const int nbt = (int)gridDim.x - nsm;
+    if ((int)blockIdx.x >= nbt) {
+        small_merge_fold<kWG>((int)blockIdx.x - nbt, mr, e, pmax, w, gmax, fuse_max, smem);
+        return;
+    }
     if ((int)blockIdx.x >= nbn) {
         const int* items = w.witems;
-        secular_wide<kWideWaves>((int)blockIdx.x - nbn, (int)gridDim.x - nbn, mr, M, e, pmax, w, items, smem);
+        secular_wide<kWideWaves>((int)blockIdx.x - nbn, nbt - nbn, mr, M, e, pmax, w, items, smem);
         return;
     }
     double* sD = smem;
@@ -1926,6 +1942,19 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     if (G >= 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else if (G >= 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+}
+
+template <int NT>
+__device__ void small_merge_fold(int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
+                                 const unsigned long long* __restrict__ pmax, const Work& w, int gmax, int fuse_max,
+                                 double* stage) {
+    const MergeRec R = mr[m];
+    const MergeSpan sp = merge_span(R, w.scan);
+    const int K = sp.K;
+    if (K < 1 || K > fuse_max || K > kFoldCap) return;  // block-uniform
+    static_assert(sizeof(SmallStageT<kFoldCap>) <= 2 * kStage * sizeof(double), "stage fits the tiles' LDS");
+    SmallStageT<kFoldCap>& sg = *reinterpret_cast<SmallStageT<kFoldCap>*>(stage);
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax);
 }
 
 // One workgroup of NT threads per merge of the level; CAP >= the level's
@@ -2712,15 +2741,18 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
                            const Work& w, int gmax, int wblocks, int fuse_few, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = level_fuse_max(M, fuse_few);
-    // merges with at most fuse_max active roots: one workgroup each
-    launch_small(smax, mr, M, e, w, gmax, fuse_max, stream);
-    if (smax <= fuse_max) return;  // no merge of the level can have more
     const bool wide = smax >= wmin;
     const int wide_min = wide ? wmin : 0x7fffffff;
     int nbn, nbw;
     root_grid(N, G, wide, &nbn, &nbw, wblocks);
     // every merge too large for k_small_merge is wide: no regular tiles
     if (wide_min <= fuse_max + 1) nbn = 0;
+    // merges with at most fuse_max active roots: one workgroup each, inside
+    // the tiles' secular launch when there are tiles and those merges are
+    // small, else a launch of their own
+    const int nsm = (smax > fuse_max && nbn > 0 && fuse_max <= kFoldCap) ? M : 0;
+    if (nsm == 0) launch_small(smax, mr, M, e, w, gmax, fuse_max, stream);
+    if (smax <= fuse_max) return;  // no merge of the level can have more
     const unsigned grid = (unsigned)(nbn + nbw);
     // one k_wide_items launch serves the three root kernels of the level (on
     // wide-only levels of few merges the secular kernel builds the table)
@@ -2737,8 +2769,8 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
         TDE_LAUNCH_K(KIND_ROWS, k_rows_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, w);
         return;
     }
-    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw), kWG, stream, mr, M, N, e, pm, w, wide_min,
-                 fuse_max, nbs, (int)rf);
+    TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw + nsm), kWG, stream, mr, M, N, e, pm, w, wide_min,
+                 fuse_max, nbs, (int)rf, nsm, gmax);
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn,
                  (const int*)nullptr, Grad{}, 0, 0);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn);
