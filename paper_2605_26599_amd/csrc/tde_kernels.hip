@@ -2736,9 +2736,12 @@ static void launch_level_block(int smax, const MergeRec* mr, int M, const double
         TDE_LAUNCH_K(KIND_LEVEL, (k_level_block<64, 64>), g, 64, stream, mr, e, pm, w, out, gmax);
 }
 
+// no_rows: every merge of the level is a problem's top merge and no rows
+// are requested, so the Loewner and row steps would find nothing to do and
+// are not launched.
 template <int G>
 static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                           const Work& w, int gmax, int wblocks, int fuse_few, void* stream) {
+                           const Work& w, int gmax, int wblocks, int fuse_few, bool no_rows, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = level_fuse_max(M, fuse_few);
     const bool wide = smax >= wmin;
@@ -2765,25 +2768,27 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
         const unsigned bw = kWideWavesOnly * 64;
         TDE_LAUNCH_K(KIND_SECULAR, k_secular_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w,
                      wide_min, fuse_max, own_items);
+        if (no_rows) return;
         TDE_LAUNCH_K(KIND_LOWNER, k_lowner_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
         TDE_LAUNCH_K(KIND_ROWS, k_rows_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, w);
         return;
     }
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw + nsm), kWG, stream, mr, M, N, e, pm, w, wide_min,
                  fuse_max, nbs, (int)rf, nsm, gmax);
+    if (no_rows) return;
     TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn,
                  (const int*)nullptr, Grad{}, 0, 0);
     TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn);
 }
 
 static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                         const Work& w, int gmax, int wblocks, int fuse_few, void* stream) {
+                         const Work& w, int gmax, int wblocks, int fuse_few, bool no_rows, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
-        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
-        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
-        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
-        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, stream); break;
+        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
+        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
+        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
+        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
+        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
     }
 }
 
@@ -2919,7 +2924,8 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
         launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max),
-                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few, stream);
+                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few,
+                     L.all_root && !w.rows_out, stream);
         if (N <= kWideSearchCols)
             TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble<true>, nb, kWG, stream, mr, blkm, N,
                          (const unsigned long long*)w.pmax, wl, out);

@@ -19,6 +19,7 @@ struct LevelInfo {
     int wpstart;  // levels of merges of at most kLeafMax columns: first entry of the
                   // in-wave pack table (first merge of every pack, then M) in h_blkm
     int nwp;      // packs of such a level (0: none)
+    int all_root; // 1 when every merge of the level is a problem's top merge
 };
 
 struct Plan {

@@ -67,6 +67,9 @@ int plan_host(Plan* p) {
             }
             p->h_blkm.push_back(info.M);
         }
+        info.all_root = 1;
+        for (int j = 0; j < info.M; ++j)
+            if (!(t.merges[info.mstart + j].flags & MF_ROOT)) info.all_root = 0;
         maxM = std::max(maxM, info.M);
         maxN = std::max(maxN, info.N);
         p->levels.push_back(info);

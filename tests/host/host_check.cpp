@@ -65,6 +65,7 @@ static void check_plan(const std::vector<long long>& offs, int leaf, bool dc) {
         CHECK(I.mstart >= 0 && I.mstart + I.M <= (int)p.h_merges.size());
         long long pk = 0;
         int smax = 0;
+        bool all_root = true;
         std::vector<std::pair<long long, long long>> made;
         for (int m = 0; m < I.M; ++m) {
             const MergeRec& R = p.h_merges[(size_t)(I.mstart + m)];
@@ -74,11 +75,13 @@ static void check_plan(const std::vector<long long>& offs, int leaf, bool dc) {
             CHECK(R.off >= offs[R.prob] && R.off + R.nL + R.nR <= offs[R.prob + 1]);
             const bool whole = (R.off == offs[R.prob] && R.off + R.nL + R.nR == offs[R.prob + 1]);
             CHECK(((R.flags & MF_ROOT) != 0) == whole);
+            all_root = all_root && whole;
             pk += R.nL + R.nR;
             smax = std::max(smax, R.nL + R.nR);
             made.push_back({R.off, (long long)(R.nL + R.nR)});
         }
         CHECK(pk == I.N && smax == I.smax);
+        CHECK((I.all_root != 0) == all_root);  // levels whose Loewner and row steps are skipped
         for (auto& x : made) done.insert(x);
         // block-to-merge map: entry b names the merge holding column min(b*kWG, N-1)
         CHECK(I.bstart == (int)bi);
