@@ -984,14 +984,19 @@ TDE_DEV void store_rows(const Work& w, long long P, double bl, double bh) {
     if (w.qlast) w.qlast[P] = sg * bh;
 }
 
+//
+// part 1 places only the roots (i < K), part 2 only the deflated columns, so
+// that the roots can be placed by the kernels that finish them.
 template <bool Wide = false>
 TDE_DEV void body_assemble(long long t, int m, const MergeRec* __restrict__ mr,
-                           const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out) {
+                           const unsigned long long* __restrict__ pmax, const Work& w, double* __restrict__ out,
+                           int part = 0) {
     const MergeRec R = mr[m];
     const int s = R.nL + R.nR;
     const int i = (int)(t - R.pk);
     const long long ks = w.scan[R.pk];
     const int K = (int)(w.scan[R.pk + s] - ks);
+    if ((part == 1 && i >= K) || (part == 2 && i < K)) return;
     const long long rs = w.scanR[R.pk];
     const int nr = (int)(w.scanR[R.pk + s] - rs);
     const long long ns = R.pk - ks - rs;

@@ -1200,13 +1200,13 @@ constexpr int kFoldCap = 64;
 template <int NT>
 __device__ void small_merge_fold(int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                  const unsigned long long* __restrict__ pmax, const Work& w, int gmax, int fuse_max,
-                                 double* stage);
+                                 double* stage, double* out, int amode);
 
 template <int G>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_secular(
     const MergeRec* __restrict__ mr, int M, long long N, const double* __restrict__ e,
     const unsigned long long* __restrict__ pmax, Work w, int wide_min, int fuse_max, int nbn, int refill, int nsm,
-    int gmax) {
+    int gmax, double* __restrict__ out, int amode) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ long long s_r0;
@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     // the tiles skip them), beside the tiles instead of in a launch of their own
     const int nbt = (int)gridDim.x - nsm;
     if ((int)blockIdx.x >= nbt) {
-        small_merge_fold<kWG>((int)blockIdx.x - nbt, mr, e, pmax, w, gmax, fuse_max, smem);
+        small_merge_fold<kWG>((int)blockIdx.x - nbt, mr, e, pmax, w, gmax, fuse_max, smem, out, amode);
         return;
     }
     if ((int)blockIdx.x >= nbn) {
@@ -1917,10 +1917,15 @@ using SmallStage = SmallStageT<kFuseMax>;
 // Roots, Loewner z and rows of one merge with 1 <= K <= CAP active columns at
 // active index ks (the whole workgroup; block-uniform arguments).  gmax caps
 // the lanes per root (4, 8 or 16); the results do not depend on it.
+// With amr (the level's merge table, the merge at index am), the merge's roots
+// are then also placed at their parent positions (body_assemble part 1;
+// awide: 8-way searches), to aout for a problem's top merge.
 template <int NT, class Stage>
 __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long long ks, const double* e,
                                                   const unsigned long long* __restrict__ pmax, const Work& w,
-                                                  Stage& sg, int cbase, int gmax) {
+                                                  Stage& sg, int cbase, int gmax,
+                                                  const MergeRec* __restrict__ amr = nullptr, int am = 0,
+                                                  double* __restrict__ aout = nullptr, int awide = 0) {
     for (int i = threadIdx.x; i < K; i += NT) {
         sg.D[i] = w.Da[ks + i];
         sg.W[i] = w.Wa[ks + i];
@@ -1942,19 +1947,26 @@ __device__ __forceinline__ void small_merge_solve(const MergeRec& R, int K, long
     if (G >= 16) small_merge_body<NT, 16>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else if (G >= 8) small_merge_body<NT, 8>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
     else small_merge_body<NT, 4>(R, K, ks, rho, w, sg.D, sg.W, sg.Z, sg.T, sg.H, sg.L, sg.R, sg.O, cbase);
+    if (amr != nullptr) {  // block-uniform
+        __syncthreads();    // every root's value and rows are stored
+        for (int k = threadIdx.x; k < K; k += NT) {
+            if (awide) body_assemble<true>(R.pk + k, am, amr, pmax, w, aout, 1);
+            else body_assemble<false>(R.pk + k, am, amr, pmax, w, aout, 1);
+        }
+    }
 }
 
 template <int NT>
 __device__ void small_merge_fold(int m, const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                  const unsigned long long* __restrict__ pmax, const Work& w, int gmax, int fuse_max,
-                                 double* stage) {
+                                 double* stage, double* out, int amode) {
     const MergeRec R = mr[m];
     const MergeSpan sp = merge_span(R, w.scan);
     const int K = sp.K;
     if (K < 1 || K > fuse_max || K > kFoldCap) return;  // block-uniform
     static_assert(sizeof(SmallStageT<kFoldCap>) <= 2 * kStage * sizeof(double), "stage fits the tiles' LDS");
     SmallStageT<kFoldCap>& sg = *reinterpret_cast<SmallStageT<kFoldCap>*>(stage);
-    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax);
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax, amode ? mr : nullptr, m, out, amode == 2);
 }
 
 // One workgroup of NT threads per merge of the level; CAP >= the level's
@@ -1962,14 +1974,15 @@ __device__ void small_merge_fold(int m, const MergeRec* __restrict__ mr, const d
 template <int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_small_merge(const MergeRec* __restrict__ mr, const double* __restrict__ e,
                                                     const unsigned long long* __restrict__ pmax, Work w, int gmax,
-                                                    int fuse_max) {
+                                                    int fuse_max, double* __restrict__ out, int amode) {
     if (input_nonfinite(w)) return;
     const MergeRec R = mr[blockIdx.x];
     const MergeSpan sp = merge_span(R, w.scan);
     const int K = sp.K;
     if (K < 1 || K > fuse_max || K > CAP) return;  // block-uniform
     __shared__ SmallStageT<CAP> sg;
-    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax);
+    small_merge_solve<NT>(R, K, sp.ks, e, pmax, w, sg, CNT_SM_TERMS, gmax, amode ? mr : nullptr, (int)blockIdx.x, out,
+                          amode == 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -2129,20 +2142,29 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
                                                 const double* __restrict__ e,
                                                 const unsigned long long* __restrict__ pmax, Work w, int wide_min,
                                                 int fuse_max, int nbn, const int* __restrict__ blkm, Grad gr,
-                                                int nbu, int wsearch) {
+                                                int nbu, int wsearch, double* __restrict__ out) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[2 * kStage];
     __shared__ int sO[kStage];
     __shared__ long long s_r0;
     __shared__ int s_staged;
-    // reverse pass: the last nbu workgroups gather the parent's adjoints onto
-    // the level's three lists (independent of z-hat, so in the same launch)
+    // the last nbu workgroups: in the reverse pass they gather the parent's
+    // adjoints onto the level's three lists, in the forward pass they place
+    // the deflated columns at their parent positions (body_assemble part 2;
+    // the roots are placed by the kernels that finish them); neither needs
+    // z-hat, so both share its launch
     const int nbl = (int)gridDim.x - nbu;
-    if (WithRoot && (int)blockIdx.x >= nbl) {
+    if ((int)blockIdx.x >= nbl) {
         const long long t = ((long long)blockIdx.x - nbl) * kWG + threadIdx.x;
         if (t < N) {
-            if (wsearch) body_bwd_unassemble<true>(t, merge_of(mr, blkm, t), mr, w, gr);
-            else body_bwd_unassemble<false>(t, merge_of(mr, blkm, t), mr, w, gr);
+            const int m = merge_of(mr, blkm, t);
+            if (WithRoot) {
+                if (wsearch) body_bwd_unassemble<true>(t, m, mr, w, gr);
+                else body_bwd_unassemble<false>(t, m, mr, w, gr);
+            } else {
+                if (wsearch) body_assemble<true>(t, m, mr, pmax, w, out, 2);
+                else body_assemble<false>(t, m, mr, pmax, w, out, 2);
+            }
         }
         return;
     }
@@ -2188,9 +2210,14 @@ __global__ __launch_bounds__(kWG) void k_lowner(const MergeRec* __restrict__ mr,
     count_add(w.counters, CNT_LOW_PAIRS, pairs);
 }
 
+// amode 1 or 2 (no wide blocks then): each root is also placed at its parent
+// position by the lane that stored its rows (body_assemble part 1; 2: 8-way
+// searches), to out for a problem's top merge.
 template <int G>
 __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, int M, long long N, Work w,
-                                              int wide_min, int fuse_max, int nbn) {
+                                              int wide_min, int fuse_max, int nbn,
+                                              const unsigned long long* __restrict__ pmax, double* __restrict__ out,
+                                              int amode) {
     if (input_nonfinite(w)) return;
     __shared__ double smem[4 * kStageRows];
     __shared__ long long s_r0;
@@ -2234,6 +2261,11 @@ __global__ __launch_bounds__(kWG) void k_rows(const MergeRec* __restrict__ mr, i
             if (ns >= 0) body_rows<RedGroup<G>>(g, m, mr, w, sub, G, sD, sH, sL, sR, r0);
             else body_rows<RedGroup<G>>(g, m, mr, w, sub, G, w.Da, w.zhat, w.RLa, w.RHa, 0);
             if (sub == 0 && (!(mr[m].flags & MF_ROOT) || w.rows_out)) pairs += (unsigned long long)merge_span(mr[m], w.scan).K;
+            if (amode && sub == 0) {
+                const long long t = mr[m].pk + (g - merge_span(mr[m], w.scan).ks);
+                if (amode == 2) body_assemble<true>(t, m, mr, pmax, w, out, 1);
+                else body_assemble<false>(t, m, mr, pmax, w, out, 1);
+            }
         }
         __syncthreads();
     }
@@ -2699,22 +2731,28 @@ static int level_fuse_max(int M, int fuse_few) { return (M < kFewMerges && fuse_
 // Fused small merges of one level: a workgroup per merge; on levels of many
 // merges its shape follows the level's largest merge (LDS room and threads
 // for that many active columns), on levels of few it is the full size.
+// Assembly searches its three lists 8 ways at a time on levels of at most
+// kWideSearchCols columns (few threads, each latency-bound: uniform n = 65536,
+// 94 -> 77 us of assembly per solve), binary on larger levels (a batch of
+// 4096 problems: the 8-way search was 2% slower there).
+constexpr long long kWideSearchCols = 1LL << 18;
+
 static void launch_small(int smax, const MergeRec* mr, int M, const double* e, const Work& w, int gmax, int fuse_max,
-                         void* stream) {
+                         double* out, int amode, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const unsigned g = (unsigned)M;
     if (smax >= kFuseWideS)
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<2 * kFuseThreads, kFuseMax>), g, 2 * kFuseThreads, stream, mr, e, pm,
-                     w, gmax, fuse_max);
+                     w, gmax, fuse_max, out, amode);
     else if (smax > 256 || M < kFewMerges)
         TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<kFuseThreads, kFuseMax>), g, kFuseThreads, stream, mr, e, pm, w, gmax,
-                     fuse_max);
+                     fuse_max, out, amode);
     else if (smax > 128)
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<256, 256>), g, 256, stream, mr, e, pm, w, gmax, fuse_max);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<256, 256>), g, 256, stream, mr, e, pm, w, gmax, fuse_max, out, amode);
     else if (smax > 64)
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 128>), g, 128, stream, mr, e, pm, w, gmax, fuse_max);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 128>), g, 128, stream, mr, e, pm, w, gmax, fuse_max, out, amode);
     else
-        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax, fuse_max);
+        TDE_LAUNCH_K(KIND_SMALL, (k_small_merge<128, 64>), g, 128, stream, mr, e, pm, w, gmax, fuse_max, out, amode);
 }
 
 // Levels of at most this many merges of more than 128 columns (at most one
@@ -2749,8 +2787,9 @@ static void launch_level_block(int smax, const MergeRec* mr, int M, const double
 // are requested, so the Loewner and row steps would find nothing to do and
 // are not launched.
 template <int G>
-static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                           const Work& w, int gmax, int wblocks, int fuse_few, bool no_rows, void* stream) {
+static bool launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, const int* blkm, int M,
+                           const double* e, const Work& w, double* out, int gmax, int wblocks, int fuse_few,
+                           bool no_rows, void* stream) {
     const unsigned long long* pm = (const unsigned long long*)w.pmax;
     const int fuse_max = level_fuse_max(M, fuse_few);
     const bool wide = smax >= wmin;
@@ -2759,12 +2798,18 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
     root_grid(N, G, wide, &nbn, &nbw, wblocks);
     // every merge too large for k_small_merge is wide: no regular tiles
     if (wide_min <= fuse_max + 1) nbn = 0;
+    // Levels whose roots all come from the fused workgroups and the regular
+    // tiles, with row steps: the kernels that finish a root also place it,
+    // and the Loewner launch places the deflated columns, so the level needs
+    // no assembly launch of its own (the caller is told so).
+    const bool placed = !no_rows && smax > fuse_max && nbn > 0 && nbw == 0;
+    const int amode = placed ? (N <= kWideSearchCols ? 2 : 1) : 0;
     // merges with at most fuse_max active roots: one workgroup each, inside
     // the tiles' secular launch when there are tiles and those merges are
     // small, else a launch of their own
     const int nsm = (smax > fuse_max && nbn > 0 && fuse_max <= kFoldCap) ? M : 0;
-    if (nsm == 0) launch_small(smax, mr, M, e, w, gmax, fuse_max, stream);
-    if (smax <= fuse_max) return;  // no merge of the level can have more
+    if (nsm == 0) launch_small(smax, mr, M, e, w, gmax, fuse_max, out, amode, stream);
+    if (smax <= fuse_max) return false;  // no merge of the level can have more
     const unsigned grid = (unsigned)(nbn + nbw);
     // one k_wide_items launch serves the three root kernels of the level (on
     // wide-only levels of few merges the secular kernel builds the table)
@@ -2777,27 +2822,33 @@ static void launch_roots_g(int smax, int wmin, long long N, const MergeRec* mr, 
         const unsigned bw = kWideWavesOnly * 64;
         TDE_LAUNCH_K(KIND_SECULAR, k_secular_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w,
                      wide_min, fuse_max, own_items);
-        if (no_rows) return;
+        if (no_rows) return false;
         TDE_LAUNCH_K(KIND_LOWNER, k_lowner_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, e, pm, w);
         TDE_LAUNCH_K(KIND_ROWS, k_rows_wide<kWideWavesOnly>, (unsigned)nbw, bw, stream, mr, M, w);
-        return;
+        return false;
     }
     TDE_LAUNCH_K(KIND_SECULAR, k_secular<G>, (unsigned)(nbs + nbw + nsm), kWG, stream, mr, M, N, e, pm, w, wide_min,
-                 fuse_max, nbs, (int)rf, nsm, gmax);
-    if (no_rows) return;
-    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max, nbn,
-                 (const int*)nullptr, Grad{}, 0, 0);
-    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn);
+                 fuse_max, nbs, (int)rf, nsm, gmax, out, amode);
+    if (no_rows) return false;
+    const unsigned nba = placed ? nblk(N, kWG) : 0u;
+    TDE_LAUNCH_K(KIND_LOWNER, (k_lowner<G, false>), grid + nba, kWG, stream, mr, M, N, e, pm, w, wide_min, fuse_max,
+                 nbn, blkm, Grad{}, (int)nba, N <= kWideSearchCols ? 1 : 0, out);
+    TDE_LAUNCH_K(KIND_ROWS, k_rows<G>, grid, kWG, stream, mr, M, N, w, wide_min, fuse_max, nbn, pm, out, amode);
+    return placed;
 }
 
-static void launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, int M, const double* e,
-                         const Work& w, int gmax, int wblocks, int fuse_few, bool no_rows, void* stream) {
+// Returns true when the level's columns were placed at their parent
+// positions by the root kernels (no assembly launch needed).
+static bool launch_roots(int smax, int cols, int wmin, long long N, const MergeRec* mr, const int* blkm, int M,
+                         const double* e, const Work& w, double* out, int gmax, int wblocks, int fuse_few,
+                         bool no_rows, void* stream) {
     switch (lanes_per_root(smax, cols)) {
-        case 1: launch_roots_g<1>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
-        case 2: launch_roots_g<2>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
-        case 4: launch_roots_g<4>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
-        case 8: launch_roots_g<8>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
-        default: launch_roots_g<16>(smax, wmin, N, mr, M, e, w, gmax, wblocks, fuse_few, no_rows, stream); break;
+        case 1: return launch_roots_g<1>(smax, wmin, N, mr, blkm, M, e, w, out, gmax, wblocks, fuse_few, no_rows, stream);
+        case 2: return launch_roots_g<2>(smax, wmin, N, mr, blkm, M, e, w, out, gmax, wblocks, fuse_few, no_rows, stream);
+        case 4: return launch_roots_g<4>(smax, wmin, N, mr, blkm, M, e, w, out, gmax, wblocks, fuse_few, no_rows, stream);
+        case 8: return launch_roots_g<8>(smax, wmin, N, mr, blkm, M, e, w, out, gmax, wblocks, fuse_few, no_rows, stream);
+        default:
+            return launch_roots_g<16>(smax, wmin, N, mr, blkm, M, e, w, out, gmax, wblocks, fuse_few, no_rows, stream);
     }
 }
 
@@ -2866,12 +2917,6 @@ static int leaves_per_wave(int nleaves) {
     return per;
 }
 
-// Assembly searches its three lists 8 ways at a time on levels of at most
-// kWideSearchCols columns (few threads, each latency-bound: uniform n = 65536,
-// 94 -> 77 us of assembly per solve), binary on larger levels (a batch of
-// 4096 problems: the 8-way search was 2% slower there).
-constexpr long long kWideSearchCols = 1LL << 18;
-
 int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e, double* out, void* stream,
                   const Ckpt* ck, const Ckpt* xsrc) {
     if (p.ntot == 0) return 0;
@@ -2932,10 +2977,13 @@ int enqueue_solve(const Plan& p, const Work& w, const double* d, const double* e
         }
         launch_merge(KIND_MERGE, L, mr, blkm, e, wl, stream);
         enqueue_deflate(mr, blkm, N, wl, stream);
-        launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, M, e, wl, fused_gmax(M, p.group_max),
-                     p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few,
-                     L.all_root && !w.rows_out, stream);
-        if (N <= kWideSearchCols)
+        const bool placed = launch_roots(L.smax, p.sweep_cols, p.wide_min, N, mr, blkm, M, e, wl, out,
+                                         fused_gmax(M, p.group_max),
+                                         p.wide_blocks > 0 ? p.wide_blocks : (int)kWideGridMax, p.fuse_few,
+                                         L.all_root && !w.rows_out, stream);
+        if (placed)
+            continue;
+        else if (N <= kWideSearchCols)
             TDE_LAUNCH_K(KIND_ASSEMBLE, k_assemble<true>, nb, kWG, stream, mr, blkm, N,
                          (const unsigned long long*)w.pmax, wl, out);
         else
@@ -2959,7 +3007,7 @@ static void launch_bwd_roots_g(int smax, int wmin, long long N, const MergeRec* 
     const unsigned nbu = nblk(N, kWG);
     if (wide) TDE_LAUNCH_K(KIND_BACKWARD, k_wide_items, 1, 1024, stream, mr, M, w, wide_min, 0);
     TDE_LAUNCH_K(KIND_BACKWARD, (k_lowner<G, true>), (unsigned)(nbn + nbw) + nbu, kWG, stream, mr, M, N, e, pm, w,
-                 wide_min, 0, nbn, blkm, gr, (int)nbu, N <= kWideSearchCols ? 1 : 0);
+                 wide_min, 0, nbn, blkm, gr, (int)nbu, N <= kWideSearchCols ? 1 : 0, (double*)nullptr);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_roots<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
     TDE_LAUNCH_K(KIND_BACKWARD, k_bwd_poles<G>, (unsigned)nbn, kWG, stream, mr, N, w, gr, cs);
 }

@@ -94,6 +94,24 @@ def test_selrows_match_oracle(tde, fam, leaf):
         _compare(d, e, rows, lam, Q)
 
 
+def test_selrows_with_fuse_few_tiles(tde):
+    """Requested rows when the larger merges of few-merge levels take the
+    regular tiles (fuse_few 32, no wide sweeps): those levels' columns are
+    then placed by the root kernels themselves, with no assembly launch."""
+    g = np.random.default_rng(5)
+    tde.set_defaults(fuse_few=32, wide_min=1 << 30)
+    try:
+        for fam, n in [("uniform", 4097), ("normal", 3000), ("clustered", 2049), ("toeplitz", 1000)]:
+            pick = list(g.choice(n, 6, replace=False))
+            rows = [0, n - 1] + pick + [pick[0]]
+            _step(f"selrows fuse_few=32 tiles fam={fam} n={n}")
+            d, e = tdgen.tridiag(fam, n, cfg=tdgen.CFG_TEST)
+            lam, Q = _sel(tde, d, e, rows, leaf=32)
+            _compare(d, e, rows, lam, Q)
+    finally:
+        tde.set_defaults()
+
+
 def test_selrows_gauss_legendre(tde):
     n = 300
     k = np.arange(1, n, dtype=np.float64)
